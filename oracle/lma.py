@@ -1,0 +1,189 @@
+"""The Lattice Multislice Algorithm, written from Sec. 4.2 of the paper. TEST INFRASTRUCTURE ONLY.
+
+Steps in the paper's order (Fig. lma_pseudocode):
+  initialisation  input wave u (here the probe, Sec. 4.2.3: u = psi_0^init), input-wave
+                  lattice I and its every-f-th sublattice I_f (Sec. 4.2.1, option (i)),
+                  L nearest translates per probe (option (iii)), least-squares
+                  coefficients (Sec. 4.2.2) reused across probes (eqs.
+                  lma_approximation_exit1 / lma_approximation_exit2)
+  step 1          U_i = multislice(u_i) for i in I_f
+  step 2          psi_p^exit ~ sum_j alpha_{p,j} U_{i_j}, then the detector (Sec. 3.1)
+
+Readings (the paper is silent or garbled):
+  * translate u_i(x) = u(x - i) (Sec. 2 definition; the later u o t_i with t_i(x) = x + i
+    has the opposite sign and is not used);
+  * lattice cover: R_x r_x = l_x, the offset free (the printed cover equation subtracts
+    the offset, which cannot hold for the paper's own I = P + p/2);
+  * the offset of I is given as a fraction of the spacing r of I and is kept exact;
+  * the coefficient-reuse structure is taken between P and I_f: along each axis one of
+    P and R/f must divide the other (Case 1 / Case 2), and the number of coefficient sets
+    along that axis is P / gcd(P, R/f);
+  * "the L closest input waves": rank by squared periodic distance, minimum-image offset
+    taken in [-l/2, l/2); exact ties broken by the offset (probe minus translate) in y,
+    then in x, smaller first. Distances are exact rationals;
+  * coefficients are the minimum-norm least-squares solution over the whole grid
+    (numpy.linalg.lstsq, rcond=None).
+"""
+from __future__ import annotations
+
+from fractions import Fraction
+from math import gcd
+
+import numpy as np
+
+from . import physics as ph
+from .multislice import Setup, multislice
+
+
+def _frac(x) -> Fraction:
+    return x if isinstance(x, Fraction) else Fraction(x).limit_denominator(1 << 24)
+
+
+def _min_image(d: Fraction, length: Fraction) -> Fraction:
+    """Periodic offset in [-l/2, l/2)."""
+    half = length / 2
+    return (d + half) % length - half
+
+
+class Lattice:
+    """Probe lattice P and input-wave lattice I_f with the nearest-translate rule."""
+
+    def __init__(self, setup: Setup, R, f: int, offset_frac, L: int):
+        self.setup = setup
+        self.Rx, self.Ry = int(R[0]), int(R[1])
+        self.f = int(f)
+        if self.Rx % self.f or self.Ry % self.f:
+            raise ValueError("R must be a multiple of f (Sec. 4.2.1, option (i))")
+        self.Rfx, self.Rfy = self.Rx // self.f, self.Ry // self.f
+        self.L = int(L)
+        if not 1 <= self.L <= self.Rfx * self.Rfy:
+            raise ValueError("L out of range")
+        self.lx, self.ly = Fraction(setup.lx), Fraction(setup.ly)
+        self.rx, self.ry = self.lx / self.Rx, self.ly / self.Ry
+        self.ox, self.oy = _frac(offset_frac[0]) * self.rx, _frac(offset_frac[1]) * self.ry
+        Px, Py = setup.Px, setup.Py
+        for P, Rf in ((Px, self.Rfx), (Py, self.Rfy)):
+            if P % Rf and Rf % P:
+                raise ValueError("probe and input-wave lattices incompatible (Case 1 / Case 2)")
+        self.ncls_x = Px // gcd(Px, self.Rfx)
+        self.ncls_y = Py // gcd(Py, self.Rfy)
+
+    # --- positions -----------------------------------------------------------------
+    def translate_position(self, a: int, b: int):
+        """Exact position of I_f point (a, b): a f r_x e1 + b f r_y e2 + I_offset."""
+        return (a * self.f * self.rx + self.ox, b * self.f * self.ry + self.oy)
+
+    def probe_position_exact(self, a: int, b: int):
+        return (a * self.lx / self.setup.Px, b * self.ly / self.setup.Py)
+
+    @property
+    def n_translates(self) -> int:
+        return self.Rfx * self.Rfy
+
+    def translate_index(self, a: int, b: int) -> int:
+        return b * self.Rfx + a
+
+    # --- option (iii): the L closest input waves -----------------------------------
+    def nearest(self, a: int, b: int):
+        """I_{f,p,L} for probe (a, b) as a list of (ta, tb) translate indices, nearest first."""
+        px, py = self.probe_position_exact(a, b)
+        keys = []
+        for tb in range(self.Rfy):
+            for ta in range(self.Rfx):
+                tx, ty = self.translate_position(ta, tb)
+                dx = _min_image(px - tx, self.lx)
+                dy = _min_image(py - ty, self.ly)
+                keys.append((dx * dx + dy * dy, dy, dx, ta, tb))
+        keys.sort()
+        return [(k[3], k[4]) for k in keys[:self.L]]
+
+    def coefficient_class(self, a: int, b: int):
+        """Index of the coefficient set used by probe (a, b) (Case 1: one set; Case 2: c*d)."""
+        return (a % self.ncls_x, b % self.ncls_y)
+
+
+def translate_wave(setup: Setup, spec_u: np.ndarray, pos) -> np.ndarray:
+    """u_i = u(. - i) on the grid, by Fourier modulation (exact roll for whole-pixel shifts)."""
+    return np.fft.ifft2(ph.shift_spectrum(spec_u, setup.lx, setup.ly, (float(pos[0]), float(pos[1]))))
+
+
+def least_squares(setup: Setup, lat: Lattice, spec_u: np.ndarray, a: int, b: int):
+    """alpha = argmin || psi_p^init - sum_j alpha_j u_{i_j} ||_2 over the grid (Sec. 4.2.2),
+    minimum-norm solution; returns (alpha, neighbours, relative residual)."""
+    nbr = lat.nearest(a, b)
+    B = np.stack([translate_wave(setup, spec_u, lat.translate_position(ta, tb)).ravel()
+                  for ta, tb in nbr], axis=1)
+    target = setup.probe(a, b).ravel()
+    alpha, *_ = np.linalg.lstsq(B, target, rcond=None)
+    res = np.linalg.norm(target - B @ alpha) / np.linalg.norm(target)
+    return alpha, nbr, res
+
+
+class LMA:
+    """LMA with u = psi_0^init (Sec. 4.2.3). Coefficients are computed once per class
+    (the Case 1 / Case 2 reuse of Sec. 4.2.2)."""
+
+    def __init__(self, setup: Setup, lat: Lattice, spec_u: np.ndarray | None = None):
+        self.setup, self.lat = setup, lat
+        self.spec_u = setup.spec0 if spec_u is None else spec_u
+        self.alpha = {}
+        self.residual = {}
+        for sy in range(lat.ncls_y):
+            for sx in range(lat.ncls_x):
+                al, _, res = least_squares(setup, lat, self.spec_u, sx, sy)
+                self.alpha[(sx, sy)] = al
+                self.residual[(sx, sy)] = res
+
+    def approximant(self, a: int, b: int) -> np.ndarray:
+        """sum_j alpha_j u_{i_j} for probe (a, b) in real space."""
+        al = self.alpha[self.lat.coefficient_class(a, b)]
+        nbr = self.lat.nearest(a, b)
+        out = np.zeros((self.setup.ny, self.setup.nx), dtype=np.complex128)
+        for c, (ta, tb) in zip(al, nbr):
+            out += c * translate_wave(self.setup, self.spec_u, self.lat.translate_position(ta, tb))
+        return out
+
+    def propagate(self, potential: np.ndarray, translates, batch: int = 16) -> dict:
+        """Step 1: U_i for the given (ta, tb) translates; returns {(ta, tb): DFT(U_i)}."""
+        out = {}
+        translates = list(translates)
+        for s in range(0, len(translates), batch):
+            chunk = translates[s:s + batch]
+            u0 = np.stack([translate_wave(self.setup, self.spec_u, self.lat.translate_position(ta, tb))
+                           for ta, tb in chunk])
+            ex = np.fft.fft2(multislice(u0, potential, self.setup.sigma, self.setup.prop))
+            for t, e in zip(chunk, ex):
+                out[t] = e
+        return out
+
+    def needed_translates(self, probes):
+        need = []
+        seen = set()
+        for a, b in probes:
+            for t in self.lat.nearest(a, b):
+                if t not in seen:
+                    seen.add(t)
+                    need.append(t)
+        return need
+
+    def image(self, potential: np.ndarray, probes=None, basis: dict | None = None) -> np.ndarray:
+        """Step 2 plus the detector: float64 [n_det][Py][Px], NaN where not computed."""
+        st = self.setup
+        if probes is None:
+            probes = [(a, b) for b in range(st.Py) for a in range(st.Px)]
+        probes = list(probes)
+        if basis is None:
+            basis = self.propagate(potential, self.needed_translates(probes))
+        img = np.full((len(st.detectors), st.Py, st.Px), np.nan)
+        for a, b in probes:
+            al = self.alpha[self.lat.coefficient_class(a, b)]
+            spec = np.zeros((st.ny, st.nx), dtype=np.complex128)
+            for c, t in zip(al, self.lat.nearest(a, b)):
+                spec += c * basis[t]
+            img[:, b, a] = ph.detector_values(spec, st.masks)
+        return img
+
+
+def phonon_average(images) -> np.ndarray:
+    """Frozen-phonon image: the mean of the per-configuration images (Sec. 3.1)."""
+    return np.mean(np.stack(list(images)), axis=0)

@@ -1,0 +1,182 @@
+"""Seeded synthetic crystal specimens and the named workloads.
+
+A specimen is a set of atom sites on a simple-cubic or FCC lattice inside a periodic
+lx x ly cell of thickness nslices*dz. Each site carries a projected-potential amplitude
+(V*Angstrom, read as the peak value of its Gaussian). A frozen-phonon configuration
+displaces every site by independent N(0, sigma_d^2) offsets per coordinate. The
+potential of slice j is the sum, over the atoms whose displaced z falls in slice j, of
+isotropic Gaussians of standard deviation 0.3 Angstrom evaluated on the pixel grid
+with periodic minimum-image distances and truncated at 2.4 Angstrom per axis.
+
+Seeds: ``numpy.random.default_rng([workload_id, stream, index])``; species draws use
+stream 0 (fixed across phonon configurations), displacements of configuration c use
+stream 1, index c.
+
+The result is float32 [nslices][ny][nx]; every consumer (GPU path and oracle) reads
+the same float32 array.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+import math
+
+import numpy as np
+
+ATOM_SIGMA = 0.3     # Angstrom, Gaussian width of one projected atom
+ATOM_CUTOFF = 2.4    # Angstrom, per-axis truncation of the Gaussian
+
+
+@dataclass(frozen=True)
+class Workload:
+    name: str
+    wid: int                      # seed component
+    nx: int
+    ny: int
+    lx: float                     # Angstrom
+    ly: float
+    nslices: int
+    dz: float                     # Angstrom
+    lattice: str                  # "sc" | "fcc"
+    a: float                      # lattice constant, Angstrom
+    amplitudes: tuple             # V*Angstrom per species
+    probs: tuple                  # species probabilities
+    sigma_d: float                # displacement std, Angstrom
+    kv: float                     # accelerating voltage, kV
+    alpha_mrad: float             # probe aperture semi-angle
+    defocus: float                # Z, Angstrom
+    cs: float                     # C_s, Angstrom
+    bandlimit: float              # fraction of Nyquist
+    scan: tuple                   # (Px, Py)
+    basis_px: int                 # spacing of the propagated translate lattice, pixels
+    offset_frac: tuple            # translate-lattice offset as a fraction of its spacing
+    L: int                        # nearest translates per probe
+    n_phonons: int
+    detectors: tuple = field(default_factory=tuple)   # ((name, inner_mrad, outer_mrad), ...)
+
+    @property
+    def thickness(self) -> float:
+        return self.nslices * self.dz
+
+
+_STD_DET = (("BF", 0.0, 15.0), ("ADF", 16.0, 40.0), ("HAADF", 41.0, 200.0))
+
+WORKLOADS = {
+    # 128^2 over 12.8 A, 10 x 2 A slices, simple cubic a=4 A, one species of 20 V*A.
+    "tiny": Workload("tiny", 1, 128, 128, 12.8, 12.8, 10, 2.0, "sc", 4.0, (20.0,), (1.0,),
+                     0.05, 200.0, 20.0, 0.0, 0.0, 2.0 / 3.0, (16, 16), 4, (0.5, 0.5), 64, 1,
+                     (("HAADF70", 70.0, 200.0),) + _STD_DET),
+    # 512^2 over 51.2 A, 100 x 2 A slices, FCC a=4.05 A, species {14,29,79} V*A.
+    "medium": Workload("medium", 2, 512, 512, 51.2, 51.2, 100, 2.0, "fcc", 4.05, (14.0, 29.0, 79.0),
+                       (1 / 3, 1 / 3, 1 / 3), 0.08, 200.0, 20.0, 0.0, 0.0, 2.0 / 3.0, (128, 128), 4,
+                       (0.5, 0.5), 144, 8, _STD_DET),
+    # 2048^2 over 204.8 A, 250 x 2 A slices, FCC random alloy {29,79} V*A, 300 kV.
+    "large": Workload("large", 3, 2048, 2048, 204.8, 204.8, 250, 2.0, "fcc", 4.05, (29.0, 79.0),
+                      (0.5, 0.5), 0.1, 300.0, 25.0, -50.0, 0.0, 2.0 / 3.0, (256, 256), 4, (0.5, 0.5),
+                      144, 16, _STD_DET),
+}
+
+
+def _basis(lattice: str) -> np.ndarray:
+    if lattice == "sc":
+        return np.zeros((1, 3))
+    if lattice == "fcc":
+        return np.array([[0.0, 0.0, 0.0], [0.5, 0.5, 0.0], [0.5, 0.0, 0.5], [0.0, 0.5, 0.5]])
+    raise ValueError(f"unknown lattice {lattice!r}")
+
+
+def atom_sites(w: Workload):
+    """Undisplaced sites (n,3) in Angstrom and per-site amplitude (n,), species fixed by seed."""
+    b = _basis(w.lattice)
+    nxc = int(math.ceil(w.lx / w.a)) + 1
+    nyc = int(math.ceil(w.ly / w.a)) + 1
+    nzc = int(math.ceil(w.thickness / w.a)) + 1
+    i, j, k = np.meshgrid(np.arange(nxc), np.arange(nyc), np.arange(nzc), indexing="ij")
+    cells = np.stack([i.ravel(), j.ravel(), k.ravel()], axis=1).astype(np.float64)
+    sites = (cells[:, None, :] + b[None, :, :]).reshape(-1, 3) * w.a
+    keep = (sites[:, 0] < w.lx) & (sites[:, 1] < w.ly) & (sites[:, 2] < w.thickness)
+    sites = sites[keep]
+    # deterministic order: by z, then y, then x
+    order = np.lexsort((sites[:, 0], sites[:, 1], sites[:, 2]))
+    sites = sites[order]
+    rng = np.random.default_rng([w.wid, 0, 0])
+    species = rng.choice(len(w.amplitudes), size=len(sites), p=np.asarray(w.probs))
+    amps = np.asarray(w.amplitudes, dtype=np.float64)[species]
+    return sites, amps
+
+
+def phonon_positions(w: Workload, config: int, sites: np.ndarray | None = None) -> np.ndarray:
+    """Sites displaced for frozen-phonon configuration ``config`` (x, y wrapped into the cell)."""
+    if sites is None:
+        sites, _ = atom_sites(w)
+    rng = np.random.default_rng([w.wid, 1, config])
+    pos = sites + rng.normal(0.0, w.sigma_d, size=sites.shape)
+    pos[:, 0] = np.mod(pos[:, 0], w.lx)
+    pos[:, 1] = np.mod(pos[:, 1], w.ly)
+    return pos
+
+
+def _axis_factors(coord: np.ndarray, n: int, length: float) -> np.ndarray:
+    """Truncated 1-D Gaussian factors [n_atoms, n] with periodic minimum-image distance."""
+    grid = np.arange(n, dtype=np.float64) * (length / n)
+    d = grid[None, :] - coord[:, None]
+    d = d - length * np.round(d / length)
+    g = np.exp(-(d * d) / (2.0 * ATOM_SIGMA * ATOM_SIGMA))
+    g[np.abs(d) > ATOM_CUTOFF] = 0.0
+    return g
+
+
+def potential_from_atoms(w: Workload, pos: np.ndarray, amps: np.ndarray,
+                         slices: range | None = None) -> np.ndarray:
+    """Projected potential float32 [len(slices)][ny][nx] from atom positions and amplitudes."""
+    if slices is None:
+        slices = range(w.nslices)
+    sl = np.clip(np.floor(pos[:, 2] / w.dz).astype(np.int64), 0, w.nslices - 1)
+    out = np.zeros((len(slices), w.ny, w.nx), dtype=np.float32)
+    for o, j in enumerate(slices):
+        sel = np.nonzero(sl == j)[0]
+        if sel.size == 0:
+            continue
+        gx = _axis_factors(pos[sel, 0], w.nx, w.lx)
+        gy = _axis_factors(pos[sel, 1], w.ny, w.ly)
+        out[o] = ((gy * amps[sel, None]).T @ gx).astype(np.float32)
+    return out
+
+
+def potential_slices(w: Workload, config: int = 0) -> np.ndarray:
+    """float32 [nslices][ny][nx] potential (V*Angstrom) of phonon configuration ``config``."""
+    sites, amps = atom_sites(w)
+    pos = phonon_positions(w, config, sites)
+    return potential_from_atoms(w, pos, amps)
+
+
+def edit_column(w: Workload, config: int, col_xy: tuple, seed: int = 0):
+    """A local edit: the atoms of the undisplaced site column nearest ``col_xy`` (Angstrom)
+    get a new amplitude drawn from the species set and each keeps its site with
+    probability 1/2. Returns (pos, amps) of the edited specimen for configuration ``config``
+    and the (x0, y0, x1, y1) pixel box, half-open, that bounds the edited Gaussians."""
+    sites, amps = atom_sites(w)
+    pos = phonon_positions(w, config, sites)
+    dx = sites[:, 0] - col_xy[0]
+    dy = sites[:, 1] - col_xy[1]
+    d2 = dx * dx + dy * dy
+    col = np.nonzero(d2 <= d2.min() + 1e-9)[0]
+    rng = np.random.default_rng([w.wid, 2, seed])
+    new_amp = float(np.asarray(w.amplitudes)[rng.integers(len(w.amplitudes))])
+    keep = rng.random(col.size) < 0.5
+    amps = amps.copy()
+    amps[col] = new_amp
+    drop = col[~keep]
+    mask = np.ones(len(amps), dtype=bool)
+    mask[drop] = False
+    cx, cy = sites[col[0], 0], sites[col[0], 1]
+    rx = pos[col, 0] - cx
+    rx -= w.lx * np.round(rx / w.lx)
+    ry = pos[col, 1] - cy
+    ry -= w.ly * np.round(ry / w.ly)
+    px = w.lx / w.nx
+    py = w.ly / w.ny
+    x0 = int(math.floor((cx + rx.min() - ATOM_CUTOFF) / px))
+    x1 = int(math.ceil((cx + rx.max() + ATOM_CUTOFF) / px)) + 1
+    y0 = int(math.floor((cy + ry.min() - ATOM_CUTOFF) / py))
+    y1 = int(math.ceil((cy + ry.max() + ATOM_CUTOFF) / py)) + 1
+    return pos[mask], amps[mask], (x0, y0, x1, y1)

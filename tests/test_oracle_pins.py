@@ -1,0 +1,342 @@
+"""Pins of the FP64 oracle against values the paper prints, closed forms, invariants and
+brute force. None of these recompute the oracle's own formula as its expected value."""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import pytest
+
+from oracle import physics as ph
+from oracle import costs
+from oracle.dft import dft2
+from oracle.lma import LMA, Lattice, least_squares, translate_wave
+from oracle.multislice import Setup, multislice, plain_image
+from oracle.partition import multislice_calls, union
+from tests._cases import rel_l2
+
+
+def _setup(nx=32, ny=32, lx=6.4, ly=6.4, kv=200.0, dz=2.0, bandlimit=2 / 3, alpha=0.02,
+           defocus=0.0, cs=0.0, scan=(4, 4), detectors=((0.0, 0.015), (0.016, 0.04), (0.041, 0.2))):
+    return Setup(nx, ny, lx, ly, ph.electron_wavelength(kv), ph.interaction_constant(kv), dz,
+                 bandlimit, alpha, defocus, cs, scan, detectors)
+
+
+# ---------------------------------------------------------------------------------------
+# constants: values printed in the paper, and an independent SI route
+# ---------------------------------------------------------------------------------------
+def test_wavelength_matches_printed_value():
+    # Fig. 6 / 7 / 8 captions: lambda = 0.0250793 A at 200 kV
+    assert abs(ph.electron_wavelength(200.0) - 0.0250793) < 5e-8
+
+
+def test_gaussian_width_matches_printed_value():
+    # Sec. 4.2.3 Gaussians: sigma = lambda / (2 alpha_max) printed as 0.482 A for 26 mrad
+    assert round(ph.electron_wavelength(200.0) / (2 * 0.026), 3) == 0.482
+
+
+def test_interaction_constant_si_route():
+    # sigma = 2 pi m e lambda / h^2 with the relativistic mass, in SI, then per V*Angstrom
+    m0, e, h, c = 9.1093837015e-31, 1.602176634e-19, 6.62607015e-34, 299792458.0
+    for kv in (100.0, 200.0, 300.0):
+        V = kv * 1e3
+        m = m0 * (1 + e * V / (m0 * c * c))
+        lam = h / math.sqrt(2 * m0 * e * V * (1 + e * V / (2 * m0 * c * c)))
+        sig_si = 2 * math.pi * m * e * lam / h ** 2          # rad / (V m)
+        assert abs(lam * 1e10 - ph.electron_wavelength(kv)) / (lam * 1e10) < 1e-7
+        assert abs(sig_si * 1e-10 - ph.interaction_constant(kv)) / (sig_si * 1e-10) < 1e-6
+
+
+# ---------------------------------------------------------------------------------------
+# FFT step against the DFT definition (brute force)
+# ---------------------------------------------------------------------------------------
+def test_slice_step_matches_bruteforce_dft():
+    rng = np.random.default_rng(1)
+    st = _setup(nx=6, ny=4, lx=1.3, ly=0.9, bandlimit=2.0)
+    v = rng.uniform(0, 30, size=(1, 4, 6)).astype(np.float32)
+    psi0 = rng.standard_normal((4, 6)) + 1j * rng.standard_normal((4, 6))
+    got = multislice(psi0, v, st.sigma, st.prop)
+    t = np.exp(1j * st.sigma * v[0].astype(np.float64))
+    spec = np.array(dft2((t * psi0).tolist()))
+    want = np.array(dft2((st.prop * spec).tolist(), inverse=True))
+    assert rel_l2(got, want) < 1e-13
+
+
+def test_fft_parseval_and_delta():
+    rng = np.random.default_rng(2)
+    a = rng.standard_normal((5, 7)) + 1j * rng.standard_normal((5, 7))
+    A = np.array(dft2(a.tolist()))
+    assert abs((np.abs(A) ** 2).sum() - a.size * (np.abs(a) ** 2).sum()) < 1e-10
+    d = np.zeros((4, 4))
+    d[0, 0] = 1
+    assert np.allclose(np.array(dft2(d.tolist())), 1.0)
+
+
+# ---------------------------------------------------------------------------------------
+# propagator: sign and scale by the Gaussian closed form; composition
+# ---------------------------------------------------------------------------------------
+@pytest.mark.parametrize("nslices,dz", [(1, 50.0), (4, 25.0)])
+def test_fresnel_gaussian_closed_form(nslices, dz):
+    # exp(-x^2/(2 a^2) - y^2/(2 b^2)) propagated over z in free space becomes
+    # prod over axes of (s0/s) exp(-r^2/(2 s^2)) with s^2 = s0^2 + i lambda z / (2 pi).
+    # Non-square grid and cell so that a swapped kx/ky would fail.
+    nx, ny, lx, ly = 96, 64, 19.2, 12.8
+    st = _setup(nx=nx, ny=ny, lx=lx, ly=ly, bandlimit=1.0)
+    lam = st.wavelength
+    z = nslices * dz
+    st = Setup(nx, ny, lx, ly, lam, st.sigma, dz, 1.0, 0.02, 0.0, 0.0, (1, 1), [(0, 1)])
+    x = (np.arange(nx) - nx // 2) * (lx / nx)
+    y = (np.arange(ny) - ny // 2) * (ly / ny)
+    X, Y = np.meshgrid(x, y)
+    a0, b0 = 1.1, 0.8
+    psi0 = np.exp(-X ** 2 / (2 * a0 ** 2) - Y ** 2 / (2 * b0 ** 2))
+    got = multislice(psi0, np.zeros((nslices, ny, nx), np.float32), st.sigma, st.prop)
+    sa2 = a0 ** 2 + 1j * lam * z / (2 * np.pi)
+    sb2 = b0 ** 2 + 1j * lam * z / (2 * np.pi)
+    want = (a0 / np.sqrt(sa2)) * (b0 / np.sqrt(sb2)) * np.exp(-X ** 2 / (2 * sa2) - Y ** 2 / (2 * sb2))
+    assert rel_l2(got, want) < 1e-10
+    # the opposite sign convention is far off
+    wrong = (a0 / np.sqrt(np.conj(sa2))) * (b0 / np.sqrt(np.conj(sb2))) * np.exp(
+        -X ** 2 / (2 * np.conj(sa2)) - Y ** 2 / (2 * np.conj(sb2)))
+    assert rel_l2(got, wrong) > 1e-2
+
+
+def test_propagator_composition_two_dz_equals_2dz():
+    rng = np.random.default_rng(3)
+    st1 = _setup(nx=40, ny=48, lx=4.0, ly=5.6, dz=1.5)
+    st2 = _setup(nx=40, ny=48, lx=4.0, ly=5.6, dz=3.0)
+    psi0 = rng.standard_normal((48, 40)) + 1j * rng.standard_normal((48, 40))
+    two = multislice(psi0, np.zeros((2, 48, 40), np.float32), st1.sigma, st1.prop)
+    one = multislice(psi0, np.zeros((1, 48, 40), np.float32), st2.sigma, st2.prop)
+    assert rel_l2(two, one) < 1e-13
+
+
+def test_defocus_equals_free_propagation():
+    # eq. aberration_function and the propagator agree: an in-focus probe propagated over z
+    # in vacuum equals the probe with focus Z = -z (both band-limited identically).
+    z = 40.0
+    st0 = _setup(nx=64, ny=64, lx=12.8, ly=12.8, dz=z, defocus=0.0, bandlimit=1.0)
+    stz = _setup(nx=64, ny=64, lx=12.8, ly=12.8, dz=z, defocus=-z, bandlimit=1.0)
+    psi = multislice(st0.probe(0, 0), np.zeros((1, 64, 64), np.float32), st0.sigma, st0.prop)
+    assert rel_l2(psi, stz.probe(0, 0)) < 1e-12
+
+
+# ---------------------------------------------------------------------------------------
+# transmission, norm, linearity, equivariance
+# ---------------------------------------------------------------------------------------
+def test_transmission_zero_and_constant_potential():
+    rng = np.random.default_rng(4)
+    st = _setup()
+    psi0 = st.probe(1, 2)
+    free = multislice(psi0, np.zeros((3, 32, 32), np.float32), st.sigma, st.prop)
+    v0 = 17.0
+    const = multislice(psi0, np.full((3, 32, 32), v0, np.float32), st.sigma, st.prop)
+    assert rel_l2(const, np.exp(1j * st.sigma * v0 * 3) * free) < 1e-13
+    assert rel_l2(const, np.exp(-1j * st.sigma * v0 * 3) * free) > 1e-2
+    t = ph.transmission(rng.uniform(0, 100, (32, 32)).astype(np.float32), st.sigma)
+    assert np.allclose(np.abs(t), 1.0)
+
+
+def test_norm_non_increasing_and_conserved_inside_band():
+    rng = np.random.default_rng(5)
+    st = _setup()
+    v = rng.uniform(0, 60, (6, 32, 32)).astype(np.float32)
+    psi = st.probe(0, 0)
+    norms = [np.linalg.norm(psi)]
+    for j in range(6):
+        psi = multislice(psi, v[j:j + 1], st.sigma, st.prop)
+        norms.append(np.linalg.norm(psi))
+    assert abs(norms[0] - 1.0) < 1e-12
+    assert all(b <= a + 1e-13 for a, b in zip(norms, norms[1:]))
+    assert norms[-1] < norms[0] - 1e-6          # the band limit removed something
+    free = multislice(st.probe(0, 0), np.zeros((6, 32, 32), np.float32), st.sigma, st.prop)
+    assert abs(np.linalg.norm(free) - 1.0) < 1e-12
+
+
+def test_linearity():
+    rng = np.random.default_rng(6)
+    st = _setup()
+    v = rng.uniform(0, 60, (4, 32, 32)).astype(np.float32)
+    u1, u2 = st.probe(0, 0), st.probe(1, 3)
+    a, b = 0.3 - 1.2j, -0.7 + 0.4j
+    lhs = multislice(a * u1 + b * u2, v, st.sigma, st.prop)
+    rhs = a * multislice(u1, v, st.sigma, st.prop) + b * multislice(u2, v, st.sigma, st.prop)
+    assert rel_l2(lhs, rhs) < 1e-13
+
+
+def test_translation_equivariance_and_roll():
+    rng = np.random.default_rng(7)
+    st = _setup(nx=32, ny=32, lx=6.4, ly=6.4)
+    patch = rng.uniform(0, 60, (3, 8, 8)).astype(np.float32)
+    v = np.tile(patch, (1, 4, 4))                 # periodic with 8 px
+    u = st.probe(0, 0)
+    sx, sy = 8, 16
+    shifted = translate_wave(st, st.spec0, (sx * st.lx / st.nx, sy * st.ly / st.ny))
+    assert rel_l2(shifted, np.roll(u, (sy, sx), axis=(0, 1))) < 1e-12
+    out = multislice(shifted, v, st.sigma, st.prop)
+    ref = np.roll(multislice(u, v, st.sigma, st.prop), (sy, sx), axis=(0, 1))
+    assert rel_l2(out, ref) < 1e-12
+
+
+def test_probe_aperture_and_band_pixel_counts():
+    # pixel counts of the aperture and band discs against their areas pi r^2 / dk^2
+    st = _setup(nx=256, ny=256, lx=25.6, ly=25.6)
+    dk = 1 / 25.6
+    n_ap = (np.abs(st.spec0) > 0).sum()
+    assert abs(n_ap - math.pi * (0.02 / st.wavelength / dk) ** 2) / n_ap < 0.03
+    n_band = ph.band_mask(256, 256, 25.6, 25.6, 2 / 3).sum()
+    assert abs(n_band - math.pi * ((2 / 3) * 5.0 / dk) ** 2) / n_band < 0.01
+    assert abs(np.linalg.norm(st.probe(3, 1)) - 1.0) < 1e-12
+
+
+# ---------------------------------------------------------------------------------------
+# detector rings
+# ---------------------------------------------------------------------------------------
+def test_detector_rings_partition_the_band():
+    rng = np.random.default_rng(8)
+    st = _setup()
+    spec = np.fft.fft2(rng.standard_normal((32, 32)) + 1j * rng.standard_normal((32, 32)))
+    rings = [(0.0, 0.03), (0.03, 0.07), (0.07, 10.0)]
+    masks = ph.ring_masks(32, 32, st.lx, st.ly, st.wavelength, st.bandlimit, rings)
+    vals = ph.detector_values(spec, masks)
+    band = ph.band_mask(32, 32, st.lx, st.ly, st.bandlimit) > 0
+    assert abs(vals.sum() - (np.abs(spec[band]) ** 2).sum() / 1024) < 1e-9 * vals.sum()
+    assert not np.any(masks[0] & masks[1]) and not np.any(masks[1] & masks[2])
+
+
+def test_detector_ring_inner_edge_inclusive_outer_exclusive():
+    lam = 0.5                                    # exactly representable
+    masks = ph.ring_masks(8, 8, 1.0, 1.0, lam, 1.0, [(0.5, 1.0), (0.0, 0.5)])
+    # frequency (kx, ky) = (1, 0) /A -> theta = 0.5 exactly: in [0.5, 1.0), not in [0, 0.5)
+    assert masks[0][0, 1] and not masks[1][0, 1]
+
+
+# ---------------------------------------------------------------------------------------
+# LMA: special cases, error bound, staircase, coefficient reuse
+# ---------------------------------------------------------------------------------------
+def test_lma_reduces_to_plain_multislice():
+    # u = psi_0, I = P, f = 1, L = 1 gives back the standard algorithm (Sec. 4.2.3)
+    rng = np.random.default_rng(9)
+    st = _setup(scan=(4, 4))
+    lat = Lattice(st, (4, 4), 1, (0, 0), 1)
+    lma = LMA(st, lat)
+    assert abs(lma.alpha[(0, 0)][0] - 1.0) < 1e-12
+    v = rng.uniform(0, 50, (3, 32, 32)).astype(np.float32)
+    probes = [(0, 0), (1, 2), (3, 3)]
+    assert rel_l2(lma.image(v, probes)[:, [0, 2, 3], [0, 1, 3]],
+                  plain_image(st, v, probes)[:, [0, 2, 3], [0, 1, 3]]) < 1e-12
+
+
+def test_lma_case1_without_offset_is_exact():
+    # R_f = 2 P and zero offset: every probe sits on a translate, alpha is a delta
+    st = _setup(scan=(4, 4))
+    lat = Lattice(st, (8, 8), 1, (0, 0), 5)
+    al, nbr, res = least_squares(st, lat, st.spec0, 0, 0)
+    assert res < 1e-12
+    assert abs(al[0] - 1) < 1e-10 and np.all(np.abs(al[1:]) < 1e-10)
+
+
+def test_lma_exit_error_bounded_by_probe_residual():
+    # propagation is linear and each slice a contraction, so the LMA exit-wave error is at
+    # most the residual of the initial approximation
+    rng = np.random.default_rng(10)
+    st = _setup(scan=(4, 4))
+    lat = Lattice(st, (8, 8), 1, (0.5, 0.5), 12)
+    lma = LMA(st, lat)
+    v = rng.uniform(0, 50, (4, 32, 32)).astype(np.float32)
+    for a, b in [(0, 0), (2, 1)]:
+        approx = lma.approximant(a, b)
+        exact = st.probe(a, b)
+        e_init = np.linalg.norm(approx - exact)
+        e_exit = np.linalg.norm(multislice(approx, v, st.sigma, st.prop) - multislice(exact, v, st.sigma, st.prop))
+        assert e_exit <= e_init * (1 + 1e-9)
+        assert e_init > 1e-4                         # non-trivial case
+
+
+def test_residual_staircase_non_increasing_in_L():
+    st = _setup(nx=64, ny=64, lx=12.8, ly=12.8, scan=(16, 16))
+    res = []
+    for L in (1, 4, 8, 12, 16, 24, 36):
+        lat = Lattice(st, (32, 32), 1, (0.5, 0.5), L)
+        res.append(least_squares(st, lat, st.spec0, 0, 0)[2])
+    assert all(b <= a + 1e-12 for a, b in zip(res, res[1:]))
+    assert res[-1] < 0.1 * res[0]
+
+
+def test_coefficient_reuse_case2_same_error_for_shifted_probe():
+    # Case 2 (P = c R_f): probes a and a + c share coefficients (eq. lma_approximation_exit2)
+    st = _setup(nx=32, ny=32, lx=6.4, ly=6.4, scan=(8, 8))
+    lat = Lattice(st, (4, 4), 1, (0.5, 0.5), 9)
+    assert (lat.ncls_x, lat.ncls_y) == (2, 2)
+    lma = LMA(st, lat)
+    for a, b in [(2, 4), (3, 5), (5, 2)]:
+        al_direct, nbr, res = least_squares(st, lat, st.spec0, a, b)
+        approx = lma.approximant(a, b)
+        assert rel_l2(approx, st.probe(a, b)) == pytest.approx(res, rel=1e-8)
+        assert lma.residual[lat.coefficient_class(a, b)] == pytest.approx(res, rel=1e-8)
+
+
+def test_nearest_translates_complete_first_shell():
+    # offset (1/2, 1/2) of the spacing, Case 1 with c = 1: the 4 nearest are the four
+    # translates at (+-1/2, +-1/2) spacing from the probe
+    st = _setup(nx=32, ny=32, lx=6.4, ly=6.4, scan=(8, 8))
+    lat = Lattice(st, (8, 8), 1, (0.5, 0.5), 4)
+    got = set(lat.nearest(3, 5))
+    assert got == {(3, 5), (2, 5), (3, 4), (2, 4)}
+
+
+# ---------------------------------------------------------------------------------------
+# lattice counts, partition counts and the cost model printed in the paper
+# ---------------------------------------------------------------------------------------
+def test_printed_translate_and_probe_counts():
+    # Sec. 4.2.6: (Px, Py) = (424, 400), I = P + p/2, f = 2 -> |I_f| = 212 * 200 = 42400
+    st = Setup(16, 16, 84.536, 79.941, 0.0250793, 7e-4, 2.0, 2 / 3, 0.026, 100.0, -2000.0,
+               (424, 400), [(0.0, 0.015)])
+    lat = Lattice(st, (424, 400), 2, (0.5, 0.5), 59)
+    assert lat.n_translates == 42400 and st.Px * st.Py == 169600
+    assert (lat.ncls_x, lat.ncls_y) == (2, 2)
+
+
+def _partition_example_sets(L):
+    # Fig. lmastrategy_examples: X = 512, P = 158, l = 31.208 A, I = P + p/2, f = 2, 48 x 48
+    # sub-image. Neighbour lists of the four class representatives are computed by the
+    # oracle and shifted to every probe (the shift rule is checked by the Case 2 test above).
+    st = Setup(8, 8, 31.208, 31.208, 0.0250793, 7e-4, 2.0, 2 / 3, 0.026, 100.0, -2000.0,
+               (158, 158), [(0.0, 0.015)])
+    lat = Lattice(st, (158, 158), 2, (0.5, 0.5), L)
+    reps = {(cx, cy): lat.nearest(cx, cy) for cx in (0, 1) for cy in (0, 1)}
+    sets = {}
+    for b in range(48):
+        for a in range(48):
+            A, B = a + 1, b + 1                  # the sub-image starts at an odd index
+            sets[(a, b)] = [((ta + A // 2) % lat.Rfx, (tb + B // 2) % lat.Rfy)
+                            for ta, tb in reps[(A % 2, B % 2)]]
+    return sets
+
+
+@pytest.mark.slow
+def test_printed_minimum_multislice_calls_L75():
+    sets = _partition_example_sets(75)
+    assert len(union(sets, sets.keys())) == 1077
+    # full-width strips reach the minimum (the paper's second example, row strategy)
+    strips = [[(a, b) for a in range(48)] for b in range(48)]
+    assert multislice_calls(sets, strips) == 1077
+    assert multislice_calls(sets, [list(sets.keys())]) == 1077
+
+
+def test_cost_model_log_base_two():
+    # Sec. 4.2.1: at 2048^2 with a 25 x 25 kernel, real-space propagation wins iff f >= 4
+    assert math.ceil(costs.realspace_breakeven_f(2048, 2048, 25, 25)) == 4
+    assert math.ceil(costs.realspace_breakeven_f(2048, 2048, 25, 25, log=math.log)) != 4
+    assert costs.t_multislice(1, 4, 4) == 2 * 16 + 2 * 16 * 4
+
+
+def test_phonon_average_linear():
+    rng = np.random.default_rng(11)
+    st = _setup(scan=(2, 2))
+    vs = [rng.uniform(0, 50, (2, 32, 32)).astype(np.float32) for _ in range(3)]
+    imgs = [plain_image(st, v) for v in vs]
+    from oracle.lma import phonon_average
+    avg = phonon_average(imgs)
+    assert np.allclose(avg, (imgs[0] + imgs[1] + imgs[2]) / 3, rtol=1e-14)
+    assert np.array_equal(phonon_average(imgs[:1]), imgs[0])
