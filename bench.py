@@ -1,0 +1,255 @@
+"""Benchmark: STEM pixels/s of the LMA hot path against plain multislice on one MI355X.
+
+One step = one frozen-phonon configuration of the medium workload pushed through the whole
+hot path: lma_propagate (initial translates, 100 x [row pass: row IFFT, transmission, row FFT;
+column pass: column FFT, propagator, column IFFT], exit spectra kept at the detector pixels)
+then lma_probe_image (coefficient contraction and detector rings, accumulated with weight
+1/n_phonons). The plain multislice comparator (lma_plain_image) runs the same configurations.
+Potentials of every configuration are resident in HBM before the timed region.
+
+Prints one JSON line. Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+WORKLOAD = "medium"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "kernels.hpp"):
+        with open(os.path.join(ROOT, "paper_2310_16829_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(kernel: str):
+    """HBM traffic per launch from the committed rocprofv3 counter summary, if it was taken on
+    the current kernel source; else None."""
+    p = os.path.join(ROOT, "profiles", "traffic_medium.json")
+    if not os.path.exists(p):
+        return None
+    with open(p) as fh:
+        d = json.load(fh)
+    if d.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    k = d.get("kernels", {}).get(kernel)
+    return None if k is None else k.get("hbm_bytes_per_launch")
+
+
+# ------------------------------------------------------------------------------------------
+# CPU baseline: the FP64 oracle on a bounded sample of the same workload
+# ------------------------------------------------------------------------------------------
+def _oracle_wave(args):
+    import numpy as np
+    from oracle.lma import translate_wave
+    from oracle.multislice import multislice
+    pos = args
+    st, v = _oracle_wave.st, _oracle_wave.v
+    u0 = translate_wave(st, st.spec0, pos)
+    return np.fft.fft2(multislice(u0, v, st.sigma, st.prop))
+
+
+def _oracle_init(spec):
+    from oracle import physics as ph
+    from oracle.multislice import Setup
+    from synth import WORKLOADS, potential_slices
+    w = WORKLOADS[spec]
+    _oracle_wave.v = potential_slices(w, 0)
+    _oracle_wave.st = Setup(w.nx, w.ny, w.lx, w.ly, ph.electron_wavelength(w.kv), ph.interaction_constant(w.kv),
+                            w.dz, w.bandlimit, w.alpha_mrad * 1e-3, w.defocus, w.cs, w.scan,
+                            [(a * 1e-3, b * 1e-3) for _, a, b in w.detectors])
+
+
+def cpu_baseline(w, n_translates, n_probes):
+    """Times the oracle on a sample (waves propagated in parallel, one process per core, then
+    the per-probe combination and detector sums) and scales to one full image of one phonon
+    configuration: T = |I_f| t_wave + |P| t_probe."""
+    import numpy as np
+    from concurrent.futures import ProcessPoolExecutor
+    from oracle import physics as ph
+    cores = max(1, min(16, len(os.sched_getaffinity(0))))
+    n_waves = cores
+    rng = np.random.default_rng(0)
+    positions = [(float(x), float(y)) for x, y in rng.uniform(0, w.lx, size=(n_waves, 2))]
+    with ProcessPoolExecutor(cores, initializer=_oracle_init, initargs=(WORKLOAD,)) as ex:
+        list(ex.map(_oracle_wave, positions[:cores]))          # start-up and potential generation
+        t0 = time.perf_counter()
+        spectra = list(ex.map(_oracle_wave, positions))
+        t_waves = time.perf_counter() - t0
+    t_wave = t_waves / n_waves                                  # wall time per wave at `cores` workers
+    # combination of L translates and the detector sums for a few probes (single process)
+    _oracle_init(WORKLOAD)
+    st = _oracle_wave.st
+    n_p = 2
+    t0 = time.perf_counter()
+    for _ in range(n_p):
+        spec = np.zeros_like(spectra[0])
+        for j in range(w.L):
+            spec += (0.5 + 0.1j) * spectra[j % len(spectra)]
+        ph.detector_values(spec, st.masks)
+    t_probe = (time.perf_counter() - t0) / n_p / cores          # probes spread over the same cores
+    t_image = n_translates * t_wave + n_probes * t_probe
+    t_plain = n_probes * t_wave
+    return {
+        "value": n_probes / t_image, "unit": "STEM pixels/s", "cores": cores, "kind": "oracle",
+        "plain_value": n_probes / t_plain,
+        "sample": (f"{n_waves} medium-workload waves (512^2, 100 slices) propagated by the FP64 oracle on "
+                   f"{cores} processes ({t_wave:.3f} s wall per wave) plus {n_p} probe combinations of "
+                   f"L={w.L} translates ({t_probe * cores:.3f} s each); scaled to one phonon image: "
+                   f"{n_translates} translates + {n_probes} probes"),
+    }
+
+
+# ------------------------------------------------------------------------------------------
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=8)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--batch", type=int, default=0)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import paper_2310_16829_amd as lma
+    from synth import WORKLOADS, potential_slices
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    w = WORKLOADS[WORKLOAD]
+    K, W = args.steps, args.warmup
+    n_cfg = w.n_phonons
+    log(f"bench: generating {min(n_cfg, K + W + 1)} phonon potentials")
+    pots = [torch.from_numpy(potential_slices(w, c)).cuda() for c in range(min(n_cfg, K + W + 1))]
+    torch.cuda.synchronize()
+
+    lam, sig = lma.electron_constants(w.kv)
+    rings = [(a * 1e-3, b * 1e-3) for _, a, b in w.detectors]
+    opt = lma.optics(w.nx, w.ny, w.lx, w.ly, lam, sig, w.dz, w.bandlimit, w.alpha_mrad * 1e-3, w.defocus, w.cs)
+    R = (w.nx // w.basis_px, w.ny // w.basis_px)
+    lat = lma.lattice(w.scan[0], w.scan[1], R[0], R[1], 1, w.offset_frac, w.L, batch=args.batch)
+    t0 = time.perf_counter()
+    plan = lma.Plan(opt, lat, lma.detectors(rings))
+    t_build = time.perf_counter() - t0
+    info = plan.info()
+    n_probes = info.n_probes
+    log(f"bench: plan built in {t_build:.2f} s: {info.n_rows} translates, D={info.n_pix}, batch={info.batch}, "
+        f"residual {info.max_residual:.2e}, {info.device_bytes / 2**30:.1f} GiB")
+    stream = torch.cuda.current_stream()
+    img = torch.zeros(plan.image_shape(), dtype=torch.float64, device="cuda")
+    pimg = torch.zeros_like(img)
+
+    def lma_step(c):
+        plan.propagate(pots[c % len(pots)])
+        plan.probe_image(img, flags=lma.LMA_ACCUMULATE, weight=1.0 / n_cfg)
+
+    def plain_step(c):
+        plan.plain_image(pots[c % len(pots)], pimg, flags=lma.LMA_ACCUMULATE, weight=1.0 / n_cfg)
+
+    def timed(step, label):
+        for c in range(W):
+            step(c)
+        torch.cuda.synchronize()
+        img.zero_()
+        pimg.zero_()
+        lat_ms = []
+        torch.cuda.synchronize()
+        t_start = time.perf_counter()
+        for c in range(K):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            step(W + c)
+            e1.record(stream)
+            e1.synchronize()
+            lat_ms.append(e0.elapsed_time(e1))
+            log(f"bench: {label} step {c + 1}/{K}: {lat_ms[-1]:.1f} ms")
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t_start
+        # one more step with a hipEvent pair around every launch, for per-kernel durations
+        # (kept out of the timed region)
+        plan.timing(reset=True)
+        plan.set_timing(True)
+        step(W + K)
+        kt = plan.timing(reset=True)
+        plan.set_timing(False)
+        return elapsed, lat_ms, kt
+
+    el, lat_ms, kt = timed(lma_step, "lma")
+    value = n_probes * K / el
+    plain = None
+    if not args.no_plain:
+        pel, plat_ms, pkt = timed(plain_step, "plain")
+        plain = {"value": n_probes * K / pel, "ms_per_step": 1e3 * pel / K,
+                 "p50_ms": float(np.percentile(plat_ms, 50)), "p99_ms": float(np.percentile(plat_ms, 99))}
+    # roofline of the dominant kernel: a slice pass reads and writes every pixel of every wave
+    # of its launch once (16 B per pixel per wave) and reads one 8 B/pixel table
+    dom = max(("row_pass", "col_pass"), key=lambda k: kt.get(k, (0, 0.0))[1])
+    launches, total_ms = kt[dom]
+    XY = w.nx * w.ny
+    n_waves = info.n_rows
+    batches = -(-n_waves // info.batch)
+    waves_per_launch = n_waves / batches
+    bytes_per_launch = waves_per_launch * XY * 16 + XY * 8
+    avg_s = total_ms / launches * 1e-3
+    achieved = bytes_per_launch / avg_s / 1e9
+    traffic = load_traffic(dom)
+    out = {
+        "metric": "STEM pixels/s, LMA vs plain multislice, same GPU at <=1e-4 rel err; p99 latency",
+        "value": value,
+        "unit": "STEM pixels/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": W,
+        "ms_per_step": 1e3 * el / K,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": ("medium: 512x512 px over 51.2 A, 100 slices of 2 A, FCC a=4.05 A, amplitudes "
+                                "{14,29,79} V*A, 200 kV, 20 mrad, scan 128x128, LMA translate spacing 4 px "
+                                "(offset 1/2), L=144, 8 frozen-phonon configurations; one step = one configuration"),
+                   "scan": [w.scan[0], w.scan[1]], "grid": [w.nx, w.ny], "slices": w.nslices,
+                   "translates": n_waves, "L": w.L, "batch": info.batch},
+        "latency_ms": {"p50": float(np.percentile(lat_ms, 50)), "p99": float(np.percentile(lat_ms, 99)),
+                       "what": "one phonon configuration of the full image (propagate + probe_image)"},
+        "plain": plain,
+        "speedup_vs_plain": (value / plain["value"]) if plain else None,
+        "lma_probe_residual": info.max_residual,
+        "kernels_ms": {k: {"launches": v[0], "total_ms": v[1]} for k, v in kt.items()},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic,
+                     "algorithmic_bytes_per_launch": bytes_per_launch,
+                     "avg_launch_ms": avg_s * 1e3},
+        "plan_build_s": t_build,
+    }
+    if not args.no_cpu_baseline:
+        log("bench: oracle CPU baseline")
+        out["cpu_baseline"] = cpu_baseline(w, n_waves, n_probes)
+    plan.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

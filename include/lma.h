@@ -1,0 +1,205 @@
+/*
+ * lma.h -- C ABI of liblma.so, the MI355X (gfx950) hot path of the Lattice Multislice
+ * Algorithm (LMA) for STEM image simulation (Doberstein & Binev, "Lattice Multislice
+ * Algorithm for Fast Simulation of Scanning Transmission Electron Microscopy Images").
+ *
+ * Conventions shared by every entry point
+ *  - Ownership: callers own every pointer they pass; the library only borrows it for the
+ *    duration of the call (device pointers: until the call's stream work completes). A plan
+ *    owns every device buffer it allocates (tables, coefficients, the resident propagated
+ *    basis) and frees them in lma_destroy.
+ *  - Pointers: host pointers unless LMA_PTR_DEVICE is set in `flags`; device pointers must
+ *    be on the plan's device.
+ *  - Streams: all device work of a plan is ordered on the hipStream_t given to
+ *    lma_build_basis (NULL = the legacy default stream). Calls that read or write host
+ *    memory synchronise that stream before returning; calls on device memory are
+ *    stream-ordered and return before the work completes.
+ *  - Errors: no exception or abort crosses the ABI. Every call validates its arguments
+ *    before any device work and returns an lma_status; lma_last_error() gives a message
+ *    for the calling thread's last non-OK status. A failed lma_propagate marks the
+ *    resident basis invalid: lma_probe_image returns LMA_ERR_STATE until a propagate
+ *    succeeds.
+ *  - Threads: a plan is not thread-safe; separate plans may run concurrently on separate
+ *    streams.
+ *  - Units: lengths in Angstrom, angles in radians, potentials in V*Angstrom (projected
+ *    potential of one slice), the interaction constant in rad/(V*Angstrom).
+ *  - Layouts: row-major, x fastest. Complex numbers are interleaved (re, im).
+ *  - Transforms: forward DFT F(psi)[k] = sum_x psi[x] exp(-2 pi i k.x); frequencies in
+ *    FFT order (k = m/l for m < X/2, (m - X)/l otherwise).
+ */
+#ifndef LMA_H
+#define LMA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  LMA_OK = 0,
+  LMA_ERR_ARG = -1,          /* invalid argument; nothing was done                   */
+  LMA_ERR_OOM = -2,          /* device or host allocation failed / over the budget   */
+  LMA_ERR_DEVICE = -3,       /* a HIP call failed                                    */
+  LMA_ERR_STATE = -4,        /* the plan cannot do this now (no valid basis, host-only plan) */
+  LMA_ERR_UNSUPPORTED = -5   /* valid request outside what this build implements     */
+} lma_status;
+
+typedef struct lma_plan lma_plan;   /* opaque */
+
+/* lma_lattice.basis_kind */
+enum { LMA_BASIS_PROBE = 0 };                 /* u = psi_0^init (Sec. 4.2.3) */
+/* lma_lattice.precision: arithmetic of the probe-coefficient contraction */
+enum { LMA_GEMM_FP32 = 0, LMA_GEMM_SPLIT_BF16 = 1 };
+/* flags */
+enum {
+  LMA_PTR_DEVICE = 1,        /* pointer arguments are device pointers                */
+  LMA_ACCUMULATE = 2,        /* image += weight * I instead of image = weight * I     */
+  LMA_HOST_ONLY = 4          /* lma_build_basis: plan on the host, no device work     */
+};
+
+/* Microscope and grid: eqs. probe_wave_function, aberration_function, aperture_function,
+ * schroedinger_equation and Sec. 3.2 of the paper. */
+typedef struct {
+  int32_t nx, ny;            /* X x Y grid; powers of two in [16, 2048]               */
+  double lx, ly;             /* periodic cell lx x ly (lx != ly allowed)             */
+  double wavelength;         /* lambda                                               */
+  double sigma;              /* interaction constant                                 */
+  double dz;                 /* slice thickness epsilon                              */
+  double bandlimit;          /* |k| < bandlimit * min(X/(2 lx), Y/(2 ly)), in (0, 1]  */
+  double alpha_max;          /* aperture: A(k) = 1 iff lambda |k| < alpha_max         */
+  double defocus;            /* Z in chi(k) = 1/2 pi Cs lambda^3 |k|^4 - pi Z lambda |k|^2 */
+  double cs;                 /* C_s                                                   */
+} lma_optics;
+
+/* Probe lattice P, input-wave lattice I and its sublattice I_f, nearest-translate count L
+ * (Sec. 4.2.1, options (i) and (iii); Sec. 4.2.2). */
+typedef struct {
+  int32_t px, py;            /* scan Px x Py, probe a at (a lx/Px, b ly/Py)          */
+  int32_t rx, ry;            /* I has Rx x Ry points at spacing r = l/R              */
+  int32_t f;                 /* I_f keeps every f-th point of I; R % f == 0           */
+  double offset_x, offset_y; /* I_offset as a fraction of r; must be a multiple of
+                                1/(2 lcm(P, R)) of the cell                           */
+  int32_t L;                 /* nearest translates per probe, 1 <= L <= |I_f|         */
+  int32_t basis_kind;        /* LMA_BASIS_PROBE                                      */
+  int32_t precision;         /* LMA_GEMM_FP32 | LMA_GEMM_SPLIT_BF16                  */
+  int32_t window[4];         /* scan window a0, b0, width, height (0,0,0,0 = all)    */
+  int32_t batch;             /* waves per propagation batch (0 = automatic)          */
+  int64_t hbm_budget_bytes;  /* device-memory budget of the plan (0 = free memory)   */
+} lma_lattice;
+
+/* 2-D STEM detectors (Sec. 3.1, step 3): ring r collects lambda|k| in [inner, outer). */
+typedef struct {
+  int32_t n;                 /* 1..8                                                 */
+  const double* inner;       /* [n], radians, >= 0                                   */
+  const double* outer;       /* [n], radians, > inner                                */
+} lma_detectors;
+
+/* Summary of a built plan. */
+typedef struct {
+  int32_t nx, ny;
+  int32_t n_translates;      /* |I_f|                                                */
+  int32_t rfx, rfy;          /* I_f is Rfx x Rfy                                     */
+  int32_t n_sets;            /* coefficient sets (Case 1: 1, Case 2: c d)             */
+  int32_t ncls_x, ncls_y;    /* sets along x and y                                   */
+  int32_t L;
+  int32_t n_det;
+  int32_t n_pix;             /* D: detector pixels kept per exit wave                */
+  int32_t n_probes;          /* probes in the window                                 */
+  int32_t n_rows;            /* translates the window needs (resident basis rows)    */
+  int32_t batch;             /* waves per propagation batch                          */
+  int32_t n_aperture;        /* |K|, frequencies inside the aperture                 */
+  int32_t basis_valid;       /* 1 after a successful lma_propagate                   */
+  int32_t host_only;
+  double max_residual;       /* largest relative LSQ residual over the sets          */
+  int64_t device_bytes;      /* device memory held by the plan                       */
+} lma_info;
+
+/* Per-kernel timing of the last timed calls (enable with lma_set_timing). */
+typedef struct {
+  char name[32];
+  int64_t launches;
+  double total_ms;
+} lma_kernel_time;
+
+/* Relativistic electron wavelength (Angstrom) and interaction constant (rad/(V*A)) for an
+ * accelerating voltage in kV (textbook formulas; the paper prints lambda(200 kV) =
+ * 0.0250793 A). Either output pointer may be NULL. LMA_ERR_ARG if kv <= 0. */
+lma_status lma_electron_constants(double kv, double* wavelength, double* sigma);
+
+/* Plan an LMA simulation (initialisation step of Fig. lma_pseudocode): probe spectrum
+ * (eq. probe_wave_function), propagator, detector pixel list, the input-wave lattice I_f,
+ * the L nearest translates of every coefficient set and their least-squares coefficients
+ * (Sec. 4.2.2, computed on the host in FP64), and the translates the scan window needs.
+ * Uploads the tables and allocates the resident basis unless flags has LMA_HOST_ONLY.
+ * hip_stream: a hipStream_t (may be NULL). On success *out owns the plan. */
+lma_status lma_build_basis(const lma_optics* optics, const lma_lattice* lattice,
+                           const lma_detectors* detectors, void* hip_stream, int32_t flags,
+                           lma_plan** out);
+
+/* Step 1 of Fig. lma_pseudocode: multislice (Fig. multislice_pseudocode) of every needed
+ * translate u_i = u(. - i): per slice, transmission by exp(i sigma v_j), forward FFT,
+ * Fresnel propagator with band limit, inverse FFT; the exit wave is kept in Fourier
+ * space at the D detector pixels as the resident basis.
+ * potential: float [nslices][ny][nx] (host, or device with LMA_PTR_DEVICE).
+ * Phase arguments sigma*v are formed in FP64. */
+lma_status lma_propagate(lma_plan* plan, const float* potential, int32_t nslices, int32_t flags);
+
+/* Step 2 of Fig. lma_pseudocode plus the detector: for every probe p in the window,
+ * psi_p^exit = sum_j alpha_{s(p),j} U_{i_j(p)} (eqs. lma_approximation_exit1/2) and
+ * I_r(p) = sum over ring r of |F(psi_p^exit)|^2 / (XY).
+ * image: double [n_det][h][w] of the window; image = weight*I, or += with LMA_ACCUMULATE
+ * (frozen-phonon averaging: weight = 1/n_phonons). Needs a valid basis. */
+lma_status lma_probe_image(lma_plan* plan, double* image, int32_t flags, double weight);
+
+/* Plain multislice comparator (Sec. 3.1 steps 1-3): every probe of the window propagated
+ * directly, same kernels, same detectors, same image layout and flags as lma_probe_image.
+ * Does not touch the resident basis. */
+lma_status lma_plain_image(lma_plan* plan, const float* potential, int32_t nslices,
+                           double* image, int32_t flags, double weight);
+
+/* Local recompute after a specimen edit (Sec. 4.2.6): re-propagate the resident translates
+ * whose centre lies within radius_A of the edited pixel box, with the new potential, and
+ * re-form the probes whose translate set meets them; their image values are replaced in
+ * `image` (host, the layout of lma_probe_image, holding the previous image). bbox_px:
+ * x0, y0, x1, y1, half-open, periodic. radius_A <= 0 selects every translate (the full
+ * recompute). Outputs: counts of re-propagated translates and re-formed probes. */
+lma_status lma_recompute_local(lma_plan* plan, const float* potential_new, int32_t nslices,
+                               const int32_t bbox_px[4], double radius_A, double* image,
+                               int32_t* n_translates_redone, int32_t* n_probes_redone);
+
+/* Device bytes a plan with these arguments would hold for nslices slices. */
+lma_status lma_footprint(const lma_optics* optics, const lma_lattice* lattice,
+                         const lma_detectors* detectors, int32_t nslices, int64_t* bytes);
+
+/* Inspection (host logic; work on host-only plans). Arrays are caller-allocated with the
+ * sizes given by lma_plan_info. */
+lma_status lma_plan_info(const lma_plan* plan, lma_info* out);
+/* I_f positions, double [n_translates][2], Angstrom, translate t = b*Rfx + a. */
+lma_status lma_get_translates(const lma_plan* plan, double* pos);
+/* Per coefficient set s (s = sy*ncls_x + sx): translate indices of its L nearest
+ * translates (int32 [n_sets][L]) and their coefficients (double [n_sets][L][2]). */
+lma_status lma_get_coefficients(const lma_plan* plan, int32_t* translate, double* alpha);
+/* Detector pixels: flat index ky*nx + kx (int32 [D]) and ring bit mask (uint32 [D]). */
+lma_status lma_get_detector_pixels(const lma_plan* plan, int32_t* flat, uint32_t* mask);
+/* Normalised probe spectrum psi_0-hat (sum |.|^2 = XY), double [ny][nx][2]. */
+lma_status lma_get_probe_spectrum(const lma_plan* plan, double* spec);
+/* Resident-basis rows first..first+count-1 (rows in increasing translate order, see
+ * lma_get_rows): F(U_i) at the D detector pixels, float [count][D][2] on the host. */
+lma_status lma_get_basis_rows(lma_plan* plan, int32_t first, int32_t count, float* out);
+/* Translate index of each resident row, int32 [n_rows]. */
+lma_status lma_get_rows(const lma_plan* plan, int32_t* translate);
+
+/* Kernel timing with hipEvents around every launch (adds a little overhead). */
+lma_status lma_set_timing(lma_plan* plan, int32_t enable);
+/* Fills up to max entries, returns the count in *n; resets the counters if reset != 0. */
+lma_status lma_get_timing(lma_plan* plan, lma_kernel_time* out, int32_t max, int32_t* n,
+                          int32_t reset);
+
+void lma_destroy(lma_plan* plan);
+const char* lma_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LMA_H */

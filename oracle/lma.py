@@ -67,6 +67,7 @@ class Lattice:
                 raise ValueError("probe and input-wave lattices incompatible (Case 1 / Case 2)")
         self.ncls_x = Px // gcd(Px, self.Rfx)
         self.ncls_y = Py // gcd(Py, self.Rfy)
+        self._nearest = {}
 
     # --- positions -----------------------------------------------------------------
     def translate_position(self, a: int, b: int):
@@ -86,6 +87,12 @@ class Lattice:
     # --- option (iii): the L closest input waves -----------------------------------
     def nearest(self, a: int, b: int):
         """I_{f,p,L} for probe (a, b) as a list of (ta, tb) translate indices, nearest first."""
+        key = (a, b)
+        if key not in self._nearest:
+            self._nearest[key] = self._nearest_uncached(a, b)
+        return self._nearest[key]
+
+    def _nearest_uncached(self, a: int, b: int):
         px, py = self.probe_position_exact(a, b)
         keys = []
         for tb in range(self.Rfy):
@@ -187,3 +194,42 @@ class LMA:
 def phonon_average(images) -> np.ndarray:
     """Frozen-phonon image: the mean of the per-configuration images (Sec. 3.1)."""
     return np.mean(np.stack(list(images)), axis=0)
+
+
+def recompute_sets(lat: Lattice, bbox_px, rho: float):
+    """Local recompute after a specimen edit (Sec. 4.2.6).
+
+    Reading of "close enough to the changes": a translate is re-propagated when its centre
+    lies within ``rho`` (Angstrom) of the edited pixels, the box x0..x1-1, y0..y1-1 (pixel
+    indices, periodic; distance along each axis to the box's span of pixel positions,
+    combined as a Euclidean distance). rho <= 0 selects every translate. The probes to
+    re-form are those whose L-nearest set contains a re-propagated translate.
+    Returns (translates R as a set of (ta, tb), probes P' as a set of (a, b))."""
+    st = lat.setup
+    x0, y0, x1, y1 = bbox_px
+    dx, dy = lat.lx / st.nx, lat.ly / st.ny
+    lo_x, hi_x = x0 * dx, (x1 - 1) * dx
+    lo_y, hi_y = y0 * dy, (y1 - 1) * dy
+
+    def axis(c, lo, hi, length):
+        if hi - lo >= length:
+            return Fraction(0)
+        t = (c - lo) % length
+        if t <= hi - lo:
+            return Fraction(0)
+        return min(t - (hi - lo), length - t)
+
+    R = set()
+    r2 = _frac(rho) ** 2 if rho > 0 else None
+    for tb in range(lat.Rfy):
+        for ta in range(lat.Rfx):
+            tx, ty = lat.translate_position(ta, tb)
+            d2 = axis(tx, lo_x, hi_x, lat.lx) ** 2 + axis(ty, lo_y, hi_y, lat.ly) ** 2
+            if r2 is None or d2 <= r2:
+                R.add((ta, tb))
+    Pp = set()
+    for b in range(st.Py):
+        for a in range(st.Px):
+            if any(t in R for t in lat.nearest(a, b)):
+                Pp.add((a, b))
+    return R, Pp

@@ -1,0 +1,232 @@
+"""Python binding of liblma.so: the MI355X hot path of the Lattice Multislice Algorithm.
+
+Argument marshalling only: every step of the simulation runs in the library (host planner
+in C++, kernels in HIP for gfx950). Host data are numpy arrays; device data are torch
+tensors on the GPU (passed by pointer with LMA_PTR_DEVICE). The library is loaded from
+this directory and there is no fallback when it is missing.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+
+from . import _lib
+from ._lib import (LMA_ACCUMULATE, LMA_BASIS_PROBE, LMA_GEMM_FP32, LMA_GEMM_SPLIT_BF16, LMA_HOST_ONLY,
+                   LMA_PTR_DEVICE, lma_detectors, lma_info, lma_kernel_time, lma_lattice, lma_optics)
+
+__all__ = ["LmaError", "Plan", "electron_constants", "footprint", "optics", "lattice", "detectors",
+           "LMA_ACCUMULATE", "LMA_PTR_DEVICE", "LMA_HOST_ONLY", "LMA_GEMM_FP32", "LMA_GEMM_SPLIT_BF16",
+           "LMA_BASIS_PROBE", "lib"]
+
+
+class LmaError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"liblma status {status}: {msg}")
+        self.status = status
+
+
+def lib():
+    return _lib.load()
+
+
+def _check(status):
+    if status != 0:
+        raise LmaError(status, lib().lma_last_error().decode())
+
+
+def electron_constants(kv: float):
+    lam, sig = C.c_double(), C.c_double()
+    _check(lib().lma_electron_constants(float(kv), C.byref(lam), C.byref(sig)))
+    return lam.value, sig.value
+
+
+def optics(nx, ny, lx, ly, wavelength, sigma, dz, bandlimit, alpha_max, defocus=0.0, cs=0.0) -> lma_optics:
+    return lma_optics(int(nx), int(ny), float(lx), float(ly), float(wavelength), float(sigma), float(dz),
+                      float(bandlimit), float(alpha_max), float(defocus), float(cs))
+
+
+def lattice(px, py, rx, ry, f=1, offset=(0.5, 0.5), L=1, precision=LMA_GEMM_FP32, window=(0, 0, 0, 0),
+            batch=0, hbm_budget_bytes=0, basis_kind=LMA_BASIS_PROBE) -> lma_lattice:
+    lat = lma_lattice()
+    lat.px, lat.py, lat.rx, lat.ry, lat.f = int(px), int(py), int(rx), int(ry), int(f)
+    lat.offset_x, lat.offset_y = float(offset[0]), float(offset[1])
+    lat.L, lat.basis_kind, lat.precision = int(L), int(basis_kind), int(precision)
+    for i in range(4):
+        lat.window[i] = int(window[i])
+    lat.batch, lat.hbm_budget_bytes = int(batch), int(hbm_budget_bytes)
+    return lat
+
+
+class _Detectors:
+    """lma_detectors plus the arrays it points into."""
+
+    def __init__(self, rings):
+        rings = list(rings)
+        self.inner = (C.c_double * len(rings))(*[float(a) for a, _ in rings])
+        self.outer = (C.c_double * len(rings))(*[float(b) for _, b in rings])
+        self.s = lma_detectors(len(rings), self.inner, self.outer)
+
+
+def detectors(rings) -> _Detectors:
+    """rings: sequence of (inner_rad, outer_rad)."""
+    return _Detectors(rings)
+
+
+def footprint(opt: lma_optics, lat: lma_lattice, det: _Detectors, nslices: int) -> int:
+    b = C.c_int64()
+    _check(lib().lma_footprint(C.byref(opt), C.byref(lat), C.byref(det.s), int(nslices), C.byref(b)))
+    return b.value
+
+
+def _is_torch(x) -> bool:
+    return type(x).__module__.startswith("torch")
+
+
+def _ptr(x, dtype):
+    """(pointer, flags) of a host numpy array or a device torch tensor."""
+    if _is_torch(x):
+        import torch
+        want = {np.float32: torch.float32, np.float64: torch.float64}[dtype]
+        if not x.is_cuda or x.dtype != want or not x.is_contiguous():
+            raise ValueError("device tensors must be contiguous, on the GPU, of the expected dtype")
+        return C.c_void_p(x.data_ptr()), LMA_PTR_DEVICE
+    if not isinstance(x, np.ndarray) or x.dtype != dtype or not x.flags.c_contiguous:
+        raise ValueError(f"host arrays must be C-contiguous numpy {np.dtype(dtype).name}")
+    return C.c_void_p(x.ctypes.data), 0
+
+
+def _current_stream():
+    try:
+        import torch
+        if torch.cuda.is_available():
+            return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    except Exception:
+        pass
+    return C.c_void_p(None)
+
+
+class Plan:
+    """An lma_plan. Methods carry the names of the C entry points without the prefix."""
+
+    def __init__(self, opt: lma_optics, lat: lma_lattice, det: _Detectors, flags: int = 0, stream=None):
+        self._h = C.c_void_p()
+        self._det = det
+        self.host_only = bool(flags & LMA_HOST_ONLY)
+        st = C.c_void_p(None) if self.host_only else (_current_stream() if stream is None else C.c_void_p(stream))
+        _check(lib().lma_build_basis(C.byref(opt), C.byref(lat), C.byref(det.s), st, int(flags), C.byref(self._h)))
+        self.nx, self.ny = opt.nx, opt.ny
+        i = self.info()
+        self.n_det, self.n_pix, self.n_rows = i.n_det, i.n_pix, i.n_rows
+        w = list(lat.window)
+        self.window = (0, 0, lat.px, lat.py) if w == [0, 0, 0, 0] else tuple(w)
+
+    # --- lifetime ----------------------------------------------------------------------
+    def close(self):
+        if self._h:
+            lib().lma_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # --- hot path ----------------------------------------------------------------------
+    def image_shape(self):
+        return (self.n_det, self.window[3], self.window[2])
+
+    def _image_out(self, image, like_device):
+        if image is None:
+            if like_device:
+                import torch
+                image = torch.zeros(self.image_shape(), dtype=torch.float64, device="cuda")
+            else:
+                image = np.zeros(self.image_shape(), dtype=np.float64)
+        return image
+
+    def propagate(self, potential, flags: int = 0):
+        p, f = _ptr(potential, np.float32)
+        _check(lib().lma_propagate(self._h, p, int(potential.shape[0]), int(flags) | f))
+
+    def probe_image(self, image=None, flags: int = 0, weight: float = 1.0, device: bool = False):
+        image = self._image_out(image, device)
+        p, f = _ptr(image, np.float64)
+        _check(lib().lma_probe_image(self._h, p, int(flags) | f, float(weight)))
+        return image
+
+    def plain_image(self, potential, image=None, flags: int = 0, weight: float = 1.0, device: bool = False):
+        pp, fp = _ptr(potential, np.float32)
+        image = self._image_out(image, device)
+        pi, fi = _ptr(image, np.float64)
+        if fp != fi:
+            raise ValueError("potential and image must both be host or both be device")
+        _check(lib().lma_plain_image(self._h, pp, int(potential.shape[0]), pi, int(flags) | fi, float(weight)))
+        return image
+
+    def recompute_local(self, potential_new, bbox, radius: float, image):
+        pp, fp = _ptr(potential_new, np.float32)
+        pi, fi = _ptr(image, np.float64)
+        if fp or fi:
+            raise ValueError("recompute_local takes host arrays")
+        bb = (C.c_int32 * 4)(*[int(x) for x in bbox])
+        nt, npr = C.c_int32(), C.c_int32()
+        _check(lib().lma_recompute_local(self._h, pp, int(potential_new.shape[0]), bb, float(radius), pi,
+                                         C.byref(nt), C.byref(npr)))
+        return nt.value, npr.value
+
+    # --- inspection --------------------------------------------------------------------
+    def info(self) -> lma_info:
+        i = lma_info()
+        _check(lib().lma_plan_info(self._h, C.byref(i)))
+        return i
+
+    def translates(self) -> np.ndarray:
+        out = np.zeros((self.info().n_translates, 2))
+        _check(lib().lma_get_translates(self._h, C.c_void_p(out.ctypes.data)))
+        return out
+
+    def coefficients(self):
+        i = self.info()
+        t = np.zeros((i.n_sets, i.L), dtype=np.int32)
+        a = np.zeros((i.n_sets, i.L, 2))
+        _check(lib().lma_get_coefficients(self._h, C.c_void_p(t.ctypes.data), C.c_void_p(a.ctypes.data)))
+        return t, a[..., 0] + 1j * a[..., 1]
+
+    def detector_pixels(self):
+        n = self.info().n_pix
+        flat = np.zeros(n, dtype=np.int32)
+        mask = np.zeros(n, dtype=np.uint32)
+        _check(lib().lma_get_detector_pixels(self._h, C.c_void_p(flat.ctypes.data), C.c_void_p(mask.ctypes.data)))
+        return flat, mask
+
+    def probe_spectrum(self) -> np.ndarray:
+        out = np.zeros((self.ny, self.nx, 2))
+        _check(lib().lma_get_probe_spectrum(self._h, C.c_void_p(out.ctypes.data)))
+        return out[..., 0] + 1j * out[..., 1]
+
+    def rows(self) -> np.ndarray:
+        out = np.zeros(self.info().n_rows, dtype=np.int32)
+        _check(lib().lma_get_rows(self._h, C.c_void_p(out.ctypes.data)))
+        return out
+
+    def basis_rows(self, first: int, count: int) -> np.ndarray:
+        out = np.zeros((count, self.n_pix, 2), dtype=np.float32)
+        _check(lib().lma_get_basis_rows(self._h, int(first), int(count), C.c_void_p(out.ctypes.data)))
+        return out[..., 0].astype(np.complex128) + 1j * out[..., 1]
+
+    def set_timing(self, enable: bool):
+        _check(lib().lma_set_timing(self._h, int(bool(enable))))
+
+    def timing(self, reset: bool = False) -> dict:
+        arr = (lma_kernel_time * 32)()
+        n = C.c_int32()
+        _check(lib().lma_get_timing(self._h, arr, 32, C.byref(n), int(bool(reset))))
+        return {arr[i].name.decode(): (arr[i].launches, arr[i].total_ms) for i in range(n.value)}

@@ -1,0 +1,765 @@
+// extern "C" entry points of liblma.so: argument checks, device buffers of a plan, and the
+// order of kernel launches for propagation, image formation and local recompute.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "kernels.hpp"
+#include "lma.h"
+#include "planner.hpp"
+
+using lma::HostPlan;
+using lma::cd;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+lma_status fail(lma_status s, const std::string& msg) {
+  g_last_error = msg;
+  return s;
+}
+
+struct TimedLaunch {
+  const char* name;
+  hipEvent_t a, b;
+};
+
+struct KernelTotals {
+  std::string name;
+  int64_t launches = 0;
+  double ms = 0.0;
+};
+
+}  // namespace
+
+struct lma_plan {
+  HostPlan h;
+  bool host_only = false;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  int B = 1;                         // waves per batch
+  bool basis_valid = false;
+  int64_t dev_bytes = 0;
+  std::vector<void*> allocs;
+
+  // tables
+  float2 *d_spec = nullptr, *d_prop = nullptr, *d_twx = nullptr, *d_twy = nullptr;
+  int32_t* d_comp_map = nullptr;
+  uint32_t* d_detmask = nullptr;
+  int32_t *d_row_of = nullptr, *d_set_dx = nullptr, *d_set_dy = nullptr;
+  int32_t *d_chunk_start = nullptr, *d_chunk_len = nullptr;
+  uint32_t* d_chunk_mask = nullptr;
+  float2* d_alpha = nullptr;
+  int64_t* d_row_u = nullptr;        // [n_rows][2] translate positions in lattice units
+  int32_t* d_row_id = nullptr;       // [n_rows] 0..n_rows-1
+  int64_t* d_probe_u = nullptr;      // [n_probes][2]
+  int32_t* d_probe_out = nullptr;    // [n_probes] image index
+  // work
+  void* d_basis = nullptr;           // [n_rows][D] x 8 bytes
+  float2* d_work = nullptr;          // [B][ny][nx]
+  float2* d_trans = nullptr;         // [cap][ny][nx]
+  int trans_cap = 0;
+  float* d_pot = nullptr;            // staging for host potentials
+  int pot_cap = 0;
+  double* d_img = nullptr;           // [ndet][n_probes]
+  int32_t* d_list = nullptr;         // scratch index list (recompute)
+  int64_t* d_list_u = nullptr;
+  int list_cap = 0;
+
+  // timing
+  bool timing = false;
+  std::vector<TimedLaunch> pending;
+  std::vector<hipEvent_t> event_pool;
+  std::vector<KernelTotals> totals;
+};
+
+namespace {
+
+#define HIP_TRY(expr)                                                                  \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      return fail(LMA_ERR_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));  \
+  } while (0)
+
+lma_status dalloc(lma_plan* p, void** ptr, size_t bytes) {
+  if (bytes == 0) bytes = 16;
+  if (p->h.lat.hbm_budget_bytes > 0 && p->dev_bytes + (int64_t)bytes > p->h.lat.hbm_budget_bytes)
+    return fail(LMA_ERR_OOM, "device-memory budget exceeded");
+  hipError_t e = hipMalloc(ptr, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    *ptr = nullptr;
+    return fail(LMA_ERR_OOM, std::string("hipMalloc of ") + std::to_string(bytes) + " bytes failed: " +
+                                 hipGetErrorString(e));
+  }
+  p->allocs.push_back(*ptr);
+  p->dev_bytes += (int64_t)bytes;
+  return LMA_OK;
+}
+
+template <class T>
+lma_status upload(lma_plan* p, T** dst, const T* src, size_t n) {
+  lma_status s = dalloc(p, reinterpret_cast<void**>(dst), n * sizeof(T));
+  if (s != LMA_OK) return s;
+  if (n) HIP_TRY(hipMemcpy(*dst, src, n * sizeof(T), hipMemcpyHostToDevice));
+  return LMA_OK;
+}
+
+void free_one(lma_plan* p, void* ptr, size_t bytes) {
+  if (!ptr) return;
+  auto it = std::find(p->allocs.begin(), p->allocs.end(), ptr);
+  if (it != p->allocs.end()) p->allocs.erase(it);
+  (void)hipFree(ptr);
+  p->dev_bytes -= (int64_t)bytes;
+}
+
+lma::dev::Tables tables(const lma_plan* p) {
+  lma::dev::Tables t;
+  t.nx = p->h.op.nx;
+  t.ny = p->h.op.ny;
+  t.Qx = p->h.Qx;
+  t.Qy = p->h.Qy;
+  t.spec_init = p->d_spec;
+  t.prop = p->d_prop;
+  t.twx = p->d_twx;
+  t.twy = p->d_twy;
+  t.comp_map = p->d_comp_map;
+  t.detmask = p->d_detmask;
+  return t;
+}
+
+std::vector<float2> twiddles(int n) {
+  std::vector<float2> w(n);
+  const double pi = 3.14159265358979323846;
+  for (int t = 0; t < n; ++t) {
+    double a = -2.0 * pi * (double)t / (double)n;
+    w[t] = make_float2((float)std::cos(a), (float)std::sin(a));
+  }
+  return w;
+}
+
+int64_t wave_bytes(const lma_optics& op) { return (int64_t)op.nx * op.ny * (int64_t)sizeof(float2); }
+
+int auto_batch(const HostPlan& h) {
+  if (h.lat.batch > 0) return h.lat.batch;
+  // about 512 MiB of wave batch
+  int64_t b = ((int64_t)512 << 20) / wave_bytes(h.op);
+  return (int)std::max<int64_t>(1, std::min<int64_t>(b, 4096));
+}
+
+// launch bookkeeping for kernel timing
+struct Launch {
+  lma_plan* p;
+  const char* name;
+  hipEvent_t a = nullptr;
+  Launch(lma_plan* plan, const char* n) : p(plan), name(n) {
+    if (!p->timing) return;
+    a = take_event(p);
+    (void)hipEventRecord(a, p->stream);
+  }
+  static hipEvent_t take_event(lma_plan* p) {
+    if (!p->event_pool.empty()) {
+      hipEvent_t e = p->event_pool.back();
+      p->event_pool.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    (void)hipEventCreate(&e);
+    return e;
+  }
+  void done() {
+    if (!p->timing) return;
+    hipEvent_t b = take_event(p);
+    (void)hipEventRecord(b, p->stream);
+    p->pending.push_back({name, a, b});
+  }
+};
+
+void collect_timing(lma_plan* p) {
+  if (p->pending.empty()) return;
+  (void)hipStreamSynchronize(p->stream);
+  for (auto& t : p->pending) {
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, t.a, t.b);
+    auto it = std::find_if(p->totals.begin(), p->totals.end(), [&](const KernelTotals& k) { return k.name == t.name; });
+    if (it == p->totals.end()) {
+      p->totals.push_back({t.name, 0, 0.0});
+      it = p->totals.end() - 1;
+    }
+    it->launches += 1;
+    it->ms += ms;
+    p->event_pool.push_back(t.a);
+    p->event_pool.push_back(t.b);
+  }
+  p->pending.clear();
+}
+
+#define LAUNCH(plan, name, call)                                                          \
+  do {                                                                                    \
+    Launch l_(plan, name);                                                                \
+    hipError_t e_ = (call);                                                               \
+    l_.done();                                                                            \
+    if (e_ != hipSuccess) return fail(LMA_ERR_DEVICE, std::string(name) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+// transmission tables t_j = exp(i sigma v_j) for the given potential
+lma_status prepare_transmission(lma_plan* p, const float* potential, int nslices, int32_t flags) {
+  const int64_t XY = (int64_t)p->h.op.nx * p->h.op.ny;
+  if (nslices > p->trans_cap) {
+    free_one(p, p->d_trans, (size_t)p->trans_cap * XY * sizeof(float2));
+    p->d_trans = nullptr;
+    p->trans_cap = 0;
+    lma_status s = dalloc(p, reinterpret_cast<void**>(&p->d_trans), (size_t)nslices * XY * sizeof(float2));
+    if (s != LMA_OK) return s;
+    p->trans_cap = nslices;
+  }
+  const float* src = potential;
+  if (!(flags & LMA_PTR_DEVICE)) {
+    if (nslices > p->pot_cap) {
+      free_one(p, p->d_pot, (size_t)p->pot_cap * XY * sizeof(float));
+      p->d_pot = nullptr;
+      p->pot_cap = 0;
+      lma_status s = dalloc(p, reinterpret_cast<void**>(&p->d_pot), (size_t)nslices * XY * sizeof(float));
+      if (s != LMA_OK) return s;
+      p->pot_cap = nslices;
+    }
+    HIP_TRY(hipMemcpyAsync(p->d_pot, potential, (size_t)nslices * XY * sizeof(float), hipMemcpyHostToDevice, p->stream));
+    src = p->d_pot;
+  }
+  LAUNCH(p, "transmission", lma::dev::transmission(src, p->d_trans, (int64_t)nslices * XY, p->h.op.sigma, p->stream));
+  return LMA_OK;
+}
+
+// multislice of waves [first, first + n) of a position list; the last column pass either
+// gathers basis rows (wave_row != null) or reduces into the image (wave_out != null)
+lma_status run_waves(lma_plan* p, const int64_t* d_u, const int32_t* d_row, const int32_t* d_out, int n, int nslices) {
+  const lma::dev::Tables T = tables(p);
+  const int64_t XY = (int64_t)p->h.op.nx * p->h.op.ny;
+  const int split = p->h.lat.precision == LMA_GEMM_SPLIT_BF16;
+  for (int first = 0; first < n; first += p->B) {
+    const int nb = std::min(p->B, n - first);
+    LAUNCH(p, "init", lma::dev::init_waves(T, p->d_work, d_u + 2 * (int64_t)first, nb, p->stream));
+    for (int j = 0; j < nslices; ++j) {
+      LAUNCH(p, "row_pass", lma::dev::row_pass(T, p->d_work, p->d_trans + (size_t)j * XY, nb, p->stream));
+      if (j + 1 < nslices) {
+        LAUNCH(p, "col_pass", lma::dev::col_pass(T, p->d_work, nb, p->stream));
+      } else if (d_row) {
+        LAUNCH(p, "col_gather", lma::dev::col_gather(T, p->d_work, nb, p->d_basis, p->h.D(), d_row + first, split, p->stream));
+      } else {
+        LAUNCH(p, "col_reduce", lma::dev::col_reduce(T, p->d_work, nb, d_out + first, p->d_img, p->h.ndet,
+                                                     p->h.n_probes(), (double)XY, p->stream));
+      }
+    }
+  }
+  return LMA_OK;
+}
+
+lma_status ensure_list(lma_plan* p, int n) {
+  if (n <= p->list_cap) return LMA_OK;
+  free_one(p, p->d_list, (size_t)p->list_cap * sizeof(int32_t));
+  free_one(p, p->d_list_u, (size_t)p->list_cap * 2 * sizeof(int64_t));
+  p->d_list = nullptr;
+  p->d_list_u = nullptr;
+  p->list_cap = 0;
+  lma_status s = dalloc(p, reinterpret_cast<void**>(&p->d_list), (size_t)n * sizeof(int32_t));
+  if (s != LMA_OK) return s;
+  s = dalloc(p, reinterpret_cast<void**>(&p->d_list_u), (size_t)n * 2 * sizeof(int64_t));
+  if (s != LMA_OK) return s;
+  p->list_cap = n;
+  return LMA_OK;
+}
+
+lma::dev::Contraction contraction(const lma_plan* p) {
+  const HostPlan& h = p->h;
+  lma::dev::Contraction c;
+  c.basis = p->d_basis;
+  c.split_bf16 = h.lat.precision == LMA_GEMM_SPLIT_BF16;
+  c.D = h.D();
+  c.row_of = p->d_row_of;
+  c.set_dx = p->d_set_dx;
+  c.set_dy = p->d_set_dy;
+  c.alpha = p->d_alpha;
+  c.L = h.lat.L;
+  c.Rfx = h.Rfx;
+  c.Rfy = h.Rfy;
+  c.ncls_x = h.ncls_x;
+  c.ncls_y = h.ncls_y;
+  c.stepx = h.Rfx / h.gx;
+  c.stepy = h.Rfy / h.gy;
+  c.wa0 = h.wa0;
+  c.wb0 = h.wb0;
+  c.ww = h.ww;
+  c.wh = h.wh;
+  c.chunk_start = p->d_chunk_start;
+  c.chunk_len = p->d_chunk_len;
+  c.chunk_mask = p->d_chunk_mask;
+  c.nchunks = (int)h.chunk_start.size();
+  c.ndet = h.ndet;
+  c.scale = (double)h.op.nx * h.op.ny;
+  c.img = p->d_img;
+  return c;
+}
+
+lma_status write_image(lma_plan* p, double* image, int32_t flags, double weight) {
+  const int64_t n = (int64_t)p->h.ndet * p->h.n_probes();
+  if (flags & LMA_PTR_DEVICE) {
+    LAUNCH(p, "scale_out", lma::dev::scale_out(image, p->d_img, n, weight, (flags & LMA_ACCUMULATE) ? 1 : 0, p->stream));
+    return LMA_OK;
+  }
+  std::vector<double> tmp((size_t)n);
+  HIP_TRY(hipMemcpyAsync(tmp.data(), p->d_img, (size_t)n * sizeof(double), hipMemcpyDeviceToHost, p->stream));
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  if (flags & LMA_ACCUMULATE)
+    for (int64_t i = 0; i < n; ++i) image[i] += weight * tmp[i];
+  else
+    for (int64_t i = 0; i < n; ++i) image[i] = weight * tmp[i];
+  return LMA_OK;
+}
+
+int64_t footprint_of(const HostPlan& h, int B, int nslices, bool with_basis) {
+  const int64_t XY = (int64_t)h.op.nx * h.op.ny;
+  int64_t b = 0;
+  b += XY * (8 + 8 + 4 + 4);                          // spectrum, propagator, compaction map, ring masks
+  b += (int64_t)(h.op.nx + h.op.ny) * 8;              // twiddles
+  b += h.n_translates() * 4;                          // row map
+  b += (int64_t)h.nsets * h.lat.L * (4 + 4 + 8);      // neighbours, coefficients
+  b += (int64_t)h.chunk_start.size() * 12;
+  b += (int64_t)h.rows.size() * 20 + h.n_probes() * 20;
+  b += (int64_t)h.ndet * h.n_probes() * 8;            // image
+  b += (int64_t)B * XY * 8;                           // wave batch
+  b += (int64_t)nslices * XY * (8 + 4);               // transmission tables and potential staging
+  if (with_basis) b += (int64_t)h.rows.size() * h.D() * 8;
+  return b;
+}
+
+}  // namespace
+
+// ==============================================================================================
+// extern "C"
+// ==============================================================================================
+extern "C" {
+
+const char* lma_last_error(void) { return g_last_error.c_str(); }
+
+lma_status lma_electron_constants(double kv, double* wavelength, double* sigma) {
+  if (!(kv > 0) || !std::isfinite(kv)) return fail(LMA_ERR_ARG, "kv must be positive");
+  lma::electron_constants(kv, wavelength, sigma);
+  return LMA_OK;
+}
+
+lma_status lma_footprint(const lma_optics* optics, const lma_lattice* lattice, const lma_detectors* detectors,
+                         int32_t nslices, int64_t* bytes) {
+  if (!bytes) return fail(LMA_ERR_ARG, "bytes is null");
+  if (nslices < 1) return fail(LMA_ERR_ARG, "nslices must be >= 1");
+  try {
+    HostPlan h;
+    std::string err;
+    lma_status s = lma::build_host_plan(optics, lattice, detectors, &h, &err);
+    if (s != LMA_OK) return fail(s, err);
+    int B = auto_batch(h);
+    B = (int)std::min<int64_t>(B, std::max<int64_t>(std::max<int64_t>((int64_t)h.rows.size(), h.n_probes()), 1));
+    *bytes = footprint_of(h, B, nslices, true);
+    return LMA_OK;
+  } catch (const std::bad_alloc&) {
+    return fail(LMA_ERR_OOM, "host allocation failed");
+  } catch (const std::exception& e) {
+    return fail(LMA_ERR_ARG, e.what());
+  }
+}
+
+static void release(lma_plan* p) {
+  if (!p) return;
+  for (auto& t : p->pending) {
+    (void)hipEventDestroy(t.a);
+    (void)hipEventDestroy(t.b);
+  }
+  for (auto e : p->event_pool) (void)hipEventDestroy(e);
+  for (void* a : p->allocs) (void)hipFree(a);
+  delete p;
+}
+
+void lma_destroy(lma_plan* plan) {
+  if (!plan) return;
+  if (!plan->host_only) (void)hipStreamSynchronize(plan->stream);
+  release(plan);
+}
+
+lma_status lma_build_basis(const lma_optics* optics, const lma_lattice* lattice, const lma_detectors* detectors,
+                           void* hip_stream, int32_t flags, lma_plan** out) {
+  if (!out) return fail(LMA_ERR_ARG, "out is null");
+  *out = nullptr;
+  lma_plan* p = nullptr;
+  try {
+    p = new lma_plan();
+    std::string err;
+    lma_status s = lma::build_host_plan(optics, lattice, detectors, &p->h, &err);
+    if (s != LMA_OK) {
+      delete p;
+      return fail(s, err);
+    }
+    p->host_only = (flags & LMA_HOST_ONLY) != 0;
+    p->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    const HostPlan& h = p->h;
+    p->B = std::max(1, std::min<int>(auto_batch(h), (int)std::max<int64_t>(std::max<int64_t>((int64_t)h.rows.size(), h.n_probes()), 1)));
+    if (p->host_only) {
+      *out = p;
+      return LMA_OK;
+    }
+    if (hipGetDevice(&p->device) != hipSuccess) {
+      delete p;
+      return fail(LMA_ERR_DEVICE, "no HIP device");
+    }
+    const int64_t XY = (int64_t)h.op.nx * h.op.ny;
+    if (h.lat.hbm_budget_bytes == 0) {
+      size_t fr = 0, tot = 0;
+      if (hipMemGetInfo(&fr, &tot) == hipSuccess) {
+        int64_t need = footprint_of(h, p->B, 1, true);
+        if (need > (int64_t)fr) {
+          release(p);
+          return fail(LMA_ERR_OOM, "the resident basis and wave batch exceed free device memory (" +
+                                       std::to_string(need) + " > " + std::to_string(fr) + " bytes)");
+        }
+      }
+    }
+    // tables
+    std::vector<float2> v((size_t)XY);
+    auto to_f2 = [&](const std::vector<cd>& src, double scale) {
+      for (int64_t i = 0; i < XY; ++i) v[i] = make_float2((float)(src[i].real() * scale), (float)(src[i].imag() * scale));
+    };
+    to_f2(h.spec, 1.0 / (double)XY);
+    if ((s = upload(p, &p->d_spec, v.data(), v.size())) != LMA_OK) { release(p); return s; }
+    to_f2(h.prop, 1.0);
+    if ((s = upload(p, &p->d_prop, v.data(), v.size())) != LMA_OK) { release(p); return s; }
+    auto twx = twiddles(h.op.nx), twy = twiddles(h.op.ny);
+    if ((s = upload(p, &p->d_twx, twx.data(), twx.size())) != LMA_OK) { release(p); return s; }
+    if ((s = upload(p, &p->d_twy, twy.data(), twy.size())) != LMA_OK) { release(p); return s; }
+    if ((s = upload(p, &p->d_comp_map, h.comp_map.data(), h.comp_map.size())) != LMA_OK) { release(p); return s; }
+    if ((s = upload(p, &p->d_detmask, h.detmask.data(), h.detmask.size())) != LMA_OK) { release(p); return s; }
+    if ((s = upload(p, &p->d_row_of, h.row_of.data(), h.row_of.size())) != LMA_OK) { release(p); return s; }
+    if ((s = upload(p, &p->d_set_dx, h.set_dx.data(), h.set_dx.size())) != LMA_OK) { release(p); return s; }
+    if ((s = upload(p, &p->d_set_dy, h.set_dy.data(), h.set_dy.size())) != LMA_OK) { release(p); return s; }
+    if ((s = upload(p, &p->d_chunk_start, h.chunk_start.data(), h.chunk_start.size())) != LMA_OK) { release(p); return s; }
+    if ((s = upload(p, &p->d_chunk_len, h.chunk_len.data(), h.chunk_len.size())) != LMA_OK) { release(p); return s; }
+    if ((s = upload(p, &p->d_chunk_mask, h.chunk_mask.data(), h.chunk_mask.size())) != LMA_OK) { release(p); return s; }
+    std::vector<float2> al(h.alpha.size());
+    for (size_t i = 0; i < al.size(); ++i) al[i] = make_float2((float)h.alpha[i].real(), (float)h.alpha[i].imag());
+    if ((s = upload(p, &p->d_alpha, al.data(), al.size())) != LMA_OK) { release(p); return s; }
+    // wave position lists
+    std::vector<int64_t> ru(h.rows.size() * 2);
+    std::vector<int32_t> rid(h.rows.size());
+    for (size_t r = 0; r < h.rows.size(); ++r) {
+      int t = h.rows[r];
+      ru[2 * r] = ((t % h.Rfx) * h.stepTx + h.oxu) % h.Qx;
+      ru[2 * r + 1] = ((t / h.Rfx) * h.stepTy + h.oyu) % h.Qy;
+      rid[r] = (int32_t)r;
+    }
+    if ((s = upload(p, &p->d_row_u, ru.data(), ru.size())) != LMA_OK) { release(p); return s; }
+    if ((s = upload(p, &p->d_row_id, rid.data(), rid.size())) != LMA_OK) { release(p); return s; }
+    std::vector<int64_t> pu((size_t)h.n_probes() * 2);
+    std::vector<int32_t> po((size_t)h.n_probes());
+    for (int b = 0; b < h.wh; ++b)
+      for (int a = 0; a < h.ww; ++a) {
+        int64_t i = (int64_t)b * h.ww + a;
+        pu[2 * i] = ((int64_t)(h.wa0 + a) * h.stepPx) % h.Qx;
+        pu[2 * i + 1] = ((int64_t)(h.wb0 + b) * h.stepPy) % h.Qy;
+        po[i] = (int32_t)i;
+      }
+    if ((s = upload(p, &p->d_probe_u, pu.data(), pu.size())) != LMA_OK) { release(p); return s; }
+    if ((s = upload(p, &p->d_probe_out, po.data(), po.size())) != LMA_OK) { release(p); return s; }
+    // buffers
+    if ((s = dalloc(p, (void**)&p->d_img, (size_t)h.ndet * h.n_probes() * sizeof(double))) != LMA_OK) { release(p); return s; }
+    if ((s = dalloc(p, (void**)&p->d_work, (size_t)p->B * XY * sizeof(float2))) != LMA_OK) { release(p); return s; }
+    if ((s = dalloc(p, &p->d_basis, (size_t)h.rows.size() * h.D() * 8)) != LMA_OK) { release(p); return s; }
+    *out = p;
+    return LMA_OK;
+  } catch (const std::bad_alloc&) {
+    if (p) release(p);
+    return fail(LMA_ERR_OOM, "host allocation failed");
+  } catch (const std::exception& e) {
+    if (p) release(p);
+    return fail(LMA_ERR_ARG, e.what());
+  }
+}
+
+static lma_status check_device_call(lma_plan* p, const void* ptr, int32_t nslices) {
+  if (!p) return fail(LMA_ERR_ARG, "plan is null");
+  if (p->host_only) return fail(LMA_ERR_STATE, "host-only plan has no device state");
+  if (!ptr) return fail(LMA_ERR_ARG, "null data pointer");
+  if (nslices < 1) return fail(LMA_ERR_ARG, "nslices must be >= 1");
+  return LMA_OK;
+}
+
+lma_status lma_propagate(lma_plan* plan, const float* potential, int32_t nslices, int32_t flags) {
+  lma_status s = check_device_call(plan, potential, nslices);
+  if (s != LMA_OK) return s;
+  plan->basis_valid = false;
+  try {
+    if ((s = prepare_transmission(plan, potential, nslices, flags)) != LMA_OK) return s;
+    if ((s = run_waves(plan, plan->d_row_u, plan->d_row_id, nullptr, (int)plan->h.rows.size(), nslices)) != LMA_OK) return s;
+    if (!(flags & LMA_PTR_DEVICE)) HIP_TRY(hipStreamSynchronize(plan->stream));
+    plan->basis_valid = true;
+    return LMA_OK;
+  } catch (const std::exception& e) {
+    return fail(LMA_ERR_DEVICE, e.what());
+  }
+}
+
+lma_status lma_probe_image(lma_plan* plan, double* image, int32_t flags, double weight) {
+  lma_status s = check_device_call(plan, image, 1);
+  if (s != LMA_OK) return s;
+  if (!plan->basis_valid) return fail(LMA_ERR_STATE, "no valid propagated basis (call lma_propagate)");
+  if (!std::isfinite(weight)) return fail(LMA_ERR_ARG, "weight must be finite");
+  try {
+    HIP_TRY(hipMemsetAsync(plan->d_img, 0, (size_t)plan->h.ndet * plan->h.n_probes() * sizeof(double), plan->stream));
+    LAUNCH(plan, "contract", lma::dev::contract(contraction(plan), plan->stream));
+    return write_image(plan, image, flags, weight);
+  } catch (const std::exception& e) {
+    return fail(LMA_ERR_DEVICE, e.what());
+  }
+}
+
+lma_status lma_plain_image(lma_plan* plan, const float* potential, int32_t nslices, double* image, int32_t flags,
+                           double weight) {
+  lma_status s = check_device_call(plan, potential, nslices);
+  if (s != LMA_OK) return s;
+  if (!image) return fail(LMA_ERR_ARG, "image is null");
+  if (!std::isfinite(weight)) return fail(LMA_ERR_ARG, "weight must be finite");
+  try {
+    if ((s = prepare_transmission(plan, potential, nslices, flags)) != LMA_OK) return s;
+    HIP_TRY(hipMemsetAsync(plan->d_img, 0, (size_t)plan->h.ndet * plan->h.n_probes() * sizeof(double), plan->stream));
+    if ((s = run_waves(plan, plan->d_probe_u, nullptr, plan->d_probe_out, (int)plan->h.n_probes(), nslices)) != LMA_OK) return s;
+    return write_image(plan, image, flags, weight);
+  } catch (const std::exception& e) {
+    return fail(LMA_ERR_DEVICE, e.what());
+  }
+}
+
+lma_status lma_recompute_local(lma_plan* plan, const float* potential_new, int32_t nslices, const int32_t bbox_px[4],
+                               double radius_A, double* image, int32_t* n_translates_redone,
+                               int32_t* n_probes_redone) {
+  lma_status s = check_device_call(plan, potential_new, nslices);
+  if (s != LMA_OK) return s;
+  if (!image || !bbox_px) return fail(LMA_ERR_ARG, "null argument");
+  if (!plan->basis_valid) return fail(LMA_ERR_STATE, "no valid propagated basis (call lma_propagate)");
+  if (!std::isfinite(radius_A)) return fail(LMA_ERR_ARG, "radius must be finite");
+  const HostPlan& h = plan->h;
+  const int nx = h.op.nx, ny = h.op.ny;
+  if (bbox_px[2] <= bbox_px[0] || bbox_px[3] <= bbox_px[1]) return fail(LMA_ERR_ARG, "empty edit box");
+  try {
+    // translates whose centre lies within radius_A of the edited pixels (periodic distance)
+    const double dx = h.op.lx / nx, dy = h.op.ly / ny;
+    auto axis_dist = [](double c, double lo, double hi, double l) {
+      // distance from c to the periodic interval [lo, hi] (hi - lo < l means a proper interval)
+      if (hi - lo >= l) return 0.0;
+      double t = std::fmod(c - lo, l);
+      if (t < 0) t += l;
+      double w = hi - lo;
+      if (t <= w) return 0.0;
+      return std::min(t - w, l - t);
+    };
+    const double x0 = bbox_px[0] * dx, x1 = (bbox_px[2] - 1) * dx;
+    const double y0 = bbox_px[1] * dy, y1 = (bbox_px[3] - 1) * dy;
+    std::vector<int32_t> redo_rows;
+    std::vector<uint8_t> redo_t((size_t)h.n_translates(), 0);
+    for (size_t r = 0; r < h.rows.size(); ++r) {
+      int t = h.rows[r];
+      double fx, fy;
+      h.translate_frac(t, &fx, &fy);
+      double ddx = axis_dist(fx * h.op.lx, x0, x1, h.op.lx);
+      double ddy = axis_dist(fy * h.op.ly, y0, y1, h.op.ly);
+      if (radius_A <= 0 || ddx * ddx + ddy * ddy <= radius_A * radius_A) {
+        redo_rows.push_back((int32_t)r);
+        redo_t[t] = 1;
+      }
+    }
+    // probes whose L-nearest set meets the re-propagated translates
+    std::vector<int32_t> redo_probes;
+    for (int b = 0; b < h.wh; ++b)
+      for (int a = 0; a < h.ww; ++a) {
+        int set, shx, shy;
+        h.probe_set(h.wa0 + a, h.wb0 + b, &set, &shx, &shy);
+        bool hit = false;
+        for (int j = 0; j < h.lat.L && !hit; ++j) {
+          int ta = (h.set_dx[(size_t)set * h.lat.L + j] + shx) % h.Rfx;
+          int tb = (h.set_dy[(size_t)set * h.lat.L + j] + shy) % h.Rfy;
+          hit = redo_t[(size_t)tb * h.Rfx + ta] != 0;
+        }
+        if (hit) redo_probes.push_back(b * h.ww + a);
+      }
+    if (n_translates_redone) *n_translates_redone = (int32_t)redo_rows.size();
+    if (n_probes_redone) *n_probes_redone = (int32_t)redo_probes.size();
+    if (redo_rows.empty()) return LMA_OK;
+    plan->basis_valid = false;
+    if ((s = prepare_transmission(plan, potential_new, nslices, 0)) != LMA_OK) return s;
+    const int n = (int)std::max(redo_rows.size(), redo_probes.size());
+    if ((s = ensure_list(plan, n)) != LMA_OK) return s;
+    std::vector<int64_t> u(redo_rows.size() * 2);
+    for (size_t i = 0; i < redo_rows.size(); ++i) {
+      int t = h.rows[redo_rows[i]];
+      u[2 * i] = ((t % h.Rfx) * h.stepTx + h.oxu) % h.Qx;
+      u[2 * i + 1] = ((t / h.Rfx) * h.stepTy + h.oyu) % h.Qy;
+    }
+    HIP_TRY(hipMemcpy(plan->d_list_u, u.data(), u.size() * sizeof(int64_t), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(plan->d_list, redo_rows.data(), redo_rows.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    if ((s = run_waves(plan, plan->d_list_u, plan->d_list, nullptr, (int)redo_rows.size(), nslices)) != LMA_OK) return s;
+    plan->basis_valid = true;
+    HIP_TRY(hipStreamSynchronize(plan->stream));
+    // re-form the affected probes
+    HIP_TRY(hipMemcpy(plan->d_list, redo_probes.data(), redo_probes.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemsetAsync(plan->d_img, 0, (size_t)h.ndet * h.n_probes() * sizeof(double), plan->stream));
+    lma::dev::Contraction c = contraction(plan);
+    c.probe_list = plan->d_list;
+    c.n_list = (int)redo_probes.size();
+    LAUNCH(plan, "contract", lma::dev::contract(c, plan->stream));
+    std::vector<double> tmp((size_t)h.ndet * h.n_probes());
+    HIP_TRY(hipMemcpyAsync(tmp.data(), plan->d_img, tmp.size() * sizeof(double), hipMemcpyDeviceToHost, plan->stream));
+    HIP_TRY(hipStreamSynchronize(plan->stream));
+    const int64_t np = h.n_probes();
+    for (int r = 0; r < h.ndet; ++r)
+      for (int32_t p : redo_probes) image[r * np + p] = tmp[r * np + p];
+    return LMA_OK;
+  } catch (const std::exception& e) {
+    return fail(LMA_ERR_DEVICE, e.what());
+  }
+}
+
+lma_status lma_plan_info(const lma_plan* p, lma_info* out) {
+  if (!p || !out) return fail(LMA_ERR_ARG, "null argument");
+  const HostPlan& h = p->h;
+  std::memset(out, 0, sizeof(*out));
+  out->nx = h.op.nx;
+  out->ny = h.op.ny;
+  out->n_translates = (int32_t)h.n_translates();
+  out->rfx = h.Rfx;
+  out->rfy = h.Rfy;
+  out->n_sets = h.nsets;
+  out->ncls_x = h.ncls_x;
+  out->ncls_y = h.ncls_y;
+  out->L = h.lat.L;
+  out->n_det = h.ndet;
+  out->n_pix = h.D();
+  out->n_probes = (int32_t)h.n_probes();
+  out->n_rows = (int32_t)h.rows.size();
+  out->batch = p->B;
+  out->n_aperture = h.n_aperture;
+  out->basis_valid = p->basis_valid ? 1 : 0;
+  out->host_only = p->host_only ? 1 : 0;
+  out->max_residual = h.residual.empty() ? 0.0 : *std::max_element(h.residual.begin(), h.residual.end());
+  out->device_bytes = p->dev_bytes;
+  return LMA_OK;
+}
+
+lma_status lma_get_translates(const lma_plan* p, double* pos) {
+  if (!p || !pos) return fail(LMA_ERR_ARG, "null argument");
+  const HostPlan& h = p->h;
+  for (int64_t t = 0; t < h.n_translates(); ++t) {
+    double fx, fy;
+    h.translate_frac((int)t, &fx, &fy);
+    pos[2 * t] = fx * h.op.lx;
+    pos[2 * t + 1] = fy * h.op.ly;
+  }
+  return LMA_OK;
+}
+
+lma_status lma_get_coefficients(const lma_plan* p, int32_t* translate, double* alpha) {
+  if (!p) return fail(LMA_ERR_ARG, "null argument");
+  const HostPlan& h = p->h;
+  for (size_t i = 0; i < h.set_nbr.size(); ++i) {
+    if (translate) translate[i] = h.set_nbr[i];
+    if (alpha) {
+      alpha[2 * i] = h.alpha[i].real();
+      alpha[2 * i + 1] = h.alpha[i].imag();
+    }
+  }
+  return LMA_OK;
+}
+
+lma_status lma_get_detector_pixels(const lma_plan* p, int32_t* flat, uint32_t* mask) {
+  if (!p) return fail(LMA_ERR_ARG, "null argument");
+  const HostPlan& h = p->h;
+  for (int d = 0; d < h.D(); ++d) {
+    if (flat) flat[d] = h.comp_flat[d];
+    if (mask) mask[d] = h.comp_mask[d];
+  }
+  return LMA_OK;
+}
+
+lma_status lma_get_probe_spectrum(const lma_plan* p, double* spec) {
+  if (!p || !spec) return fail(LMA_ERR_ARG, "null argument");
+  for (size_t i = 0; i < p->h.spec.size(); ++i) {
+    spec[2 * i] = p->h.spec[i].real();
+    spec[2 * i + 1] = p->h.spec[i].imag();
+  }
+  return LMA_OK;
+}
+
+lma_status lma_get_rows(const lma_plan* p, int32_t* translate) {
+  if (!p || !translate) return fail(LMA_ERR_ARG, "null argument");
+  std::copy(p->h.rows.begin(), p->h.rows.end(), translate);
+  return LMA_OK;
+}
+
+lma_status lma_get_basis_rows(lma_plan* p, int32_t first, int32_t count, float* out) {
+  if (!p || !out) return fail(LMA_ERR_ARG, "null argument");
+  if (p->host_only) return fail(LMA_ERR_STATE, "host-only plan has no device state");
+  if (!p->basis_valid) return fail(LMA_ERR_STATE, "no valid propagated basis");
+  if (first < 0 || count < 0 || (int64_t)first + count > (int64_t)p->h.rows.size())
+    return fail(LMA_ERR_ARG, "row range outside the resident basis");
+  const int D = p->h.D();
+  const double XY = (double)p->h.op.nx * p->h.op.ny;
+  std::vector<uint16_t> raw((size_t)count * D * 4);
+  HIP_TRY(hipMemcpyAsync(raw.data(), (const char*)p->d_basis + (size_t)first * D * 8, raw.size() * 2,
+                         hipMemcpyDeviceToHost, p->stream));
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  const bool split = p->h.lat.precision == LMA_GEMM_SPLIT_BF16;
+  for (size_t i = 0; i < (size_t)count * D; ++i) {
+    float re, im;
+    if (split) {
+      auto bf = [](uint16_t b) { uint32_t u = (uint32_t)b << 16; float f; std::memcpy(&f, &u, 4); return f; };
+      re = bf(raw[4 * i]) + bf(raw[4 * i + 1]);
+      im = bf(raw[4 * i + 2]) + bf(raw[4 * i + 3]);
+    } else {
+      std::memcpy(&re, &raw[4 * i], 4);
+      std::memcpy(&im, &raw[4 * i + 2], 4);
+    }
+    out[2 * i] = (float)(re * XY);
+    out[2 * i + 1] = (float)(im * XY);
+  }
+  return LMA_OK;
+}
+
+lma_status lma_set_timing(lma_plan* p, int32_t enable) {
+  if (!p) return fail(LMA_ERR_ARG, "plan is null");
+  if (p->host_only) return fail(LMA_ERR_STATE, "host-only plan has no device state");
+  collect_timing(p);
+  p->timing = enable != 0;
+  return LMA_OK;
+}
+
+lma_status lma_get_timing(lma_plan* p, lma_kernel_time* out, int32_t max, int32_t* n, int32_t reset) {
+  if (!p || !n || (max > 0 && !out)) return fail(LMA_ERR_ARG, "null argument");
+  collect_timing(p);
+  int k = 0;
+  for (auto& t : p->totals) {
+    if (k >= max) break;
+    std::memset(&out[k], 0, sizeof(lma_kernel_time));
+    std::snprintf(out[k].name, sizeof(out[k].name), "%s", t.name.c_str());
+    out[k].launches = t.launches;
+    out[k].total_ms = t.ms;
+    ++k;
+  }
+  *n = k;
+  if (reset) p->totals.clear();
+  return LMA_OK;
+}
+
+}  // extern "C"

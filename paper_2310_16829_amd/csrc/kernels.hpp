@@ -1,0 +1,63 @@
+// Launchers of the gfx950 kernels (host-callable, implemented in kernels.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace lma {
+namespace dev {
+
+// Device tables of a plan (all device pointers).
+struct Tables {
+  int nx = 0, ny = 0;
+  int64_t Qx = 1, Qy = 1;            // lattice units per cell (wave positions are in units)
+  const float2* spec_init = nullptr; // probe spectrum / (XY)          [ny][nx]
+  const float2* prop = nullptr;      // propagator * band limit / (XY) [ny][nx]
+  const float2* twx = nullptr;       // exp(-2 pi i t / nx)            [nx]
+  const float2* twy = nullptr;       // exp(-2 pi i t / ny)            [ny]
+  const int32_t* comp_map = nullptr; // frequency -> detector pixel or -1 [ny][nx]
+  const uint32_t* detmask = nullptr; // ring bits per frequency        [ny][nx]
+};
+
+struct Contraction {
+  const void* basis = nullptr;       // [rows][D] float2, or 4 x bf16 (hi_re, lo_re, hi_im, lo_im)
+  int split_bf16 = 0;
+  int D = 0;
+  const int32_t* row_of = nullptr;   // [Rfy*Rfx] -> resident row
+  const int32_t* set_dx = nullptr;   // [nsets][L]
+  const int32_t* set_dy = nullptr;   // [nsets][L]
+  const float2* alpha = nullptr;     // [nsets][L]
+  int L = 0, Rfx = 0, Rfy = 0, ncls_x = 1, ncls_y = 1, stepx = 0, stepy = 0;
+  int wa0 = 0, wb0 = 0, ww = 0, wh = 0;
+  const int32_t* chunk_start = nullptr;
+  const int32_t* chunk_len = nullptr;
+  const uint32_t* chunk_mask = nullptr;
+  int nchunks = 0;
+  int ndet = 0;
+  double scale = 1.0;                // XY (exit spectra are stored divided by XY)
+  double* img = nullptr;             // [ndet][wh][ww]
+  const int32_t* probe_list = nullptr;  // optional subset of window probes (index b*ww + a)
+  int n_list = 0;
+};
+
+bool supported(int nx, int ny);
+
+hipError_t transmission(const float* v, float2* t, int64_t n, double sigma, hipStream_t s);
+// initial waves u(. - pos_w) in the mixed (kx, y) domain: column IFFT of spec * modulation
+hipError_t init_waves(const Tables& T, float2* work, const int64_t* wave_u, int B, hipStream_t s);
+// row pass of slice j: row IFFT, * t_j, row FFT
+hipError_t row_pass(const Tables& T, float2* work, const float2* trans_j, int B, hipStream_t s);
+// column pass of a middle slice: column FFT, * P, column IFFT
+hipError_t col_pass(const Tables& T, float2* work, int B, hipStream_t s);
+// last column pass, LMA: column FFT, * P, keep the detector pixels as basis rows
+hipError_t col_gather(const Tables& T, const float2* work, int B, void* basis, int D,
+                      const int32_t* wave_row, int split_bf16, hipStream_t s);
+// last column pass, plain: column FFT, * P, ring sums of |.|^2 added to img[r][wave_out[w]]
+hipError_t col_reduce(const Tables& T, const float2* work, int B, const int32_t* wave_out,
+                      double* img, int ndet, int64_t img_stride, double scale, hipStream_t s);
+// probe-coefficient contraction and detector reduction
+hipError_t contract(const Contraction& c, hipStream_t s);
+// out = (acc ? out : 0) + w * img, n doubles, device memory
+hipError_t scale_out(double* out, const double* img, int64_t n, double w, int acc, hipStream_t s);
+
+}  // namespace dev
+}  // namespace lma

@@ -1,0 +1,335 @@
+// Host planner: argument validation, probe spectrum, propagator, detector pixel list,
+// input-wave lattice, nearest translates and least-squares coefficients. FP64.
+#include "planner.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+
+#include "lsq.hpp"
+
+namespace lma {
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kHcEvA = 12398.4198;   // h c, eV * Angstrom
+constexpr double kM0c2Ev = 510998.95;   // electron rest energy, eV
+constexpr int kChunk = 256;             // detector pixels per contraction chunk
+
+bool pow2_in(int n, int lo, int hi) { return n >= lo && n <= hi && (n & (n - 1)) == 0; }
+
+// spatial frequency index in FFT order
+inline int freq_index(int m, int n) { return m < (n + 1) / 2 ? m : m - n; }
+
+int64_t lcm64(int64_t a, int64_t b) { return a / std::gcd(a, b) * b; }
+
+// minimum-image offset in [-Q/2, Q/2)
+inline int64_t min_image(int64_t d, int64_t Q) {
+  int64_t h = Q / 2;
+  int64_t r = ((d + h) % Q + Q) % Q;
+  return r - h;
+}
+
+bool finite(double x) { return std::isfinite(x); }
+
+}  // namespace
+
+void electron_constants(double kv, double* lambda, double* sigma) {
+  double ev = kv * 1e3;
+  double lam = kHcEvA / std::sqrt(ev * (2.0 * kM0c2Ev + ev));
+  if (lambda) *lambda = lam;
+  if (sigma) *sigma = 2.0 * kPi / (lam * ev) * (kM0c2Ev + ev) / (2.0 * kM0c2Ev + ev);
+}
+
+lma_status check_arguments(const lma_optics* op, const lma_lattice* lat, const lma_detectors* det,
+                           std::string* err) {
+  if (!op || !lat || !det) { *err = "null argument"; return LMA_ERR_ARG; }
+  if (!pow2_in(op->nx, 16, 2048) || !pow2_in(op->ny, 16, 2048)) {
+    *err = "nx and ny must be powers of two in [16, 2048]";
+    return LMA_ERR_UNSUPPORTED;
+  }
+  if (!(op->lx > 0) || !(op->ly > 0) || !finite(op->lx) || !finite(op->ly)) { *err = "cell size must be positive"; return LMA_ERR_ARG; }
+  if (!(op->wavelength > 0) || !finite(op->wavelength)) { *err = "wavelength must be positive"; return LMA_ERR_ARG; }
+  if (!finite(op->sigma)) { *err = "sigma must be finite"; return LMA_ERR_ARG; }
+  if (!(op->dz > 0) || !finite(op->dz)) { *err = "dz must be positive"; return LMA_ERR_ARG; }
+  if (!(op->bandlimit > 0) || !(op->bandlimit <= 1.0)) { *err = "bandlimit must be in (0, 1]"; return LMA_ERR_ARG; }
+  if (!(op->alpha_max > 0) || !finite(op->alpha_max)) { *err = "alpha_max must be positive"; return LMA_ERR_ARG; }
+  if (!finite(op->defocus) || !finite(op->cs)) { *err = "defocus and cs must be finite"; return LMA_ERR_ARG; }
+  if (lat->px < 1 || lat->py < 1 || lat->px > (1 << 20) || lat->py > (1 << 20)) { *err = "scan size out of range"; return LMA_ERR_ARG; }
+  if (lat->rx < 1 || lat->ry < 1 || lat->rx > (1 << 20) || lat->ry > (1 << 20)) { *err = "input-wave lattice size out of range"; return LMA_ERR_ARG; }
+  if (lat->f < 1 || lat->rx % lat->f || lat->ry % lat->f) { *err = "f must be >= 1 and divide rx and ry"; return LMA_ERR_ARG; }
+  int rfx = lat->rx / lat->f, rfy = lat->ry / lat->f;
+  if ((lat->px % rfx && rfx % lat->px) || (lat->py % rfy && rfy % lat->py)) {
+    *err = "probe and input-wave lattices incompatible: along each axis one of P and R/f must divide the other";
+    return LMA_ERR_ARG;
+  }
+  if ((int64_t)rfx * rfy > (int64_t)1 << 28) { *err = "too many translates"; return LMA_ERR_UNSUPPORTED; }
+  if (lat->L < 1 || (int64_t)lat->L > (int64_t)rfx * rfy) { *err = "L must be in [1, |I_f|]"; return LMA_ERR_ARG; }
+  if (lat->L > 2048) { *err = "L above 2048"; return LMA_ERR_UNSUPPORTED; }
+  if (lat->basis_kind != LMA_BASIS_PROBE) { *err = "only the probe input wave is implemented"; return LMA_ERR_UNSUPPORTED; }
+  if (lat->precision != LMA_GEMM_FP32 && lat->precision != LMA_GEMM_SPLIT_BF16) { *err = "unknown precision"; return LMA_ERR_ARG; }
+  const int32_t* w = lat->window;
+  bool whole = w[0] == 0 && w[1] == 0 && w[2] == 0 && w[3] == 0;
+  if (!whole && (w[0] < 0 || w[1] < 0 || w[2] < 1 || w[3] < 1 || w[0] + w[2] > lat->px || w[1] + w[3] > lat->py)) {
+    *err = "scan window outside the scan";
+    return LMA_ERR_ARG;
+  }
+  if (lat->batch < 0 || lat->hbm_budget_bytes < 0) { *err = "batch and budget must be >= 0"; return LMA_ERR_ARG; }
+  if (!finite(lat->offset_x) || !finite(lat->offset_y)) { *err = "offset must be finite"; return LMA_ERR_ARG; }
+  for (int ax = 0; ax < 2; ++ax) {
+    int64_t P = ax ? lat->py : lat->px, R = ax ? lat->ry : lat->rx;
+    int64_t Q = 2 * lcm64(P, R);
+    double off = (ax ? lat->offset_y : lat->offset_x) * (double)(Q / R);
+    if (std::fabs(off - std::nearbyint(off)) > 1e-9) {
+      *err = "offset must be a multiple of 1/(2 lcm(P, R)) of the cell";
+      return LMA_ERR_ARG;
+    }
+  }
+  if (det->n < 1 || det->n > kMaxDet || !det->inner || !det->outer) { *err = "1 to 8 detectors required"; return LMA_ERR_ARG; }
+  for (int r = 0; r < det->n; ++r) {
+    if (!(det->inner[r] >= 0) || !(det->outer[r] > det->inner[r]) || !finite(det->outer[r])) {
+      *err = "detector angles must satisfy 0 <= inner < outer";
+      return LMA_ERR_ARG;
+    }
+  }
+  return LMA_OK;
+}
+
+void HostPlan::probe_set(int a, int b, int* set, int* sx, int* sy) const {
+  int cx = a % ncls_x, cy = b % ncls_y;
+  *set = cy * ncls_x + cx;
+  *sx = (a / ncls_x) * (Rfx / gx);
+  *sy = (b / ncls_y) * (Rfy / gy);
+}
+
+void HostPlan::translate_frac(int t, double* fx, double* fy) const {
+  int ta = t % Rfx, tb = t / Rfx;
+  *fx = (double)((ta * stepTx + oxu) % Qx) / (double)Qx;
+  *fy = (double)((tb * stepTy + oyu) % Qy) / (double)Qy;
+}
+
+void HostPlan::probe_frac(int a, int b, double* fx, double* fy) const {
+  *fx = (double)(a * stepPx % Qx) / (double)Qx;
+  *fy = (double)(b * stepPy % Qy) / (double)Qy;
+}
+
+lma_status build_host_plan(const lma_optics* op, const lma_lattice* lat, const lma_detectors* det,
+                           HostPlan* hp, std::string* err) {
+  lma_status st = check_arguments(op, lat, det, err);
+  if (st != LMA_OK) return st;
+  HostPlan& h = *hp;
+  h.op = *op;
+  h.lat = *lat;
+  h.ndet = det->n;
+  h.det_inner.assign(det->inner, det->inner + det->n);
+  h.det_outer.assign(det->outer, det->outer + det->n);
+  const int nx = op->nx, ny = op->ny;
+  const double XY = (double)nx * ny;
+  const double lam = op->wavelength;
+
+  // ---- probe spectrum, propagator, ring masks (eqs. probe_wave_function, aberration_function,
+  //      aperture_function; Fresnel propagator of Sec. 3.2 in Fourier space) ---------------------
+  h.spec.assign((size_t)nx * ny, cd(0.0));
+  h.prop.assign((size_t)nx * ny, cd(0.0));
+  h.detmask.assign((size_t)nx * ny, 0u);
+  const double kbw = op->bandlimit * std::min(nx / (2.0 * op->lx), ny / (2.0 * op->ly));
+  const double kbw2 = kbw * kbw;
+  const double amax2 = op->alpha_max * op->alpha_max;
+  int nap = 0;
+  for (int my = 0; my < ny; ++my) {
+    double ky = (double)freq_index(my, ny) / op->ly;
+    for (int mx = 0; mx < nx; ++mx) {
+      double kx = (double)freq_index(mx, nx) / op->lx;
+      double k2 = kx * kx + ky * ky;
+      double t2 = (lam * lam) * k2;
+      size_t i = (size_t)my * nx + mx;
+      if (t2 < amax2) {
+        double chi = 0.5 * kPi * op->cs * (lam * lam * lam) * k2 * k2 - kPi * op->defocus * lam * k2;
+        h.spec[i] = cd(std::cos(chi), -std::sin(chi));
+        ++nap;
+      }
+      bool band = k2 < kbw2;
+      if (band) {
+        double ph = -kPi * lam * op->dz * k2;
+        h.prop[i] = cd(std::cos(ph), std::sin(ph)) / XY;
+        uint32_t m = 0;
+        for (int r = 0; r < h.ndet; ++r) {
+          double lo = h.det_inner[r], hi = h.det_outer[r];
+          if (t2 >= lo * lo && t2 < hi * hi) m |= 1u << r;
+        }
+        h.detmask[i] = m;
+      }
+    }
+  }
+  if (nap == 0) { *err = "the aperture contains no grid frequency"; return LMA_ERR_ARG; }
+  h.n_aperture = nap;
+  const double norm = std::sqrt(XY / nap);
+  for (auto& s : h.spec) s *= norm;
+
+  // ---- detector pixel list: sorted by (ring mask, flat index), cut into uniform chunks --------
+  std::vector<int32_t> pix;
+  for (int i = 0; i < nx * ny; ++i)
+    if (h.detmask[i]) pix.push_back(i);
+  if (pix.empty()) { *err = "no detector pixel lies inside the band limit"; return LMA_ERR_ARG; }
+  std::stable_sort(pix.begin(), pix.end(), [&](int32_t a, int32_t b) { return h.detmask[a] < h.detmask[b]; });
+  h.comp_flat = pix;
+  h.comp_mask.resize(pix.size());
+  h.comp_map.assign((size_t)nx * ny, -1);
+  for (size_t d = 0; d < pix.size(); ++d) {
+    h.comp_mask[d] = h.detmask[pix[d]];
+    h.comp_map[pix[d]] = (int32_t)d;
+  }
+  h.chunk_start.clear(); h.chunk_len.clear(); h.chunk_mask.clear();
+  for (size_t d = 0; d < pix.size();) {
+    size_t e = d;
+    while (e < pix.size() && h.comp_mask[e] == h.comp_mask[d] && e - d < (size_t)kChunk) ++e;
+    h.chunk_start.push_back((int32_t)d);
+    h.chunk_len.push_back((int32_t)(e - d));
+    h.chunk_mask.push_back(h.comp_mask[d]);
+    d = e;
+  }
+
+  // ---- lattices in exact integer units (Sec. 4.2.1) --------------------------------------------
+  h.Rfx = lat->rx / lat->f;
+  h.Rfy = lat->ry / lat->f;
+  h.Qx = 2 * lcm64(lat->px, lat->rx);
+  h.Qy = 2 * lcm64(lat->py, lat->ry);
+  h.stepPx = h.Qx / lat->px;
+  h.stepPy = h.Qy / lat->py;
+  h.stepTx = (h.Qx / lat->rx) * lat->f;
+  h.stepTy = (h.Qy / lat->ry) * lat->f;
+  h.oxu = ((int64_t)std::llround(lat->offset_x * (double)(h.Qx / lat->rx)) % h.Qx + h.Qx) % h.Qx;
+  h.oyu = ((int64_t)std::llround(lat->offset_y * (double)(h.Qy / lat->ry)) % h.Qy + h.Qy) % h.Qy;
+  h.gx = std::gcd(lat->px, h.Rfx);
+  h.gy = std::gcd(lat->py, h.Rfy);
+  h.ncls_x = lat->px / h.gx;
+  h.ncls_y = lat->py / h.gy;
+  h.nsets = h.ncls_x * h.ncls_y;
+
+  // squared distance in exact integers when the units are square (l_x/Q_x == l_y/Q_y exactly)
+  double p1 = op->lx * (double)h.Qy, e1 = std::fma(op->lx, (double)h.Qy, -p1);
+  double p2 = op->ly * (double)h.Qx, e2 = std::fma(op->ly, (double)h.Qx, -p2);
+  const bool square = (p1 == p2 && e1 == e2);
+  const long double ux = (long double)op->lx / (long double)h.Qx;
+  const long double uy = (long double)op->ly / (long double)h.Qy;
+
+  const int L = lat->L;
+  const int64_t NT = h.n_translates();
+  h.set_nbr.assign((size_t)h.nsets * L, 0);
+  h.set_dx.assign((size_t)h.nsets * L, 0);
+  h.set_dy.assign((size_t)h.nsets * L, 0);
+  h.alpha.assign((size_t)h.nsets * L, cd(0.0));
+  h.residual.assign(h.nsets, 0.0);
+
+  // aperture frequencies for the least-squares system (exact in Fourier space: u = psi_0 and
+  // every probe vanish outside the aperture, and the DFT preserves the residual up to XY)
+  std::vector<int32_t> kidx;
+  for (int i = 0; i < nx * ny; ++i)
+    if (std::abs(h.spec[i]) > 0.0) kidx.push_back(i);
+  const int m = (int)kidx.size();
+
+  struct Key { long double d2; int64_t i2; int64_t dy, dx; int32_t t; };
+  std::vector<Key> keys((size_t)NT);
+  for (int sy = 0; sy < h.ncls_y; ++sy) {
+    for (int sx = 0; sx < h.ncls_x; ++sx) {
+      const int s = sy * h.ncls_x + sx;
+      const int64_t pxu = (int64_t)sx * h.stepPx, pyu = (int64_t)sy * h.stepPy;
+      for (int tb = 0; tb < h.Rfy; ++tb) {
+        int64_t tyu = (tb * h.stepTy + h.oyu) % h.Qy;
+        int64_t dy = min_image(pyu - tyu, h.Qy);
+        for (int ta = 0; ta < h.Rfx; ++ta) {
+          int64_t txu = (ta * h.stepTx + h.oxu) % h.Qx;
+          int64_t dx = min_image(pxu - txu, h.Qx);
+          Key& k = keys[(size_t)tb * h.Rfx + ta];
+          k.i2 = dx * dx + dy * dy;
+          long double fx = dx * ux, fy = dy * uy;
+          k.d2 = fx * fx + fy * fy;
+          k.dy = dy; k.dx = dx;
+          k.t = tb * h.Rfx + ta;
+        }
+      }
+      auto less = [square](const Key& a, const Key& b) {
+        if (square) { if (a.i2 != b.i2) return a.i2 < b.i2; }
+        else if (a.d2 != b.d2) return a.d2 < b.d2;
+        if (a.dy != b.dy) return a.dy < b.dy;
+        return a.dx < b.dx;
+      };
+      std::partial_sort(keys.begin(), keys.begin() + L, keys.end(), less);
+      for (int j = 0; j < L; ++j) {
+        h.set_nbr[(size_t)s * L + j] = keys[j].t;
+        h.set_dx[(size_t)s * L + j] = keys[j].t % h.Rfx;
+        h.set_dy[(size_t)s * L + j] = keys[j].t / h.Rfx;
+      }
+      // least squares over the aperture frequencies (Sec. 4.2.2):
+      //   min || psi_hat_p - sum_j alpha_j u_hat e^{-2 pi i k.i_j} ||
+      std::vector<cd> A((size_t)m * L), b(m);
+      auto phase = [&](int k, int64_t xu, int64_t yu) {
+        int mx = freq_index(k % nx, nx), my = freq_index(k / nx, ny);
+        int64_t ax = ((int64_t)mx * xu % h.Qx + h.Qx) % h.Qx;
+        int64_t ay = ((int64_t)my * yu % h.Qy + h.Qy) % h.Qy;
+        double turns = (double)ax / (double)h.Qx + (double)ay / (double)h.Qy;
+        double a = -2.0 * kPi * turns;
+        return cd(std::cos(a), std::sin(a));
+      };
+      for (int j = 0; j < L; ++j) {
+        int t = h.set_nbr[(size_t)s * L + j];
+        int64_t txu = ((t % h.Rfx) * h.stepTx + h.oxu) % h.Qx;
+        int64_t tyu = ((t / h.Rfx) * h.stepTy + h.oyu) % h.Qy;
+        for (int r = 0; r < m; ++r) A[(size_t)j * m + r] = h.spec[kidx[r]] * phase(kidx[r], txu, tyu);
+      }
+      double bn2 = 0.0;
+      for (int r = 0; r < m; ++r) {
+        b[r] = h.spec[kidx[r]] * phase(kidx[r], pxu, pyu);
+        bn2 += std::norm(b[r]);
+      }
+      const double rcond = 2.220446049250313e-16 * XY;
+      if (m < L) {
+        // fewer equations than unknowns: pad with zero rows (the minimum-norm solution is unchanged)
+        std::vector<cd> A2((size_t)L * L, cd(0.0)), b2(L, cd(0.0));
+        for (int j = 0; j < L; ++j)
+          for (int r = 0; r < m; ++r) A2[(size_t)j * L + r] = A[(size_t)j * m + r];
+        for (int r = 0; r < m; ++r) b2[r] = b[r];
+        LsqResult res = lsq_min_norm(std::move(A2), L, L, std::move(b2), rcond);
+        for (int j = 0; j < L; ++j) h.alpha[(size_t)s * L + j] = res.x[j];
+        h.residual[s] = res.residual / std::sqrt(bn2);
+      } else {
+        LsqResult res = lsq_min_norm(std::move(A), m, L, std::move(b), rcond);
+        for (int j = 0; j < L; ++j) h.alpha[(size_t)s * L + j] = res.x[j];
+        h.residual[s] = res.residual / std::sqrt(bn2);
+      }
+    }
+  }
+
+  // ---- window and resident rows ---------------------------------------------------------------
+  const int32_t* w = lat->window;
+  if (w[0] == 0 && w[1] == 0 && w[2] == 0 && w[3] == 0) {
+    h.wa0 = 0; h.wb0 = 0; h.ww = lat->px; h.wh = lat->py;
+  } else {
+    h.wa0 = w[0]; h.wb0 = w[1]; h.ww = w[2]; h.wh = w[3];
+  }
+  std::vector<uint8_t> need((size_t)NT, 0);
+  // probes with the same set and shift share rows; walk the distinct (set, shift) pairs
+  for (int b = h.wb0; b < h.wb0 + h.wh; ++b) {
+    for (int a = h.wa0; a < h.wa0 + h.ww; ++a) {
+      int s, shx, shy;
+      h.probe_set(a, b, &s, &shx, &shy);
+      for (int j = 0; j < L; ++j) {
+        int ta = (h.set_dx[(size_t)s * L + j] + shx) % h.Rfx;
+        int tb = (h.set_dy[(size_t)s * L + j] + shy) % h.Rfy;
+        need[(size_t)tb * h.Rfx + ta] = 1;
+      }
+    }
+  }
+  h.rows.clear();
+  h.row_of.assign((size_t)NT, -1);
+  for (int64_t t = 0; t < NT; ++t)
+    if (need[t]) {
+      h.row_of[t] = (int32_t)h.rows.size();
+      h.rows.push_back((int32_t)t);
+    }
+  return LMA_OK;
+}
+
+}  // namespace lma

@@ -1,0 +1,343 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle on the same seeded inputs.
+
+Tolerances (relative L2): 1e-4 for FP32 exit waves and images, 1e-3 for images whose basis
+is stored as split BF16 (hi + lo).
+"""
+from __future__ import annotations
+
+import os
+import sys
+from concurrent.futures import ProcessPoolExecutor
+
+import numpy as np
+import pytest
+
+import paper_2310_16829_amd as lma
+from oracle import physics as ph
+from oracle.lma import LMA, Lattice, phonon_average, recompute_sets
+from oracle.multislice import Setup, plain_image
+from synth import WORKLOADS, potential_slices
+from synth.specimen import edit_column, potential_from_atoms
+from tests._cases import det_rad, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+TOL32 = 1e-4
+TOL_BF16 = 1e-3
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def build(w, L=None, scan=None, R=None, f=1, offset=None, window=(0, 0, 0, 0), precision=0, batch=0, nx=None,
+          ny=None, lx=None, ly=None, detectors=None):
+    lam, sig = lma.electron_constants(w.kv)
+    nx, ny = nx or w.nx, ny or w.ny
+    lx, ly = lx or w.lx, ly or w.ly
+    opt = lma.optics(nx, ny, lx, ly, lam, sig, w.dz, w.bandlimit, w.alpha_mrad * 1e-3, w.defocus, w.cs)
+    scan = scan or w.scan
+    if R is None:
+        R = (nx // w.basis_px * f, ny // w.basis_px * f)
+    L = w.L if L is None else L
+    offset = offset or w.offset_frac
+    rings = detectors or det_rad(w)
+    lat = lma.lattice(scan[0], scan[1], R[0], R[1], f, offset, L, precision, window, batch)
+    plan = lma.Plan(opt, lat, lma.detectors(rings))
+    st = Setup(nx, ny, lx, ly, lam, sig, w.dz, w.bandlimit, w.alpha_mrad * 1e-3, w.defocus, w.cs, scan, rings)
+    ol = Lattice(st, R, f, offset, L)
+    return plan, st, ol
+
+
+def window_probes(plan):
+    a0, b0, ww, wh = plan.window
+    return [(a0 + a, b0 + b) for b in range(wh) for a in range(ww)]
+
+
+def crop(img, plan):
+    a0, b0, ww, wh = plan.window
+    return img[:, b0:b0 + wh, a0:a0 + ww]
+
+
+def per_det(gpu, ref):
+    return [rel_l2(gpu[r], ref[r]) for r in range(ref.shape[0])]
+
+
+RESOLVABLE = 1e-6   # ring intensity fraction above the FP32 noise floor
+
+
+def image_errors(gpu, ref, tol, wave_tol=TOL32):
+    """Checks an image against the oracle. Rings whose mean intensity is at least RESOLVABLE
+    of the (unit) incident intensity must agree to ``tol`` in relative L2. Every pixel of
+    every ring must satisfy the bound that the exit-wave tolerance e implies by
+    Cauchy-Schwarz: |dI| <= 2 e sqrt(I) + e^2 (incident intensity 1). Returns the per-ring
+    relative L2 errors."""
+    errs = per_det(gpu, ref)
+    for r in range(ref.shape[0]):
+        if np.mean(ref[r]) >= RESOLVABLE:
+            assert errs[r] < tol, f"ring {r}: relative L2 {errs[r]:.3e} >= {tol}"
+        bound = 2 * wave_tol * np.sqrt(np.abs(ref[r])) + wave_tol ** 2
+        assert np.all(np.abs(gpu[r] - ref[r]) <= bound), f"ring {r} outside the exit-wave bound"
+    return errs
+
+
+@pytest.fixture(scope="module")
+def tiny():
+    w = WORKLOADS["tiny"]
+    v = potential_slices(w, 0)
+    plan, st, ol = build(w)
+    say("tiny: oracle LMA (1024 translates)")
+    om = LMA(st, ol)
+    basis = om.propagate(v, [(t % ol.Rfx, t // ol.Rfx) for t in range(ol.n_translates)])
+    img_lma = om.image(v, basis=basis)
+    img_plain = plain_image(st, v)
+    return dict(w=w, v=v, plan=plan, st=st, ol=ol, om=om, basis=basis, img_lma=img_lma, img_plain=img_plain)
+
+
+def test_tiny_exit_waves(tiny):
+    say("tiny exit waves")
+    plan, ol = tiny["plan"], tiny["ol"]
+    plan.propagate(tiny["v"])
+    rows = plan.rows()
+    flat, _ = plan.detector_pixels()
+    got = plan.basis_rows(0, len(rows))
+    errs = []
+    for r, t in enumerate(rows):
+        ref = tiny["basis"][(t % ol.Rfx, t // ol.Rfx)].ravel()[flat]
+        errs.append(rel_l2(got[r], ref))
+    say("  max exit-wave rel L2", max(errs))
+    assert max(errs) < TOL32
+
+
+def test_tiny_lma_image(tiny):
+    say("tiny LMA image")
+    plan = tiny["plan"]
+    plan.propagate(tiny["v"])
+    img = plan.probe_image()
+    e = image_errors(img, tiny["img_lma"], TOL32)
+    say("  per-detector rel L2", e)
+
+
+def test_tiny_plain_image(tiny):
+    say("tiny plain image")
+    img = tiny["plan"].plain_image(tiny["v"])
+    e = image_errors(img, tiny["img_plain"], TOL32)
+    say("  per-detector rel L2", e)
+
+
+def test_tiny_split_bf16_image(tiny):
+    say("tiny split-bf16 LMA image")
+    plan, _, _ = build(tiny["w"], precision=lma.LMA_GEMM_SPLIT_BF16)
+    plan.propagate(tiny["v"])
+    e = image_errors(plan.probe_image(), tiny["img_lma"], TOL_BF16)
+    say("  per-detector rel L2", e)
+
+
+def test_lma_with_L1_on_probe_lattice_equals_plain(tiny):
+    # u = psi_0, I = P, f = 1, L = 1 (Sec. 4.2.3): both GPU paths give the plain image
+    say("L = 1 special case")
+    w = tiny["w"]
+    plan, _, _ = build(w, L=1, R=w.scan, offset=(0.0, 0.0))
+    plan.propagate(tiny["v"])
+    a = plan.probe_image()
+    b = plan.plain_image(tiny["v"])
+    assert max(per_det(a, b)) < 1e-6
+    image_errors(a, tiny["img_plain"], TOL32)
+
+
+def test_ragged_batch_and_wrapping_window(tiny):
+    say("ragged batch, window at the cell edge")
+    w = tiny["w"]
+    n_rows = build(w, window=(13, 14, 3, 2))[0].info().n_rows
+    batch = next(b for b in (7, 9, 11, 13) if n_rows % b)
+    plan, st, ol = build(w, window=(13, 14, 3, 2), batch=batch)
+    plan.propagate(tiny["v"])
+    img = plan.probe_image()
+    ref = crop(tiny["img_lma"], plan)
+    image_errors(img, ref, TOL32)
+    pimg = plan.plain_image(tiny["v"])
+    image_errors(pimg, crop(tiny["img_plain"], plan), TOL32)
+
+
+def test_case2_nonsquare_f2():
+    # nx != ny, lx != ly; I = P + p/2 with f = 2 makes P = 2 R_f: Case 2 with four sets
+    say("Case 2, non-square grid, f = 2")
+    w = WORKLOADS["tiny"]
+    nx, ny, lx, ly = 128, 64, 12.8, 7.2
+    scan = (16, 8)
+    rng = np.random.default_rng(5)
+    v = rng.uniform(0, 40, size=(4, ny, nx)).astype(np.float32)
+    plan, st, ol = build(w, nx=nx, ny=ny, lx=lx, ly=ly, scan=scan, R=scan, f=2, offset=(0.5, 0.5), L=20,
+                         window=(3, 2, 6, 5), batch=5)
+    assert (plan.info().ncls_x, plan.info().ncls_y) == (2, 2)
+    plan.propagate(v)
+    probes = window_probes(plan)
+    om = LMA(st, ol)
+    ref = crop(om.image(v, probes), plan)
+    image_errors(plan.probe_image(), ref, TOL32)
+    image_errors(plan.plain_image(v), crop(plain_image(st, v, probes), plan), TOL32)
+
+
+@pytest.mark.parametrize("n", [16, 32, 256])
+def test_small_and_mid_grids(n):
+    say(f"grid {n}^2")
+    w = WORKLOADS["tiny"]
+    l = n * 0.1
+    rng = np.random.default_rng(n)
+    v = rng.uniform(0, 40, size=(3, n, n)).astype(np.float32)
+    scan = (n // 8, n // 8)
+    plan, st, ol = build(w, nx=n, ny=n, lx=l, ly=l, scan=scan, R=(n // 4, n // 4), L=min(9, (n // 4) ** 2),
+                         window=(0, 0, min(4, n // 8), min(3, n // 8)))
+    plan.propagate(v)
+    probes = window_probes(plan)
+    ref = crop(LMA(st, ol).image(v, probes), plan)
+    image_errors(plan.probe_image(), ref, TOL32)
+    image_errors(plan.plain_image(v), crop(plain_image(st, v, probes), plan), TOL32)
+
+
+def test_largest_grid_2048():
+    say("grid 2048^2, 2 slices, 2 probes")
+    w = WORKLOADS["large"]
+    rng = np.random.default_rng(2048)
+    v = (rng.uniform(0, 30, size=(2, 2048, 2048))).astype(np.float32)
+    plan, st, ol = build(w, L=4, window=(5, 7, 2, 1), detectors=det_rad(w))
+    plan.propagate(v)
+    probes = window_probes(plan)
+    om = LMA(st, ol)
+    ref = crop(om.image(v, probes), plan)
+    image_errors(plan.probe_image(), ref, TOL32)
+    image_errors(plan.plain_image(v), crop(plain_image(st, v, probes), plan), TOL32)
+
+
+def test_device_pointers_and_phonon_accumulation():
+    import torch
+    say("device pointers, phonon accumulation")
+    w = WORKLOADS["tiny"]
+    vs = [potential_slices(w, c) for c in range(2)]
+    plan, st, ol = build(w, window=(2, 3, 5, 4))
+    probes = window_probes(plan)
+    out = torch.zeros(plan.image_shape(), dtype=torch.float64, device="cuda")
+    pout = torch.zeros_like(out)
+    for v in vs:
+        vt = torch.from_numpy(v).cuda()
+        plan.propagate(vt)
+        plan.probe_image(out, flags=lma.LMA_ACCUMULATE, weight=0.5)
+        plan.plain_image(vt, pout, flags=lma.LMA_ACCUMULATE, weight=0.5)
+    torch.cuda.synchronize()
+    om = LMA(st, ol)
+    ref = crop(phonon_average([om.image(v, probes) for v in vs]), plan)
+    pref = crop(phonon_average([plain_image(st, v, probes) for v in vs]), plan)
+    image_errors(out.cpu().numpy(), ref, TOL32)
+    image_errors(pout.cpu().numpy(), pref, TOL32)
+
+
+def test_probe_image_requires_a_basis():
+    w = WORKLOADS["tiny"]
+    plan, _, _ = build(w, window=(0, 0, 2, 2))
+    with pytest.raises(lma.LmaError) as e:
+        plan.probe_image()
+    assert e.value.status == lma._lib.LMA_ERR_STATE
+
+
+def test_local_recompute(tiny):
+    # Sec. 4.2.6: after an edit, re-propagate only the translates near it and re-form only the
+    # probes that use them. Parity: the oracle applying the same selection rule.
+    say("local recompute")
+    w = tiny["w"]
+    plan, st, ol = build(w)
+    v0 = tiny["v"]
+    pos, amps, bbox = edit_column(w, 0, (4.0, 8.0), seed=1)
+    v1 = potential_from_atoms(w, pos, amps)
+    assert np.any(v1 != v0)
+    om = tiny["om"]
+    allt = [(t % ol.Rfx, t // ol.Rfx) for t in range(ol.n_translates)]
+    b0 = tiny["basis"]
+    b1 = om.propagate(v1, allt)
+    full_ref = om.image(v1, basis=b1)
+    for rho in (2.05, 0.0):
+        plan.propagate(v0)
+        img = plan.probe_image()
+        nt, npr = plan.recompute_local(v1, bbox, rho, img)
+        R, Pp = recompute_sets(ol, bbox, rho)
+        say(f"  radius {rho} A: {nt} translates, {npr} probes redone (oracle {len(R)}, {len(Pp)})")
+        assert (nt, npr) == (len(R), len(Pp))
+        mixed = dict(b0)
+        for t in R:
+            mixed[t] = b1[t]
+        ref = om.image(v1, basis=mixed)
+        e = image_errors(img, ref, TOL32)
+        say("  vs oracle with the same selection, per-detector rel L2", e)
+        say("  approximation vs full recompute (oracle), per-detector rel L2", per_det(ref, full_ref))
+    assert (nt, npr) == (ol.n_translates, st.Px * st.Py)
+    image_errors(img, full_ref, TOL32)
+
+
+# ------------------------------------------------------------------------------------------
+# medium workload at full size, in the benchmark's launch configuration, on sampled outputs
+# ------------------------------------------------------------------------------------------
+def _oracle_exit(args):
+    w_name, t, spec_pos = args
+    w = WORKLOADS[w_name]
+    v = _oracle_exit.v
+    st = _oracle_exit.st
+    from oracle.lma import translate_wave
+    from oracle.multislice import multislice
+    u0 = translate_wave(st, st.spec0, spec_pos)
+    return t, np.fft.fft2(multislice(u0, v, st.sigma, st.prop))
+
+
+def _pool_init(w_name):
+    w = WORKLOADS[w_name]
+    _oracle_exit.v = potential_slices(w, 0)
+    lam, sig = ph.electron_wavelength(w.kv), ph.interaction_constant(w.kv)
+    _oracle_exit.st = Setup(w.nx, w.ny, w.lx, w.ly, lam, sig, w.dz, w.bandlimit, w.alpha_mrad * 1e-3, w.defocus,
+                            w.cs, w.scan, det_rad(w))
+
+
+@pytest.mark.slow
+def test_medium_full_size_sampled():
+    w = WORKLOADS["medium"]
+    say("medium: potential")
+    v = potential_slices(w, 0)
+    plan, st, ol = build(w)
+    say("medium: GPU propagate + images")
+    plan.propagate(v)
+    img = plan.probe_image()
+    pimg = plan.plain_image(v)
+    rows = plan.rows()
+    flat, _ = plan.detector_pixels()
+    # sampled outputs: two translates' exit waves, three plain pixels, one LMA pixel
+    probe = (37, 101)
+    nbr = ol.nearest(*probe)
+    sample_t = [int(rows[0]), int(rows[-1])]
+    jobs = {}
+    for ta, tb in nbr:
+        jobs[tb * ol.Rfx + ta] = ol.translate_position(ta, tb)
+    for t in sample_t:
+        jobs[t] = ol.translate_position(t % ol.Rfx, t // ol.Rfx)
+    n_workers = max(1, min(16, len(os.sched_getaffinity(0))))
+    say(f"medium: oracle for {len(jobs)} translates on {n_workers} processes")
+    with ProcessPoolExecutor(n_workers, initializer=_pool_init, initargs=("medium",)) as ex:
+        res = dict(ex.map(_oracle_exit, [("medium", t, (float(p[0]), float(p[1]))) for t, p in jobs.items()]))
+    row_of = {int(t): r for r, t in enumerate(rows)}
+    for t in sample_t:
+        got = plan.basis_rows(row_of[t], 1)[0]
+        e = rel_l2(got, res[t].ravel()[flat])
+        say(f"  exit wave of translate {t}: rel L2 {e:.2e}")
+        assert e < TOL32
+    # LMA pixel: combination with the oracle's own coefficients
+    om_alpha, _, _ = __import__("oracle.lma", fromlist=["least_squares"]).least_squares(st, ol, st.spec0, *probe)
+    spec = sum(a * res[tb * ol.Rfx + ta] for a, (ta, tb) in zip(om_alpha, nbr))
+    ref = ph.detector_values(spec, st.masks)
+    got = img[:, probe[1], probe[0]]
+    e = np.abs(got - ref) / np.abs(ref)
+    say("  LMA pixel per-detector rel err", e)
+    assert e.max() < TOL32
+    # plain pixels
+    probes = [(0, 0), (64, 17), (127, 127)]
+    pref = plain_image(st, v, probes)
+    for a, b in probes:
+        e = np.abs(pimg[:, b, a] - pref[:, b, a]) / np.abs(pref[:, b, a])
+        say(f"  plain pixel {(a, b)} rel err", e)
+        assert e.max() < TOL32

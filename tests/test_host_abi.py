@@ -1,0 +1,183 @@
+"""CPU tests of the C-ABI library: symbols, argument checks and the host planner (on host-only
+plans) against the FP64 oracle. No device work is requested here."""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2310_16829_amd as lma
+from paper_2310_16829_amd import _lib
+from oracle import physics as ph
+from oracle.lma import LMA, Lattice, translate_wave
+from oracle.multislice import Setup
+from synth import WORKLOADS
+from tests._cases import det_rad, oracle_lattice, oracle_setup, rel_l2
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _header_functions():
+    txt = open(os.path.join(ROOT, "include", "lma.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:lma_status|void|const char\*)\s+(lma_\w+)\s*\(", txt, flags=re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    names = _header_functions()
+    assert len(names) >= 18
+    lib = ctypes.CDLL(_lib.LIB_PATH)
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(_lib.SIGNATURES), "binding and header disagree"
+
+
+def test_product_does_not_import_the_oracle():
+    pkg = os.path.join(ROOT, "paper_2310_16829_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".cpp", ".hip", ".hpp", ".h")):
+                txt = open(os.path.join(dirpath, f)).read()
+                assert not re.search(r"^\s*(from|import)\s+oracle", txt, flags=re.M), f
+                assert "oracle/" not in txt, f
+
+
+def _plan_args(w, L=None, scan=None, R=None, f=1, offset=None, window=(0, 0, 0, 0), precision=0, nx=None, ny=None,
+               lx=None, ly=None, batch=0):
+    lam, sig = lma.electron_constants(w.kv)
+    opt = lma.optics(nx or w.nx, ny or w.ny, lx or w.lx, ly or w.ly, lam, sig, w.dz, w.bandlimit,
+                     w.alpha_mrad * 1e-3, w.defocus, w.cs)
+    scan = scan or w.scan
+    if R is None:
+        R = ((nx or w.nx) // w.basis_px * f, (ny or w.ny) // w.basis_px * f)
+    lat = lma.lattice(scan[0], scan[1], R[0], R[1], f, offset or w.offset_frac, w.L if L is None else L, precision,
+                      window, batch)
+    det = lma.detectors(det_rad(w))
+    return opt, lat, det
+
+
+def test_electron_constants_match_oracle():
+    for kv in (80.0, 200.0, 300.0):
+        lam, sig = lma.electron_constants(kv)
+        assert abs(lam - ph.electron_wavelength(kv)) < 1e-15
+        assert abs(sig - ph.interaction_constant(kv)) < 1e-15
+    with pytest.raises(lma.LmaError):
+        lma.electron_constants(-1.0)
+
+
+@pytest.mark.parametrize("case", ["tiny", "case2", "nonsquare", "f2_paper_style"])
+def test_host_plan_matches_oracle(case):
+    w = WORKLOADS["tiny"]
+    kw = {}
+    okw = {}
+    if case == "case2":          # P = 2 R_f: four coefficient sets
+        kw = dict(scan=(16, 16), R=(8, 8), L=16)
+    elif case == "nonsquare":    # nx != ny, lx != ly, Case 1 with c = 2 along x and 1 along y
+        kw = dict(nx=128, ny=64, lx=12.8, ly=7.2, scan=(16, 16), R=(32, 16), L=24)
+    elif case == "f2_paper_style":  # I = P + p/2, f = 2 (Sec. 4.2.3)
+        kw = dict(scan=(32, 32), R=(32, 32), f=2, L=25, offset=(0.5, 0.5))
+    opt, lat, det = _plan_args(w, **kw)
+    plan = lma.Plan(opt, lat, det, flags=lma.LMA_HOST_ONLY)
+    info = plan.info()
+    st = Setup(opt.nx, opt.ny, opt.lx, opt.ly, opt.wavelength, opt.sigma, opt.dz, opt.bandlimit, opt.alpha_max,
+               opt.defocus, opt.cs, (lat.px, lat.py), det_rad(w))
+    ol = Lattice(st, (lat.rx, lat.ry), lat.f, (lat.offset_x, lat.offset_y), lat.L)
+    assert (info.ncls_x, info.ncls_y) == (ol.ncls_x, ol.ncls_y)
+    assert info.n_translates == ol.n_translates
+    # probe spectrum
+    assert np.abs(plan.probe_spectrum() - st.spec0).max() < 1e-12
+    # detector pixels and ring masks: bit-exact
+    flat, mask = plan.detector_pixels()
+    om = np.zeros(opt.nx * opt.ny, np.uint32)
+    for r, m in enumerate(st.masks):
+        om |= m.ravel().astype(np.uint32) << np.uint32(r)
+    assert np.array_equal(np.sort(flat), np.nonzero(om)[0])
+    assert np.array_equal(om[flat], mask)
+    # translate positions
+    pos = plan.translates()
+    for t in (0, 1, ol.Rfx, ol.n_translates - 1):
+        ta, tb = t % ol.Rfx, t // ol.Rfx
+        ex = ol.translate_position(ta, tb)
+        assert abs(pos[t, 0] - float(ex[0])) < 1e-12 and abs(pos[t, 1] - float(ex[1])) < 1e-12
+    # neighbour lists (ordered, exact) and approximants of every coefficient set
+    tr, al = plan.coefficients()
+    lm = LMA(st, ol)
+    for sy in range(ol.ncls_y):
+        for sx in range(ol.ncls_x):
+            s = sy * ol.ncls_x + sx
+            want = [tb * ol.Rfx + ta for ta, tb in ol.nearest(sx, sy)]
+            assert list(tr[s]) == want
+            appr = sum(a * translate_wave(st, st.spec0, ol.translate_position(t % ol.Rfx, t // ol.Rfx))
+                       for a, t in zip(al[s], tr[s]))
+            assert rel_l2(appr, lm.approximant(sx, sy)) < 1e-8
+    assert info.max_residual == pytest.approx(max(lm.residual.values()), rel=1e-6)
+
+
+def test_window_rows_are_the_union_of_neighbour_sets():
+    w = WORKLOADS["tiny"]
+    opt, lat, det = _plan_args(w, window=(3, 14, 4, 2), L=16)
+    plan = lma.Plan(opt, lat, det, flags=lma.LMA_HOST_ONLY)
+    st = oracle_setup(w)
+    ol = oracle_lattice(w, st, L=16)
+    need = set()
+    for b in range(14, 16):
+        for a in range(3, 7):
+            need.update(tb * ol.Rfx + ta for ta, tb in ol.nearest(a, b))
+    assert sorted(need) == list(plan.rows())
+    assert plan.image_shape() == (4, 2, 4)
+
+
+@pytest.mark.parametrize("bad", [
+    dict(nx=96), dict(nx=4096), dict(scan=(12, 16)), dict(L=0), dict(L=5000), dict(offset=(0.3, 0.5)),
+    dict(window=(10, 0, 8, 4)), dict(f=3, R=(32, 32)), dict(batch=-1),
+])
+def test_invalid_arguments_are_rejected(bad):
+    w = WORKLOADS["tiny"]
+    kw = dict(bad)
+    nx = kw.pop("nx", None)
+    batch = kw.pop("batch", 0)
+    opt, lat, det = _plan_args(w, nx=nx, batch=max(batch, 0), **kw)
+    if batch < 0:
+        lat.batch = batch
+    with pytest.raises(lma.LmaError) as e:
+        lma.Plan(opt, lat, det, flags=lma.LMA_HOST_ONLY)
+    assert e.value.status in (_lib.LMA_ERR_ARG, _lib.LMA_ERR_UNSUPPORTED)
+
+
+def test_invalid_detectors_and_optics_are_rejected():
+    w = WORKLOADS["tiny"]
+    opt, lat, det = _plan_args(w)
+    for rings in ([(0.02, 0.01)], [], [(0, 0.1)] * 9, [(-0.01, 0.02)]):
+        with pytest.raises(lma.LmaError):
+            lma.Plan(opt, lat, lma.detectors(rings), flags=lma.LMA_HOST_ONLY)
+    for field, val in (("wavelength", 0.0), ("dz", -2.0), ("bandlimit", 1.5), ("alpha_max", 0.0), ("lx", float("nan"))):
+        o2 = lma.optics(opt.nx, opt.ny, opt.lx, opt.ly, opt.wavelength, opt.sigma, opt.dz, opt.bandlimit,
+                        opt.alpha_max)
+        setattr(o2, field, val)
+        with pytest.raises(lma.LmaError):
+            lma.Plan(o2, lat, det, flags=lma.LMA_HOST_ONLY)
+
+
+def test_host_only_plan_refuses_device_work():
+    w = WORKLOADS["tiny"]
+    opt, lat, det = _plan_args(w)
+    plan = lma.Plan(opt, lat, det, flags=lma.LMA_HOST_ONLY)
+    v = np.zeros((2, w.ny, w.nx), np.float32)
+    for call in (lambda: plan.propagate(v), lambda: plan.probe_image(), lambda: plan.plain_image(v),
+                 lambda: plan.basis_rows(0, 1)):
+        with pytest.raises(lma.LmaError) as e:
+            call()
+        assert e.value.status == _lib.LMA_ERR_STATE
+
+
+def test_footprint_grows_with_slices_and_basis():
+    w = WORKLOADS["medium"]
+    opt, lat, det = _plan_args(w)
+    b1 = lma.footprint(opt, lat, det, 1)
+    b100 = lma.footprint(opt, lat, det, 100)
+    assert b100 > b1 > 16384 * 90081 * 8          # the resident basis alone is ~11.8 GB
+    with pytest.raises(lma.LmaError):
+        lma.footprint(opt, lat, det, 0)
