@@ -6,6 +6,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -50,10 +51,10 @@ struct lma_plan {
   int64_t dev_bytes = 0;
   std::vector<void*> allocs;
 
-  // tables
-  float2 *d_spec = nullptr, *d_prop = nullptr, *d_twx = nullptr, *d_twy = nullptr;
-  int32_t* d_comp_map = nullptr;
-  uint32_t* d_detmask = nullptr;
+  // tables (those read by column passes transposed, [kx][ky])
+  float2 *d_specT = nullptr, *d_propT = nullptr, *d_twx = nullptr, *d_twy = nullptr;
+  int32_t* d_compT = nullptr;
+  uint32_t* d_maskT = nullptr;
   int32_t *d_row_of = nullptr, *d_set_dx = nullptr, *d_set_dy = nullptr;
   int32_t *d_chunk_start = nullptr, *d_chunk_len = nullptr;
   uint32_t* d_chunk_mask = nullptr;
@@ -65,6 +66,7 @@ struct lma_plan {
   // work
   void* d_basis = nullptr;           // [n_rows][D] x 8 bytes
   float2* d_work = nullptr;          // [B][ny][nx]
+  float2* d_workT = nullptr;         // [B][nx][ny]
   float2* d_trans = nullptr;         // [cap][ny][nx]
   int trans_cap = 0;
   float* d_pot = nullptr;            // staging for host potentials
@@ -128,12 +130,12 @@ lma::dev::Tables tables(const lma_plan* p) {
   t.ny = p->h.op.ny;
   t.Qx = p->h.Qx;
   t.Qy = p->h.Qy;
-  t.spec_init = p->d_spec;
-  t.prop = p->d_prop;
+  t.specT = p->d_specT;
+  t.propT = p->d_propT;
   t.twx = p->d_twx;
   t.twy = p->d_twy;
-  t.comp_map = p->d_comp_map;
-  t.detmask = p->d_detmask;
+  t.compT = p->d_compT;
+  t.maskT = p->d_maskT;
   return t;
 }
 
@@ -249,13 +251,13 @@ lma_status run_waves(lma_plan* p, const int64_t* d_u, const int32_t* d_row, cons
     const int nb = std::min(p->B, n - first);
     LAUNCH(p, "init", lma::dev::init_waves(T, p->d_work, d_u + 2 * (int64_t)first, nb, p->stream));
     for (int j = 0; j < nslices; ++j) {
-      LAUNCH(p, "row_pass", lma::dev::row_pass(T, p->d_work, p->d_trans + (size_t)j * XY, nb, p->stream));
+      LAUNCH(p, "row_pass", lma::dev::row_pass(T, p->d_work, p->d_workT, p->d_trans + (size_t)j * XY, nb, p->stream));
       if (j + 1 < nslices) {
-        LAUNCH(p, "col_pass", lma::dev::col_pass(T, p->d_work, nb, p->stream));
+        LAUNCH(p, "col_pass", lma::dev::col_pass(T, p->d_workT, p->d_work, nb, p->stream));
       } else if (d_row) {
-        LAUNCH(p, "col_gather", lma::dev::col_gather(T, p->d_work, nb, p->d_basis, p->h.D(), d_row + first, split, p->stream));
+        LAUNCH(p, "col_gather", lma::dev::col_gather(T, p->d_workT, nb, p->d_basis, p->h.D(), d_row + first, split, p->stream));
       } else {
-        LAUNCH(p, "col_reduce", lma::dev::col_reduce(T, p->d_work, nb, d_out + first, p->d_img, p->h.ndet,
+        LAUNCH(p, "col_reduce", lma::dev::col_reduce(T, p->d_workT, nb, d_out + first, p->d_img, p->h.ndet,
                                                      p->h.n_probes(), (double)XY, p->stream));
       }
     }
@@ -335,7 +337,7 @@ int64_t footprint_of(const HostPlan& h, int B, int nslices, bool with_basis) {
   b += (int64_t)h.chunk_start.size() * 12;
   b += (int64_t)h.rows.size() * 20 + h.n_probes() * 20;
   b += (int64_t)h.ndet * h.n_probes() * 8;            // image
-  b += (int64_t)B * XY * 8;                           // wave batch
+  b += (int64_t)B * XY * 8 * 2;                       // wave batch, two layouts
   b += (int64_t)nslices * XY * (8 + 4);               // transmission tables and potential staging
   if (with_basis) b += (int64_t)h.rows.size() * h.D() * 8;
   return b;
@@ -430,20 +432,33 @@ lma_status lma_build_basis(const lma_optics* optics, const lma_lattice* lattice,
         }
       }
     }
-    // tables
+    // tables; those read by column passes are transposed to [kx][ky]
+    const int nx = h.op.nx, ny = h.op.ny;
     std::vector<float2> v((size_t)XY);
-    auto to_f2 = [&](const std::vector<cd>& src, double scale) {
-      for (int64_t i = 0; i < XY; ++i) v[i] = make_float2((float)(src[i].real() * scale), (float)(src[i].imag() * scale));
+    auto to_f2T = [&](const std::vector<cd>& src, double scale) {
+      for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x) {
+          const cd& z = src[(size_t)y * nx + x];
+          v[(size_t)x * ny + y] = make_float2((float)(z.real() * scale), (float)(z.imag() * scale));
+        }
     };
-    to_f2(h.spec, 1.0 / (double)XY);
-    if ((s = upload(p, &p->d_spec, v.data(), v.size())) != LMA_OK) { release(p); return s; }
-    to_f2(h.prop, 1.0);
-    if ((s = upload(p, &p->d_prop, v.data(), v.size())) != LMA_OK) { release(p); return s; }
-    auto twx = twiddles(h.op.nx), twy = twiddles(h.op.ny);
+    to_f2T(h.spec, 1.0 / (double)XY);
+    if ((s = upload(p, &p->d_specT, v.data(), v.size())) != LMA_OK) { release(p); return s; }
+    to_f2T(h.prop, 1.0);
+    if ((s = upload(p, &p->d_propT, v.data(), v.size())) != LMA_OK) { release(p); return s; }
+    auto twx = twiddles(nx), twy = twiddles(ny);
     if ((s = upload(p, &p->d_twx, twx.data(), twx.size())) != LMA_OK) { release(p); return s; }
     if ((s = upload(p, &p->d_twy, twy.data(), twy.size())) != LMA_OK) { release(p); return s; }
-    if ((s = upload(p, &p->d_comp_map, h.comp_map.data(), h.comp_map.size())) != LMA_OK) { release(p); return s; }
-    if ((s = upload(p, &p->d_detmask, h.detmask.data(), h.detmask.size())) != LMA_OK) { release(p); return s; }
+    std::vector<int32_t> compT((size_t)XY);
+    std::vector<uint32_t> maskT((size_t)XY);
+    for (int y = 0; y < ny; ++y)
+      for (int x = 0; x < nx; ++x) {
+        compT[(size_t)x * ny + y] = h.comp_map[(size_t)y * nx + x];
+        maskT[(size_t)x * ny + y] = h.detmask[(size_t)y * nx + x];
+      }
+    if ((s = upload(p, &p->d_compT, compT.data(), compT.size())) != LMA_OK) { release(p); return s; }
+    if ((s = upload(p, &p->d_maskT, maskT.data(), maskT.size())) != LMA_OK) { release(p); return s; }
+    if (const char* e = std::getenv("LMA_PASS_WAVES")) lma::dev::set_pass_waves(std::atoi(e));
     if ((s = upload(p, &p->d_row_of, h.row_of.data(), h.row_of.size())) != LMA_OK) { release(p); return s; }
     if ((s = upload(p, &p->d_set_dx, h.set_dx.data(), h.set_dx.size())) != LMA_OK) { release(p); return s; }
     if ((s = upload(p, &p->d_set_dy, h.set_dy.data(), h.set_dy.size())) != LMA_OK) { release(p); return s; }
@@ -478,6 +493,7 @@ lma_status lma_build_basis(const lma_optics* optics, const lma_lattice* lattice,
     // buffers
     if ((s = dalloc(p, (void**)&p->d_img, (size_t)h.ndet * h.n_probes() * sizeof(double))) != LMA_OK) { release(p); return s; }
     if ((s = dalloc(p, (void**)&p->d_work, (size_t)p->B * XY * sizeof(float2))) != LMA_OK) { release(p); return s; }
+    if ((s = dalloc(p, (void**)&p->d_workT, (size_t)p->B * XY * sizeof(float2))) != LMA_OK) { release(p); return s; }
     if ((s = dalloc(p, &p->d_basis, (size_t)h.rows.size() * h.D() * 8)) != LMA_OK) { release(p); return s; }
     *out = p;
     return LMA_OK;

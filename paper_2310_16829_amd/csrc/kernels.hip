@@ -91,30 +91,70 @@ __host__ __device__ constexpr int fft_span(int n, int s) {  // product of the ra
   return p;
 }
 
-// LDS exchange layouts. Row transforms: one padded row per transform. Column transforms:
-// [position][column] so that a wavefront touches consecutive columns.
+// ------------------------------------------------------------------------------------------
+// twiddles held in registers: for every stage after the first, the r-1 factors of each of
+// the thread's 8/r butterflies
+// ------------------------------------------------------------------------------------------
+__host__ __device__ constexpr int tw_off(int n, int s) {
+  int o = 0;
+  for (int i = 1; i < s; ++i) o += 8 - 8 / fft_radix(n, i);
+  return o;
+}
+__host__ __device__ constexpr int tw_count(int n) { return tw_off(n, fft_nstages(n)) > 0 ? tw_off(n, fft_nstages(n)) : 1; }
+
+template <int N, int S>
+__device__ __forceinline__ void tw_load_stage(float2* w, const float2* __restrict__ tab, int j) {
+  constexpr int r = fft_radix(N, S), Ns = fft_span(N, S), Q = 8 / r, T = N / 8;
+  constexpr int off = tw_off(N, S);
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int k = (j + T * q) & (Ns - 1);
+#pragma unroll
+    for (int m = 1; m < r; ++m) w[off + q * (r - 1) + (m - 1)] = tab[m * k * (N / (Ns * r))];
+  }
+}
+
 template <int N>
-struct RowLds {
-  float2* base;  // this transform's row
-  __device__ __forceinline__ int idx(int p) const { return p + (p >> 3); }
-  __device__ __forceinline__ void put(int p, float2 v) const { base[idx(p)] = v; }
-  __device__ __forceinline__ float2 get(int p) const { return base[idx(p)]; }
-  static constexpr int kSize = N + N / 8;
-};
-template <int C>
-struct ColLds {
-  float2* base;  // base + column
-  __device__ __forceinline__ void put(int p, float2 v) const { base[p * C] = v; }
-  __device__ __forceinline__ float2 get(int p) const { return base[p * C]; }
+__device__ __forceinline__ void tw_load(float2* w, const float2* __restrict__ tab, int j) {
+  constexpr int ns = fft_nstages(N);
+  if constexpr (ns > 1) tw_load_stage<N, 1>(w, tab, j);
+  if constexpr (ns > 2) tw_load_stage<N, (ns > 2 ? 2 : 1)>(w, tab, j);
+  if constexpr (ns > 3) tw_load_stage<N, (ns > 3 ? 3 : 1)>(w, tab, j);
+}
+
+// One transform's exchange slot inside the pass tile: position p lives at p + p/2^PAD (one
+// pad element every 2^PAD keeps the stride-8 Stockham writes on distinct banks of the
+// 64 x 4-byte LDS).
+#ifndef LMA_SLOT_PAD
+#define LMA_SLOT_PAD 3
+#endif
+#ifndef LMA_TILE_EXTRA
+#define LMA_TILE_EXTRA 3
+#endif
+__host__ __device__ constexpr int slot_pos(int p) { return p + (p >> LMA_SLOT_PAD); }
+struct Slot {
+  float2* base;
+  __device__ __forceinline__ void put(int p, float2 v) const { base[slot_pos(p)] = v; }
+  __device__ __forceinline__ float2 get(int p) const { return base[slot_pos(p)]; }
 };
 
-template <int N, int DIR, int S, class Lds>
-__device__ __forceinline__ void fft_stage(float2 (&v)[8], int j, const float2* __restrict__ tw, const Lds& lds) {
+// Exchange ordering: a transform held by one wavefront only needs the compiler to keep its
+// LDS writes before its reads (a wavefront's LDS operations execute in order); a transform
+// spread over several wavefronts needs the workgroup barrier.
+template <bool WAVE_LOCAL>
+__device__ __forceinline__ void exchange_sync() {
+  if constexpr (WAVE_LOCAL) __builtin_amdgcn_wave_barrier();
+  else __syncthreads();
+}
+
+template <int N, int DIR, int S, bool WL>
+__device__ __forceinline__ void fft_stage(float2 (&v)[8], int j, const float2* w, const Slot& slot) {
   constexpr int r = fft_radix(N, S);
   constexpr int Ns = fft_span(N, S);
   constexpr int Q = 8 / r;
   constexpr int T = N / 8;
   constexpr bool last = (S == fft_nstages(N) - 1);
+  constexpr int off = tw_off(N, S);
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
     float2 a[r];
@@ -124,7 +164,7 @@ __device__ __forceinline__ void fft_stage(float2 (&v)[8], int j, const float2* _
     const int k = b & (Ns - 1);
     if constexpr (Ns > 1) {
 #pragma unroll
-      for (int m = 1; m < r; ++m) a[m] = cmul(a[m], conj_if_inv<DIR>(tw[m * k * (N / (Ns * r))]));
+      for (int m = 1; m < r; ++m) a[m] = cmul(a[m], conj_if_inv<DIR>(w[off + q * (r - 1) + (m - 1)]));
     }
     dft_r<r, DIR>(a);
     if constexpr (last) {
@@ -133,26 +173,26 @@ __device__ __forceinline__ void fft_stage(float2 (&v)[8], int j, const float2* _
     } else {
       const int base = (b / Ns) * Ns * r + k;
 #pragma unroll
-      for (int m = 0; m < r; ++m) lds.put(base + m * Ns, a[m]);
+      for (int m = 0; m < r; ++m) slot.put(base + m * Ns, a[m]);
     }
   }
   if constexpr (!last) {
-    __syncthreads();
+    exchange_sync<WL>();
 #pragma unroll
-    for (int m = 0; m < 8; ++m) v[m] = lds.get(j + T * m);
-    __syncthreads();
+    for (int m = 0; m < 8; ++m) v[m] = slot.get(j + T * m);
+    exchange_sync<WL>();
   }
 }
 
 // N-point transform of the 8 values held by thread j (of N/8); input and output at
 // positions j + (N/8) m, natural order.
-template <int N, int DIR, class Lds>
-__device__ __forceinline__ void fft(float2 (&v)[8], int j, const float2* __restrict__ tw, const Lds& lds) {
+template <int N, int DIR, bool WL>
+__device__ __forceinline__ void fft(float2 (&v)[8], int j, const float2* w, const Slot& slot) {
   constexpr int ns = fft_nstages(N);
-  fft_stage<N, DIR, 0>(v, j, tw, lds);
-  if constexpr (ns > 1) fft_stage<N, DIR, (ns > 1 ? 1 : 0)>(v, j, tw, lds);
-  if constexpr (ns > 2) fft_stage<N, DIR, (ns > 2 ? 2 : 0)>(v, j, tw, lds);
-  if constexpr (ns > 3) fft_stage<N, DIR, (ns > 3 ? 3 : 0)>(v, j, tw, lds);
+  fft_stage<N, DIR, 0, WL>(v, j, w, slot);
+  if constexpr (ns > 1) fft_stage<N, DIR, (ns > 1 ? 1 : 0), WL>(v, j, w, slot);
+  if constexpr (ns > 2) fft_stage<N, DIR, (ns > 2 ? 2 : 0), WL>(v, j, w, slot);
+  if constexpr (ns > 3) fft_stage<N, DIR, (ns > 3 ? 3 : 0), WL>(v, j, w, slot);
 }
 
 // Blocks are dispatched round-robin over the 8 XCDs; give each XCD a contiguous range of
@@ -176,69 +216,48 @@ __global__ void k_transmission(const float* __restrict__ v, float2* __restrict__
 }
 
 // ------------------------------------------------------------------------------------------
-// row pass
+// slice pass
+//
+// Reads rows of length N from in[B][rows][N] (contiguous), transforms them, and stores the
+// result transposed, out[B][N][rows], through an LDS tile of ROWS rows so that every store
+// writes ROWS consecutive values. The row pass (rows = y, N = nx) takes the mixed domain
+// [y][kx] to [kx][y]; the column pass (rows = kx, N = ny) takes [kx][y] back to [y][kx].
+// Tables used by column passes are stored transposed, [kx][ky].
 // ------------------------------------------------------------------------------------------
-template <int NX>
-struct RowCfg {
-  static constexpr int T = NX / 8;
-  static constexpr int Rmax = (256 / T) > 0 ? 256 / T : 1;
+enum { PASS_ROW = 0, PASS_COL = 1, PASS_INIT = 2, PASS_GATHER = 3, PASS_REDUCE = 4 };
+
+template <int N>
+struct PassCfg {
+  static constexpr int T = N / 8;                                   // threads per transform
+  static constexpr bool WL = T <= 64;                               // transform inside one wavefront
+  static constexpr int S = WL ? ((64 / T) < 16 ? 64 / T : 16) : 1;  // transforms per wavefront
+  static constexpr int WPT = WL ? 1 : T / 64;                       // wavefronts per transform
+  static constexpr int ROWS = N <= 512 ? 16 : (N == 1024 ? 8 : 4);  // tile rows
+  // tile row stride: a padded slot plus LMA_TILE_EXTRA, chosen so that the 16 rows read at one
+  // column by the transposed store fall on distinct banks
+  static constexpr int RS = slot_pos(N - 1) + 1 + LMA_TILE_EXTRA;
+  static constexpr int NTW = tw_count(N);
 };
 
-template <int NX, int R>
-__global__ __launch_bounds__(R * (NX / 8)) void k_row_pass(float2* __restrict__ work, const float2* __restrict__ trans,
-                                                          const float2* __restrict__ tw, int ny) {
-  constexpr int T = NX / 8;
-  __shared__ float2 sm[R * RowLds<NX>::kSize];
-  const int blk = xcd_remap(blockIdx.x, gridDim.x);
-  const int r = threadIdx.x / T, j = threadIdx.x % T;
-  // logical block = (row group, wave) with the wave fastest: an XCD owns a range of y
-  const int B = gridDim.x / (ny / R);
-  const int yg = blk / B, w = blk % B;
-  const int y = yg * R + r;
-  float2* row = work + ((size_t)w * ny + y) * NX;
-  const float2* trow = trans + (size_t)y * NX;
-  RowLds<NX> lds{sm + r * RowLds<NX>::kSize};
-  float2 v[8];
-#pragma unroll
-  for (int m = 0; m < 8; ++m) v[m] = row[j + T * m];
-  fft<NX, +1>(v, j, tw, lds);
-#pragma unroll
-  for (int m = 0; m < 8; ++m) v[m] = cmul(v[m], trow[j + T * m]);
-  fft<NX, -1>(v, j, tw, lds);
-#pragma unroll
-  for (int m = 0; m < 8; ++m) row[j + T * m] = v[m];
-}
-
-// ------------------------------------------------------------------------------------------
-// column passes
-// ------------------------------------------------------------------------------------------
-enum { COL_INIT = 0, COL_MID = 1, COL_GATHER = 2, COL_REDUCE = 3 };
-
-template <int NY>
-struct ColCfg {
-  static constexpr int C = NY <= 512 ? 16 : (NY == 1024 ? 8 : 4);
-  static constexpr int T = NY / 8;
-  static constexpr int kThreads = C * T;
-};
-
-struct ColArgs {
-  float2* work;
-  const float2* spec;      // INIT
-  const float2* prop;      // MID / GATHER / REDUCE
-  const float2* tw;
-  const int64_t* wave_u;   // INIT: [B][2] lattice units
+struct PassArgs {
+  const float2* in;
+  float2* out;
+  int rows;                  // rows per batch entry
+  const float2* table;       // ROW: t_j [rows][N]; COL/GATHER/REDUCE: P^T [rows][N]; INIT: spectrum^T
+  const float2* tw;          // twiddles exp(-2 pi i t / N), t < N
+  const int64_t* wave_u;     // INIT: [B][2] lattice units of each wave's position
   int64_t Qx, Qy;
-  void* basis;             // GATHER
+  int nrow_freq;             // INIT: number of rows (kx) for the frequency index; N is ky
+  void* basis;               // GATHER
   int D;
-  const int32_t* comp_map;
-  const int32_t* wave_row; // GATHER: basis row per wave; REDUCE: image index per wave
+  const int32_t* comp;       // GATHER: detector pixel index [rows][N] or -1
+  const int32_t* wave_row;   // GATHER: basis row per wave; REDUCE: image index per wave
   int split_bf16;
-  const uint32_t* detmask; // REDUCE
+  const uint32_t* mask;      // REDUCE: ring bits [rows][N]
   double* img;
   int ndet;
   int64_t img_stride;
   double scale;
-  int nx, ny;
 };
 
 __device__ __forceinline__ void split_bf16(float x, __hip_bfloat16& hi, __hip_bfloat16& lo) {
@@ -246,97 +265,154 @@ __device__ __forceinline__ void split_bf16(float x, __hip_bfloat16& hi, __hip_bf
   lo = __float2bfloat16(x - __bfloat162float(hi));
 }
 
-template <int NY, int MODE>
-__global__ __launch_bounds__(ColCfg<NY>::kThreads) void k_col_pass(ColArgs a) {
-  constexpr int C = ColCfg<NY>::C;
-  constexpr int T = ColCfg<NY>::T;
-  __shared__ float2 sm[NY * C];
-  const int nx = a.nx;
-  const int tiles = nx / C;
+template <int N, int WAVES, int MODE>
+__global__ __launch_bounds__(WAVES * 64) void k_pass(PassArgs a) {
+  using C = PassCfg<N>;
+  constexpr int T = C::T, S = C::S, ROWS = C::ROWS, RS = C::RS;
+  constexpr int TPB = WAVES * S / C::WPT;                  // transforms in flight per block
+  static_assert(TPB >= 1 && ROWS % TPB == 0, "tile rows must split evenly over the block");
+  constexpr int RPW = ROWS / TPB;                          // rounds per block
+  __shared__ float2 tile[(ROWS + 1) * RS];                 // last row: scratch of idle lanes
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int sub = C::WL ? lane / T : 0;                    // transform within the wavefront
+  const int j = C::WL ? lane % T : tid % T;                // thread within the transform
+  const int tslot = C::WL ? (tid >> 6) * S + sub : tid / T;  // transform slot within the block
+  const bool active = !C::WL || sub < S;
+  const int groups = a.rows / ROWS;
   const int blk = xcd_remap(blockIdx.x, gridDim.x);
-  const int B = gridDim.x / tiles;
-  const int tile = blk / B, w = blk % B;   // an XCD owns a range of columns
-  const int c = threadIdx.x % C, j = threadIdx.x / C;
-  const int col = tile * C + c;
-  ColLds<C> lds{sm + c};
-  float2* base = a.work + (size_t)w * NY * nx + col;
-  float2 v[8];
-  if constexpr (MODE == COL_INIT) {
-    // u(. - pos_w): spectrum times exp(-2 pi i (mx ux / Qx + my uy / Qy)), exact in units
-    const int mx = freq_index(col, nx);
-    const int64_t ux = a.wave_u[2 * w], uy = a.wave_u[2 * w + 1];
-    const int64_t ax = (((int64_t)mx * ux) % a.Qx + a.Qx) % a.Qx;
+  const int B = gridDim.x / groups;
+  const int grp = blk / B, w = blk % B;                    // an XCD owns a range of rows
+  const int row0 = grp * ROWS;
+
+  float2 tw[C::NTW];
+  tw_load<N>(tw, a.tw, j);
+
+  [[maybe_unused]] double acc[8];
+  if constexpr (MODE == PASS_REDUCE) {
 #pragma unroll
-    for (int m = 0; m < 8; ++m) {
-      const int ky = j + T * m;
-      const int my = freq_index(ky, NY);
-      const int64_t ay = (((int64_t)my * uy) % a.Qy + a.Qy) % a.Qy;
-      double turns = (double)ax / (double)a.Qx + (double)ay / (double)a.Qy;
-      double s, cc;
-      sincospi(-2.0 * turns, &s, &cc);
-      v[m] = cmul(a.spec[(size_t)ky * nx + col], make_float2((float)cc, (float)s));
-    }
-    fft<NY, +1>(v, j, a.tw, lds);
+    for (int r = 0; r < 8; ++r) acc[r] = 0.0;
+  }
+
+  // rows are prefetched one round ahead so that their loads overlap the current transforms
+  [[maybe_unused]] float2 nxt[8];
+  if constexpr (MODE != PASS_INIT) {
+    const float2* src = a.in + ((size_t)w * a.rows + row0 + (active ? tslot : 0)) * N;
 #pragma unroll
-    for (int m = 0; m < 8; ++m) base[(size_t)(j + T * m) * nx] = v[m];
-    return;
-  } else {
-#pragma unroll
-    for (int m = 0; m < 8; ++m) v[m] = base[(size_t)(j + T * m) * nx];
-    fft<NY, -1>(v, j, a.tw, lds);
-#pragma unroll
-    for (int m = 0; m < 8; ++m) v[m] = cmul(v[m], a.prop[(size_t)(j + T * m) * nx + col]);
-    if constexpr (MODE == COL_MID) {
-      fft<NY, +1>(v, j, a.tw, lds);
-#pragma unroll
-      for (int m = 0; m < 8; ++m) base[(size_t)(j + T * m) * nx] = v[m];
-    } else if constexpr (MODE == COL_GATHER) {
-      const int64_t row = a.wave_row[w];
+    for (int m = 0; m < 8; ++m) nxt[m] = src[j + T * m];
+  }
+
+#pragma unroll 1
+  for (int rr = 0; rr < RPW; ++rr) {
+    const int r = rr * TPB + (active ? tslot : 0);         // tile row
+    const int row = row0 + r;
+    const Slot slot{tile + (active ? r : ROWS) * RS};
+    float2 v[8];
+    if constexpr (MODE == PASS_INIT) {
+      // u(. - pos_w): spectrum times exp(-2 pi i (mx ux / Qx + my uy / Qy)), reduced exactly in
+      // lattice units, phase in FP64; rows are kx, positions ky
+      const int mx = freq_index(row, a.nrow_freq);
+      const int64_t ux = a.wave_u[2 * w], uy = a.wave_u[2 * w + 1];
+      const int64_t ax = (((int64_t)mx * ux) % a.Qx + a.Qx) % a.Qx;
+      const float2* src = a.table + (size_t)row * N;
 #pragma unroll
       for (int m = 0; m < 8; ++m) {
-        const int d = a.comp_map[(size_t)(j + T * m) * nx + col];
-        if (d >= 0) {
-          if (a.split_bf16) {
-            __hip_bfloat16 q[4];
-            split_bf16(v[m].x, q[0], q[1]);
-            split_bf16(v[m].y, q[2], q[3]);
-            reinterpret_cast<uint2*>(a.basis)[row * a.D + d] = *reinterpret_cast<uint2*>(q);
-          } else {
-            reinterpret_cast<float2*>(a.basis)[row * a.D + d] = v[m];
+        const int ky = j + T * m;
+        const int my = freq_index(ky, N);
+        const int64_t ay = (((int64_t)my * uy) % a.Qy + a.Qy) % a.Qy;
+        double sn, cs;
+        sincospi(-2.0 * ((double)ax / (double)a.Qx + (double)ay / (double)a.Qy), &sn, &cs);
+        v[m] = cmul(src[ky], make_float2((float)cs, (float)sn));
+      }
+      fft<N, +1, C::WL>(v, j, tw, slot);
+    } else {
+#pragma unroll
+      for (int m = 0; m < 8; ++m) v[m] = nxt[m];
+      if (rr + 1 < RPW) {
+        const float2* src = a.in + ((size_t)w * a.rows + row + TPB) * N;
+#pragma unroll
+        for (int m = 0; m < 8; ++m) nxt[m] = src[j + T * m];
+      }
+      const float2* tab = a.table + (size_t)row * N;
+      if constexpr (MODE == PASS_ROW) {
+        fft<N, +1, C::WL>(v, j, tw, slot);
+#pragma unroll
+        for (int m = 0; m < 8; ++m) v[m] = cmul(v[m], tab[j + T * m]);
+        fft<N, -1, C::WL>(v, j, tw, slot);
+      } else {
+        fft<N, -1, C::WL>(v, j, tw, slot);
+#pragma unroll
+        for (int m = 0; m < 8; ++m) v[m] = cmul(v[m], tab[j + T * m]);
+        if constexpr (MODE == PASS_COL) {
+          fft<N, +1, C::WL>(v, j, tw, slot);
+        } else if constexpr (MODE == PASS_GATHER) {
+          if (active) {
+            const int64_t brow = a.wave_row[w];
+            const int32_t* cm = a.comp + (size_t)row * N;
+#pragma unroll
+            for (int m = 0; m < 8; ++m) {
+              const int d = cm[j + T * m];
+              if (d >= 0) {
+                if (a.split_bf16) {
+                  __hip_bfloat16 q[4];
+                  split_bf16(v[m].x, q[0], q[1]);
+                  split_bf16(v[m].y, q[2], q[3]);
+                  reinterpret_cast<uint2*>(a.basis)[brow * a.D + d] = *reinterpret_cast<uint2*>(q);
+                } else {
+                  reinterpret_cast<float2*>(a.basis)[brow * a.D + d] = v[m];
+                }
+              }
+            }
+          }
+        } else if constexpr (MODE == PASS_REDUCE) {
+          if (active) {
+            const uint32_t* mk = a.mask + (size_t)row * N;
+#pragma unroll
+            for (int m = 0; m < 8; ++m) {
+              const uint32_t bits = mk[j + T * m];
+              const double p = (double)v[m].x * v[m].x + (double)v[m].y * v[m].y;
+#pragma unroll
+              for (int q = 0; q < 8; ++q)
+                if (bits & (1u << q)) acc[q] += p;
+            }
           }
         }
       }
-    } else {  // COL_REDUCE
-      double acc[8];
+    }
+    if constexpr (MODE == PASS_ROW || MODE == PASS_COL || MODE == PASS_INIT) {
+      if (active) {
 #pragma unroll
-      for (int r = 0; r < 8; ++r) acc[r] = 0.0;
-#pragma unroll
-      for (int m = 0; m < 8; ++m) {
-        const uint32_t mask = a.detmask[(size_t)(j + T * m) * nx + col];
-        const double p = (double)v[m].x * v[m].x + (double)v[m].y * v[m].y;
-#pragma unroll
-        for (int r = 0; r < 8; ++r)
-          if (mask & (1u << r)) acc[r] += p;
-      }
-      // block reduction: wavefront shuffles, then one partial per wavefront in LDS (the
-      // exchange buffer is free: every thread has passed the last exchange's barrier)
-      double* part = reinterpret_cast<double*>(sm);
-      const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-#pragma unroll
-      for (int r = 0; r < 8; ++r) {
-        double x = acc[r];
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
-        if (lane == 0) part[wv * 8 + r] = x;
-      }
-      __syncthreads();
-      if (threadIdx.x < a.ndet) {
-        double s = 0.0;
-        const int nw = (ColCfg<NY>::kThreads + 63) / 64;
-        for (int i = 0; i < nw; ++i) s += part[i * 8 + threadIdx.x];
-        atomicAdd(a.img + threadIdx.x * a.img_stride + a.wave_row[w], s * a.scale);
+        for (int m = 0; m < 8; ++m) slot.put(j + T * m, v[m]);
       }
     }
+  }
+
+  if constexpr (MODE == PASS_REDUCE) {
+    // block reduction of the ring sums: wavefront shuffles, then LDS
+    __syncthreads();
+    double* part = reinterpret_cast<double*>(tile);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      double x = acc[q];
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+      if (lane == 0) part[(tid >> 6) * 8 + q] = x;
+    }
+    __syncthreads();
+    if (tid < a.ndet) {
+      double sum = 0.0;
+      for (int i = 0; i < WAVES; ++i) sum += part[i * 8 + tid];
+      atomicAdd(a.img + tid * a.img_stride + a.wave_row[w], sum * a.scale);
+    }
+  } else if constexpr (MODE != PASS_GATHER) {
+    __syncthreads();
+    // transposed store: out[w][x][row0 + r] for x < N, r < ROWS
+    constexpr int NT = WAVES * 64;
+    constexpr int XPER = NT / ROWS;
+    const int tr = tid % ROWS, tx = tid / ROWS;
+    float2* dst = a.out + (size_t)w * N * a.rows + row0 + tr;
+#pragma unroll 4
+    for (int x = tx; x < N; x += XPER) dst[(size_t)x * a.rows] = tile[tr * RS + slot_pos(x)];
   }
 }
 
@@ -444,101 +520,118 @@ hipError_t transmission(const float* v, float2* t, int64_t n, double sigma, hipS
   return hipGetLastError();
 }
 
-template <int NX>
-static hipError_t row_pass_n(const Tables& T, float2* work, const float2* trans_j, int B, hipStream_t s) {
-  constexpr int R0 = RowCfg<NX>::Rmax;
-  const int ny = T.ny;
-  // R rows per block must divide ny
-  if (ny % R0 == 0) {
-    k_row_pass<NX, R0><<<(unsigned)(B * (ny / R0)), R0 * (NX / 8), 0, s>>>(work, trans_j, T.twx, ny);
+// wavefronts per block of the slice pass (tunable; clamped to what the size allows)
+static int g_pass_waves = 4;
+void set_pass_waves(int w) { g_pass_waves = w; }
+
+template <int N>
+constexpr int max_waves() {
+  using C = PassCfg<N>;
+  return C::WL ? C::ROWS / C::S : C::WPT;
+}
+
+template <int N, int WAVES, int MODE>
+static hipError_t pass_launch(const PassArgs& a, int B, hipStream_t s) {
+  const int groups = a.rows / PassCfg<N>::ROWS;
+  const unsigned grid = (unsigned)(B * groups);
+  k_pass<N, WAVES, MODE><<<grid, WAVES * 64, 0, s>>>(a);
+  return hipGetLastError();
+}
+
+template <int N, int MODE>
+static hipError_t pass_waves(const PassArgs& a, int B, hipStream_t s) {
+  if (a.rows % PassCfg<N>::ROWS) return hipErrorInvalidValue;
+  constexpr int MW = max_waves<N>();
+  if constexpr (!PassCfg<N>::WL) {
+    return pass_launch<N, MW, MODE>(a, B, s);
   } else {
-    k_row_pass<NX, 1><<<(unsigned)(B * ny), NX / 8, 0, s>>>(work, trans_j, T.twx, ny);
+    int w = g_pass_waves;
+    if (w > MW) w = MW;
+    if constexpr (MW >= 16) { if (w >= 16) return pass_launch<N, 16, MODE>(a, B, s); }
+    if constexpr (MW >= 8) { if (w >= 8) return pass_launch<N, 8, MODE>(a, B, s); }
+    if constexpr (MW >= 4) { if (w >= 4) return pass_launch<N, 4, MODE>(a, B, s); }
+    if constexpr (MW >= 2) { if (w >= 2) return pass_launch<N, 2, MODE>(a, B, s); }
+    return pass_launch<N, 1, MODE>(a, B, s);
   }
-  return hipGetLastError();
-}
-
-hipError_t row_pass(const Tables& T, float2* work, const float2* trans_j, int B, hipStream_t s) {
-  switch (T.nx) {
-    case 16: return row_pass_n<16>(T, work, trans_j, B, s);
-    case 32: return row_pass_n<32>(T, work, trans_j, B, s);
-    case 64: return row_pass_n<64>(T, work, trans_j, B, s);
-    case 128: return row_pass_n<128>(T, work, trans_j, B, s);
-    case 256: return row_pass_n<256>(T, work, trans_j, B, s);
-    case 512: return row_pass_n<512>(T, work, trans_j, B, s);
-    case 1024: return row_pass_n<1024>(T, work, trans_j, B, s);
-    case 2048: return row_pass_n<2048>(T, work, trans_j, B, s);
-  }
-  return hipErrorInvalidValue;
-}
-
-template <int NY, int MODE>
-static hipError_t col_launch(const ColArgs& a, int B, hipStream_t s) {
-  constexpr int C = ColCfg<NY>::C;
-  if (a.nx % C) return hipErrorInvalidValue;
-  const unsigned grid = (unsigned)(B * (a.nx / C));
-  k_col_pass<NY, MODE><<<grid, ColCfg<NY>::kThreads, 0, s>>>(a);
-  return hipGetLastError();
 }
 
 template <int MODE>
-static hipError_t col_dispatch(const ColArgs& a, int B, hipStream_t s) {
-  switch (a.ny) {
-    case 16: return col_launch<16, MODE>(a, B, s);
-    case 32: return col_launch<32, MODE>(a, B, s);
-    case 64: return col_launch<64, MODE>(a, B, s);
-    case 128: return col_launch<128, MODE>(a, B, s);
-    case 256: return col_launch<256, MODE>(a, B, s);
-    case 512: return col_launch<512, MODE>(a, B, s);
-    case 1024: return col_launch<1024, MODE>(a, B, s);
-    case 2048: return col_launch<2048, MODE>(a, B, s);
+static hipError_t pass_dispatch(int N, const PassArgs& a, int B, hipStream_t s) {
+  switch (N) {
+    case 16: return pass_waves<16, MODE>(a, B, s);
+    case 32: return pass_waves<32, MODE>(a, B, s);
+    case 64: return pass_waves<64, MODE>(a, B, s);
+    case 128: return pass_waves<128, MODE>(a, B, s);
+    case 256: return pass_waves<256, MODE>(a, B, s);
+    case 512: return pass_waves<512, MODE>(a, B, s);
+    case 1024: return pass_waves<1024, MODE>(a, B, s);
+    case 2048: return pass_waves<2048, MODE>(a, B, s);
   }
   return hipErrorInvalidValue;
 }
 
-static ColArgs base_args(const Tables& T, float2* work) {
-  ColArgs a{};
-  a.work = work;
-  a.spec = T.spec_init;
-  a.prop = T.prop;
+hipError_t init_waves(const Tables& T, float2* out, const int64_t* wave_u, int B, hipStream_t s) {
+  PassArgs a{};
+  a.out = out;
+  a.rows = T.nx;
+  a.table = T.specT;
   a.tw = T.twy;
+  a.wave_u = wave_u;
   a.Qx = T.Qx;
   a.Qy = T.Qy;
-  a.comp_map = T.comp_map;
-  a.detmask = T.detmask;
-  a.nx = T.nx;
-  a.ny = T.ny;
-  return a;
+  a.nrow_freq = T.nx;
+  return pass_dispatch<PASS_INIT>(T.ny, a, B, s);
 }
 
-hipError_t init_waves(const Tables& T, float2* work, const int64_t* wave_u, int B, hipStream_t s) {
-  ColArgs a = base_args(T, work);
-  a.wave_u = wave_u;
-  return col_dispatch<COL_INIT>(a, B, s);
+hipError_t row_pass(const Tables& T, const float2* in, float2* out, const float2* trans_j, int B, hipStream_t s) {
+  PassArgs a{};
+  a.in = in;
+  a.out = out;
+  a.rows = T.ny;
+  a.table = trans_j;
+  a.tw = T.twx;
+  return pass_dispatch<PASS_ROW>(T.nx, a, B, s);
 }
 
-hipError_t col_pass(const Tables& T, float2* work, int B, hipStream_t s) {
-  return col_dispatch<COL_MID>(base_args(T, work), B, s);
+hipError_t col_pass(const Tables& T, const float2* in, float2* out, int B, hipStream_t s) {
+  PassArgs a{};
+  a.in = in;
+  a.out = out;
+  a.rows = T.nx;
+  a.table = T.propT;
+  a.tw = T.twy;
+  return pass_dispatch<PASS_COL>(T.ny, a, B, s);
 }
 
-hipError_t col_gather(const Tables& T, const float2* work, int B, void* basis, int D, const int32_t* wave_row,
+hipError_t col_gather(const Tables& T, const float2* in, int B, void* basis, int D, const int32_t* wave_row,
                       int split, hipStream_t s) {
-  ColArgs a = base_args(T, const_cast<float2*>(work));
+  PassArgs a{};
+  a.in = in;
+  a.rows = T.nx;
+  a.table = T.propT;
+  a.tw = T.twy;
   a.basis = basis;
   a.D = D;
+  a.comp = T.compT;
   a.wave_row = wave_row;
   a.split_bf16 = split;
-  return col_dispatch<COL_GATHER>(a, B, s);
+  return pass_dispatch<PASS_GATHER>(T.ny, a, B, s);
 }
 
-hipError_t col_reduce(const Tables& T, const float2* work, int B, const int32_t* wave_out, double* img, int ndet,
+hipError_t col_reduce(const Tables& T, const float2* in, int B, const int32_t* wave_out, double* img, int ndet,
                       int64_t img_stride, double scale, hipStream_t s) {
-  ColArgs a = base_args(T, const_cast<float2*>(work));
+  PassArgs a{};
+  a.in = in;
+  a.rows = T.nx;
+  a.table = T.propT;
+  a.tw = T.twy;
+  a.mask = T.maskT;
   a.wave_row = wave_out;
   a.img = img;
   a.ndet = ndet;
   a.img_stride = img_stride;
   a.scale = scale;
-  return col_dispatch<COL_REDUCE>(a, B, s);
+  return pass_dispatch<PASS_REDUCE>(T.ny, a, B, s);
 }
 
 template <int SPLIT, int PT>

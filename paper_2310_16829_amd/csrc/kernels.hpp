@@ -6,16 +6,17 @@
 namespace lma {
 namespace dev {
 
-// Device tables of a plan (all device pointers).
+// Device tables of a plan (all device pointers). Tables read by column passes are stored
+// transposed, [kx][ky].
 struct Tables {
   int nx = 0, ny = 0;
   int64_t Qx = 1, Qy = 1;            // lattice units per cell (wave positions are in units)
-  const float2* spec_init = nullptr; // probe spectrum / (XY)          [ny][nx]
-  const float2* prop = nullptr;      // propagator * band limit / (XY) [ny][nx]
+  const float2* specT = nullptr;     // probe spectrum / (XY)          [nx][ny]
+  const float2* propT = nullptr;     // propagator * band limit / (XY) [nx][ny]
   const float2* twx = nullptr;       // exp(-2 pi i t / nx)            [nx]
   const float2* twy = nullptr;       // exp(-2 pi i t / ny)            [ny]
-  const int32_t* comp_map = nullptr; // frequency -> detector pixel or -1 [ny][nx]
-  const uint32_t* detmask = nullptr; // ring bits per frequency        [ny][nx]
+  const int32_t* compT = nullptr;    // frequency -> detector pixel or -1 [nx][ny]
+  const uint32_t* maskT = nullptr;   // ring bits per frequency        [nx][ny]
 };
 
 struct Contraction {
@@ -42,18 +43,22 @@ struct Contraction {
 bool supported(int nx, int ny);
 
 hipError_t transmission(const float* v, float2* t, int64_t n, double sigma, hipStream_t s);
-// initial waves u(. - pos_w) in the mixed (kx, y) domain: column IFFT of spec * modulation
-hipError_t init_waves(const Tables& T, float2* work, const int64_t* wave_u, int B, hipStream_t s);
-// row pass of slice j: row IFFT, * t_j, row FFT
-hipError_t row_pass(const Tables& T, float2* work, const float2* trans_j, int B, hipStream_t s);
-// column pass of a middle slice: column FFT, * P, column IFFT
-hipError_t col_pass(const Tables& T, float2* work, int B, hipStream_t s);
+// Wave batches alternate between two layouts: A = [B][ny][nx] (mixed domain, y spatial,
+// x frequency) and At = [B][nx][ny].
+// initial waves u(. - pos_w) into A: column IFFT of spectrum * modulation
+hipError_t init_waves(const Tables& T, float2* outA, const int64_t* wave_u, int B, hipStream_t s);
+// row pass of slice j, A -> At: row IFFT, * t_j, row FFT
+hipError_t row_pass(const Tables& T, const float2* inA, float2* outAt, const float2* trans_j, int B, hipStream_t s);
+// column pass of a middle slice, At -> A: column FFT, * P, column IFFT
+hipError_t col_pass(const Tables& T, const float2* inAt, float2* outA, int B, hipStream_t s);
 // last column pass, LMA: column FFT, * P, keep the detector pixels as basis rows
-hipError_t col_gather(const Tables& T, const float2* work, int B, void* basis, int D,
+hipError_t col_gather(const Tables& T, const float2* inAt, int B, void* basis, int D,
                       const int32_t* wave_row, int split_bf16, hipStream_t s);
 // last column pass, plain: column FFT, * P, ring sums of |.|^2 added to img[r][wave_out[w]]
-hipError_t col_reduce(const Tables& T, const float2* work, int B, const int32_t* wave_out,
+hipError_t col_reduce(const Tables& T, const float2* inAt, int B, const int32_t* wave_out,
                       double* img, int ndet, int64_t img_stride, double scale, hipStream_t s);
+// wavefronts per block of the slice passes (tuning knob)
+void set_pass_waves(int waves);
 // probe-coefficient contraction and detector reduction
 hipError_t contract(const Contraction& c, hipStream_t s);
 // out = (acc ? out : 0) + w * img, n doubles, device memory
