@@ -65,8 +65,7 @@ struct lma_plan {
   int32_t* d_probe_out = nullptr;    // [n_probes] image index
   // work
   void* d_basis = nullptr;           // [n_rows][D] x 8 bytes
-  float2* d_work = nullptr;          // [B][ny][nx]
-  float2* d_workT = nullptr;         // [B][nx][ny]
+  float2* d_work = nullptr;          // [B][ny/TW][nx/TW][TW][TW] tiled waves
   float2* d_trans = nullptr;         // [cap][ny][nx]
   int trans_cap = 0;
   float* d_pot = nullptr;            // staging for host potentials
@@ -153,8 +152,8 @@ int64_t wave_bytes(const lma_optics& op) { return (int64_t)op.nx * op.ny * (int6
 
 int auto_batch(const HostPlan& h) {
   if (h.lat.batch > 0) return h.lat.batch;
-  // about 512 MiB of wave batch
-  int64_t b = ((int64_t)512 << 20) / wave_bytes(h.op);
+  // about 1 GiB of wave batch
+  int64_t b = ((int64_t)1024 << 20) / wave_bytes(h.op);
   return (int)std::max<int64_t>(1, std::min<int64_t>(b, 4096));
 }
 
@@ -251,13 +250,13 @@ lma_status run_waves(lma_plan* p, const int64_t* d_u, const int32_t* d_row, cons
     const int nb = std::min(p->B, n - first);
     LAUNCH(p, "init", lma::dev::init_waves(T, p->d_work, d_u + 2 * (int64_t)first, nb, p->stream));
     for (int j = 0; j < nslices; ++j) {
-      LAUNCH(p, "row_pass", lma::dev::row_pass(T, p->d_work, p->d_workT, p->d_trans + (size_t)j * XY, nb, p->stream));
+      LAUNCH(p, "row_pass", lma::dev::row_pass(T, p->d_work, p->d_trans + (size_t)j * XY, nb, p->stream));
       if (j + 1 < nslices) {
-        LAUNCH(p, "col_pass", lma::dev::col_pass(T, p->d_workT, p->d_work, nb, p->stream));
+        LAUNCH(p, "col_pass", lma::dev::col_pass(T, p->d_work, nb, p->stream));
       } else if (d_row) {
-        LAUNCH(p, "col_gather", lma::dev::col_gather(T, p->d_workT, nb, p->d_basis, p->h.D(), d_row + first, split, p->stream));
+        LAUNCH(p, "col_gather", lma::dev::col_gather(T, p->d_work, nb, p->d_basis, p->h.D(), d_row + first, split, p->stream));
       } else {
-        LAUNCH(p, "col_reduce", lma::dev::col_reduce(T, p->d_workT, nb, d_out + first, p->d_img, p->h.ndet,
+        LAUNCH(p, "col_reduce", lma::dev::col_reduce(T, p->d_work, nb, d_out + first, p->d_img, p->h.ndet,
                                                      p->h.n_probes(), (double)XY, p->stream));
       }
     }
@@ -337,7 +336,7 @@ int64_t footprint_of(const HostPlan& h, int B, int nslices, bool with_basis) {
   b += (int64_t)h.chunk_start.size() * 12;
   b += (int64_t)h.rows.size() * 20 + h.n_probes() * 20;
   b += (int64_t)h.ndet * h.n_probes() * 8;            // image
-  b += (int64_t)B * XY * 8 * 2;                       // wave batch, two layouts
+  b += (int64_t)B * XY * 8;                           // wave batch
   b += (int64_t)nslices * XY * (8 + 4);               // transmission tables and potential staging
   if (with_basis) b += (int64_t)h.rows.size() * h.D() * 8;
   return b;
@@ -458,7 +457,7 @@ lma_status lma_build_basis(const lma_optics* optics, const lma_lattice* lattice,
       }
     if ((s = upload(p, &p->d_compT, compT.data(), compT.size())) != LMA_OK) { release(p); return s; }
     if ((s = upload(p, &p->d_maskT, maskT.data(), maskT.size())) != LMA_OK) { release(p); return s; }
-    if (const char* e = std::getenv("LMA_PASS_WAVES")) lma::dev::set_pass_waves(std::atoi(e));
+    if (const char* e = std::getenv("LMA_TILE_WIDTH")) lma::dev::set_tile_width(std::atoi(e));
     if ((s = upload(p, &p->d_row_of, h.row_of.data(), h.row_of.size())) != LMA_OK) { release(p); return s; }
     if ((s = upload(p, &p->d_set_dx, h.set_dx.data(), h.set_dx.size())) != LMA_OK) { release(p); return s; }
     if ((s = upload(p, &p->d_set_dy, h.set_dy.data(), h.set_dy.size())) != LMA_OK) { release(p); return s; }
@@ -493,7 +492,6 @@ lma_status lma_build_basis(const lma_optics* optics, const lma_lattice* lattice,
     // buffers
     if ((s = dalloc(p, (void**)&p->d_img, (size_t)h.ndet * h.n_probes() * sizeof(double))) != LMA_OK) { release(p); return s; }
     if ((s = dalloc(p, (void**)&p->d_work, (size_t)p->B * XY * sizeof(float2))) != LMA_OK) { release(p); return s; }
-    if ((s = dalloc(p, (void**)&p->d_workT, (size_t)p->B * XY * sizeof(float2))) != LMA_OK) { release(p); return s; }
     if ((s = dalloc(p, &p->d_basis, (size_t)h.rows.size() * h.D() * 8)) != LMA_OK) { release(p); return s; }
     *out = p;
     return LMA_OK;

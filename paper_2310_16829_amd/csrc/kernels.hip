@@ -14,6 +14,8 @@
 #include <hip/hip_runtime.h>
 #include <hip/hip_bf16.h>
 
+#include <algorithm>
+
 #include "kernels.hpp"
 
 namespace lma {
@@ -218,42 +220,47 @@ __global__ void k_transmission(const float* __restrict__ v, float2* __restrict__
 // ------------------------------------------------------------------------------------------
 // slice pass
 //
-// Reads rows of length N from in[B][rows][N] (contiguous), transforms them, and stores the
-// result transposed, out[B][N][rows], through an LDS tile of ROWS rows so that every store
-// writes ROWS consecutive values. The row pass (rows = y, N = nx) takes the mixed domain
-// [y][kx] to [kx][y]; the column pass (rows = kx, N = ny) takes [kx][y] back to [y][kx].
-// Tables used by column passes are stored transposed, [kx][ky].
+// Waves live in HBM in TW x TW tiles, in place for every pass: element (y, x) of wave w is at
+//   w*XY + ((y/TW)*(nx/TW) + x/TW)*TW*TW + (y%TW)*TW + x%TW.
+// A workgroup owns TW lines of one wave: a row pass (lines y, positions x) takes one tile row,
+// a contiguous TW*nx block; a column pass (lines x, positions y) takes one tile column, ny/TW
+// contiguous tiles. Lines are staged through an LDS tile (whole tiles move between HBM and LDS,
+// with non-temporal hints), transformed with wavefront-local exchanges inside their LDS line,
+// and written back to the same place. Between passes a wave is in the mixed domain (y
+// spatial, x frequency). Tables read by column passes are stored transposed, [kx][ky].
 // ------------------------------------------------------------------------------------------
 enum { PASS_ROW = 0, PASS_COL = 1, PASS_INIT = 2, PASS_GATHER = 3, PASS_REDUCE = 4 };
 
-template <int N>
+template <int N, int TW>
 struct PassCfg {
   static constexpr int T = N / 8;                                   // threads per transform
   static constexpr bool WL = T <= 64;                               // transform inside one wavefront
-  static constexpr int S = WL ? ((64 / T) < 16 ? 64 / T : 16) : 1;  // transforms per wavefront
+  static constexpr int S = WL ? ((64 / T) < TW ? 64 / T : TW) : 1;  // transforms per wavefront
   static constexpr int WPT = WL ? 1 : T / 64;                       // wavefronts per transform
-  static constexpr int ROWS = N <= 512 ? 16 : (N == 1024 ? 8 : 4);  // tile rows
-  // tile row stride: a padded slot plus LMA_TILE_EXTRA, chosen so that the 16 rows read at one
-  // column by the transposed store fall on distinct banks
+  static constexpr int WAVES = WL ? ((TW / S) < 4 ? TW / S : 4) : WPT;
+  static constexpr int TPB = WAVES * S / WPT;                       // transforms in flight
+  static constexpr int RPW = TW / TPB;                              // rounds per workgroup
+  // LDS line stride: a padded slot plus LMA_TILE_EXTRA, so that the TW lines touched by one
+  // tile row fall on distinct banks
   static constexpr int RS = slot_pos(N - 1) + 1 + LMA_TILE_EXTRA;
   static constexpr int NTW = tw_count(N);
+  static_assert(TPB >= 1 && TW % TPB == 0, "lines must split evenly over the workgroup");
 };
 
 struct PassArgs {
-  const float2* in;
-  float2* out;
-  int rows;                  // rows per batch entry
-  const float2* table;       // ROW: t_j [rows][N]; COL/GATHER/REDUCE: P^T [rows][N]; INIT: spectrum^T
-  const float2* tw;          // twiddles exp(-2 pi i t / N), t < N
+  float2* work;              // [B][tiles] waves, updated in place
+  int nx, ny;
+  int B;                     // waves in the batch
+  const float2* table;       // ROW: t_j [ny][nx]; COL/GATHER/REDUCE: P^T [nx][ny]; INIT: spectrum^T
+  const float2* tw;          // twiddles exp(-2 pi i t / N), t < N, N = line length
   const int64_t* wave_u;     // INIT: [B][2] lattice units of each wave's position
   int64_t Qx, Qy;
-  int nrow_freq;             // INIT: number of rows (kx) for the frequency index; N is ky
   void* basis;               // GATHER
   int D;
-  const int32_t* comp;       // GATHER: detector pixel index [rows][N] or -1
+  const int32_t* comp;       // GATHER: detector pixel index [nx][ny] or -1
   const int32_t* wave_row;   // GATHER: basis row per wave; REDUCE: image index per wave
   int split_bf16;
-  const uint32_t* mask;      // REDUCE: ring bits [rows][N]
+  const uint32_t* mask;      // REDUCE: ring bits [nx][ny]
   double* img;
   int ndet;
   int64_t img_stride;
@@ -265,154 +272,261 @@ __device__ __forceinline__ void split_bf16(float x, __hip_bfloat16& hi, __hip_bf
   lo = __float2bfloat16(x - __bfloat162float(hi));
 }
 
-template <int N, int WAVES, int MODE>
-__global__ __launch_bounds__(WAVES * 64) void k_pass(PassArgs a) {
-  using C = PassCfg<N>;
-  constexpr int T = C::T, S = C::S, ROWS = C::ROWS, RS = C::RS;
-  constexpr int TPB = WAVES * S / C::WPT;                  // transforms in flight per block
-  static_assert(TPB >= 1 && ROWS % TPB == 0, "tile rows must split evenly over the block");
-  constexpr int RPW = ROWS / TPB;                          // rounds per block
-  __shared__ float2 tile[(ROWS + 1) * RS];                 // last row: scratch of idle lanes
+__device__ __forceinline__ float2 load_stream(const float2* p) {
+  const unsigned long long u = __builtin_nontemporal_load(reinterpret_cast<const unsigned long long*>(p));
+  return __builtin_bit_cast(float2, u);
+}
+__device__ __forceinline__ void store_stream(float2* p, float2 v) {
+  __builtin_nontemporal_store(__builtin_bit_cast(unsigned long long, v), reinterpret_cast<unsigned long long*>(p));
+}
+
+// Element c of a work item (TW lines x N positions) <-> its LDS index and its offset from the
+// item's first element in HBM. A row item (tile row g) is one contiguous block; a column item
+// (tile column g) is N/TW tiles, one every nx/TW tiles.
+template <int N, int TW, bool ROWS>
+struct TileMap {
+  static constexpr int TT = TW * TW;
+  static constexpr int RS = PassCfg<N, TW>::RS;
+  __device__ __forceinline__ static int64_t item_base(int g, int nx) {
+    return ROWS ? (int64_t)g * TW * nx : (int64_t)g * TT;
+  }
+  __device__ __forceinline__ static void at(int c, int stride_q, int& lds, int& off) {
+    const int q = c / TT, rem = c % TT;
+    int line, pos;
+    if constexpr (ROWS) {
+      line = rem / TW;
+      pos = q * TW + rem % TW;
+      off = c;
+    } else {
+      line = rem % TW;
+      pos = q * TW + rem / TW;
+      off = q * stride_q + rem;
+    }
+    lds = line * RS + slot_pos(pos);
+  }
+};
+
+// Work items of a pass are (line group g, wave w) pairs, item l = g*B + w. Workgroups are
+// persistent: each walks a strided sequence of items, and the items of one XCD form one
+// contiguous range (so an XCD reads one part of the shared tables).
+struct ItemWalk {
+  int l, end, step;
+  __device__ __forceinline__ ItemWalk(int W) {
+    const int G = gridDim.x, b = blockIdx.x;
+    if ((G & 7) == 0 && (W & 7) == 0 && G >= 8) {
+      const int x = b & 7, per = W >> 3;
+      l = x * per + (b >> 3);
+      end = (x + 1) * per;
+      step = G >> 3;
+    } else {
+      l = b;
+      end = W;
+      step = G;
+    }
+  }
+  __device__ __forceinline__ bool valid(int i) const { return i < end; }
+};
+
+template <int N, int TW, int MODE>
+__global__ __launch_bounds__((PassCfg<N, TW>::WAVES * 64)) void k_pass(PassArgs a) {
+  using C = PassCfg<N, TW>;
+  constexpr int T = C::T, S = C::S, RS = C::RS, TPB = C::TPB, RPW = C::RPW;
+  constexpr int NT = C::WAVES * 64;
+  constexpr bool ROWS = (MODE == PASS_ROW);
+  constexpr int TOTAL = TW * N;                            // elements of one work item
+  constexpr int EPT = TOTAL / NT;                          // per thread
+#ifndef LMA_PREFETCH
+#define LMA_PREFETCH 1
+#endif
+  constexpr bool PREF = LMA_PREFETCH && EPT <= 16;         // next item prefetched into registers
+  constexpr int CHUNK = 16;                                // staging step otherwise
+  static_assert(TOTAL % NT == 0, "work item must split evenly over the threads");
+  __shared__ float2 tile[(TW + (C::WL ? 1 : 0)) * RS];     // extra line: scratch of idle lanes
+  [[maybe_unused]] __shared__ double part[C::WAVES][8];
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int sub = C::WL ? lane / T : 0;                    // transform within the wavefront
   const int j = C::WL ? lane % T : tid % T;                // thread within the transform
   const int tslot = C::WL ? (tid >> 6) * S + sub : tid / T;  // transform slot within the block
   const bool active = !C::WL || sub < S;
-  const int groups = a.rows / ROWS;
-  const int blk = xcd_remap(blockIdx.x, gridDim.x);
-  const int B = gridDim.x / groups;
-  const int grp = blk / B, w = blk % B;                    // an XCD owns a range of rows
-  const int row0 = grp * ROWS;
+  const int ngroups = (ROWS ? a.ny : a.nx) / TW;
+  const int B = a.B;
+  const int ntx = a.nx / TW;
+  const ItemWalk walk(B * ngroups);
 
   float2 tw[C::NTW];
   tw_load<N>(tw, a.tw, j);
 
-  [[maybe_unused]] double acc[8];
-  if constexpr (MODE == PASS_REDUCE) {
+  using M = TileMap<N, TW, ROWS>;
+  const int stride_q = ntx * M::TT;                        // column items: tile-to-tile stride
+  auto item_ptr = [&](int l) -> float2* {
+    const int g = l / B, w = l % B;
+    return a.work + (size_t)w * a.nx * a.ny + M::item_base(g, a.nx);
+  };
+  [[maybe_unused]] float2 buf[PREF ? EPT : 1];
+  auto load_item = [&](int l) {
+    const float2* src = item_ptr(l);
 #pragma unroll
-    for (int r = 0; r < 8; ++r) acc[r] = 0.0;
-  }
-
-  // rows are prefetched one round ahead so that their loads overlap the current transforms
-  [[maybe_unused]] float2 nxt[8];
-  if constexpr (MODE != PASS_INIT) {
-    const float2* src = a.in + ((size_t)w * a.rows + row0 + (active ? tslot : 0)) * N;
-#pragma unroll
-    for (int m = 0; m < 8; ++m) nxt[m] = src[j + T * m];
+    for (int k = 0; k < EPT; ++k) {
+      int lds, off;
+      M::at(k * NT + tid, stride_q, lds, off);
+      buf[k] = load_stream(src + off);
+    }
+  };
+  if constexpr (PREF && MODE != PASS_INIT) {
+    if (walk.valid(walk.l)) load_item(walk.l);
   }
 
 #pragma unroll 1
-  for (int rr = 0; rr < RPW; ++rr) {
-    const int r = rr * TPB + (active ? tslot : 0);         // tile row
-    const int row = row0 + r;
-    const Slot slot{tile + (active ? r : ROWS) * RS};
-    float2 v[8];
-    if constexpr (MODE == PASS_INIT) {
-      // u(. - pos_w): spectrum times exp(-2 pi i (mx ux / Qx + my uy / Qy)), reduced exactly in
-      // lattice units, phase in FP64; rows are kx, positions ky
-      const int mx = freq_index(row, a.nrow_freq);
-      const int64_t ux = a.wave_u[2 * w], uy = a.wave_u[2 * w + 1];
-      const int64_t ax = (((int64_t)mx * ux) % a.Qx + a.Qx) % a.Qx;
-      const float2* src = a.table + (size_t)row * N;
+  for (int l = walk.l; walk.valid(l); l += walk.step) {
+    const int g = l / B, w = l % B;
+    float2* item = item_ptr(l);
+    __syncthreads();                                       // the previous item is out of LDS
+
+    // ---- stage the item's lines into LDS, then start loading the next item ----------------
+    if constexpr (MODE != PASS_INIT) {
+      if constexpr (PREF) {
 #pragma unroll
-      for (int m = 0; m < 8; ++m) {
-        const int ky = j + T * m;
-        const int my = freq_index(ky, N);
-        const int64_t ay = (((int64_t)my * uy) % a.Qy + a.Qy) % a.Qy;
-        double sn, cs;
-        sincospi(-2.0 * ((double)ax / (double)a.Qx + (double)ay / (double)a.Qy), &sn, &cs);
-        v[m] = cmul(src[ky], make_float2((float)cs, (float)sn));
-      }
-      fft<N, +1, C::WL>(v, j, tw, slot);
-    } else {
-#pragma unroll
-      for (int m = 0; m < 8; ++m) v[m] = nxt[m];
-      if (rr + 1 < RPW) {
-        const float2* src = a.in + ((size_t)w * a.rows + row + TPB) * N;
-#pragma unroll
-        for (int m = 0; m < 8; ++m) nxt[m] = src[j + T * m];
-      }
-      const float2* tab = a.table + (size_t)row * N;
-      if constexpr (MODE == PASS_ROW) {
-        fft<N, +1, C::WL>(v, j, tw, slot);
-#pragma unroll
-        for (int m = 0; m < 8; ++m) v[m] = cmul(v[m], tab[j + T * m]);
-        fft<N, -1, C::WL>(v, j, tw, slot);
+        for (int k = 0; k < EPT; ++k) {
+          int lds, off;
+          M::at(k * NT + tid, stride_q, lds, off);
+          tile[lds] = buf[k];
+        }
+        __syncthreads();
+        if (walk.valid(l + walk.step)) load_item(l + walk.step);
       } else {
-        fft<N, -1, C::WL>(v, j, tw, slot);
+#pragma unroll 1
+        for (int c0 = 0; c0 < TOTAL; c0 += NT * CHUNK) {
+          float2 st[CHUNK];
 #pragma unroll
-        for (int m = 0; m < 8; ++m) v[m] = cmul(v[m], tab[j + T * m]);
-        if constexpr (MODE == PASS_COL) {
+          for (int k = 0; k < CHUNK; ++k) {
+            int lds, off;
+            M::at(c0 + k * NT + tid, stride_q, lds, off);
+            st[k] = load_stream(item + off);
+          }
+#pragma unroll
+          for (int k = 0; k < CHUNK; ++k) {
+            int lds, off;
+            M::at(c0 + k * NT + tid, stride_q, lds, off);
+            tile[lds] = st[k];
+          }
+        }
+        __syncthreads();
+      }
+    }
+
+    [[maybe_unused]] double acc[8];
+    if constexpr (MODE == PASS_REDUCE) {
+#pragma unroll
+      for (int q = 0; q < 8; ++q) acc[q] = 0.0;
+    }
+
+#pragma unroll 1
+    for (int rr = 0; rr < RPW; ++rr) {
+      const int r = rr * TPB + (active ? tslot : 0);       // line within the workgroup
+      const int line = g * TW + r;                          // y (row pass) or x (column passes)
+      const Slot slot{tile + (active ? r : TW) * RS};
+      const float2* tab = a.table + (size_t)line * N;
+      float2 v[8];
+      if constexpr (MODE == PASS_INIT) {
+        // u(. - pos_w): spectrum times exp(-2 pi i (mx ux / Qx + my uy / Qy)), reduced exactly
+        // in lattice units, phase in FP64; lines are kx, positions ky
+        const int mx = freq_index(line, a.nx);
+        const int64_t ux = a.wave_u[2 * w], uy = a.wave_u[2 * w + 1];
+        const int64_t ax = (((int64_t)mx * ux) % a.Qx + a.Qx) % a.Qx;
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+          const int ky = j + T * m;
+          const int my = freq_index(ky, N);
+          const int64_t ay = (((int64_t)my * uy) % a.Qy + a.Qy) % a.Qy;
+          double sn, cs;
+          sincospi(-2.0 * ((double)ax / (double)a.Qx + (double)ay / (double)a.Qy), &sn, &cs);
+          v[m] = cmul(tab[ky], make_float2((float)cs, (float)sn));
+        }
+        fft<N, +1, C::WL>(v, j, tw, slot);
+      } else {
+#pragma unroll
+        for (int m = 0; m < 8; ++m) v[m] = slot.get(j + T * m);
+        // the first stage overwrites the line: every thread of the transform must have read it
+        exchange_sync<C::WL>();
+        if constexpr (MODE == PASS_ROW) {
           fft<N, +1, C::WL>(v, j, tw, slot);
-        } else if constexpr (MODE == PASS_GATHER) {
-          if (active) {
-            const int64_t brow = a.wave_row[w];
-            const int32_t* cm = a.comp + (size_t)row * N;
 #pragma unroll
-            for (int m = 0; m < 8; ++m) {
-              const int d = cm[j + T * m];
-              if (d >= 0) {
-                if (a.split_bf16) {
-                  __hip_bfloat16 q[4];
-                  split_bf16(v[m].x, q[0], q[1]);
-                  split_bf16(v[m].y, q[2], q[3]);
-                  reinterpret_cast<uint2*>(a.basis)[brow * a.D + d] = *reinterpret_cast<uint2*>(q);
-                } else {
-                  reinterpret_cast<float2*>(a.basis)[brow * a.D + d] = v[m];
+          for (int m = 0; m < 8; ++m) v[m] = cmul(v[m], tab[j + T * m]);
+          fft<N, -1, C::WL>(v, j, tw, slot);
+        } else {
+          fft<N, -1, C::WL>(v, j, tw, slot);
+#pragma unroll
+          for (int m = 0; m < 8; ++m) v[m] = cmul(v[m], tab[j + T * m]);
+          if constexpr (MODE == PASS_COL) {
+            fft<N, +1, C::WL>(v, j, tw, slot);
+          } else if constexpr (MODE == PASS_GATHER) {
+            if (active) {
+              const int64_t brow = a.wave_row[w];
+              const int32_t* cm = a.comp + (size_t)line * N;
+#pragma unroll
+              for (int m = 0; m < 8; ++m) {
+                const int d = cm[j + T * m];
+                if (d >= 0) {
+                  if (a.split_bf16) {
+                    __hip_bfloat16 q[4];
+                    split_bf16(v[m].x, q[0], q[1]);
+                    split_bf16(v[m].y, q[2], q[3]);
+                    reinterpret_cast<uint2*>(a.basis)[brow * a.D + d] = *reinterpret_cast<uint2*>(q);
+                  } else {
+                    reinterpret_cast<float2*>(a.basis)[brow * a.D + d] = v[m];
+                  }
                 }
               }
             }
-          }
-        } else if constexpr (MODE == PASS_REDUCE) {
-          if (active) {
-            const uint32_t* mk = a.mask + (size_t)row * N;
+          } else if constexpr (MODE == PASS_REDUCE) {
+            if (active) {
+              const uint32_t* mk = a.mask + (size_t)line * N;
 #pragma unroll
-            for (int m = 0; m < 8; ++m) {
-              const uint32_t bits = mk[j + T * m];
-              const double p = (double)v[m].x * v[m].x + (double)v[m].y * v[m].y;
+              for (int m = 0; m < 8; ++m) {
+                const uint32_t bits = mk[j + T * m];
+                const double p = (double)v[m].x * v[m].x + (double)v[m].y * v[m].y;
 #pragma unroll
-              for (int q = 0; q < 8; ++q)
-                if (bits & (1u << q)) acc[q] += p;
+                for (int q = 0; q < 8; ++q)
+                  if (bits & (1u << q)) acc[q] += p;
+              }
             }
           }
         }
       }
-    }
-    if constexpr (MODE == PASS_ROW || MODE == PASS_COL || MODE == PASS_INIT) {
-      if (active) {
+      if constexpr (MODE == PASS_ROW || MODE == PASS_COL || MODE == PASS_INIT) {
+        if (active) {
 #pragma unroll
-        for (int m = 0; m < 8; ++m) slot.put(j + T * m, v[m]);
+          for (int m = 0; m < 8; ++m) slot.put(j + T * m, v[m]);
+        }
       }
     }
-  }
 
-  if constexpr (MODE == PASS_REDUCE) {
-    // block reduction of the ring sums: wavefront shuffles, then LDS
-    __syncthreads();
-    double* part = reinterpret_cast<double*>(tile);
+    if constexpr (MODE == PASS_REDUCE) {
+      // ring sums of this item: wavefront shuffles, then one partial per wavefront
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      double x = acc[q];
+      for (int q = 0; q < 8; ++q) {
+        double x = acc[q];
 #pragma unroll
-      for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
-      if (lane == 0) part[(tid >> 6) * 8 + q] = x;
+        for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+        if (lane == 0) part[tid >> 6][q] = x;
+      }
+      __syncthreads();
+      if (tid < a.ndet) {
+        double sum = 0.0;
+        for (int i = 0; i < C::WAVES; ++i) sum += part[i][tid];
+        atomicAdd(a.img + tid * a.img_stride + a.wave_row[w], sum * a.scale);
+      }
+    } else if constexpr (MODE != PASS_GATHER) {
+      // ---- write the lines back, whole tiles, in place ------------------------------------
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < EPT; ++k) {
+        int lds, off;
+        M::at(k * NT + tid, stride_q, lds, off);
+        store_stream(item + off, tile[lds]);
+      }
     }
-    __syncthreads();
-    if (tid < a.ndet) {
-      double sum = 0.0;
-      for (int i = 0; i < WAVES; ++i) sum += part[i * 8 + tid];
-      atomicAdd(a.img + tid * a.img_stride + a.wave_row[w], sum * a.scale);
-    }
-  } else if constexpr (MODE != PASS_GATHER) {
-    __syncthreads();
-    // transposed store: out[w][x][row0 + r] for x < N, r < ROWS
-    constexpr int NT = WAVES * 64;
-    constexpr int XPER = NT / ROWS;
-    const int tr = tid % ROWS, tx = tid / ROWS;
-    float2* dst = a.out + (size_t)w * N * a.rows + row0 + tr;
-#pragma unroll 4
-    for (int x = tx; x < N; x += XPER) dst[(size_t)x * a.rows] = tile[tr * RS + slot_pos(x)];
   }
 }
 
@@ -520,94 +634,106 @@ hipError_t transmission(const float* v, float2* t, int64_t n, double sigma, hipS
   return hipGetLastError();
 }
 
-// wavefronts per block of the slice pass (tunable; clamped to what the size allows)
-static int g_pass_waves = 4;
-void set_pass_waves(int w) { g_pass_waves = w; }
-
-template <int N>
-constexpr int max_waves() {
-  using C = PassCfg<N>;
-  return C::WL ? C::ROWS / C::S : C::WPT;
+static int device_cus() {
+  static int cus = 0;
+  if (cus == 0) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+      cus = 256;
+  }
+  return cus;
 }
 
-template <int N, int WAVES, int MODE>
-static hipError_t pass_launch(const PassArgs& a, int B, hipStream_t s) {
-  const int groups = a.rows / PassCfg<N>::ROWS;
-  const unsigned grid = (unsigned)(B * groups);
-  k_pass<N, WAVES, MODE><<<grid, WAVES * 64, 0, s>>>(a);
+template <int N, int TW, int MODE>
+static hipError_t pass_launch(const PassArgs& a0, int lines, int B, hipStream_t s) {
+  if (lines % TW) return hipErrorInvalidValue;
+  constexpr int threads = PassCfg<N, TW>::WAVES * 64;
+  static int resident = 0;   // workgroups of this kernel resident per CU
+  if (resident == 0) {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)k_pass<N, TW, MODE>, threads, 0) != hipSuccess || nb <= 0)
+      nb = 1;
+    resident = nb;
+  }
+  PassArgs a = a0;
+  a.B = B;
+  const int64_t items = (int64_t)B * (lines / TW);
+  int64_t grid = std::min<int64_t>(items, (int64_t)resident * device_cus());
+  if (grid >= 8) grid &= ~(int64_t)7;
+  k_pass<N, TW, MODE><<<(unsigned)grid, threads, 0, s>>>(a);
   return hipGetLastError();
 }
 
-template <int N, int MODE>
-static hipError_t pass_waves(const PassArgs& a, int B, hipStream_t s) {
-  if (a.rows % PassCfg<N>::ROWS) return hipErrorInvalidValue;
-  constexpr int MW = max_waves<N>();
-  if constexpr (!PassCfg<N>::WL) {
-    return pass_launch<N, MW, MODE>(a, B, s);
-  } else {
-    int w = g_pass_waves;
-    if (w > MW) w = MW;
-    if constexpr (MW >= 16) { if (w >= 16) return pass_launch<N, 16, MODE>(a, B, s); }
-    if constexpr (MW >= 8) { if (w >= 8) return pass_launch<N, 8, MODE>(a, B, s); }
-    if constexpr (MW >= 4) { if (w >= 4) return pass_launch<N, 4, MODE>(a, B, s); }
-    if constexpr (MW >= 2) { if (w >= 2) return pass_launch<N, 2, MODE>(a, B, s); }
-    return pass_launch<N, 1, MODE>(a, B, s);
-  }
-}
-
 template <int MODE>
-static hipError_t pass_dispatch(int N, const PassArgs& a, int B, hipStream_t s) {
-  switch (N) {
-    case 16: return pass_waves<16, MODE>(a, B, s);
-    case 32: return pass_waves<32, MODE>(a, B, s);
-    case 64: return pass_waves<64, MODE>(a, B, s);
-    case 128: return pass_waves<128, MODE>(a, B, s);
-    case 256: return pass_waves<256, MODE>(a, B, s);
-    case 512: return pass_waves<512, MODE>(a, B, s);
-    case 1024: return pass_waves<1024, MODE>(a, B, s);
-    case 2048: return pass_waves<2048, MODE>(a, B, s);
+static hipError_t pass_dispatch(int N, int TW, int lines, const PassArgs& a, int B, hipStream_t s) {
+  if (TW == 16) {
+    switch (N) {
+      case 16: return pass_launch<16, 16, MODE>(a, lines, B, s);
+      case 32: return pass_launch<32, 16, MODE>(a, lines, B, s);
+      case 64: return pass_launch<64, 16, MODE>(a, lines, B, s);
+      case 128: return pass_launch<128, 16, MODE>(a, lines, B, s);
+      case 256: return pass_launch<256, 16, MODE>(a, lines, B, s);
+      case 512: return pass_launch<512, 16, MODE>(a, lines, B, s);
+    }
+  } else if (TW == 8) {
+    switch (N) {
+      case 16: return pass_launch<16, 8, MODE>(a, lines, B, s);
+      case 32: return pass_launch<32, 8, MODE>(a, lines, B, s);
+      case 64: return pass_launch<64, 8, MODE>(a, lines, B, s);
+      case 128: return pass_launch<128, 8, MODE>(a, lines, B, s);
+      case 256: return pass_launch<256, 8, MODE>(a, lines, B, s);
+      case 512: return pass_launch<512, 8, MODE>(a, lines, B, s);
+      case 1024: return pass_launch<1024, 8, MODE>(a, lines, B, s);
+      case 2048: return pass_launch<2048, 8, MODE>(a, lines, B, s);
+    }
   }
   return hipErrorInvalidValue;
 }
 
-hipError_t init_waves(const Tables& T, float2* out, const int64_t* wave_u, int B, hipStream_t s) {
+// 8 x 8 tiles (512 B) keep the LDS tile of a workgroup at ~41 KB for 512-point lines, so three
+// workgroups share a CU; 16 x 16 tiles (2 KB) measured slower on gfx950 and need N <= 512.
+static int g_tile_width = 0;   // 0: default; 8 or 16 forces a tile width (tuning)
+void set_tile_width(int tw) { g_tile_width = (tw == 8 || tw == 16) ? tw : 0; }
+int tile_width(int nx, int ny) {
+  if (nx > 512 || ny > 512) return 8;
+  return g_tile_width ? g_tile_width : 8;
+}
+
+static PassArgs pass_args(const Tables& T, float2* work) {
   PassArgs a{};
-  a.out = out;
-  a.rows = T.nx;
+  a.work = work;
+  a.nx = T.nx;
+  a.ny = T.ny;
+  a.Qx = T.Qx;
+  a.Qy = T.Qy;
+  return a;
+}
+
+hipError_t init_waves(const Tables& T, float2* work, const int64_t* wave_u, int B, hipStream_t s) {
+  PassArgs a = pass_args(T, work);
   a.table = T.specT;
   a.tw = T.twy;
   a.wave_u = wave_u;
-  a.Qx = T.Qx;
-  a.Qy = T.Qy;
-  a.nrow_freq = T.nx;
-  return pass_dispatch<PASS_INIT>(T.ny, a, B, s);
+  return pass_dispatch<PASS_INIT>(T.ny, tile_width(T.nx, T.ny), T.nx, a, B, s);
 }
 
-hipError_t row_pass(const Tables& T, const float2* in, float2* out, const float2* trans_j, int B, hipStream_t s) {
-  PassArgs a{};
-  a.in = in;
-  a.out = out;
-  a.rows = T.ny;
+hipError_t row_pass(const Tables& T, float2* work, const float2* trans_j, int B, hipStream_t s) {
+  PassArgs a = pass_args(T, work);
   a.table = trans_j;
   a.tw = T.twx;
-  return pass_dispatch<PASS_ROW>(T.nx, a, B, s);
+  return pass_dispatch<PASS_ROW>(T.nx, tile_width(T.nx, T.ny), T.ny, a, B, s);
 }
 
-hipError_t col_pass(const Tables& T, const float2* in, float2* out, int B, hipStream_t s) {
-  PassArgs a{};
-  a.in = in;
-  a.out = out;
-  a.rows = T.nx;
+hipError_t col_pass(const Tables& T, float2* work, int B, hipStream_t s) {
+  PassArgs a = pass_args(T, work);
   a.table = T.propT;
   a.tw = T.twy;
-  return pass_dispatch<PASS_COL>(T.ny, a, B, s);
+  return pass_dispatch<PASS_COL>(T.ny, tile_width(T.nx, T.ny), T.nx, a, B, s);
 }
 
-hipError_t col_gather(const Tables& T, const float2* in, int B, void* basis, int D, const int32_t* wave_row,
-                      int split, hipStream_t s) {
-  PassArgs a{};
-  a.in = in;
-  a.rows = T.nx;
+hipError_t col_gather(const Tables& T, float2* work, int B, void* basis, int D, const int32_t* wave_row, int split,
+                      hipStream_t s) {
+  PassArgs a = pass_args(T, work);
   a.table = T.propT;
   a.tw = T.twy;
   a.basis = basis;
@@ -615,14 +741,12 @@ hipError_t col_gather(const Tables& T, const float2* in, int B, void* basis, int
   a.comp = T.compT;
   a.wave_row = wave_row;
   a.split_bf16 = split;
-  return pass_dispatch<PASS_GATHER>(T.ny, a, B, s);
+  return pass_dispatch<PASS_GATHER>(T.ny, tile_width(T.nx, T.ny), T.nx, a, B, s);
 }
 
-hipError_t col_reduce(const Tables& T, const float2* in, int B, const int32_t* wave_out, double* img, int ndet,
+hipError_t col_reduce(const Tables& T, float2* work, int B, const int32_t* wave_out, double* img, int ndet,
                       int64_t img_stride, double scale, hipStream_t s) {
-  PassArgs a{};
-  a.in = in;
-  a.rows = T.nx;
+  PassArgs a = pass_args(T, work);
   a.table = T.propT;
   a.tw = T.twy;
   a.mask = T.maskT;
@@ -631,7 +755,7 @@ hipError_t col_reduce(const Tables& T, const float2* in, int B, const int32_t* w
   a.ndet = ndet;
   a.img_stride = img_stride;
   a.scale = scale;
-  return pass_dispatch<PASS_REDUCE>(T.ny, a, B, s);
+  return pass_dispatch<PASS_REDUCE>(T.ny, tile_width(T.nx, T.ny), T.nx, a, B, s);
 }
 
 template <int SPLIT, int PT>

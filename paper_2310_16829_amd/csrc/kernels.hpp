@@ -43,22 +43,23 @@ struct Contraction {
 bool supported(int nx, int ny);
 
 hipError_t transmission(const float* v, float2* t, int64_t n, double sigma, hipStream_t s);
-// Wave batches alternate between two layouts: A = [B][ny][nx] (mixed domain, y spatial,
-// x frequency) and At = [B][nx][ny].
-// initial waves u(. - pos_w) into A: column IFFT of spectrum * modulation
-hipError_t init_waves(const Tables& T, float2* outA, const int64_t* wave_u, int B, hipStream_t s);
-// row pass of slice j, A -> At: row IFFT, * t_j, row FFT
-hipError_t row_pass(const Tables& T, const float2* inA, float2* outAt, const float2* trans_j, int B, hipStream_t s);
-// column pass of a middle slice, At -> A: column FFT, * P, column IFFT
-hipError_t col_pass(const Tables& T, const float2* inAt, float2* outA, int B, hipStream_t s);
+// A wave batch is stored [B][ny/TW][nx/TW][TW][TW] (TW x TW tiles, TW = tile_width) and every
+// pass updates it in place. Between passes a wave is in the mixed domain (y spatial, x frequency).
+int tile_width(int nx, int ny);
+// forces the tile width (8 or 16; anything else restores the default), a tuning knob
+void set_tile_width(int tw);
+// initial waves u(. - pos_w): column IFFT of spectrum * modulation
+hipError_t init_waves(const Tables& T, float2* work, const int64_t* wave_u, int B, hipStream_t s);
+// row pass of slice j: row IFFT, * t_j, row FFT
+hipError_t row_pass(const Tables& T, float2* work, const float2* trans_j, int B, hipStream_t s);
+// column pass of a middle slice: column FFT, * P, column IFFT
+hipError_t col_pass(const Tables& T, float2* work, int B, hipStream_t s);
 // last column pass, LMA: column FFT, * P, keep the detector pixels as basis rows
-hipError_t col_gather(const Tables& T, const float2* inAt, int B, void* basis, int D,
-                      const int32_t* wave_row, int split_bf16, hipStream_t s);
+hipError_t col_gather(const Tables& T, float2* work, int B, void* basis, int D, const int32_t* wave_row,
+                      int split_bf16, hipStream_t s);
 // last column pass, plain: column FFT, * P, ring sums of |.|^2 added to img[r][wave_out[w]]
-hipError_t col_reduce(const Tables& T, const float2* inAt, int B, const int32_t* wave_out,
-                      double* img, int ndet, int64_t img_stride, double scale, hipStream_t s);
-// wavefronts per block of the slice passes (tuning knob)
-void set_pass_waves(int waves);
+hipError_t col_reduce(const Tables& T, float2* work, int B, const int32_t* wave_out, double* img, int ndet,
+                      int64_t img_stride, double scale, hipStream_t s);
 // probe-coefficient contraction and detector reduction
 hipError_t contract(const Contraction& c, hipStream_t s);
 // out = (acc ? out : 0) + w * img, n doubles, device memory

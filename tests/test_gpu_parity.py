@@ -210,6 +210,23 @@ def test_largest_grid_2048():
     image_errors(plan.plain_image(v), crop(plain_image(st, v, probes), plan), TOL32)
 
 
+def test_mixed_grid_1024_by_256():
+    # 1024 x 256: row transforms span several wavefronts, column transforms fit in one, and
+    # the waves are stored in 8 x 8 tiles
+    say("grid 1024 x 256, 3 slices")
+    w = WORKLOADS["tiny"]
+    nx, ny, lx, ly = 1024, 256, 102.4, 25.6
+    rng = np.random.default_rng(1024)
+    v = rng.uniform(0, 40, size=(3, ny, nx)).astype(np.float32)
+    plan, st, ol = build(w, nx=nx, ny=ny, lx=lx, ly=ly, scan=(128, 32), R=(256, 64), L=9,
+                         window=(60, 3, 3, 2), batch=3)
+    plan.propagate(v)
+    probes = window_probes(plan)
+    ref = crop(LMA(st, ol).image(v, probes), plan)
+    image_errors(plan.probe_image(), ref, TOL32)
+    image_errors(plan.plain_image(v), crop(plain_image(st, v, probes), plan), TOL32)
+
+
 def test_device_pointers_and_phonon_accumulation():
     import torch
     say("device pointers, phonon accumulation")
