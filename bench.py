@@ -115,6 +115,50 @@ def cpu_baseline(w, n_translates, n_probes):
     }
 
 
+def spacing_study(w):
+    """Speed and LMA-vs-plain error of the medium workload (configuration 0) at translate
+    spacings of 4, 8 and 16 px (0.4, 0.8, 1.6 A; the probe needs <= lambda/(2 alpha) = 0.63 A)."""
+    import numpy as np
+    import torch
+    import paper_2310_16829_amd as lma
+    from synth import potential_slices
+    v = torch.from_numpy(potential_slices(w, 0)).cuda()
+    lam, sig = lma.electron_constants(w.kv)
+    rings = [(a * 1e-3, b * 1e-3) for _, a, b in w.detectors]
+    opt = lma.optics(w.nx, w.ny, w.lx, w.ly, lam, sig, w.dz, w.bandlimit, w.alpha_mrad * 1e-3, w.defocus, w.cs)
+
+    def run(fn):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = fn()
+        torch.cuda.synchronize()
+        return out, time.perf_counter() - t0
+
+    base = lma.Plan(opt, lma.lattice(w.scan[0], w.scan[1], 128, 128, 1, (0.5, 0.5), w.L), lma.detectors(rings))
+    plain, t_plain = run(lambda: base.plain_image(v, device=True))
+    plain = plain.cpu().numpy()
+    base.close()
+    rows = []
+    for spacing_px, L in ((4, 144), (8, 144), (16, 148)):
+        R = w.nx // spacing_px
+        plan = lma.Plan(opt, lma.lattice(w.scan[0], w.scan[1], R, R, 1, (0.5, 0.5), L), lma.detectors(rings))
+
+        def step():
+            plan.propagate(v)
+            return plan.probe_image(device=True)
+        img, t = run(step)
+        img = img.cpu().numpy()
+        err = [float(np.linalg.norm(img[r] - plain[r]) / np.linalg.norm(plain[r])) for r in range(len(rings))]
+        rows.append({"spacing_px": spacing_px, "spacing_A": spacing_px * w.lx / w.nx, "L": L,
+                     "translates": plan.info().n_rows, "probe_residual": plan.info().max_residual,
+                     "seconds": t, "speedup_vs_plain": t_plain / t,
+                     "lma_vs_plain_rel_l2": dict(zip([d[0] for d in w.detectors], err))})
+        plan.close()
+    print(json.dumps({"study": "translate spacing, medium workload, configuration 0", "plain_seconds": t_plain,
+                      "rows": rows}), flush=True)
+
+
 # ------------------------------------------------------------------------------------------
 def main():
     ap = argparse.ArgumentParser()
@@ -126,6 +170,8 @@ def main():
     ap.add_argument("--batch", type=int, default=0)
     ap.add_argument("--no-kernel-timing", action="store_true",
                     help="skip the extra step that times every launch with hipEvents")
+    ap.add_argument("--spacing-study", action="store_true",
+                    help="LMA at translate spacings 4, 8, 16 px against plain multislice (one configuration)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device-to-device copy kernel (HBM counter calibration)")
     args = ap.parse_args()
@@ -150,6 +196,9 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     w = WORKLOADS[WORKLOAD]
+    if args.spacing_study:
+        spacing_study(w)
+        return
     K, W = args.steps, args.warmup
     n_cfg = w.n_phonons
     log(f"bench: generating {min(n_cfg, K + W + 1)} phonon potentials")
