@@ -160,6 +160,43 @@ def spacing_study(w):
 
 
 # ------------------------------------------------------------------------------------------
+FP32_MFMA_PEAK_TFLOPS = 157.3
+
+
+def contraction_roofline(plan, info, kt):
+    """Flop rate of the contraction launch. Algorithmic: 8 real flops per complex multiply-add,
+    |P| L D of them. Implemented (MFMA kernel): every 4 x 4-probe sub-block multiplies a 16 x K
+    coefficient block (K = contract_k translates, zero where a translate is not a neighbour)
+    into 16-pixel slabs of each detector-pixel chunk, four real 16x16x4 products per K-step of 4."""
+    name = "contract_mfma" if info.contract_kernel else "contract"
+    if name not in kt:
+        return None
+    launches, total_ms = kt[name]
+    avg_s = total_ms / launches * 1e-3
+    _, mask = plan.detector_pixels()
+    # chunks: runs of one ring mask in the sorted pixel list, cut every 256 pixels
+    slabs = 0
+    run = 1
+    for i in range(1, len(mask) + 1):
+        if i == len(mask) or mask[i] != mask[i - 1]:
+            full, rest = divmod(run, 256)
+            slabs += full * 16 + -(-rest // 16)
+            run = 1
+        else:
+            run += 1
+    alg = 8.0 * info.n_probes * info.L * info.n_pix
+    out = {"kernel": name, "avg_launch_ms": avg_s * 1e3, "algorithmic_tflop": alg / 1e12,
+           "useful_tflops": alg / avg_s / 1e12, "L": info.L, "K": info.contract_k}
+    if info.contract_kernel:
+        ww, wh = plan.window[2], plan.window[3]
+        sub_blocks = 4 * (-(-ww // 8)) * (-(-wh // 8))
+        impl = sub_blocks * slabs * (info.contract_k // 4) * 4 * (2 * 16 * 16 * 4)
+        out.update({"bound": "mfma", "implemented_tflop": impl / 1e12,
+                    "achieved": impl / avg_s / 1e12, "peak": FP32_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
+                    "frac": impl / avg_s / 1e12 / FP32_MFMA_PEAK_TFLOPS, "density": info.L / info.contract_k})
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -277,6 +314,7 @@ def main():
     avg_s = total_ms / launches * 1e-3
     achieved = bytes_per_launch / avg_s / 1e9
     traffic = load_traffic(dom)
+    contraction = contraction_roofline(plan, info, kt)
     out = {
         "metric": "STEM pixels/s, LMA vs plain multislice, same GPU at <=1e-4 rel err; p99 latency",
         "value": value,
@@ -306,6 +344,7 @@ def main():
                      "traffic": traffic,
                      "algorithmic_bytes_per_launch": bytes_per_launch,
                      "avg_launch_ms": avg_s * 1e3},
+        "contraction": contraction,
         "plan_build_s": t_build,
     }
     if not args.no_cpu_baseline:

@@ -55,7 +55,9 @@ enum { LMA_GEMM_FP32 = 0, LMA_GEMM_SPLIT_BF16 = 1 };
 enum {
   LMA_PTR_DEVICE = 1,        /* pointer arguments are device pointers                */
   LMA_ACCUMULATE = 2,        /* image += weight * I instead of image = weight * I     */
-  LMA_HOST_ONLY = 4          /* lma_build_basis: plan on the host, no device work     */
+  LMA_HOST_ONLY = 4,         /* lma_build_basis: plan on the host, no device work     */
+  LMA_CONTRACT_PER_PIXEL = 8 /* lma_probe_image: per-pixel VALU contraction even where  */
+                             /* the banded MFMA GEMM applies (a cross-check)          */
 };
 
 /* Microscope and grid: eqs. probe_wave_function, aberration_function, aperture_function,
@@ -85,7 +87,9 @@ typedef struct {
   int32_t precision;         /* LMA_GEMM_FP32 | LMA_GEMM_SPLIT_BF16                  */
   int32_t window[4];         /* scan window a0, b0, width, height (0,0,0,0 = all)    */
   int32_t batch;             /* waves per propagation batch (0 = automatic)          */
-  int64_t hbm_budget_bytes;  /* device-memory budget of the plan (0 = free memory)   */
+  int64_t hbm_budget_bytes;  /* bytes the resident basis may hold: M = budget/(D x 8) */
+                             /* propagated translates (Sec. 4.2.4); 0 = what free     */
+                             /* device memory holds after the plan's other buffers    */
 } lma_lattice;
 
 /* 2-D STEM detectors (Sec. 3.1, step 3): ring r collects lambda|k| in [inner, outer). */
@@ -113,6 +117,15 @@ typedef struct {
   int32_t host_only;
   double max_residual;       /* largest relative LSQ residual over the sets          */
   int64_t device_bytes;      /* device memory held by the plan                       */
+  int32_t contract_kernel;   /* window contraction: 1 = banded complex GEMM on MFMA   */
+                             /* (4 x 4-probe sub-blocks), 0 = per-pixel VALU sums      */
+  int32_t contract_k;        /* translates per probe the contraction multiplies:      */
+                             /* 4 x K-steps for MFMA (of which L are non-zero), L else */
+  int32_t partitioned;       /* 1: the window is formed in rectangles (lma_image)     */
+  int32_t n_parts;           /* rectangles P_1..P_l (1 when not partitioned)          */
+  int32_t part_w, part_h;    /* rectangle size in probes (edge ones clipped)           */
+  int64_t resident_rows;     /* basis rows held on the device                         */
+  int64_t multislice_calls;  /* translates propagated per image: T_{P_1..P_l}         */
 } lma_info;
 
 /* Per-kernel timing of the last timed calls (enable with lma_set_timing). */
@@ -149,8 +162,25 @@ lma_status lma_propagate(lma_plan* plan, const float* potential, int32_t nslices
  * psi_p^exit = sum_j alpha_{s(p),j} U_{i_j(p)} (eqs. lma_approximation_exit1/2) and
  * I_r(p) = sum over ring r of |F(psi_p^exit)|^2 / (XY).
  * image: double [n_det][h][w] of the window; image = weight*I, or += with LMA_ACCUMULATE
- * (frozen-phonon averaging: weight = 1/n_phonons). Needs a valid basis. */
+ * (frozen-phonon averaging: weight = 1/n_phonons). Needs a valid basis.
+ * The combination runs as a banded complex GEMM on MFMA (FP32 products, FP32 sums over the
+ * neighbours, FP64 ring sums) when lma_info.contract_kernel is 1, else (or with
+ * LMA_CONTRACT_PER_PIXEL) as per-pixel sums on the vector units; both give the same
+ * result up to FP32 rounding order. */
 lma_status lma_probe_image(lma_plan* plan, double* image, int32_t flags, double weight);
+
+/* The whole LMA image of the window in one call (steps 1 and 2 of Fig. lma_pseudocode and
+ * the detector). A plan whose window needs more propagated translates than the residency
+ * budget holds is partitioned at lma_build_basis (lma_info.partitioned = 1) into rectangles
+ * of probes P_1..P_l (Sec. 4.2.4, rectangle strategy, row-major): for each rectangle the
+ * translates it shares with the previous one stay resident, the others are propagated into
+ * the freed rows, then the rectangle's probes are formed; lma_info.multislice_calls gives
+ * the number of propagated translates, T_{P_1..P_l}. Such a plan has no complete resident
+ * basis: lma_propagate, lma_probe_image and lma_recompute_local return LMA_ERR_STATE. On a
+ * plan that is not partitioned this equals lma_propagate followed by lma_probe_image.
+ * potential, image, flags and weight as for lma_plain_image. */
+lma_status lma_image(lma_plan* plan, const float* potential, int32_t nslices, double* image,
+                     int32_t flags, double weight);
 
 /* Plain multislice comparator (Sec. 3.1 steps 1-3): every probe of the window propagated
  * directly, same kernels, same detectors, same image layout and flags as lma_probe_image.

@@ -11,7 +11,9 @@ rectangles (the greedy one draws a random start and is not reproducible from the
 
 Reading of the rectangle strategy: among all rectangle shapes w x h, take the one of
 largest area (ties: the wider one) whose every tile in the row-major tiling of the
-region, edge tiles clipped, satisfies |I_{f,P_j,L}| <= M.
+region, edge tiles clipped, satisfies |I_{f,P_j,L}| <= M. A device may restrict the
+shapes to sides that are multiples of a granule (gx, gy), or the whole region side;
+granule (1, 1) is the strategy as the paper states it.
 """
 from __future__ import annotations
 
@@ -50,12 +52,17 @@ def row_by_row(sets_by_probe, region, M: int):
     return parts
 
 
-def rectangles(sets_by_probe, region, M: int):
+def rectangles(sets_by_probe, region, M: int, granule=(1, 1)):
     """Strategy 2 (reading in the module docstring). Returns the parts, row-major."""
     a0, b0, wd, ht = region
+    gx, gy = granule
     best = None
     for h in range(1, ht + 1):
+        if h % gy and h != ht:
+            continue
         for w in range(1, wd + 1):
+            if w % gx and w != wd:
+                continue
             if best is not None and w * h < best[0] * best[1]:
                 continue
             parts = _tiling(region, w, h)

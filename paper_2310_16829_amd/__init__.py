@@ -12,12 +12,12 @@ import ctypes as C
 import numpy as np
 
 from . import _lib
-from ._lib import (LMA_ACCUMULATE, LMA_BASIS_PROBE, LMA_GEMM_FP32, LMA_GEMM_SPLIT_BF16, LMA_HOST_ONLY,
-                   LMA_PTR_DEVICE, lma_detectors, lma_info, lma_kernel_time, lma_lattice, lma_optics)
+from ._lib import (LMA_ACCUMULATE, LMA_BASIS_PROBE, LMA_CONTRACT_PER_PIXEL, LMA_GEMM_FP32, LMA_GEMM_SPLIT_BF16,
+                   LMA_HOST_ONLY, LMA_PTR_DEVICE, lma_detectors, lma_info, lma_kernel_time, lma_lattice, lma_optics)
 
 __all__ = ["LmaError", "Plan", "electron_constants", "footprint", "optics", "lattice", "detectors",
            "LMA_ACCUMULATE", "LMA_PTR_DEVICE", "LMA_HOST_ONLY", "LMA_GEMM_FP32", "LMA_GEMM_SPLIT_BF16",
-           "LMA_BASIS_PROBE", "lib"]
+           "LMA_BASIS_PROBE", "LMA_CONTRACT_PER_PIXEL", "lib"]
 
 
 class LmaError(RuntimeError):
@@ -160,6 +160,15 @@ class Plan:
         image = self._image_out(image, device)
         p, f = _ptr(image, np.float64)
         _check(lib().lma_probe_image(self._h, p, int(flags) | f, float(weight)))
+        return image
+
+    def image(self, potential, image=None, flags: int = 0, weight: float = 1.0, device: bool = False):
+        pp, fp = _ptr(potential, np.float32)
+        image = self._image_out(image, device)
+        pi, fi = _ptr(image, np.float64)
+        if fp != fi:
+            raise ValueError("potential and image must both be host or both be device")
+        _check(lib().lma_image(self._h, pp, int(potential.shape[0]), pi, int(flags) | fi, float(weight)))
         return image
 
     def plain_image(self, potential, image=None, flags: int = 0, weight: float = 1.0, device: bool = False):

@@ -10,7 +10,7 @@ LIB_PATH = os.path.join(_HERE, "liblma.so")
 LMA_OK, LMA_ERR_ARG, LMA_ERR_OOM, LMA_ERR_DEVICE, LMA_ERR_STATE, LMA_ERR_UNSUPPORTED = 0, -1, -2, -3, -4, -5
 LMA_BASIS_PROBE = 0
 LMA_GEMM_FP32, LMA_GEMM_SPLIT_BF16 = 0, 1
-LMA_PTR_DEVICE, LMA_ACCUMULATE, LMA_HOST_ONLY = 1, 2, 4
+LMA_PTR_DEVICE, LMA_ACCUMULATE, LMA_HOST_ONLY, LMA_CONTRACT_PER_PIXEL = 1, 2, 4, 8
 
 
 class lma_optics(C.Structure):
@@ -37,7 +37,9 @@ class lma_info(C.Structure):
                 ("L", C.c_int32), ("n_det", C.c_int32), ("n_pix", C.c_int32), ("n_probes", C.c_int32),
                 ("n_rows", C.c_int32), ("batch", C.c_int32), ("n_aperture", C.c_int32),
                 ("basis_valid", C.c_int32), ("host_only", C.c_int32), ("max_residual", C.c_double),
-                ("device_bytes", C.c_int64)]
+                ("device_bytes", C.c_int64), ("contract_kernel", C.c_int32), ("contract_k", C.c_int32),
+                ("partitioned", C.c_int32), ("n_parts", C.c_int32), ("part_w", C.c_int32), ("part_h", C.c_int32),
+                ("resident_rows", C.c_int64), ("multislice_calls", C.c_int64)]
 
 
 class lma_kernel_time(C.Structure):
@@ -53,6 +55,7 @@ SIGNATURES = {
     "lma_propagate": (C.c_int, [P, P, C.c_int32, C.c_int32]),
     "lma_probe_image": (C.c_int, [P, P, C.c_int32, C.c_double]),
     "lma_plain_image": (C.c_int, [P, P, C.c_int32, P, C.c_int32, C.c_double]),
+    "lma_image": (C.c_int, [P, P, C.c_int32, P, C.c_int32, C.c_double]),
     "lma_recompute_local": (C.c_int, [P, P, C.c_int32, C.POINTER(C.c_int32), C.c_double, P,
                                       C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
     "lma_footprint": (C.c_int, [C.POINTER(lma_optics), C.POINTER(lma_lattice), C.POINTER(lma_detectors),

@@ -16,7 +16,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "liblma.so")
 
-HOST_SOURCES = ["planner.cpp", "lsq.cpp"]
+HOST_SOURCES = ["planner.cpp", "lsq.cpp", "stencil.cpp", "partition.cpp"]
 HIP_SOURCES = ["kernels.hip", "abi.hip"]
 ARCH = "gfx950"
 

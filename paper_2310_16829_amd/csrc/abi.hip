@@ -59,6 +59,17 @@ struct lma_plan {
   int32_t *d_chunk_start = nullptr, *d_chunk_len = nullptr;
   uint32_t* d_chunk_mask = nullptr;
   float2* d_alpha = nullptr;
+  lma::StencilPlan st;               // the window's contraction as a banded GEMM (if it applies)
+  int32_t* d_ks_off = nullptr;
+  float2* d_stencil_a = nullptr;
+  // rectangle partition when the window's basis exceeds the residency budget
+  bool partitioned = false;
+  lma::PartPlan pp;
+  int32_t* d_part_row_of = nullptr;  // [parts][Rfy*Rfx]
+  int64_t* d_part_u = nullptr;       // fresh translate positions of every part, in part order
+  int32_t* d_part_slot = nullptr;    // their resident rows
+  int32_t* d_part_probes = nullptr;  // window probe indices of every part (per-pixel contraction)
+  std::vector<int64_t> part_fresh_off, part_probe_off;
   int64_t* d_row_u = nullptr;        // [n_rows][2] translate positions in lattice units
   int32_t* d_row_id = nullptr;       // [n_rows] 0..n_rows-1
   int64_t* d_probe_u = nullptr;      // [n_probes][2]
@@ -93,8 +104,6 @@ namespace {
 
 lma_status dalloc(lma_plan* p, void** ptr, size_t bytes) {
   if (bytes == 0) bytes = 16;
-  if (p->h.lat.hbm_budget_bytes > 0 && p->dev_bytes + (int64_t)bytes > p->h.lat.hbm_budget_bytes)
-    return fail(LMA_ERR_OOM, "device-memory budget exceeded");
   hipError_t e = hipMalloc(ptr, bytes);
   if (e != hipSuccess) {
     (void)hipGetLastError();
@@ -310,6 +319,43 @@ lma::dev::Contraction contraction(const lma_plan* p) {
   return c;
 }
 
+lma::dev::Stencil stencil(const lma_plan* p) {
+  const HostPlan& h = p->h;
+  const lma::StencilPlan& st = p->st;
+  lma::dev::Stencil c;
+  c.basis = p->d_basis;
+  c.split_bf16 = h.lat.precision == LMA_GEMM_SPLIT_BF16;
+  c.D = h.D();
+  c.row_of = p->d_row_of;
+  c.Rfx = h.Rfx;
+  c.Rfy = h.Rfy;
+  c.nks = st.nks;
+  c.W = st.W;
+  c.H = st.H;
+  c.ox0 = st.ox0;
+  c.oy0 = st.oy0;
+  c.tile_dx = st.tile_dx;
+  c.tile_dy = st.tile_dy;
+  c.sub_dx = st.sub_dx;
+  c.sub_dy = st.sub_dy;
+  c.tiles_x = st.tiles_x;
+  c.tiles_y = st.tiles_y;
+  c.tile_x0 = 0;
+  c.tile_y0 = 0;
+  c.ks_off = p->d_ks_off;
+  c.a = p->d_stencil_a;
+  c.ww = h.ww;
+  c.wh = h.wh;
+  c.chunk_start = p->d_chunk_start;
+  c.chunk_len = p->d_chunk_len;
+  c.chunk_mask = p->d_chunk_mask;
+  c.nchunks = (int)h.chunk_start.size();
+  c.ndet = h.ndet;
+  c.scale = (double)h.op.nx * h.op.ny;
+  c.img = p->d_img;
+  return c;
+}
+
 lma_status write_image(lma_plan* p, double* image, int32_t flags, double weight) {
   const int64_t n = (int64_t)p->h.ndet * p->h.n_probes();
   if (flags & LMA_PTR_DEVICE) {
@@ -410,27 +456,41 @@ lma_status lma_build_basis(const lma_optics* optics, const lma_lattice* lattice,
     p->host_only = (flags & LMA_HOST_ONLY) != 0;
     p->stream = reinterpret_cast<hipStream_t>(hip_stream);
     const HostPlan& h = p->h;
+    lma::build_stencil(h, lma::dev::kStencilMaxKs, lma::dev::kStencilMaxRect, &p->st);
     p->B = std::max(1, std::min<int>(auto_batch(h), (int)std::max<int64_t>(std::max<int64_t>((int64_t)h.rows.size(), h.n_probes()), 1)));
+    if (!p->host_only && hipGetDevice(&p->device) != hipSuccess) {
+      delete p;
+      return fail(LMA_ERR_DEVICE, "no HIP device");
+    }
+    // residency (Sec. 4.2.4): the whole window's basis, or a rectangle partition when it needs
+    // more than M = budget / (D x 8 B) propagated translates
+    {
+      const int64_t row_bytes = (int64_t)h.D() * 8;
+      int64_t max_rows = -1;
+      if (h.lat.hbm_budget_bytes > 0) {
+        max_rows = h.lat.hbm_budget_bytes / row_bytes;
+      } else if (!p->host_only) {
+        size_t fr = 0, tot = 0;
+        if (hipMemGetInfo(&fr, &tot) == hipSuccess) {
+          const int64_t spare = (int64_t)fr - footprint_of(h, p->B, 1, false) - ((int64_t)256 << 20);
+          max_rows = std::max<int64_t>(0, spare / row_bytes);
+        }
+      }
+      if (max_rows >= 0 && (int64_t)h.rows.size() > max_rows) {
+        std::string why;
+        const int gx = p->st.ok ? 8 : h.ncls_x, gy = p->st.ok ? 8 : h.ncls_y;
+        if (!lma::build_partition(h, max_rows, gx, gy, &p->pp, &why)) {
+          delete p;
+          return fail(LMA_ERR_OOM, why);
+        }
+        p->partitioned = true;
+      }
+    }
     if (p->host_only) {
       *out = p;
       return LMA_OK;
     }
-    if (hipGetDevice(&p->device) != hipSuccess) {
-      delete p;
-      return fail(LMA_ERR_DEVICE, "no HIP device");
-    }
     const int64_t XY = (int64_t)h.op.nx * h.op.ny;
-    if (h.lat.hbm_budget_bytes == 0) {
-      size_t fr = 0, tot = 0;
-      if (hipMemGetInfo(&fr, &tot) == hipSuccess) {
-        int64_t need = footprint_of(h, p->B, 1, true);
-        if (need > (int64_t)fr) {
-          release(p);
-          return fail(LMA_ERR_OOM, "the resident basis and wave batch exceed free device memory (" +
-                                       std::to_string(need) + " > " + std::to_string(fr) + " bytes)");
-        }
-      }
-    }
     // tables; those read by column passes are transposed to [kx][ky]
     const int nx = h.op.nx, ny = h.op.ny;
     std::vector<float2> v((size_t)XY);
@@ -467,6 +527,12 @@ lma_status lma_build_basis(const lma_optics* optics, const lma_lattice* lattice,
     std::vector<float2> al(h.alpha.size());
     for (size_t i = 0; i < al.size(); ++i) al[i] = make_float2((float)h.alpha[i].real(), (float)h.alpha[i].imag());
     if ((s = upload(p, &p->d_alpha, al.data(), al.size())) != LMA_OK) { release(p); return s; }
+    if (p->st.ok) {
+      std::vector<float2> sa(p->st.a.size());
+      for (size_t i = 0; i < sa.size(); ++i) sa[i] = make_float2(p->st.a[i].real(), p->st.a[i].imag());
+      if ((s = upload(p, &p->d_stencil_a, sa.data(), sa.size())) != LMA_OK) { release(p); return s; }
+      if ((s = upload(p, &p->d_ks_off, p->st.ks_off.data(), p->st.ks_off.size())) != LMA_OK) { release(p); return s; }
+    }
     // wave position lists
     std::vector<int64_t> ru(h.rows.size() * 2);
     std::vector<int32_t> rid(h.rows.size());
@@ -492,7 +558,36 @@ lma_status lma_build_basis(const lma_optics* optics, const lma_lattice* lattice,
     // buffers
     if ((s = dalloc(p, (void**)&p->d_img, (size_t)h.ndet * h.n_probes() * sizeof(double))) != LMA_OK) { release(p); return s; }
     if ((s = dalloc(p, (void**)&p->d_work, (size_t)p->B * XY * sizeof(float2))) != LMA_OK) { release(p); return s; }
-    if ((s = dalloc(p, &p->d_basis, (size_t)h.rows.size() * h.D() * 8)) != LMA_OK) { release(p); return s; }
+    if (p->partitioned) {
+      const lma::PartPlan& pp = p->pp;
+      const size_t NT = (size_t)h.n_translates();
+      std::vector<int32_t> row_of(pp.parts.size() * NT), slot, probes;
+      std::vector<int64_t> u;
+      p->part_fresh_off.assign(1, 0);
+      p->part_probe_off.assign(1, 0);
+      for (size_t j = 0; j < pp.parts.size(); ++j) {
+        const lma::PartPlan::Part& q = pp.parts[j];
+        std::copy(q.row_of.begin(), q.row_of.end(), row_of.begin() + j * NT);
+        for (size_t i = 0; i < q.fresh.size(); ++i) {
+          const int t = q.fresh[i];
+          u.push_back(((t % h.Rfx) * h.stepTx + h.oxu) % h.Qx);
+          u.push_back(((t / h.Rfx) * h.stepTy + h.oyu) % h.Qy);
+          slot.push_back(q.fresh_slot[i]);
+        }
+        p->part_fresh_off.push_back((int64_t)slot.size());
+        if (!p->st.ok)
+          for (int b = q.b0; b < q.b0 + q.h; ++b)
+            for (int a = q.a0; a < q.a0 + q.w; ++a) probes.push_back(b * h.ww + a);
+        p->part_probe_off.push_back((int64_t)probes.size());
+      }
+      if ((s = upload(p, &p->d_part_row_of, row_of.data(), row_of.size())) != LMA_OK) { release(p); return s; }
+      if ((s = upload(p, &p->d_part_u, u.data(), u.size())) != LMA_OK) { release(p); return s; }
+      if ((s = upload(p, &p->d_part_slot, slot.data(), slot.size())) != LMA_OK) { release(p); return s; }
+      if ((s = upload(p, &p->d_part_probes, probes.data(), probes.size())) != LMA_OK) { release(p); return s; }
+      if ((s = dalloc(p, &p->d_basis, (size_t)pp.slots * h.D() * 8)) != LMA_OK) { release(p); return s; }
+    } else {
+      if ((s = dalloc(p, &p->d_basis, (size_t)h.rows.size() * h.D() * 8)) != LMA_OK) { release(p); return s; }
+    }
     *out = p;
     return LMA_OK;
   } catch (const std::bad_alloc&) {
@@ -515,6 +610,9 @@ static lma_status check_device_call(lma_plan* p, const void* ptr, int32_t nslice
 lma_status lma_propagate(lma_plan* plan, const float* potential, int32_t nslices, int32_t flags) {
   lma_status s = check_device_call(plan, potential, nslices);
   if (s != LMA_OK) return s;
+  if (plan->partitioned)
+    return fail(LMA_ERR_STATE, "the window's basis exceeds the residency budget: the plan is partitioned "
+                               "into rectangles, use lma_image");
   plan->basis_valid = false;
   try {
     if ((s = prepare_transmission(plan, potential, nslices, flags)) != LMA_OK) return s;
@@ -534,7 +632,55 @@ lma_status lma_probe_image(lma_plan* plan, double* image, int32_t flags, double 
   if (!std::isfinite(weight)) return fail(LMA_ERR_ARG, "weight must be finite");
   try {
     HIP_TRY(hipMemsetAsync(plan->d_img, 0, (size_t)plan->h.ndet * plan->h.n_probes() * sizeof(double), plan->stream));
-    LAUNCH(plan, "contract", lma::dev::contract(contraction(plan), plan->stream));
+    if (plan->st.ok && !(flags & LMA_CONTRACT_PER_PIXEL))
+      LAUNCH(plan, "contract_mfma", lma::dev::contract_stencil(stencil(plan), plan->stream));
+    else
+      LAUNCH(plan, "contract", lma::dev::contract(contraction(plan), plan->stream));
+    return write_image(plan, image, flags, weight);
+  } catch (const std::exception& e) {
+    return fail(LMA_ERR_DEVICE, e.what());
+  }
+}
+
+lma_status lma_image(lma_plan* plan, const float* potential, int32_t nslices, double* image, int32_t flags,
+                     double weight) {
+  lma_status s = check_device_call(plan, potential, nslices);
+  if (s != LMA_OK) return s;
+  if (!image) return fail(LMA_ERR_ARG, "image is null");
+  if (!std::isfinite(weight)) return fail(LMA_ERR_ARG, "weight must be finite");
+  if (!plan->partitioned) {
+    if ((s = lma_propagate(plan, potential, nslices, flags)) != LMA_OK) return s;
+    return lma_probe_image(plan, image, flags, weight);
+  }
+  const HostPlan& h = plan->h;
+  plan->basis_valid = false;
+  try {
+    if ((s = prepare_transmission(plan, potential, nslices, flags)) != LMA_OK) return s;
+    HIP_TRY(hipMemsetAsync(plan->d_img, 0, (size_t)h.ndet * h.n_probes() * sizeof(double), plan->stream));
+    const size_t NT = (size_t)h.n_translates();
+    for (size_t j = 0; j < plan->pp.parts.size(); ++j) {
+      const lma::PartPlan::Part& q = plan->pp.parts[j];
+      const int64_t f0 = plan->part_fresh_off[j], nf = plan->part_fresh_off[j + 1] - f0;
+      // step 1 for the translates this rectangle adds to the resident set
+      if (nf > 0 && (s = run_waves(plan, plan->d_part_u + 2 * f0, plan->d_part_slot + f0, nullptr, (int)nf, nslices)) != LMA_OK)
+        return s;
+      // step 2 and the detector for the rectangle's probes
+      if (plan->st.ok) {
+        lma::dev::Stencil c = stencil(plan);
+        c.row_of = plan->d_part_row_of + j * NT;
+        c.tile_x0 = q.a0 / 8;
+        c.tile_y0 = q.b0 / 8;
+        c.tiles_x = (q.w + 7) / 8;
+        c.tiles_y = (q.h + 7) / 8;
+        LAUNCH(plan, "contract_mfma", lma::dev::contract_stencil(c, plan->stream));
+      } else {
+        lma::dev::Contraction c = contraction(plan);
+        c.row_of = plan->d_part_row_of + j * NT;
+        c.probe_list = plan->d_part_probes + plan->part_probe_off[j];
+        c.n_list = (int)(plan->part_probe_off[j + 1] - plan->part_probe_off[j]);
+        LAUNCH(plan, "contract", lma::dev::contract(c, plan->stream));
+      }
+    }
     return write_image(plan, image, flags, weight);
   } catch (const std::exception& e) {
     return fail(LMA_ERR_DEVICE, e.what());
@@ -669,6 +815,14 @@ lma_status lma_plan_info(const lma_plan* p, lma_info* out) {
   out->host_only = p->host_only ? 1 : 0;
   out->max_residual = h.residual.empty() ? 0.0 : *std::max_element(h.residual.begin(), h.residual.end());
   out->device_bytes = p->dev_bytes;
+  out->partitioned = p->partitioned ? 1 : 0;
+  out->n_parts = p->partitioned ? (int32_t)p->pp.parts.size() : 1;
+  out->part_w = p->partitioned ? p->pp.w : h.ww;
+  out->part_h = p->partitioned ? p->pp.h : h.wh;
+  out->resident_rows = p->partitioned ? p->pp.slots : (int64_t)h.rows.size();
+  out->multislice_calls = p->partitioned ? p->pp.multislice_calls : (int64_t)h.rows.size();
+  out->contract_kernel = p->st.ok ? 1 : 0;
+  out->contract_k = p->st.ok ? 4 * p->st.nks : (int32_t)h.lat.L;
   return LMA_OK;
 }
 

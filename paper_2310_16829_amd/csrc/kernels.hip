@@ -613,6 +613,107 @@ __global__ __launch_bounds__(kCT) void k_contract(Contraction c) {
   }
 }
 
+// ------------------------------------------------------------------------------------------
+// contraction of a whole window as a banded complex GEMM on MFMA (v_mfma_f32_16x16x4f32):
+//   C[probe m][pixel n] = sum_k A[m][k] B[k][n]
+// A: alpha of the 16 probes of a 4 x 4 sub-block against the K translates of the union of
+// their neighbour sets (zero where a translate is not a probe's neighbour), held in registers
+// for the whole workgroup; B: the basis rows of the super-tile's translate rectangle at 16
+// detector pixels, staged in LDS. Fragment layouts of the 16x16x4 instruction: lane l holds
+// A[l % 16][k0 + l / 16] and B[k0 + l / 16][l % 16]; the accumulator holds
+// C[4 (l / 16) + r][l % 16], r < 4. Complex products take four real MFMAs:
+//   Re C += Re A Re B - Im A Im B,  Im C += Re A Im B + Im A Re B.
+// ------------------------------------------------------------------------------------------
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+template <int SPLIT, int KS>
+__global__ __launch_bounds__(256) void k_contract_mfma(Stencil c) {
+  extern __shared__ unsigned char dyn[];
+  const int nt = c.W * c.H;
+  float2* slab = reinterpret_cast<float2*>(dyn);                          // [nt][16]
+  int32_t* rowid = reinterpret_cast<int32_t*>(slab + (size_t)nt * 16);    // [nt]
+  const int ti = c.tile_x0 + (int)blockIdx.x % c.tiles_x, tj = c.tile_y0 + (int)blockIdx.x / c.tiles_x;
+  const int chunk = blockIdx.y;
+  const int ox = (c.ox0 + ti * c.tile_dx) % c.Rfx;
+  const int oy = (c.oy0 + tj * c.tile_dy) % c.Rfy;
+  for (int t = threadIdx.x; t < nt; t += 256) {
+    const int x = t % c.W, y = t / c.W;
+    rowid[t] = c.row_of[((oy + y) % c.Rfy) * c.Rfx + (ox + x) % c.Rfx];
+  }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int kk = lane >> 4, n = lane & 15;
+  float2 A[KS];
+#pragma unroll
+  for (int ks = 0; ks < KS; ++ks) A[ks] = ks < c.nks ? c.a[ks * 64 + lane] : make_float2(0.f, 0.f);
+  // rectangle index of this lane's B element at K-step ks is base + ks_off[ks]
+  const int base = (wv >> 1) * c.sub_dy * c.W + (wv & 1) * c.sub_dx + kk;
+  const int start = c.chunk_start[chunk], len = c.chunk_len[chunk];
+  const uint32_t mask = c.chunk_mask[chunk];
+  double val[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int d0 = 0; d0 < len; d0 += 16) {
+    __syncthreads();  // row ids written, previous slab consumed
+    const int rem = len - d0;
+    // fill the slab with kFill loads in flight per thread
+    constexpr int kFill = 8;
+    for (int i0 = threadIdx.x; i0 < nt * 16; i0 += 256 * kFill) {
+      float2 v[kFill];
+#pragma unroll
+      for (int u = 0; u < kFill; ++u) {
+        const int i = i0 + u * 256;
+        v[u] = make_float2(0.f, 0.f);
+        if (i < nt * 16) {
+          const int t = i >> 4, q = i & 15;
+          const int r = rowid[t];
+          // a translate the window does not need is not resident: it only meets zero coefficients
+          if (r >= 0 && q < rem) v[u] = load_basis<SPLIT>(c.basis, (int64_t)r * c.D + start + d0 + q);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kFill; ++u) {
+        const int i = i0 + u * 256;
+        if (i < nt * 16) slab[i] = v[u];
+      }
+    }
+    __syncthreads();
+    f32x4 cre = {0.f, 0.f, 0.f, 0.f}, cim = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      if (ks < c.nks) {
+        const float2 b = slab[(base + c.ks_off[ks]) * 16 + n];
+        cre = __builtin_amdgcn_mfma_f32_16x16x4f32(A[ks].x, b.x, cre, 0, 0, 0);
+        cim = __builtin_amdgcn_mfma_f32_16x16x4f32(A[ks].x, b.y, cim, 0, 0, 0);
+        cre = __builtin_amdgcn_mfma_f32_16x16x4f32(-A[ks].y, b.y, cre, 0, 0, 0);
+        cim = __builtin_amdgcn_mfma_f32_16x16x4f32(A[ks].y, b.x, cim, 0, 0, 0);
+      }
+    }
+    if (n < rem) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) val[r] += (double)cre[r] * cre[r] + (double)cim[r] * cim[r];
+    }
+  }
+  // ring sum over the 16 pixel lanes of each probe row
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    double x = val[r];
+#pragma unroll
+    for (int o = 8; o > 0; o >>= 1) x += __shfl_xor(x, o);
+    val[r] = x;
+  }
+  if (n == 0) {
+    const int by = tj * 8 + (wv >> 1) * 4 + kk;
+    const int64_t stride = (int64_t)c.ww * c.wh;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int bx = ti * 8 + (wv & 1) * 4 + r;
+      if (bx < c.ww && by < c.wh) {
+        const double v = val[r] * c.scale;
+        for (int d = 0; d < c.ndet; ++d)
+          if (mask & (1u << d)) atomicAdd(c.img + (int64_t)d * stride + (int64_t)by * c.ww + bx, v);
+      }
+    }
+  }
+}
+
 __global__ void k_scale_out(double* out, const double* img, int64_t n, double w, int acc) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
@@ -773,6 +874,34 @@ hipError_t contract(const Contraction& c, hipStream_t s) {
   const bool wide = (size_t)8 * c.L * (sizeof(int64_t) + sizeof(float2)) <= 60 * 1024;
   if (c.split_bf16) return wide ? contract_pt<1, 8>(c, np, s) : contract_pt<1, 1>(c, np, s);
   return wide ? contract_pt<0, 8>(c, np, s) : contract_pt<0, 1>(c, np, s);
+}
+
+template <int SPLIT, int KS>
+static hipError_t stencil_ks(const Stencil& c, hipStream_t s) {
+  const size_t shm = (size_t)c.W * c.H * (16 * sizeof(float2) + sizeof(int32_t));
+  const void* fn = reinterpret_cast<const void*>(&k_contract_mfma<SPLIT, KS>);
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+  if (e != hipSuccess) return e;
+  dim3 grid((unsigned)(c.tiles_x * c.tiles_y), (unsigned)c.nchunks);
+  k_contract_mfma<SPLIT, KS><<<grid, 256, shm, s>>>(c);
+  return hipGetLastError();
+}
+
+template <int SPLIT>
+static hipError_t stencil_split(const Stencil& c, hipStream_t s) {
+  if (c.nks <= 16) return stencil_ks<SPLIT, 16>(c, s);
+  if (c.nks <= 32) return stencil_ks<SPLIT, 32>(c, s);
+  if (c.nks <= 48) return stencil_ks<SPLIT, 48>(c, s);
+  if (c.nks <= 64) return stencil_ks<SPLIT, 64>(c, s);
+  if (c.nks <= 80) return stencil_ks<SPLIT, 80>(c, s);
+  return stencil_ks<SPLIT, 96>(c, s);
+}
+
+hipError_t contract_stencil(const Stencil& c, hipStream_t s) {
+  if (c.tiles_x <= 0 || c.tiles_y <= 0 || c.nchunks <= 0) return hipSuccess;
+  if (c.nks <= 0 || c.nks > kStencilMaxKs || c.W * c.H > kStencilMaxRect || c.W <= 0 || c.H <= 0)
+    return hipErrorInvalidValue;
+  return c.split_bf16 ? stencil_split<1>(c, s) : stencil_split<0>(c, s);
 }
 
 hipError_t scale_out(double* out, const double* img, int64_t n, double w, int acc, hipStream_t s) {

@@ -40,6 +40,34 @@ struct Contraction {
   int n_list = 0;
 };
 
+// The contraction of a whole window as a banded complex GEMM on MFMA (layout built on the host
+// by build_stencil): one workgroup per (8 x 8-probe super-tile, detector-pixel chunk).
+struct Stencil {
+  const void* basis = nullptr;       // as in Contraction
+  int split_bf16 = 0;
+  int D = 0;
+  const int32_t* row_of = nullptr;
+  int Rfx = 0, Rfy = 0;
+  int nks = 0;                       // K-steps per 4 x 4 sub-block
+  int W = 0, H = 0;                  // translate rectangle of a super-tile
+  int ox0 = 0, oy0 = 0, tile_dx = 0, tile_dy = 0, sub_dx = 0, sub_dy = 0;
+  int tiles_x = 0, tiles_y = 0;      // super-tiles of the launch: tile_x0 + [0, tiles_x) x tile_y0 + [0, tiles_y)
+  int tile_x0 = 0, tile_y0 = 0;
+  const int32_t* ks_off = nullptr;   // [nks]
+  const float2* a = nullptr;         // [nks][64] A fragments
+  int ww = 0, wh = 0;
+  const int32_t* chunk_start = nullptr;
+  const int32_t* chunk_len = nullptr;
+  const uint32_t* chunk_mask = nullptr;
+  int nchunks = 0;
+  int ndet = 0;
+  double scale = 1.0;
+  double* img = nullptr;             // [ndet][wh][ww]
+};
+// largest K-step count and translate rectangle the MFMA contraction accepts
+constexpr int kStencilMaxKs = 96;
+constexpr int kStencilMaxRect = 1152;
+
 bool supported(int nx, int ny);
 
 hipError_t transmission(const float* v, float2* t, int64_t n, double sigma, hipStream_t s);
@@ -62,6 +90,8 @@ hipError_t col_reduce(const Tables& T, float2* work, int B, const int32_t* wave_
                       int64_t img_stride, double scale, hipStream_t s);
 // probe-coefficient contraction and detector reduction
 hipError_t contract(const Contraction& c, hipStream_t s);
+// the same contraction for a whole window on MFMA
+hipError_t contract_stencil(const Stencil& c, hipStream_t s);
 // out = (acc ? out : 0) + w * img, n doubles, device memory
 hipError_t scale_out(double* out, const double* img, int64_t n, double w, int acc, hipStream_t s);
 

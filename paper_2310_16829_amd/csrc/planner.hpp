@@ -75,3 +75,70 @@ lma_status check_arguments(const lma_optics* op, const lma_lattice* lat, const l
 void electron_constants(double kv, double* lambda, double* sigma);
 
 }  // namespace lma
+
+namespace lma {
+
+// Layout of the contraction as a banded complex GEMM (the combination step of
+// Fig. lma_pseudocode, eqs. lma_approximation_exit1 / exit2) for a whole scan window.
+//
+// Probes are taken in 4 x 4 sub-blocks (M = 16 rows of a 16x16 MFMA tile); four sub-blocks
+// form an 8 x 8 super-tile handled by one workgroup. The translates the super-tile needs lie
+// in a W x H rectangle of I_f (periodic). For one sub-block, the union of its probes'
+// L-nearest sets is cut into K-steps of 4 translates adjacent along x within one row of the
+// rectangle; A[probe][translate] holds alpha where the translate is one of that probe's
+// neighbours and 0 elsewhere. The pattern is the same for every sub-block of the window up
+// to a whole-translate shift when the number of coefficient sets along each axis divides 4
+// (Case 1, or Case 2 with c in {2, 4}).
+struct StencilPlan {
+  bool ok = false;
+  std::string why;             // reason when !ok
+  int nks = 0;                 // K-steps per sub-block (implemented K = 4 nks)
+  int W = 0, H = 0;            // translate rectangle of a super-tile
+  int ox0 = 0, oy0 = 0;        // rectangle origin of super-tile (0, 0), translate index in [0, R_f)
+  int tile_dx = 0, tile_dy = 0;  // rectangle shift between super-tiles (8 probes)
+  int sub_dx = 0, sub_dy = 0;    // shift between sub-blocks (4 probes)
+  int tiles_x = 0, tiles_y = 0;  // super-tiles covering the window
+  std::vector<int32_t> ks_off;   // [nks] rectangle index (row * W + col) of each step's first translate
+  std::vector<std::complex<float>> a;  // [nks][64] A fragment: lane l holds A[l % 16][4 ks + l / 16]
+};
+
+// Builds the banded-GEMM layout for the plan's window; ok = false (with a reason) when the
+// window does not have the shift-invariant structure, the rectangle exceeds max_rect
+// translates or the sub-block needs more than max_ks K-steps.
+void build_stencil(const HostPlan& h, int max_ks, int max_rect, StencilPlan* sp);
+
+}  // namespace lma
+
+namespace lma {
+
+// Partition of the scan window into rectangles P_1..P_l under a residency budget of M
+// propagated translates (Sec. 4.2.4, rectangle strategy). Every rectangle but those clipped
+// at the window's right and bottom edges has the same size w x h: among the candidate sizes
+// (sides multiples of the granules gx, gy, or the whole window side) the one of largest area,
+// ties to the wider, whose translate set I_{f,P_j,L} holds at most M translates. Parts are
+// taken row-major; translates shared by consecutive parts stay resident, so the number of
+// multislice runs is T = sum_j |I_{f,P_j,L}| - sum_j |I_{f,P_j,L} cap I_{f,P_{j+1},L}|.
+struct PartPlan {
+  struct Part {
+    int a0 = 0, b0 = 0, w = 0, h = 0;        // probes, relative to the window origin
+    std::vector<int32_t> translates;         // I_{f,P_j,L}, increasing
+    std::vector<int32_t> fresh;              // translates not resident from the previous part
+    std::vector<int32_t> fresh_slot;         // resident row each of them is written to
+    std::vector<int32_t> row_of;             // [Rfy*Rfx] -> resident row while this part is formed, or -1
+  };
+  int64_t max_rows = 0;          // M
+  int gx = 1, gy = 1;            // side granules
+  int w = 0, h = 0;              // rectangle size
+  int64_t slots = 0;             // resident rows needed: max_j |I_{f,P_j,L}|
+  int64_t multislice_calls = 0;  // T
+  std::vector<Part> parts;
+};
+
+// The L-nearest translates of window probe (a, b) (window-relative), appended to out.
+void probe_translates(const HostPlan& h, int a, int b, std::vector<int32_t>* out);
+
+// Rectangle partition of the window for at most max_rows resident translates. Returns false
+// (with a reason) when even one granule-sized rectangle needs more than max_rows.
+bool build_partition(const HostPlan& h, int64_t max_rows, int gx, int gy, PartPlan* pp, std::string* why);
+
+}  // namespace lma

@@ -32,7 +32,7 @@ def say(*a):
 
 
 def build(w, L=None, scan=None, R=None, f=1, offset=None, window=(0, 0, 0, 0), precision=0, batch=0, nx=None,
-          ny=None, lx=None, ly=None, detectors=None):
+          ny=None, lx=None, ly=None, detectors=None, budget=0):
     lam, sig = lma.electron_constants(w.kv)
     nx, ny = nx or w.nx, ny or w.ny
     lx, ly = lx or w.lx, ly or w.ly
@@ -43,7 +43,7 @@ def build(w, L=None, scan=None, R=None, f=1, offset=None, window=(0, 0, 0, 0), p
     L = w.L if L is None else L
     offset = offset or w.offset_frac
     rings = detectors or det_rad(w)
-    lat = lma.lattice(scan[0], scan[1], R[0], R[1], f, offset, L, precision, window, batch)
+    lat = lma.lattice(scan[0], scan[1], R[0], R[1], f, offset, L, precision, window, batch, hbm_budget_bytes=budget)
     plan = lma.Plan(opt, lat, lma.detectors(rings))
     st = Setup(nx, ny, lx, ly, lam, sig, w.dz, w.bandlimit, w.alpha_mrad * 1e-3, w.defocus, w.cs, scan, rings)
     ol = Lattice(st, R, f, offset, L)
@@ -126,6 +126,80 @@ def test_tiny_plain_image(tiny):
     say("  per-detector rel L2", e)
 
 
+def test_mfma_and_per_pixel_contractions(tiny):
+    # the window contraction as a banded complex GEMM on MFMA and as per-pixel vector sums,
+    # on the same resident basis: both against the oracle, and against each other
+    say("tiny: MFMA contraction vs per-pixel contraction")
+    plan = tiny["plan"]
+    assert plan.info().contract_kernel == 1
+    plan.propagate(tiny["v"])
+    a = plan.probe_image()
+    b = plan.probe_image(flags=lma.LMA_CONTRACT_PER_PIXEL)
+    ea = image_errors(a, tiny["img_lma"], TOL32)
+    eb = image_errors(b, tiny["img_lma"], TOL32)
+    say("  MFMA", ea, " per-pixel", eb)
+    for r in range(a.shape[0]):
+        if np.mean(b[r]) >= RESOLVABLE:
+            assert rel_l2(a[r], b[r]) < 1e-5
+
+
+def test_case2_three_sets_per_axis():
+    # P = 3 R_f: nine coefficient sets; 3 does not divide the 4 x 4 sub-blocks of the MFMA
+    # contraction, so the window uses the per-pixel kernel
+    say("Case 2 with c = 3")
+    w = WORKLOADS["tiny"]
+    rng = np.random.default_rng(3)
+    v = rng.uniform(0, 40, size=(3, w.ny, w.nx)).astype(np.float32)
+    plan, st, ol = build(w, scan=(48, 48), R=(16, 16), L=12, window=(5, 7, 6, 5))
+    i = plan.info()
+    assert (i.ncls_x, i.ncls_y, i.contract_kernel) == (3, 3, 0)
+    plan.propagate(v)
+    probes = window_probes(plan)
+    image_errors(plan.probe_image(), crop(LMA(st, ol).image(v, probes), plan), TOL32)
+
+
+def test_partitioned_image_case1(tiny):
+    # a residency budget of 600 of the 1024 translates: rectangles of probes formed in turn
+    # (Sec. 4.2.4); same waves and the same contraction tiles as the resident run
+    say("tiny: rectangle partition, M = 600")
+    w = tiny["w"]
+    D = tiny["plan"].info().n_pix
+    plan, _, _ = build(w, budget=600 * D * 8)
+    i = plan.info()
+    say(f"  {i.n_parts} rectangles of {i.part_w} x {i.part_h}, {i.multislice_calls} multislice runs, "
+        f"{i.resident_rows} resident rows")
+    assert i.partitioned == 1 and i.n_parts > 1 and i.contract_kernel == 1 and i.resident_rows <= 600
+    img = plan.image(tiny["v"])
+    image_errors(img, tiny["img_lma"], TOL32)
+    tiny["plan"].propagate(tiny["v"])
+    ref = tiny["plan"].probe_image()
+    assert np.allclose(img, ref, rtol=1e-12, atol=0)
+    for call in (lambda: plan.propagate(tiny["v"]), lambda: plan.probe_image()):
+        with pytest.raises(lma.LmaError) as e:
+            call()
+        assert e.value.status == lma._lib.LMA_ERR_STATE
+    # on a plan that is not partitioned, lma_image is propagate + probe_image
+    assert np.allclose(tiny["plan"].image(tiny["v"]), ref, rtol=1e-12, atol=0)
+
+
+def test_partitioned_image_case2_three_sets():
+    say("Case 2 with c = 3: rectangle partition, per-pixel contraction")
+    w = WORKLOADS["tiny"]
+    rng = np.random.default_rng(33)
+    v = rng.uniform(0, 40, size=(3, w.ny, w.nx)).astype(np.float32)
+    args = dict(scan=(48, 48), R=(16, 16), L=12, window=(5, 7, 13, 10), batch=7)
+    plan, st, ol = build(w, **args)
+    D = plan.info().n_pix
+    plan.propagate(v)
+    ref = plan.probe_image()
+    pplan, _, _ = build(w, budget=30 * D * 8, **args)
+    i = pplan.info()
+    assert i.partitioned == 1 and i.n_parts > 1 and i.contract_kernel == 0
+    img = pplan.image(v)
+    assert np.allclose(img, ref, rtol=1e-12, atol=0)
+    image_errors(img, crop(LMA(st, ol).image(v, window_probes(plan)), plan), TOL32)
+
+
 def test_tiny_split_bf16_image(tiny):
     say("tiny split-bf16 LMA image")
     plan, _, _ = build(tiny["w"], precision=lma.LMA_GEMM_SPLIT_BF16)
@@ -170,7 +244,7 @@ def test_case2_nonsquare_f2():
     v = rng.uniform(0, 40, size=(4, ny, nx)).astype(np.float32)
     plan, st, ol = build(w, nx=nx, ny=ny, lx=lx, ly=ly, scan=scan, R=scan, f=2, offset=(0.5, 0.5), L=20,
                          window=(3, 2, 6, 5), batch=5)
-    assert (plan.info().ncls_x, plan.info().ncls_y) == (2, 2)
+    assert (plan.info().ncls_x, plan.info().ncls_y, plan.info().contract_kernel) == (2, 2, 1)
     plan.propagate(v)
     probes = window_probes(plan)
     om = LMA(st, ol)
@@ -321,6 +395,20 @@ def test_medium_full_size_sampled():
     say("medium: GPU propagate + images")
     plan.propagate(v)
     img = plan.probe_image()
+    assert plan.info().contract_kernel == 1
+    # the MFMA and per-pixel contractions over the full 128 x 128 scan
+    img_pp = plan.probe_image(flags=lma.LMA_CONTRACT_PER_PIXEL)
+    for r in range(img.shape[0]):
+        e = rel_l2(img[r], img_pp[r])
+        say(f"  ring {r}: MFMA vs per-pixel contraction rel L2 {e:.2e}")
+        assert e < 1e-5
+    # the same image in rectangles under a budget of 4096 resident translates
+    pplan, _, _ = build(w, budget=4096 * plan.info().n_pix * 8)
+    i = pplan.info()
+    say(f"medium: {i.n_parts} rectangles of {i.part_w} x {i.part_h}, {i.multislice_calls} multislice runs")
+    assert i.partitioned == 1
+    assert np.allclose(pplan.image(v), img, rtol=1e-12, atol=0)
+    pplan.close()
     pimg = plan.plain_image(v)
     rows = plan.rows()
     flat, _ = plan.detector_pixels()

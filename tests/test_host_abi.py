@@ -181,3 +181,52 @@ def test_footprint_grows_with_slices_and_basis():
     assert b100 > b1 > 16384 * 90081 * 8          # the resident basis alone is ~11.8 GB
     with pytest.raises(lma.LmaError):
         lma.footprint(opt, lat, det, 0)
+
+
+# ---------------------------------------------------------------------------------------
+# rectangle partition under a residency budget (Sec. 4.2.4)
+# ---------------------------------------------------------------------------------------
+def _partition_case(w, M, **kw):
+    from oracle.partition import multislice_calls, rectangles, union
+    opt, lat, det = _plan_args(w, **kw)
+    with lma.Plan(opt, lat, det, flags=lma.LMA_HOST_ONLY) as p:
+        info = p.info()
+        assert info.partitioned == 0 and info.multislice_calls == info.n_rows
+        D, window, stencil = info.n_pix, p.window, info.contract_kernel
+    lat.hbm_budget_bytes = M * D * 8
+    with lma.Plan(opt, lat, det, flags=lma.LMA_HOST_ONLY) as p:
+        info = p.info()
+    st = oracle_setup(w, **{k: v for k, v in kw.items() if k in ("nx", "ny", "lx", "ly", "scan")})
+    ol = oracle_lattice(w, st, **{k: v for k, v in kw.items() if k in ("R", "f", "offset", "L")})
+    a0, b0, ww, wh = window
+    sets = {(a, b): ol.nearest((a0 + a) % st.Px, (b0 + b) % st.Py) for b in range(wh) for a in range(ww)}
+    granule = (8, 8) if stencil else (ol.ncls_x, ol.ncls_y)
+    parts = rectangles(sets, (0, 0, ww, wh), M, granule)
+    assert info.partitioned == 1
+    assert (info.part_w, info.part_h) == (max(a for a, _ in parts[0]) + 1, max(b for _, b in parts[0]) + 1)
+    assert info.n_parts == len(parts)
+    assert info.multislice_calls == multislice_calls(sets, parts)
+    assert info.resident_rows == max(len(union(sets, q)) for q in parts) <= M
+    return info, parts
+
+
+def test_partition_case1_matches_oracle_rectangles():
+    # tiny workload (Case 1, two translates per probe step), MFMA contraction: sides in 8s
+    info, parts = _partition_case(WORKLOADS["tiny"], 600)
+    assert info.contract_kernel == 1 and info.n_parts > 1
+
+
+def test_partition_case2_three_sets_matches_oracle_rectangles():
+    # Case 2 with three coefficient sets per axis: per-pixel contraction, sides in 3s
+    w = WORKLOADS["tiny"]
+    info, parts = _partition_case(w, 30, scan=(48, 48), R=(16, 16), L=12, window=(5, 7, 13, 10))
+    assert info.contract_kernel == 0 and info.n_parts > 1
+
+
+def test_partition_budget_below_one_rectangle_is_refused():
+    w = WORKLOADS["tiny"]
+    opt, lat, det = _plan_args(w)
+    lat.hbm_budget_bytes = 100 * 8   # far less than one row of D pixels
+    with pytest.raises(lma.LmaError) as e:
+        lma.Plan(opt, lat, det, flags=lma.LMA_HOST_ONLY)
+    assert e.value.status == _lib.LMA_ERR_OOM
