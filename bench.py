@@ -162,6 +162,125 @@ def spacing_study(w):
 # ------------------------------------------------------------------------------------------
 FP32_MFMA_PEAK_TFLOPS = 157.3
 
+KERNEL_NAMES = (("k_contract_mfma", "contract_mfma"), ("k_contract", "contract"), ("k_transmission", "transmission"),
+                ("k_scale_out", "scale_out"))
+PASS_MODES = {"0": "row_pass", "1": "col_pass", "2": "init", "3": "col_gather", "4": "col_reduce"}
+
+
+def _short_name(kernel: str):
+    import re
+    m = re.search(r"k_pass<\d+, \d+, (\d)>", kernel)
+    if m:
+        return PASS_MODES.get(m.group(1))
+    for tag, name in KERNEL_NAMES:
+        if tag + "<" in kernel or tag + "(" in kernel:
+            return name
+    if "copyBuffer" in kernel:
+        return "copy"
+    return None
+
+
+def _counter_means(run_dir: str, counter: str):
+    """Mean per dispatch of one rocprofv3 counter (KiB for FETCH_SIZE / WRITE_SIZE), by kernel."""
+    import csv
+    import glob
+    per = {}
+    for path in glob.glob(os.path.join(run_dir, "**", "*counter_collection.csv"), recursive=True):
+        with open(path) as fh:
+            for r in csv.DictReader(fh):
+                if r["Counter_Name"] != counter:
+                    continue
+                name = _short_name(r["Kernel_Name"])
+                if name is None:
+                    continue
+                d = per.setdefault(name, {})
+                d[r["Dispatch_Id"]] = d.get(r["Dispatch_Id"], 0.0) + float(r["Counter_Value"])
+    return {k: (len(v), sum(v.values()) / len(v)) for k, v in per.items()}
+
+
+def summarize_counters(fetch_dir, write_dir, cal_fetch_dir, cal_write_dir):
+    """HBM bytes per launch of every kernel from FETCH_SIZE and WRITE_SIZE runs, each scaled by
+    what the same counter reads for a 1 GiB device copy (bench.py --copy-calibration)."""
+    copy_bytes = 1 << 30
+    cf = _counter_means(cal_fetch_dir, "FETCH_SIZE")["copy"][1]
+    cw = _counter_means(cal_write_dir, "WRITE_SIZE")["copy"][1]
+    ff, wf = copy_bytes / 1024 / cf, copy_bytes / 1024 / cw
+    fetch = _counter_means(fetch_dir, "FETCH_SIZE")
+    write = _counter_means(write_dir, "WRITE_SIZE")
+    kernels = {}
+    for k in sorted(set(fetch) & set(write)):
+        kernels[k] = {"dispatches": fetch[k][0], "FETCH_SIZE_KiB": fetch[k][1], "WRITE_SIZE_KiB": write[k][1],
+                      "hbm_bytes_per_launch": (fetch[k][1] * ff + write[k][1] * wf) * 1024}
+    print(json.dumps({"kernel_source_hash": kernel_source_hash(), "workload": WORKLOAD,
+                      "calibration": {"copy_bytes": copy_bytes, "FETCH_SIZE_KiB": cf, "WRITE_SIZE_KiB": cw,
+                                      "fetch_factor": ff, "write_factor": wf},
+                      "kernels": kernels}, indent=1))
+
+
+def paper_shaped():
+    """The paper's local-edit experiment in shape (1024^2 px over 84.536 x 79.941 A, scan
+    424 x 400, I = P + p/2, f = 2, L = 59, 200 kV, 26 mrad, Z = 100 A, C_s = -2000 A) with the
+    synthetic FCC specimen, 50 slices, one phonon configuration: the full LMA image (42400
+    propagated translates for 169600 probes), plain multislice timed on a 64 x 64-probe window
+    of the same scan (its pixel rate does not depend on the window), and the LMA-vs-plain
+    image error on that window."""
+    import numpy as np
+    import torch
+    import paper_2310_16829_amd as lma
+    from synth import WORKLOADS, potential_slices
+
+    w = WORKLOADS["paper"]
+    v = torch.from_numpy(potential_slices(w, 0)).cuda()
+    lam, sig = lma.electron_constants(w.kv)
+    rings = [(a * 1e-3, b * 1e-3) for _, a, b in w.detectors]
+    opt = lma.optics(w.nx, w.ny, w.lx, w.ly, lam, sig, w.dz, w.bandlimit, w.alpha_mrad * 1e-3, w.defocus, w.cs)
+    (Rx, Ry), f = w.lattice_size()
+    det = lma.detectors(rings)
+    win = (180, 168, 64, 64)
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = fn()
+        torch.cuda.synchronize()
+        return out, time.perf_counter() - t0
+
+    # the same kernels once on a small window first (first-launch costs out of the timings)
+    with lma.Plan(opt, lma.lattice(w.scan[0], w.scan[1], Rx, Ry, f, w.offset_frac, w.L, window=(0, 0, 8, 8)), det) as p:
+        p.propagate(v)
+        p.probe_image()
+        p.plain_image(v)
+    log("paper-shaped: LMA plan (full scan)")
+    plan = lma.Plan(opt, lma.lattice(w.scan[0], w.scan[1], Rx, Ry, f, w.offset_frac, w.L), det)
+    info = plan.info()
+    img = torch.zeros(plan.image_shape(), dtype=torch.float64, device="cuda")
+    _, t_prop = timed(lambda: plan.propagate(v))
+    _, t_img = timed(lambda: plan.probe_image(img))
+    t_lma = t_prop + t_img
+    log(f"paper-shaped: LMA {t_lma:.2f} s ({t_prop:.2f} s propagation, {t_img:.3f} s contraction)")
+    lma_win = img.cpu().numpy()[:, win[1]:win[1] + win[3], win[0]:win[0] + win[2]]
+    plan.close()
+    with lma.Plan(opt, lma.lattice(w.scan[0], w.scan[1], Rx, Ry, f, w.offset_frac, w.L, window=win), det) as pp:
+        pimg, t_plain = timed(lambda: pp.plain_image(v, device=True))
+        pimg = pimg.cpu().numpy()
+    log(f"paper-shaped: plain {t_plain:.2f} s for {win[2] * win[3]} probes")
+    n_probes = w.scan[0] * w.scan[1]
+    lma_rate = n_probes / t_lma
+    plain_rate = win[2] * win[3] / t_plain
+    err = {name: float(np.linalg.norm(lma_win[r] - pimg[r]) / np.linalg.norm(pimg[r]))
+           for r, (name, _, _) in enumerate(w.detectors)}
+    print(json.dumps({
+        "study": "paper-shaped stand-in: 1024^2 px over 84.536 x 79.941 A, scan 424x400, I=P+p/2, f=2, L=59, "
+                 "200 kV, 26 mrad, Z=100 A, Cs=-2000 A, synthetic FCC specimen, 50 slices of 2 A, one configuration",
+        "translates": info.n_rows, "probes": n_probes, "detector_pixels": info.n_pix,
+        "basis_GB": info.n_rows * info.n_pix * 8 / 1e9, "probe_residual": info.max_residual,
+        "contract_K": info.contract_k,
+        "lma_seconds": t_lma, "lma_propagate_seconds": t_prop, "lma_contract_seconds": t_img,
+        "lma_pixels_per_s": lma_rate,
+        "plain_window": list(win), "plain_seconds": t_plain, "plain_pixels_per_s": plain_rate,
+        "speedup_vs_plain": lma_rate / plain_rate,
+        "lma_vs_plain_rel_l2_on_window": err}), flush=True)
+
 
 def contraction_roofline(plan, info, kt):
     """Flop rate of the contraction launch. Algorithmic: 8 real flops per complex multiply-add,
@@ -186,7 +305,8 @@ def contraction_roofline(plan, info, kt):
             run += 1
     alg = 8.0 * info.n_probes * info.L * info.n_pix
     out = {"kernel": name, "avg_launch_ms": avg_s * 1e3, "algorithmic_tflop": alg / 1e12,
-           "useful_tflops": alg / avg_s / 1e12, "L": info.L, "K": info.contract_k}
+           "useful_tflops": alg / avg_s / 1e12, "L": info.L, "K": info.contract_k,
+           "traffic": load_traffic(name), "algorithmic_bytes": 8.0 * info.n_rows * info.n_pix}
     if info.contract_kernel:
         ww, wh = plan.window[2], plan.window[3]
         sub_blocks = 4 * (-(-ww // 8)) * (-(-wh // 8))
@@ -209,9 +329,16 @@ def main():
                     help="skip the extra step that times every launch with hipEvents")
     ap.add_argument("--spacing-study", action="store_true",
                     help="LMA at translate spacings 4, 8, 16 px against plain multislice (one configuration)")
+    ap.add_argument("--summarize-counters", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "CAL_FETCH_DIR", "CAL_WRITE_DIR"),
+                    help="print the HBM-traffic summary (JSON) of four rocprofv3 --pmc output directories")
+    ap.add_argument("--paper-shaped", action="store_true",
+                    help="LMA against plain multislice in the paper's regime (1024^2, 424x400 scan, f=2)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device-to-device copy kernel (HBM counter calibration)")
     args = ap.parse_args()
+    if args.summarize_counters:
+        summarize_counters(*args.summarize_counters)
+        return
     if args.copy_calibration:
         import torch
         a = torch.ones(1 << 27, dtype=torch.float64, device="cuda")   # 1 GiB
@@ -233,6 +360,9 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     w = WORKLOADS[WORKLOAD]
+    if args.paper_shaped:
+        paper_shaped()
+        return
     if args.spacing_study:
         spacing_study(w)
         return

@@ -52,6 +52,14 @@ class Workload:
     L: int                        # nearest translates per probe
     n_phonons: int
     detectors: tuple = field(default_factory=tuple)   # ((name, inner_mrad, outer_mrad), ...)
+    R: tuple = ()                 # input-wave lattice size (Rx, Ry) when not nx / basis_px
+    f: int = 1                    # every f-th input wave is propagated
+
+    def lattice_size(self):
+        """(Rx, Ry) of the input-wave lattice I and f, so that I_f has (Rx / f, Ry / f) points."""
+        if self.R:
+            return tuple(self.R), self.f
+        return (self.nx // self.basis_px, self.ny // self.basis_px), self.f
 
     @property
     def thickness(self) -> float:
@@ -73,6 +81,13 @@ WORKLOADS = {
     "large": Workload("large", 3, 2048, 2048, 204.8, 204.8, 250, 2.0, "fcc", 4.05, (29.0, 79.0),
                       (0.5, 0.5), 0.1, 300.0, 25.0, -50.0, 0.0, 2.0 / 3.0, (256, 256), 4, (0.5, 0.5),
                       144, 16, _STD_DET),
+    # The paper's local-edit experiment in shape only (Sec. 4.2.6): 1024^2 px over
+    # 84.536 x 79.941 A, scan 424 x 400, I = P + p/2 with f = 2 (|I_f| = 42400), L = 59,
+    # 200 kV, 26 mrad, Z = 100 A, C_s = -2000 A; the specimen is this module's synthetic FCC
+    # crystal, 50 x 2 A slices (the paper's M1 specimen and thickness are not available).
+    "paper": Workload("paper", 4, 1024, 1024, 84.536, 79.941, 50, 2.0, "fcc", 4.05, (14.0, 29.0, 79.0),
+                      (1 / 3, 1 / 3, 1 / 3), 0.08, 200.0, 26.0, 100.0, -2000.0, 2.0 / 3.0, (424, 400), 0,
+                      (0.5, 0.5), 59, 1, _STD_DET, R=(424, 400), f=2),
 }
 
 

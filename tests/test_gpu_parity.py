@@ -446,3 +446,43 @@ def test_medium_full_size_sampled():
         e = np.abs(pimg[:, b, a] - pref[:, b, a]) / np.abs(pref[:, b, a])
         say(f"  plain pixel {(a, b)} rel err", e)
         assert e.max() < TOL32
+
+
+@pytest.mark.slow
+def test_paper_shaped_full_size_sampled():
+    # the paper-shaped workload at full size: 1024^2 grid over a non-square cell, Case 2 with
+    # four coefficient sets (I = P + p/2, f = 2), defocus and C_s; one LMA pixel (with the
+    # oracle's own coefficients) and one plain pixel against the oracle
+    from oracle.lma import least_squares
+    w = WORKLOADS["paper"]
+    say("paper-shaped: potential")
+    v = potential_slices(w, 0)
+    R, f = w.lattice_size()
+    window = (201, 183, 8, 8)
+    plan, st, ol = build(w, R=R, f=f, window=window)
+    i = plan.info()
+    assert i.contract_kernel == 1 and i.n_sets == 4
+    say("paper-shaped: GPU propagate + images")
+    plan.propagate(v)
+    img = plan.probe_image()
+    pimg = plan.plain_image(v)
+    probe = (205, 186)
+    nbr = ol.nearest(*probe)
+    jobs = {tb * ol.Rfx + ta: ol.translate_position(ta, tb) for ta, tb in nbr}
+    n_workers = max(1, min(16, len(os.sched_getaffinity(0))))
+    say(f"paper-shaped: oracle for {len(jobs)} translates on {n_workers} processes")
+    with ProcessPoolExecutor(n_workers, initializer=_pool_init, initargs=("paper",)) as ex:
+        res = dict(ex.map(_oracle_exit, [("paper", t, (float(p[0]), float(p[1]))) for t, p in jobs.items()]))
+    alpha, _, resid = least_squares(st, ol, st.spec0, *probe)
+    say(f"  probe LSQ residual {resid:.3e}")
+    spec = sum(a * res[tb * ol.Rfx + ta] for a, (ta, tb) in zip(alpha, nbr))
+    ref = ph.detector_values(spec, st.masks)
+    got = img[:, probe[1] - window[1], probe[0] - window[0]]
+    e = np.abs(got - ref) / np.abs(ref)
+    say("  LMA pixel per-detector rel err", e)
+    assert e.max() < TOL32
+    pref = plain_image(st, v, [probe])[:, probe[1], probe[0]]
+    pgot = pimg[:, probe[1] - window[1], probe[0] - window[0]]
+    e = np.abs(pgot - pref) / np.abs(pref)
+    say("  plain pixel per-detector rel err", e)
+    assert e.max() < TOL32
