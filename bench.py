@@ -249,7 +249,7 @@ def paper_shaped():
     with lma.Plan(opt, lma.lattice(w.scan[0], w.scan[1], Rx, Ry, f, w.offset_frac, w.L, window=(0, 0, 8, 8)), det) as p:
         p.propagate(v)
         p.probe_image()
-        p.plain_image(v)
+        p.plain_image(v, device=True)
     log("paper-shaped: LMA plan (full scan)")
     plan = lma.Plan(opt, lma.lattice(w.scan[0], w.scan[1], Rx, Ry, f, w.offset_frac, w.L), det)
     info = plan.info()

@@ -237,7 +237,10 @@ struct PassCfg {
   static constexpr bool WL = T <= 64;                               // transform inside one wavefront
   static constexpr int S = WL ? ((64 / T) < TW ? 64 / T : TW) : 1;  // transforms per wavefront
   static constexpr int WPT = WL ? 1 : T / 64;                       // wavefronts per transform
-  static constexpr int WAVES = WL ? ((TW / S) < 4 ? TW / S : 4) : WPT;
+  // wavefronts per workgroup: up to 4 single-wavefront transforms, or 8 wavefronts of
+  // multi-wavefront transforms (several lines in flight between the workgroup barriers)
+  static constexpr int KMW = (8 / WPT) < TW ? (8 / WPT > 0 ? 8 / WPT : 1) : TW;
+  static constexpr int WAVES = WL ? ((TW / S) < 4 ? TW / S : 4) : WPT * KMW;
   static constexpr int TPB = WAVES * S / WPT;                       // transforms in flight
   static constexpr int RPW = TW / TPB;                              // rounds per workgroup
   // LDS line stride: a padded slot plus LMA_TILE_EXTRA, so that the TW lines touched by one
