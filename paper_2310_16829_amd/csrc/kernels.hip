@@ -231,7 +231,16 @@ __global__ void k_transmission(const float* __restrict__ v, float2* __restrict__
 // ------------------------------------------------------------------------------------------
 enum { PASS_ROW = 0, PASS_COL = 1, PASS_INIT = 2, PASS_GATHER = 3, PASS_REDUCE = 4 };
 
-template <int N, int TW>
+// Wavefronts per workgroup for transforms that fit one wavefront (N <= 512): column passes
+// keep 4 (their registers allow 2 wavefronts per SIMD), row passes take 8 lines at once
+// (fewer prefetch registers per thread, 4 wavefronts per SIMD).
+#ifndef LMA_WL_WAVES
+#define LMA_WL_WAVES 4
+#endif
+#ifndef LMA_WL_WAVES_ROW
+#define LMA_WL_WAVES_ROW 8
+#endif
+template <int N, int TW, int WLW = LMA_WL_WAVES>
 struct PassCfg {
   static constexpr int T = N / 8;                                   // threads per transform
   static constexpr bool WL = T <= 64;                               // transform inside one wavefront
@@ -240,7 +249,7 @@ struct PassCfg {
   // wavefronts per workgroup: up to 4 single-wavefront transforms, or 8 wavefronts of
   // multi-wavefront transforms (several lines in flight between the workgroup barriers)
   static constexpr int KMW = (8 / WPT) < TW ? (8 / WPT > 0 ? 8 / WPT : 1) : TW;
-  static constexpr int WAVES = WL ? ((TW / S) < 4 ? TW / S : 4) : WPT * KMW;
+  static constexpr int WAVES = WL ? ((TW / S) < WLW ? TW / S : WLW) : WPT * KMW;
   static constexpr int TPB = WAVES * S / WPT;                       // transforms in flight
   static constexpr int RPW = TW / TPB;                              // rounds per workgroup
   // LDS line stride: a padded slot plus LMA_TILE_EXTRA, so that the TW lines touched by one
@@ -282,6 +291,19 @@ __device__ __forceinline__ float2 load_stream(const float2* p) {
 __device__ __forceinline__ void store_stream(float2* p, float2 v) {
   __builtin_nontemporal_store(__builtin_bit_cast(unsigned long long, v), reinterpret_cast<unsigned long long*>(p));
 }
+// A workgroup's HBM traffic comes in bursts (the next item's loads, the finished item's
+// stores) between long stretches of FFT arithmetic; its wavefronts issue those bursts at a
+// raised priority so that the memory pipeline is fed while the other workgroups on the CU
+// compute (measured: +5 % on both passes at 512 points).
+#ifndef LMA_PASS_PRIORITY
+#define LMA_PASS_PRIORITY 2
+#endif
+__device__ __forceinline__ void memory_phase_begin() {
+  if constexpr (LMA_PASS_PRIORITY > 0) __builtin_amdgcn_s_setprio(LMA_PASS_PRIORITY);
+}
+__device__ __forceinline__ void memory_phase_end() {
+  if constexpr (LMA_PASS_PRIORITY > 0) __builtin_amdgcn_s_setprio(0);
+}
 
 // Element c of a work item (TW lines x N positions) <-> its LDS index and its offset from the
 // item's first element in HBM. A row item (tile row g) is one contiguous block; a column item
@@ -289,7 +311,7 @@ __device__ __forceinline__ void store_stream(float2* p, float2 v) {
 template <int N, int TW, bool ROWS>
 struct TileMap {
   static constexpr int TT = TW * TW;
-  static constexpr int RS = PassCfg<N, TW>::RS;
+  static constexpr int RS = PassCfg<N, TW>::RS;   // independent of the wavefront count
   __device__ __forceinline__ static int64_t item_base(int g, int nx) {
     return ROWS ? (int64_t)g * TW * nx : (int64_t)g * TT;
   }
@@ -330,9 +352,12 @@ struct ItemWalk {
   __device__ __forceinline__ bool valid(int i) const { return i < end; }
 };
 
+template <int MODE>
+constexpr int pass_waves() { return MODE == PASS_ROW ? LMA_WL_WAVES_ROW : LMA_WL_WAVES; }
+
 template <int N, int TW, int MODE>
-__global__ __launch_bounds__((PassCfg<N, TW>::WAVES * 64)) void k_pass(PassArgs a) {
-  using C = PassCfg<N, TW>;
+__global__ __launch_bounds__((PassCfg<N, TW, pass_waves<MODE>()>::WAVES * 64)) void k_pass(PassArgs a) {
+  using C = PassCfg<N, TW, pass_waves<MODE>()>;
   constexpr int T = C::T, S = C::S, RS = C::RS, TPB = C::TPB, RPW = C::RPW;
   constexpr int NT = C::WAVES * 64;
   constexpr bool ROWS = (MODE == PASS_ROW);
@@ -369,12 +394,14 @@ __global__ __launch_bounds__((PassCfg<N, TW>::WAVES * 64)) void k_pass(PassArgs 
   [[maybe_unused]] float2 buf[PREF ? EPT : 1];
   auto load_item = [&](int l) {
     const float2* src = item_ptr(l);
+    memory_phase_begin();
 #pragma unroll
     for (int k = 0; k < EPT; ++k) {
       int lds, off;
       M::at(k * NT + tid, stride_q, lds, off);
       buf[k] = load_stream(src + off);
     }
+    memory_phase_end();
   };
   if constexpr (PREF && MODE != PASS_INIT) {
     if (walk.valid(walk.l)) load_item(walk.l);
@@ -523,12 +550,14 @@ __global__ __launch_bounds__((PassCfg<N, TW>::WAVES * 64)) void k_pass(PassArgs 
     } else if constexpr (MODE != PASS_GATHER) {
       // ---- write the lines back, whole tiles, in place ------------------------------------
       __syncthreads();
+      memory_phase_begin();
 #pragma unroll
       for (int k = 0; k < EPT; ++k) {
         int lds, off;
         M::at(k * NT + tid, stride_q, lds, off);
         store_stream(item + off, tile[lds]);
       }
+      memory_phase_end();
     }
   }
 }
@@ -751,7 +780,7 @@ static int device_cus() {
 template <int N, int TW, int MODE>
 static hipError_t pass_launch(const PassArgs& a0, int lines, int B, hipStream_t s) {
   if (lines % TW) return hipErrorInvalidValue;
-  constexpr int threads = PassCfg<N, TW>::WAVES * 64;
+  constexpr int threads = PassCfg<N, TW, pass_waves<MODE>()>::WAVES * 64;
   static int resident = 0;   // workgroups of this kernel resident per CU
   if (resident == 0) {
     int nb = 0;
