@@ -231,11 +231,10 @@ __global__ void k_transmission(const float* __restrict__ v, float2* __restrict__
 // ------------------------------------------------------------------------------------------
 enum { PASS_ROW = 0, PASS_COL = 1, PASS_INIT = 2, PASS_GATHER = 3, PASS_REDUCE = 4 };
 
-// Wavefronts per workgroup for transforms that fit one wavefront (N <= 512): column passes
-// keep 4 (their registers allow 2 wavefronts per SIMD), row passes take 8 lines at once
-// (fewer prefetch registers per thread, 4 wavefronts per SIMD).
+// Wavefronts per workgroup for transforms that fit one wavefront (N <= 512): 8, one line each
+// (8 prefetch registers pairs per thread instead of 16; 3-4 wavefronts per SIMD).
 #ifndef LMA_WL_WAVES
-#define LMA_WL_WAVES 4
+#define LMA_WL_WAVES 8
 #endif
 #ifndef LMA_WL_WAVES_ROW
 #define LMA_WL_WAVES_ROW 8
@@ -298,6 +297,29 @@ __device__ __forceinline__ void store_stream(float2* p, float2 v) {
 #ifndef LMA_PASS_PRIORITY
 #define LMA_PASS_PRIORITY 2
 #endif
+// Column-layout passes address their items through buffer resources (32-bit offsets, 37
+// fewer registers per thread at 512 points); row passes keep 64-bit global addressing, which
+// measured faster for their contiguous items.
+#ifndef LMA_BUFFER_IO_COL
+#define LMA_BUFFER_IO_COL 1
+#endif
+#ifndef LMA_BUFFER_IO_ROW
+#define LMA_BUFFER_IO_ROW 0
+#endif
+// Raw buffer access to one work item: the resource (base, byte extent) lives in scalar
+// registers, each lane supplies a 32-bit byte offset; accesses past the extent read zero and
+// drop stores.
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t item_rsrc(const float2* base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<float2*>(base), 0, (int)bytes, 0x00020000);
+}
+__device__ __forceinline__ float2 load_item_elem(__amdgpu_buffer_rsrc_t r, int off) {
+  return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, off * 8, 0, 2));
+}
+__device__ __forceinline__ void store_item_elem(__amdgpu_buffer_rsrc_t r, int off, float2 v) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, off * 8, 0, 2);
+}
+
 __device__ __forceinline__ void memory_phase_begin() {
   if constexpr (LMA_PASS_PRIORITY > 0) __builtin_amdgcn_s_setprio(LMA_PASS_PRIORITY);
 }
@@ -392,14 +414,27 @@ __global__ __launch_bounds__((PassCfg<N, TW, pass_waves<MODE>()>::WAVES * 64)) v
     return a.work + (size_t)w * a.nx * a.ny + M::item_base(g, a.nx);
   };
   [[maybe_unused]] float2 buf[PREF ? EPT : 1];
+  constexpr bool kBufferIO = ROWS ? LMA_BUFFER_IO_ROW : LMA_BUFFER_IO_COL;
+  // bytes a work item spans in HBM (row item: TW contiguous lines; column item: N / TW tiles)
+  const uint32_t item_bytes = (uint32_t)(ROWS ? (size_t)TW * a.nx * 8 : ((size_t)(N / TW - 1) * stride_q + M::TT) * 8);
   auto load_item = [&](int l) {
     const float2* src = item_ptr(l);
     memory_phase_begin();
+    if constexpr (kBufferIO) {
+      const __amdgpu_buffer_rsrc_t r = item_rsrc(src, item_bytes);
 #pragma unroll
-    for (int k = 0; k < EPT; ++k) {
-      int lds, off;
-      M::at(k * NT + tid, stride_q, lds, off);
-      buf[k] = load_stream(src + off);
+      for (int k = 0; k < EPT; ++k) {
+        int lds, off;
+        M::at(k * NT + tid, stride_q, lds, off);
+        buf[k] = load_item_elem(r, off);
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < EPT; ++k) {
+        int lds, off;
+        M::at(k * NT + tid, stride_q, lds, off);
+        buf[k] = load_stream(src + off);
+      }
     }
     memory_phase_end();
   };
@@ -551,11 +586,21 @@ __global__ __launch_bounds__((PassCfg<N, TW, pass_waves<MODE>()>::WAVES * 64)) v
       // ---- write the lines back, whole tiles, in place ------------------------------------
       __syncthreads();
       memory_phase_begin();
+      if constexpr (kBufferIO) {
+        const __amdgpu_buffer_rsrc_t r = item_rsrc(item, item_bytes);
 #pragma unroll
-      for (int k = 0; k < EPT; ++k) {
-        int lds, off;
-        M::at(k * NT + tid, stride_q, lds, off);
-        store_stream(item + off, tile[lds]);
+        for (int k = 0; k < EPT; ++k) {
+          int lds, off;
+          M::at(k * NT + tid, stride_q, lds, off);
+          store_item_elem(r, off, tile[lds]);
+        }
+      } else {
+#pragma unroll
+        for (int k = 0; k < EPT; ++k) {
+          int lds, off;
+          M::at(k * NT + tid, stride_q, lds, off);
+          store_stream(item + off, tile[lds]);
+        }
       }
       memory_phase_end();
     }
