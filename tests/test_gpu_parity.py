@@ -143,6 +143,31 @@ def test_mfma_and_per_pixel_contractions(tiny):
             assert rel_l2(a[r], b[r]) < 1e-5
 
 
+@pytest.mark.parametrize("L,ks_template", [(4, 16), (16, 32), (25, 48), (60, 64), (100, 80), (150, 96), (180, None)])
+def test_mfma_contraction_k_steps(tiny, L, ks_template):
+    # every register capacity of the MFMA contraction (K-steps per 4 x 4-probe sub-block up to
+    # 16, 32, ..., 96) on the tiny workload, and the per-pixel fallback past 96 K-steps; each
+    # image against the oracle (whose propagated basis does not depend on L) and against the
+    # per-pixel kernel on the same resident basis
+    say(f"tiny, L = {L}: MFMA contraction")
+    w = tiny["w"]
+    plan, st, ol = build(w, L=L)
+    i = plan.info()
+    if ks_template is None:
+        assert i.contract_kernel == 0
+    else:
+        assert i.contract_kernel == 1 and ks_template - 16 < i.contract_k // 4 <= ks_template
+    plan.propagate(tiny["v"])
+    a = plan.probe_image()
+    b = plan.probe_image(flags=lma.LMA_CONTRACT_PER_PIXEL)
+    ref = LMA(st, ol).image(tiny["v"], basis=tiny["basis"])
+    e = image_errors(a, ref, TOL32)
+    say("  per-detector rel L2", e)
+    for r in range(a.shape[0]):
+        if np.mean(b[r]) >= RESOLVABLE:
+            assert rel_l2(a[r], b[r]) < 1e-5
+
+
 def test_case2_three_sets_per_axis():
     # P = 3 R_f: nine coefficient sets; 3 does not divide the 4 x 4 sub-blocks of the MFMA
     # contraction, so the window uses the per-pixel kernel
