@@ -56,8 +56,10 @@ enum {
   LMA_PTR_DEVICE = 1,        /* pointer arguments are device pointers                */
   LMA_ACCUMULATE = 2,        /* image += weight * I instead of image = weight * I     */
   LMA_HOST_ONLY = 4,         /* lma_build_basis: plan on the host, no device work     */
-  LMA_CONTRACT_PER_PIXEL = 8 /* lma_probe_image: per-pixel VALU contraction even where  */
+  LMA_CONTRACT_PER_PIXEL = 8,/* lma_probe_image: per-pixel VALU contraction even where  */
                              /* the banded MFMA GEMM applies (a cross-check)          */
+  LMA_OWN_STREAM = 16        /* lma_build_basis: the plan creates its own non-blocking */
+                             /* stream (default priority) and destroys it with the plan */
 };
 
 /* Microscope and grid: eqs. probe_wave_function, aberration_function, aperture_function,
@@ -145,7 +147,8 @@ lma_status lma_electron_constants(double kv, double* wavelength, double* sigma);
  * the L nearest translates of every coefficient set and their least-squares coefficients
  * (Sec. 4.2.2, computed on the host in FP64), and the translates the scan window needs.
  * Uploads the tables and allocates the resident basis unless flags has LMA_HOST_ONLY.
- * hip_stream: a hipStream_t (may be NULL). On success *out owns the plan. */
+ * hip_stream: a hipStream_t (may be NULL; ignored with LMA_OWN_STREAM). On success *out
+ * owns the plan. */
 lma_status lma_build_basis(const lma_optics* optics, const lma_lattice* lattice,
                            const lma_detectors* detectors, void* hip_stream, int32_t flags,
                            lma_plan** out);
@@ -198,9 +201,67 @@ lma_status lma_recompute_local(lma_plan* plan, const float* potential_new, int32
                                const int32_t bbox_px[4], double radius_A, double* image,
                                int32_t* n_translates_redone, int32_t* n_probes_redone);
 
+/* Blocks until every piece of work the plan has queued on its stream has finished. */
+lma_status lma_synchronize(lma_plan* plan);
+
 /* Device bytes a plan with these arguments would hold for nslices slices. */
 lma_status lma_footprint(const lma_optics* optics, const lma_lattice* lattice,
                          const lma_detectors* detectors, int32_t nslices, int64_t* bytes);
+
+/* ------------------------------------------------------------------------------------------
+ * Serving: a request loop with continuous batching over resident specimens.
+ *
+ * A server holds up to max_specimens resident plans (specimens), each on its own stream, and
+ * runs requests on `slots` worker threads. Requests of one specimen run one at a time in
+ * submission order; requests of different specimens run concurrently, so work that arrives
+ * while others are on the GPU starts as soon as a slot is free and overlaps on the device.
+ * Building a specimen is admitted by its device footprint (lma_footprint for the request's
+ * nslices) against budget_bytes; builds are admitted in submission order and wait until
+ * released specimens free enough memory. Latency is measured from submission to completion
+ * of the request's device work.
+ * ---------------------------------------------------------------------------------------- */
+typedef struct lma_server lma_server;
+
+enum {
+  LMA_REQ_BUILD = 1,    /* lma_build_basis (own stream) for `specimen`                     */
+  LMA_REQ_IMAGE = 2,    /* lma_image: the specimen's LMA image for a potential              */
+  LMA_REQ_EDIT = 3,     /* lma_recompute_local after a local edit (host image, patched)     */
+  LMA_REQ_PLAIN = 4,    /* lma_plain_image: plain multislice image of the specimen's window */
+  LMA_REQ_RELEASE = 5   /* lma_destroy: frees the specimen's device memory                  */
+};
+
+typedef struct {
+  int32_t kind;                    /* LMA_REQ_*                                             */
+  int32_t specimen;                /* 0 <= specimen < max_specimens                         */
+  const lma_optics* optics;        /* BUILD: copied at submission                           */
+  const lma_lattice* lattice;      /* BUILD: copied at submission                           */
+  const lma_detectors* detectors;  /* BUILD: copied at submission (ring arrays too)         */
+  const float* potential;          /* IMAGE, PLAIN, EDIT: [nslices][ny][nx]; the caller    */
+                                   /* keeps it valid until the request has completed       */
+  int32_t nslices;                 /* IMAGE, PLAIN, EDIT; BUILD: slices the footprint holds */
+  double* image;                   /* IMAGE, PLAIN: [n_det][h][w] (host, or device with    */
+                                   /* LMA_PTR_DEVICE); EDIT: host image patched in place   */
+  int32_t flags;                   /* IMAGE, PLAIN: LMA_PTR_DEVICE, LMA_ACCUMULATE          */
+  double weight;                   /* IMAGE, PLAIN                                          */
+  int32_t bbox[4];                 /* EDIT: edited pixels x0, y0, x1, y1 (half-open)        */
+  double radius;                   /* EDIT: recompute radius, Angstrom                      */
+} lma_request;
+
+/* slots >= 1 worker threads, 1 <= max_specimens <= 4096, budget_bytes > 0. */
+lma_status lma_server_create(int32_t slots, int32_t max_specimens, int64_t budget_bytes, lma_server** out);
+/* Queues a request (arguments checked here) and returns its ticket (>= 1). LMA_ERR_ARG for a
+ * malformed request; the status of the work itself is reported by lma_server_wait. */
+lma_status lma_server_submit(lma_server* server, const lma_request* request, int64_t* ticket);
+/* Blocks until the ticket's request has completed and returns its status (the call's own
+ * lma_status, with its message in lma_last_error); latency_ms (submission to completion) and
+ * service_ms (start to completion) may be NULL. Each ticket can be waited for once. */
+lma_status lma_server_wait(lma_server* server, int64_t ticket, double* latency_ms, double* service_ms);
+/* The specimen's resident plan (NULL if none); valid until a RELEASE of it completes. */
+lma_status lma_server_plan(lma_server* server, int32_t specimen, lma_plan** plan);
+/* Device bytes admitted (footprints of resident and building specimens). */
+lma_status lma_server_in_use(lma_server* server, int64_t* bytes);
+/* Runs every queued request, stops the workers and destroys the resident plans. */
+void lma_server_destroy(lma_server* server);
 
 /* Inspection (host logic; work on host-only plans). Arrays are caller-allocated with the
  * sizes given by lma_plan_info. */

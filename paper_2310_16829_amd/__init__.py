@@ -13,11 +13,13 @@ import numpy as np
 
 from . import _lib
 from ._lib import (LMA_ACCUMULATE, LMA_BASIS_PROBE, LMA_CONTRACT_PER_PIXEL, LMA_GEMM_FP32, LMA_GEMM_SPLIT_BF16,
-                   LMA_HOST_ONLY, LMA_PTR_DEVICE, lma_detectors, lma_info, lma_kernel_time, lma_lattice, lma_optics)
+                   LMA_HOST_ONLY, LMA_OWN_STREAM, LMA_PTR_DEVICE, LMA_REQ_BUILD, LMA_REQ_EDIT, LMA_REQ_IMAGE,
+                   LMA_REQ_PLAIN, LMA_REQ_RELEASE, lma_detectors, lma_info, lma_kernel_time, lma_lattice, lma_optics,
+                   lma_request)
 
 __all__ = ["LmaError", "Plan", "electron_constants", "footprint", "optics", "lattice", "detectors",
            "LMA_ACCUMULATE", "LMA_PTR_DEVICE", "LMA_HOST_ONLY", "LMA_GEMM_FP32", "LMA_GEMM_SPLIT_BF16",
-           "LMA_BASIS_PROBE", "LMA_CONTRACT_PER_PIXEL", "lib"]
+           "LMA_BASIS_PROBE", "LMA_CONTRACT_PER_PIXEL", "LMA_OWN_STREAM", "Server", "lib"]
 
 
 class LmaError(RuntimeError):
@@ -239,3 +241,108 @@ class Plan:
         n = C.c_int32()
         _check(lib().lma_get_timing(self._h, arr, 32, C.byref(n), int(bool(reset))))
         return {arr[i].name.decode(): (arr[i].launches, arr[i].total_ms) for i in range(n.value)}
+
+
+class Server:
+    """An lma_server: requests on resident specimens, run by `slots` worker threads of the
+    library with continuous batching (see include/lma.h). Every buffer a request names is
+    kept referenced here until its ticket has been waited for. Device tensors are made ready
+    (the current torch stream is synchronised) before a request that reads them is queued."""
+
+    def __init__(self, slots: int, max_specimens: int, budget_bytes: int):
+        self._h = C.c_void_p()
+        _check(lib().lma_server_create(int(slots), int(max_specimens), int(budget_bytes), C.byref(self._h)))
+        self._keep = {}
+
+    def _submit(self, req, keep):
+        t = C.c_int64()
+        _check(lib().lma_server_submit(self._h, C.byref(req), C.byref(t)))
+        self._keep[t.value] = (req, keep)
+        return t.value
+
+    @staticmethod
+    def _ready(*xs):
+        if any(_is_torch(x) for x in xs):
+            import torch
+            torch.cuda.current_stream().synchronize()
+
+    def build(self, specimen: int, opt: lma_optics, lat: lma_lattice, det: "_Detectors", nslices: int) -> int:
+        r = lma_request()
+        r.kind, r.specimen, r.nslices = LMA_REQ_BUILD, int(specimen), int(nslices)
+        r.optics, r.lattice, r.detectors = C.pointer(opt), C.pointer(lat), C.pointer(det.s)
+        return self._submit(r, (opt, lat, det))
+
+    def _image_request(self, kind, specimen, potential, image, flags, weight):
+        pp, fp = _ptr(potential, np.float32)
+        pi, fi = _ptr(image, np.float64)
+        if fp != fi:
+            raise ValueError("potential and image must both be host or both be device")
+        self._ready(potential, image)
+        r = lma_request()
+        r.kind, r.specimen, r.nslices = kind, int(specimen), int(potential.shape[0])
+        r.potential, r.image, r.flags, r.weight = pp.value, pi.value, int(flags) | fi, float(weight)
+        return self._submit(r, (potential, image))
+
+    def image(self, specimen: int, potential, image, flags: int = 0, weight: float = 1.0) -> int:
+        return self._image_request(LMA_REQ_IMAGE, specimen, potential, image, flags, weight)
+
+    def plain(self, specimen: int, potential, image, flags: int = 0, weight: float = 1.0) -> int:
+        return self._image_request(LMA_REQ_PLAIN, specimen, potential, image, flags, weight)
+
+    def edit(self, specimen: int, potential: np.ndarray, bbox, radius: float, image: np.ndarray) -> int:
+        pp, fp = _ptr(potential, np.float32)
+        pi, fi = _ptr(image, np.float64)
+        if fp or fi:
+            raise ValueError("an edit takes a host potential and patches a host image")
+        r = lma_request()
+        r.kind, r.specimen, r.nslices = LMA_REQ_EDIT, int(specimen), int(potential.shape[0])
+        r.potential, r.image, r.radius = pp.value, pi.value, float(radius)
+        for i in range(4):
+            r.bbox[i] = int(bbox[i])
+        return self._submit(r, (potential, image))
+
+    def release(self, specimen: int) -> int:
+        r = lma_request()
+        r.kind, r.specimen = LMA_REQ_RELEASE, int(specimen)
+        return self._submit(r, ())
+
+    def wait(self, ticket: int):
+        """(latency_ms, service_ms) of a completed request; raises LmaError if it failed."""
+        lat, svc = C.c_double(), C.c_double()
+        try:
+            _check(lib().lma_server_wait(self._h, int(ticket), C.byref(lat), C.byref(svc)))
+        finally:
+            self._keep.pop(int(ticket), None)
+        return lat.value, svc.value
+
+    def plan_info(self, specimen: int) -> lma_info:
+        h = C.c_void_p()
+        _check(lib().lma_server_plan(self._h, int(specimen), C.byref(h)))
+        if not h.value:
+            raise LmaError(_lib.LMA_ERR_STATE, f"specimen {specimen} is not resident")
+        i = lma_info()
+        _check(lib().lma_plan_info(h, C.byref(i)))
+        return i
+
+    def in_use(self) -> int:
+        b = C.c_int64()
+        _check(lib().lma_server_in_use(self._h, C.byref(b)))
+        return b.value
+
+    def close(self):
+        if self._h:
+            lib().lma_server_destroy(self._h)
+            self._h = C.c_void_p()
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

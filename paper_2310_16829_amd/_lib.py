@@ -10,7 +10,8 @@ LIB_PATH = os.path.join(_HERE, "liblma.so")
 LMA_OK, LMA_ERR_ARG, LMA_ERR_OOM, LMA_ERR_DEVICE, LMA_ERR_STATE, LMA_ERR_UNSUPPORTED = 0, -1, -2, -3, -4, -5
 LMA_BASIS_PROBE = 0
 LMA_GEMM_FP32, LMA_GEMM_SPLIT_BF16 = 0, 1
-LMA_PTR_DEVICE, LMA_ACCUMULATE, LMA_HOST_ONLY, LMA_CONTRACT_PER_PIXEL = 1, 2, 4, 8
+LMA_PTR_DEVICE, LMA_ACCUMULATE, LMA_HOST_ONLY, LMA_CONTRACT_PER_PIXEL, LMA_OWN_STREAM = 1, 2, 4, 8, 16
+LMA_REQ_BUILD, LMA_REQ_IMAGE, LMA_REQ_EDIT, LMA_REQ_PLAIN, LMA_REQ_RELEASE = 1, 2, 3, 4, 5
 
 
 class lma_optics(C.Structure):
@@ -42,6 +43,13 @@ class lma_info(C.Structure):
                 ("resident_rows", C.c_int64), ("multislice_calls", C.c_int64)]
 
 
+class lma_request(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("specimen", C.c_int32), ("optics", C.POINTER(lma_optics)),
+                ("lattice", C.POINTER(lma_lattice)), ("detectors", C.POINTER(lma_detectors)),
+                ("potential", C.c_void_p), ("nslices", C.c_int32), ("image", C.c_void_p), ("flags", C.c_int32),
+                ("weight", C.c_double), ("bbox", C.c_int32 * 4), ("radius", C.c_double)]
+
+
 class lma_kernel_time(C.Structure):
     _fields_ = [("name", C.c_char * 32), ("launches", C.c_int64), ("total_ms", C.c_double)]
 
@@ -70,6 +78,13 @@ SIGNATURES = {
     "lma_set_timing": (C.c_int, [P, C.c_int32]),
     "lma_get_timing": (C.c_int, [P, C.POINTER(lma_kernel_time), C.c_int32, C.POINTER(C.c_int32), C.c_int32]),
     "lma_destroy": (None, [P]),
+    "lma_synchronize": (C.c_int, [P]),
+    "lma_server_create": (C.c_int, [C.c_int32, C.c_int32, C.c_int64, C.POINTER(P)]),
+    "lma_server_submit": (C.c_int, [P, C.POINTER(lma_request), C.POINTER(C.c_int64)]),
+    "lma_server_wait": (C.c_int, [P, C.c_int64, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "lma_server_plan": (C.c_int, [P, C.c_int32, C.POINTER(P)]),
+    "lma_server_in_use": (C.c_int, [P, C.POINTER(C.c_int64)]),
+    "lma_server_destroy": (None, [P]),
     "lma_last_error": (C.c_char_p, []),
 }
 

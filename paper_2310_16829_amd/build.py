@@ -16,7 +16,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "liblma.so")
 
-HOST_SOURCES = ["planner.cpp", "lsq.cpp", "stencil.cpp", "partition.cpp"]
+HOST_SOURCES = ["planner.cpp", "lsq.cpp", "stencil.cpp", "partition.cpp", "server.cpp"]
 HIP_SOURCES = ["kernels.hip", "abi.hip"]
 ARCH = "gfx950"
 
@@ -42,7 +42,7 @@ def build(verbose: bool = False) -> str:
     objs = []
     for src in HOST_SOURCES:
         obj = os.path.join(BUILD, src + ".o")
-        _run(["g++", "-std=c++17", "-O2", "-fPIC", "-ffp-contract=off", "-Wall", "-I", INCLUDE,
+        _run(["g++", "-std=c++17", "-O2", "-fPIC", "-ffp-contract=off", "-Wall", "-pthread", "-I", INCLUDE,
               "-c", os.path.join(CSRC, src), "-o", obj])
         objs.append(obj)
     hipcc = _hipcc()
@@ -53,7 +53,7 @@ def build(verbose: bool = False) -> str:
               "-I", INCLUDE, "-I", CSRC, "-c", os.path.join(CSRC, src), "-o", obj])
         objs.append(obj)
     tmp = LIB + ".tmp"
-    _run([hipcc, "-shared", f"--offload-arch={ARCH}", "-o", tmp] + objs)
+    _run([hipcc, "-shared", f"--offload-arch={ARCH}", "-pthread", "-o", tmp] + objs)
     os.replace(tmp, LIB)
     if verbose:
         print("built", LIB)

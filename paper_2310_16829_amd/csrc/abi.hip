@@ -45,6 +45,7 @@ struct lma_plan {
   HostPlan h;
   bool host_only = false;
   hipStream_t stream = nullptr;
+  bool own_stream = false;           // created by lma_build_basis (LMA_OWN_STREAM)
   int device = 0;
   int B = 1;                         // waves per batch
   bool basis_valid = false;
@@ -393,6 +394,10 @@ int64_t footprint_of(const HostPlan& h, int B, int nslices, bool with_basis) {
 // ==============================================================================================
 // extern "C"
 // ==============================================================================================
+namespace lma {
+void set_last_error(const std::string& msg) { g_last_error = msg; }
+}  // namespace lma
+
 extern "C" {
 
 const char* lma_last_error(void) { return g_last_error.c_str(); }
@@ -431,6 +436,7 @@ static void release(lma_plan* p) {
   }
   for (auto e : p->event_pool) (void)hipEventDestroy(e);
   for (void* a : p->allocs) (void)hipFree(a);
+  if (p->own_stream && p->stream) (void)hipStreamDestroy(p->stream);
   delete p;
 }
 
@@ -461,6 +467,15 @@ lma_status lma_build_basis(const lma_optics* optics, const lma_lattice* lattice,
     if (!p->host_only && hipGetDevice(&p->device) != hipSuccess) {
       delete p;
       return fail(LMA_ERR_DEVICE, "no HIP device");
+    }
+    if (!p->host_only && (flags & LMA_OWN_STREAM)) {
+      // non-blocking: the plan's work never waits for, or holds up, the legacy default stream
+      if (hipStreamCreateWithFlags(&p->stream, hipStreamNonBlocking) != hipSuccess) {
+        (void)hipGetLastError();
+        delete p;
+        return fail(LMA_ERR_DEVICE, "stream creation failed");
+      }
+      p->own_stream = true;
     }
     // residency (Sec. 4.2.4): the whole window's basis, or a rectangle partition when it needs
     // more than M = budget / (D x 8 B) propagated translates
@@ -790,6 +805,14 @@ lma_status lma_recompute_local(lma_plan* plan, const float* potential_new, int32
   } catch (const std::exception& e) {
     return fail(LMA_ERR_DEVICE, e.what());
   }
+}
+
+lma_status lma_synchronize(lma_plan* plan) {
+  if (!plan) return fail(LMA_ERR_ARG, "plan is null");
+  if (plan->host_only) return LMA_OK;
+  hipError_t e = hipStreamSynchronize(plan->stream);
+  if (e != hipSuccess) return fail(LMA_ERR_DEVICE, std::string("hipStreamSynchronize: ") + hipGetErrorString(e));
+  return LMA_OK;
 }
 
 lma_status lma_plan_info(const lma_plan* p, lma_info* out) {

@@ -142,3 +142,8 @@ void probe_translates(const HostPlan& h, int a, int b, std::vector<int32_t>* out
 bool build_partition(const HostPlan& h, int64_t max_rows, int gx, int gy, PartPlan* pp, std::string* why);
 
 }  // namespace lma
+
+namespace lma {
+// Sets the calling thread's lma_last_error message.
+void set_last_error(const std::string& msg);
+}  // namespace lma

@@ -230,3 +230,63 @@ def test_partition_budget_below_one_rectangle_is_refused():
     with pytest.raises(lma.LmaError) as e:
         lma.Plan(opt, lat, det, flags=lma.LMA_HOST_ONLY)
     assert e.value.status == _lib.LMA_ERR_OOM
+
+
+# ---------------------------------------------------------------------------------------
+# serving loop: argument checks and host-side bookkeeping (no device work)
+# ---------------------------------------------------------------------------------------
+def test_server_arguments():
+    with pytest.raises(lma.LmaError) as e:
+        lma.Server(0, 4, 1 << 30)
+    assert e.value.status == _lib.LMA_ERR_ARG
+    with pytest.raises(lma.LmaError):
+        lma.Server(2, 0, 1 << 30)
+    with pytest.raises(lma.LmaError):
+        lma.Server(2, 4, 0)
+    w = WORKLOADS["tiny"]
+    opt, lat, det = _plan_args(w)
+    need = lma.footprint(opt, lat, det, w.nslices)
+    with lma.Server(2, 4, need - 1) as s:
+        with pytest.raises(lma.LmaError) as e:
+            s.build(0, opt, lat, det, w.nslices)          # can never be admitted
+        assert e.value.status == _lib.LMA_ERR_OOM
+        with pytest.raises(lma.LmaError) as e:
+            s.build(4, opt, lat, det, w.nslices)          # no such specimen slot
+        assert e.value.status == _lib.LMA_ERR_ARG
+        with pytest.raises(lma.LmaError) as e:
+            s.wait(99)
+        assert e.value.status == _lib.LMA_ERR_ARG
+        assert s.in_use() == 0
+
+
+def test_server_reports_request_failures():
+    # a request on a specimen that was never built fails with LMA_ERR_STATE; the server keeps
+    # running and a release of an empty slot succeeds
+    w = WORKLOADS["tiny"]
+    with lma.Server(2, 4, 1 << 30) as s:
+        v = np.zeros((w.nslices, w.ny, w.nx), dtype=np.float32)
+        img = np.zeros((4, 16, 16))
+        t = s.image(1, v, img)
+        with pytest.raises(lma.LmaError) as e:
+            s.wait(t)
+        assert e.value.status == _lib.LMA_ERR_STATE and "not resident" in str(e.value)
+        lat, svc = s.wait(s.release(1))
+        assert lat >= svc >= 0.0
+        assert s.in_use() == 0
+
+
+def test_server_build_failure_returns_its_bytes():
+    # on a machine without a GPU the build itself fails; its admitted footprint is returned
+    try:
+        import torch
+        if torch.cuda.is_available():
+            pytest.skip("a GPU is present: the build would succeed")
+    except ImportError:
+        pass
+    w = WORKLOADS["tiny"]
+    opt, lat, det = _plan_args(w)
+    with lma.Server(1, 2, 1 << 34) as s:
+        with pytest.raises(lma.LmaError) as e:
+            s.wait(s.build(0, opt, lat, det, w.nslices))
+        assert e.value.status == _lib.LMA_ERR_DEVICE
+        assert s.in_use() == 0
