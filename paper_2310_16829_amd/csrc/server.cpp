@@ -205,6 +205,7 @@ lma_status lma_server_create(int32_t slots, int32_t max_specimens, int64_t budge
 }
 
 lma_status lma_server_submit(lma_server* s, const lma_request* r, int64_t* ticket) {
+  const Clock::time_point submitted = Clock::now();
   if (!s || !r || !ticket) return server_fail(LMA_ERR_ARG, "null argument");
   if (r->specimen < 0 || r->specimen >= (int32_t)s->spec.size()) return server_fail(LMA_ERR_ARG, "specimen out of range");
   Request q;
@@ -238,7 +239,7 @@ lma_status lma_server_submit(lma_server* s, const lma_request* r, int64_t* ticke
   q.r.optics = nullptr;
   q.r.lattice = nullptr;
   q.r.detectors = nullptr;
-  q.submitted = Clock::now();
+  q.submitted = submitted;
   {
     std::lock_guard<std::mutex> lk(s->m);
     if (s->stopping) return server_fail(LMA_ERR_STATE, "server is stopping");
