@@ -217,6 +217,99 @@ def summarize_counters(fetch_dir, write_dir, cal_fetch_dir, cal_write_dir):
                       "kernels": kernels}, indent=1))
 
 
+def serve(rates=(2.0, 10.0, 50.0, 200.0), n_requests=60, slots=4):
+    """Serving under Poisson arrivals: six resident specimens of mixed sizes (128^2 x 10 slices,
+    256^2 x 20 slices, the 512^2 x 100-slice medium specimen on a 16 x 16-probe window), 70 %
+    image requests (a new frozen-phonon configuration of a random specimen) and 30 % local edits
+    (one raised 12 x 12-pixel column patch of a random specimen, recomputed locally), run by
+    the library's request loop with `slots` worker slots. Reports p50 / p99 latency (arrival to
+    completion) and throughput per arrival rate."""
+    import numpy as np
+    import torch
+    import paper_2310_16829_amd as lma
+    from synth import WORKLOADS, potential_slices
+
+    rng = np.random.default_rng(2024)
+    wt, wm = WORKLOADS["tiny"], WORKLOADS["medium"]
+    lam, sig = lma.electron_constants(200.0)
+    rings = [(a * 1e-3, b * 1e-3) for _, a, b in wt.detectors[1:]]
+    specs = []
+    for n, nsl, kind in ((128, 10, "tiny"), (128, 10, "tiny"), (256, 20, "mid"), (256, 20, "mid"),
+                         (512, 100, "medium"), (512, 100, "medium")):
+        l = n * 0.1
+        opt = lma.optics(n, n, l, l, lam, sig, 2.0, 2.0 / 3.0, 0.02)
+        if kind == "medium":
+            a0, b0 = (int(x) for x in rng.integers(0, 112, size=2))
+            lat = lma.lattice(128, 128, 128, 128, 1, (0.5, 0.5), 144, window=(a0, b0, 16, 16))
+            pots = [potential_slices(wm, c) for c in range(2)]
+        else:
+            lat = lma.lattice(n // 8, n // 8, n // 4, n // 4, 1, (0.5, 0.5), 36)
+            pots = [rng.uniform(0, 40, size=(nsl, n, n)).astype(np.float32) for _ in range(2)]
+        shape = (len(rings), lat.window[3] or lat.py, lat.window[2] or lat.px)
+        specs.append(dict(opt=opt, lat=lat, det=lma.detectors(rings), pots=[torch.from_numpy(v).cuda() for v in pots],
+                          host=pots[0], n=n, shape=shape, kind=kind))
+    torch.cuda.synchronize()
+    budget = 64 << 30
+    out = {"study": "serving: Poisson arrivals over 6 resident specimens (2 x 128^2 x 10 slices, 2 x 256^2 x 20 "
+                    "slices, 2 x the medium 512^2 x 100-slice specimen on 16 x 16-probe windows), 70 % LMA "
+                    "images, 30 % local edits", "slots": slots, "rates": []}
+    with lma.Server(slots, len(specs), budget) as srv:
+        t = [srv.build(k, s["opt"], s["lat"], s["det"], s["pots"][0].shape[0]) for k, s in enumerate(specs)]
+        for x in t:
+            srv.wait(x)
+        for k, s in enumerate(specs):
+            srv.wait(srv.image(k, s["pots"][0], torch.zeros(s["shape"], dtype=torch.float64, device="cuda")))
+        out["resident_bytes"] = srv.in_use()
+        for rate in rates:
+            n_req = max(16, min(n_requests, int(rate * 8)))     # about 8 s of arrivals at most
+            gaps = rng.exponential(1.0 / rate, size=n_req)
+            reqs = []
+            for i in range(n_req):
+                k = int(rng.integers(0, len(specs)))
+                if rng.random() < 0.3:
+                    s = specs[k]
+                    v = s["host"].copy()
+                    x0, y0 = (int(q) for q in rng.integers(0, s["n"] - 12, size=2))
+                    v[:, y0:y0 + 12, x0:x0 + 12] += 15.0
+                    reqs.append(("edit", k, v, (x0, y0, x0 + 12, y0 + 12)))
+                else:
+                    reqs.append(("image", k, int(rng.integers(0, 2)), None))
+            torch.cuda.synchronize()
+            tickets = []
+            t0 = time.monotonic()
+            arrival = t0
+            for (kind, k, arg, bbox), gap in zip(reqs, gaps):
+                arrival += gap
+                delay = arrival - time.monotonic()
+                if delay > 0:
+                    time.sleep(delay)
+                s = specs[k]
+                if kind == "edit":
+                    tickets.append((kind, srv.edit(k, arg, bbox, 2.0, np.zeros(s["shape"]))))
+                else:
+                    img = torch.empty(s["shape"], dtype=torch.float64, device="cuda")
+                    tickets.append((kind, srv.image(k, s["pots"][arg], img)))
+            lat = {"image": [], "edit": []}
+            svc = []
+            for kind, tk in tickets:
+                l, sv = srv.wait(tk)
+                lat[kind].append(l)
+                svc.append(sv)
+            wall = time.monotonic() - t0
+            allv = lat["image"] + lat["edit"]
+            row = {"rate_per_s": rate, "requests": n_req, "throughput_per_s": n_req / wall,
+                   "p50_ms": float(np.percentile(allv, 50)), "p99_ms": float(np.percentile(allv, 99)),
+                   "image_p50_ms": float(np.percentile(lat["image"], 50)) if lat["image"] else None,
+                   "image_p99_ms": float(np.percentile(lat["image"], 99)) if lat["image"] else None,
+                   "edit_p50_ms": float(np.percentile(lat["edit"], 50)) if lat["edit"] else None,
+                   "edit_p99_ms": float(np.percentile(lat["edit"], 99)) if lat["edit"] else None,
+                   "mean_service_ms": float(np.mean(svc))}
+            log(f"serve: rate {rate}/s: p50 {row['p50_ms']:.1f} ms, p99 {row['p99_ms']:.1f} ms, "
+                f"{row['throughput_per_s']:.1f} req/s")
+            out["rates"].append(row)
+    print(json.dumps(out), flush=True)
+
+
 def paper_shaped():
     """The paper's local-edit experiment in shape (1024^2 px over 84.536 x 79.941 A, scan
     424 x 400, I = P + p/2, f = 2, L = 59, 200 kV, 26 mrad, Z = 100 A, C_s = -2000 A) with the
@@ -331,6 +424,8 @@ def main():
                     help="LMA at translate spacings 4, 8, 16 px against plain multislice (one configuration)")
     ap.add_argument("--summarize-counters", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "CAL_FETCH_DIR", "CAL_WRITE_DIR"),
                     help="print the HBM-traffic summary (JSON) of four rocprofv3 --pmc output directories")
+    ap.add_argument("--serve", action="store_true",
+                    help="p50/p99 latency of the request loop under Poisson arrivals of image and local-edit requests")
     ap.add_argument("--paper-shaped", action="store_true",
                     help="LMA against plain multislice in the paper's regime (1024^2, 424x400 scan, f=2)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -362,6 +457,9 @@ def main():
     w = WORKLOADS[WORKLOAD]
     if args.paper_shaped:
         paper_shaped()
+        return
+    if args.serve:
+        serve()
         return
     if args.spacing_study:
         spacing_study(w)
