@@ -245,9 +245,10 @@ struct PassCfg {
   static constexpr bool WL = T <= 64;                               // transform inside one wavefront
   static constexpr int S = WL ? ((64 / T) < TW ? 64 / T : TW) : 1;  // transforms per wavefront
   static constexpr int WPT = WL ? 1 : T / 64;                       // wavefronts per transform
-  // wavefronts per workgroup: up to 4 single-wavefront transforms, or 8 wavefronts of
-  // multi-wavefront transforms (several lines in flight between the workgroup barriers)
-  static constexpr int KMW = (8 / WPT) < TW ? (8 / WPT > 0 ? 8 / WPT : 1) : TW;
+  // wavefronts per workgroup: single-wavefront transforms up to WLW lines at once; lines of
+  // several wavefronts two at a time between the workgroup barriers (4 wavefronts at 1024
+  // points, 8 at 2048)
+  static constexpr int KMW = TW < 2 ? TW : 2;   // multi-wavefront transforms in flight
   static constexpr int WAVES = WL ? ((TW / S) < WLW ? TW / S : WLW) : WPT * KMW;
   static constexpr int TPB = WAVES * S / WPT;                       // transforms in flight
   static constexpr int RPW = TW / TPB;                              // rounds per workgroup
@@ -853,6 +854,17 @@ static hipError_t pass_dispatch(int N, int TW, int lines, const PassArgs& a, int
       case 256: return pass_launch<256, 16, MODE>(a, lines, B, s);
       case 512: return pass_launch<512, 16, MODE>(a, lines, B, s);
     }
+  } else if (TW == 4) {
+    switch (N) {
+      case 16: return pass_launch<16, 4, MODE>(a, lines, B, s);
+      case 32: return pass_launch<32, 4, MODE>(a, lines, B, s);
+      case 64: return pass_launch<64, 4, MODE>(a, lines, B, s);
+      case 128: return pass_launch<128, 4, MODE>(a, lines, B, s);
+      case 256: return pass_launch<256, 4, MODE>(a, lines, B, s);
+      case 512: return pass_launch<512, 4, MODE>(a, lines, B, s);
+      case 1024: return pass_launch<1024, 4, MODE>(a, lines, B, s);
+      case 2048: return pass_launch<2048, 4, MODE>(a, lines, B, s);
+    }
   } else if (TW == 8) {
     switch (N) {
       case 16: return pass_launch<16, 8, MODE>(a, lines, B, s);
@@ -868,12 +880,14 @@ static hipError_t pass_dispatch(int N, int TW, int lines, const PassArgs& a, int
   return hipErrorInvalidValue;
 }
 
-// 8 x 8 tiles (512 B) keep the LDS tile of a workgroup at ~41 KB for 512-point lines, so three
-// workgroups share a CU; 16 x 16 tiles (2 KB) measured slower on gfx950 and need N <= 512.
-static int g_tile_width = 0;   // 0: default; 8 or 16 forces a tile width (tuning)
-void set_tile_width(int tw) { g_tile_width = (tw == 8 || tw == 16) ? tw : 0; }
+// 8 x 8 tiles (512 B) keep the LDS tile of a workgroup at ~41 KB for 512-point lines, so several
+// workgroups share a CU; grids with a side above 512 use 4 x 4 tiles (128 B), which halve the
+// LDS tile and prefetch registers of the long-line workgroups (measured +28 % at 1024^2);
+// 16 x 16 tiles (2 KB) measured slower and need N <= 512.
+static int g_tile_width = 0;   // 0: default; 4, 8 or 16 forces a tile width (tuning)
+void set_tile_width(int tw) { g_tile_width = (tw == 4 || tw == 8 || tw == 16) ? tw : 0; }
 int tile_width(int nx, int ny) {
-  if (nx > 512 || ny > 512) return 8;
+  if (nx > 512 || ny > 512) return g_tile_width == 8 ? 8 : 4;
   return g_tile_width ? g_tile_width : 8;
 }
 
