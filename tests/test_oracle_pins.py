@@ -227,6 +227,22 @@ def test_lma_reduces_to_plain_multislice():
                   plain_image(st, v, probes)[:, [0, 2, 3], [0, 1, 3]]) < 1e-12
 
 
+def test_pixel_input_waves_with_every_translate_are_exact():
+    # Sec. 4.3: pixel input waves (u a delta, I the pixel lattice) with L = all translates
+    # represent any probe exactly, so LMA reproduces plain multislice
+    rng = np.random.default_rng(21)
+    st = _setup(nx=8, ny=8, lx=1.6, ly=1.6, scan=(2, 2), alpha=0.03)
+    lat = Lattice(st, (8, 8), 1, (0, 0), 64)
+    delta = np.ones((8, 8), dtype=np.complex128)          # DFT of a delta at the origin
+    lma = LMA(st, lat, spec_u=delta)
+    assert max(lma.residual.values()) < 1e-12
+    v = rng.uniform(0, 50, (3, 8, 8)).astype(np.float32)
+    probes = [(0, 0), (1, 0), (1, 1)]
+    got = lma.image(v, probes)[:, [0, 0, 1], [0, 1, 1]]
+    want = plain_image(st, v, probes)[:, [0, 0, 1], [0, 1, 1]]
+    assert rel_l2(got, want) < 1e-10
+
+
 def test_lma_case1_without_offset_is_exact():
     # R_f = 2 P and zero offset: every probe sits on a translate, alpha is a delta
     st = _setup(scan=(4, 4))
