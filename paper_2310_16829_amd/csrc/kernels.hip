@@ -967,9 +967,116 @@ hipError_t contract(const Contraction& c, hipStream_t s) {
   return wide ? contract_pt<0, 8>(c, np, s) : contract_pt<0, 1>(c, np, s);
 }
 
+// The same contraction with the K-steps of every sub-block split over two wavefronts (8 per
+// workgroup): each holds half of the A fragments, the halves' complex sums meet in LDS before
+// |psi|^2. Twice the wavefronts per workgroup fill the slab and hide each other's latency.
+template <int SPLIT, int KH>
+__global__ __launch_bounds__(512) void k_contract_mfma2(Stencil c) {
+  extern __shared__ unsigned char dyn[];
+  const int nt = c.W * c.H;
+  float2* slab = reinterpret_cast<float2*>(dyn);                          // [nt][16]
+  int32_t* rowid = reinterpret_cast<int32_t*>(slab + (size_t)nt * 16);    // [nt]
+  __shared__ f32x4 part[4][2][64];                                        // upper halves' sums
+  const int ti = c.tile_x0 + (int)blockIdx.x % c.tiles_x, tj = c.tile_y0 + (int)blockIdx.x / c.tiles_x;
+  const int chunk = blockIdx.y;
+  const int ox = (c.ox0 + ti * c.tile_dx) % c.Rfx;
+  const int oy = (c.oy0 + tj * c.tile_dy) % c.Rfy;
+  for (int t = threadIdx.x; t < nt; t += 512) {
+    const int x = t % c.W, y = t / c.W;
+    rowid[t] = c.row_of[((oy + y) % c.Rfy) * c.Rfx + (ox + x) % c.Rfx];
+  }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int sb = wv & 3, kh = wv >> 2;                  // sub-block, half of the K-steps
+  const int kk = lane >> 4, n = lane & 15;
+  const int k0 = kh * KH;
+  float2 A[KH];
+#pragma unroll
+  for (int q = 0; q < KH; ++q) A[q] = k0 + q < c.nks ? c.a[(k0 + q) * 64 + lane] : make_float2(0.f, 0.f);
+  const int base = (sb >> 1) * c.sub_dy * c.W + (sb & 1) * c.sub_dx + kk;
+  const int start = c.chunk_start[chunk], len = c.chunk_len[chunk];
+  const uint32_t mask = c.chunk_mask[chunk];
+  double val[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int d0 = 0; d0 < len; d0 += 16) {
+    __syncthreads();  // row ids written, previous slab and partial sums consumed
+    const int rem = len - d0;
+    constexpr int kFill = 4;
+    for (int i0 = threadIdx.x; i0 < nt * 16; i0 += 512 * kFill) {
+      float2 v[kFill];
+#pragma unroll
+      for (int u = 0; u < kFill; ++u) {
+        const int i = i0 + u * 512;
+        v[u] = make_float2(0.f, 0.f);
+        if (i < nt * 16) {
+          const int t = i >> 4, q = i & 15;
+          const int r = rowid[t];
+          if (r >= 0 && q < rem) v[u] = load_basis<SPLIT>(c.basis, (int64_t)r * c.D + start + d0 + q);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kFill; ++u) {
+        const int i = i0 + u * 512;
+        if (i < nt * 16) slab[i] = v[u];
+      }
+    }
+    __syncthreads();
+    f32x4 cre = {0.f, 0.f, 0.f, 0.f}, cim = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int q = 0; q < KH; ++q) {
+      if (k0 + q < c.nks) {
+        const float2 b = slab[(base + c.ks_off[k0 + q]) * 16 + n];
+        cre = __builtin_amdgcn_mfma_f32_16x16x4f32(A[q].x, b.x, cre, 0, 0, 0);
+        cim = __builtin_amdgcn_mfma_f32_16x16x4f32(A[q].x, b.y, cim, 0, 0, 0);
+        cre = __builtin_amdgcn_mfma_f32_16x16x4f32(-A[q].y, b.y, cre, 0, 0, 0);
+        cim = __builtin_amdgcn_mfma_f32_16x16x4f32(A[q].y, b.x, cim, 0, 0, 0);
+      }
+    }
+    if (kh == 1) {
+      part[sb][0][lane] = cre;
+      part[sb][1][lane] = cim;
+    }
+    __syncthreads();
+    if (kh == 0 && n < rem) {
+      cre += part[sb][0][lane];
+      cim += part[sb][1][lane];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) val[r] += (double)cre[r] * cre[r] + (double)cim[r] * cim[r];
+    }
+  }
+  if (kh != 0) return;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    double x = val[r];
+#pragma unroll
+    for (int o = 8; o > 0; o >>= 1) x += __shfl_xor(x, o);
+    val[r] = x;
+  }
+  if (n == 0) {
+    const int by = tj * 8 + (sb >> 1) * 4 + kk;
+    const int64_t stride = (int64_t)c.ww * c.wh;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int bx = ti * 8 + (sb & 1) * 4 + r;
+      if (bx < c.ww && by < c.wh) {
+        const double v = val[r] * c.scale;
+        for (int d = 0; d < c.ndet; ++d)
+          if (mask & (1u << d)) atomicAdd(c.img + (int64_t)d * stride + (int64_t)by * c.ww + bx, v);
+      }
+    }
+  }
+}
+
 template <int SPLIT, int KS>
 static hipError_t stencil_ks(const Stencil& c, hipStream_t s) {
   const size_t shm = (size_t)c.W * c.H * (16 * sizeof(float2) + sizeof(int32_t));
+  // split K over two wavefronts while each half keeps 4 wavefronts per SIMD (up to 80 K-steps)
+  if constexpr (KS <= 80) {
+    const void* fn = reinterpret_cast<const void*>(&k_contract_mfma2<SPLIT, KS / 2>);
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    if (e != hipSuccess) return e;
+    dim3 grid((unsigned)(c.tiles_x * c.tiles_y), (unsigned)c.nchunks);
+    k_contract_mfma2<SPLIT, KS / 2><<<grid, 512, shm, s>>>(c);
+    return hipGetLastError();
+  }
   const void* fn = reinterpret_cast<const void*>(&k_contract_mfma<SPLIT, KS>);
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
   if (e != hipSuccess) return e;
@@ -984,6 +1091,7 @@ static hipError_t stencil_split(const Stencil& c, hipStream_t s) {
   if (c.nks <= 32) return stencil_ks<SPLIT, 32>(c, s);
   if (c.nks <= 48) return stencil_ks<SPLIT, 48>(c, s);
   if (c.nks <= 64) return stencil_ks<SPLIT, 64>(c, s);
+  if (c.nks <= 68) return stencil_ks<SPLIT, 68>(c, s);
   if (c.nks <= 80) return stencil_ks<SPLIT, 80>(c, s);
   return stencil_ks<SPLIT, 96>(c, s);
 }
