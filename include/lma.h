@@ -47,8 +47,12 @@ typedef enum {
 
 typedef struct lma_plan lma_plan;   /* opaque */
 
-/* lma_lattice.basis_kind */
-enum { LMA_BASIS_PROBE = 0 };                 /* u = psi_0^init (Sec. 4.2.3) */
+/* lma_lattice.basis_kind: the input wave u whose translates are propagated (Sec. 4.2.3) */
+enum {
+  LMA_BASIS_PROBE = 0,      /* u = psi_0^init, the probe at the origin                      */
+  LMA_BASIS_GAUSSIAN = 1    /* u = g_sigma(x) = exp(-|x|^2 / (2 sigma^2)), sigma = basis_param */
+                            /* (Angstrom; 0 selects lambda / (2 alpha_max))                  */
+};
 /* lma_lattice.precision: arithmetic of the probe-coefficient contraction */
 enum { LMA_GEMM_FP32 = 0, LMA_GEMM_SPLIT_BF16 = 1 };
 /* flags */
@@ -85,13 +89,14 @@ typedef struct {
   double offset_x, offset_y; /* I_offset as a fraction of r; must be a multiple of
                                 1/(2 lcm(P, R)) of the cell                           */
   int32_t L;                 /* nearest translates per probe, 1 <= L <= |I_f|         */
-  int32_t basis_kind;        /* LMA_BASIS_PROBE                                      */
+  int32_t basis_kind;        /* LMA_BASIS_PROBE or LMA_BASIS_GAUSSIAN                 */
   int32_t precision;         /* LMA_GEMM_FP32 | LMA_GEMM_SPLIT_BF16                  */
   int32_t window[4];         /* scan window a0, b0, width, height (0,0,0,0 = all)    */
   int32_t batch;             /* waves per propagation batch (0 = automatic)          */
   int64_t hbm_budget_bytes;  /* bytes the resident basis may hold: M = budget/(D x 8) */
                              /* propagated translates (Sec. 4.2.4); 0 = what free     */
                              /* device memory holds after the plan's other buffers    */
+  double basis_param;        /* LMA_BASIS_GAUSSIAN: sigma in Angstrom (0: default)     */
 } lma_lattice;
 
 /* 2-D STEM detectors (Sec. 3.1, step 3): ring r collects lambda|k| in [inner, outer). */
@@ -275,6 +280,8 @@ lma_status lma_get_coefficients(const lma_plan* plan, int32_t* translate, double
 lma_status lma_get_detector_pixels(const lma_plan* plan, int32_t* flat, uint32_t* mask);
 /* Normalised probe spectrum psi_0-hat (sum |.|^2 = XY), double [ny][nx][2]. */
 lma_status lma_get_probe_spectrum(const lma_plan* plan, double* spec);
+/* Normalised spectrum of the input wave u (sum |.|^2 = XY), double [ny][nx][2]. */
+lma_status lma_get_input_wave_spectrum(const lma_plan* plan, double* spec);
 /* Resident-basis rows first..first+count-1 (rows in increasing translate order, see
  * lma_get_rows): F(U_i) at the D detector pixels, float [count][D][2] on the host. */
 lma_status lma_get_basis_rows(lma_plan* plan, int32_t first, int32_t count, float* out);

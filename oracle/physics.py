@@ -73,6 +73,19 @@ def probe_spectrum(nx, ny, lx, ly, wavelength, alpha_max, defocus, cs) -> np.nda
     return spec * np.sqrt(nx * ny / nk)
 
 
+def gaussian_spectrum(nx, ny, lx, ly, sigma: float) -> np.ndarray:
+    """Input wave u = g_sigma(x) = exp(-|x|^2 / (2 sigma^2)) of Sec. 4.2.3 (Gaussians), centred
+    at the origin of the periodic cell: sampled on the grid with minimum-image distances, then
+    the DFT, scaled like the probe (sum_x |u|^2 = 1, so sum_k |u_hat|^2 = XY)."""
+    x = np.arange(nx) * (lx / nx)
+    y = np.arange(ny) * (ly / ny)
+    x = x - lx * np.round(x / lx)
+    y = y - ly * np.round(y / ly)
+    g = np.exp(-(x[None, :] ** 2 + y[:, None] ** 2) / (2.0 * sigma * sigma))
+    g = g / np.linalg.norm(g)
+    return np.fft.fft2(g)
+
+
 def shift_spectrum(spec: np.ndarray, lx: float, ly: float, pos) -> np.ndarray:
     """Spectrum of f(. - pos): multiply by the modulation mu_{-pos}(k) = exp(-2 pi i k.pos)
     (Sec. 4.1, translations become modulations)."""

@@ -12,14 +12,14 @@ import ctypes as C
 import numpy as np
 
 from . import _lib
-from ._lib import (LMA_ACCUMULATE, LMA_BASIS_PROBE, LMA_CONTRACT_PER_PIXEL, LMA_GEMM_FP32, LMA_GEMM_SPLIT_BF16,
+from ._lib import (LMA_ACCUMULATE, LMA_BASIS_GAUSSIAN, LMA_BASIS_PROBE, LMA_CONTRACT_PER_PIXEL, LMA_GEMM_FP32, LMA_GEMM_SPLIT_BF16,
                    LMA_HOST_ONLY, LMA_OWN_STREAM, LMA_PTR_DEVICE, LMA_REQ_BUILD, LMA_REQ_EDIT, LMA_REQ_IMAGE,
                    LMA_REQ_PLAIN, LMA_REQ_RELEASE, lma_detectors, lma_info, lma_kernel_time, lma_lattice, lma_optics,
                    lma_request)
 
 __all__ = ["LmaError", "Plan", "electron_constants", "footprint", "optics", "lattice", "detectors",
            "LMA_ACCUMULATE", "LMA_PTR_DEVICE", "LMA_HOST_ONLY", "LMA_GEMM_FP32", "LMA_GEMM_SPLIT_BF16",
-           "LMA_BASIS_PROBE", "LMA_CONTRACT_PER_PIXEL", "LMA_OWN_STREAM", "Server", "lib"]
+           "LMA_BASIS_PROBE", "LMA_BASIS_GAUSSIAN", "LMA_CONTRACT_PER_PIXEL", "LMA_OWN_STREAM", "Server", "lib"]
 
 
 class LmaError(RuntimeError):
@@ -49,7 +49,7 @@ def optics(nx, ny, lx, ly, wavelength, sigma, dz, bandlimit, alpha_max, defocus=
 
 
 def lattice(px, py, rx, ry, f=1, offset=(0.5, 0.5), L=1, precision=LMA_GEMM_FP32, window=(0, 0, 0, 0),
-            batch=0, hbm_budget_bytes=0, basis_kind=LMA_BASIS_PROBE) -> lma_lattice:
+            batch=0, hbm_budget_bytes=0, basis_kind=LMA_BASIS_PROBE, basis_param=0.0) -> lma_lattice:
     lat = lma_lattice()
     lat.px, lat.py, lat.rx, lat.ry, lat.f = int(px), int(py), int(rx), int(ry), int(f)
     lat.offset_x, lat.offset_y = float(offset[0]), float(offset[1])
@@ -57,6 +57,7 @@ def lattice(px, py, rx, ry, f=1, offset=(0.5, 0.5), L=1, precision=LMA_GEMM_FP32
     for i in range(4):
         lat.window[i] = int(window[i])
     lat.batch, lat.hbm_budget_bytes = int(batch), int(hbm_budget_bytes)
+    lat.basis_param = float(basis_param)
     return lat
 
 
@@ -217,6 +218,11 @@ class Plan:
         mask = np.zeros(n, dtype=np.uint32)
         _check(lib().lma_get_detector_pixels(self._h, C.c_void_p(flat.ctypes.data), C.c_void_p(mask.ctypes.data)))
         return flat, mask
+
+    def input_wave_spectrum(self) -> np.ndarray:
+        out = np.zeros((self.ny, self.nx, 2))
+        _check(lib().lma_get_input_wave_spectrum(self._h, C.c_void_p(out.ctypes.data)))
+        return out[..., 0] + 1j * out[..., 1]
 
     def probe_spectrum(self) -> np.ndarray:
         out = np.zeros((self.ny, self.nx, 2))

@@ -8,7 +8,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liblma.so")
 
 LMA_OK, LMA_ERR_ARG, LMA_ERR_OOM, LMA_ERR_DEVICE, LMA_ERR_STATE, LMA_ERR_UNSUPPORTED = 0, -1, -2, -3, -4, -5
-LMA_BASIS_PROBE = 0
+LMA_BASIS_PROBE, LMA_BASIS_GAUSSIAN = 0, 1
 LMA_GEMM_FP32, LMA_GEMM_SPLIT_BF16 = 0, 1
 LMA_PTR_DEVICE, LMA_ACCUMULATE, LMA_HOST_ONLY, LMA_CONTRACT_PER_PIXEL, LMA_OWN_STREAM = 1, 2, 4, 8, 16
 LMA_REQ_BUILD, LMA_REQ_IMAGE, LMA_REQ_EDIT, LMA_REQ_PLAIN, LMA_REQ_RELEASE = 1, 2, 3, 4, 5
@@ -25,7 +25,7 @@ class lma_lattice(C.Structure):
     _fields_ = [("px", C.c_int32), ("py", C.c_int32), ("rx", C.c_int32), ("ry", C.c_int32),
                 ("f", C.c_int32), ("offset_x", C.c_double), ("offset_y", C.c_double), ("L", C.c_int32),
                 ("basis_kind", C.c_int32), ("precision", C.c_int32), ("window", C.c_int32 * 4),
-                ("batch", C.c_int32), ("hbm_budget_bytes", C.c_int64)]
+                ("batch", C.c_int32), ("hbm_budget_bytes", C.c_int64), ("basis_param", C.c_double)]
 
 
 class lma_detectors(C.Structure):
@@ -73,6 +73,7 @@ SIGNATURES = {
     "lma_get_coefficients": (C.c_int, [P, P, P]),
     "lma_get_detector_pixels": (C.c_int, [P, P, P]),
     "lma_get_probe_spectrum": (C.c_int, [P, P]),
+    "lma_get_input_wave_spectrum": (C.c_int, [P, P]),
     "lma_get_basis_rows": (C.c_int, [P, C.c_int32, C.c_int32, P]),
     "lma_get_rows": (C.c_int, [P, P]),
     "lma_set_timing": (C.c_int, [P, C.c_int32]),

@@ -54,6 +54,7 @@ struct lma_plan {
 
   // tables (those read by column passes transposed, [kx][ky])
   float2 *d_specT = nullptr, *d_propT = nullptr, *d_twx = nullptr, *d_twy = nullptr;
+  float2* d_uspecT = nullptr;        // spectrum of the input wave u (the probe's unless another u)
   int32_t* d_compT = nullptr;
   uint32_t* d_maskT = nullptr;
   int32_t *d_row_of = nullptr, *d_set_dx = nullptr, *d_set_dy = nullptr;
@@ -258,7 +259,10 @@ lma_status run_waves(lma_plan* p, const int64_t* d_u, const int32_t* d_row, cons
   const int split = p->h.lat.precision == LMA_GEMM_SPLIT_BF16;
   for (int first = 0; first < n; first += p->B) {
     const int nb = std::min(p->B, n - first);
-    LAUNCH(p, "init", lma::dev::init_waves(T, p->d_work, d_u + 2 * (int64_t)first, nb, p->stream));
+    // translates start from u, probes from psi_0
+    lma::dev::Tables Ti = T;
+    if (d_row) Ti.specT = p->d_uspecT;
+    LAUNCH(p, "init", lma::dev::init_waves(Ti, p->d_work, d_u + 2 * (int64_t)first, nb, p->stream));
     for (int j = 0; j < nslices; ++j) {
       LAUNCH(p, "row_pass", lma::dev::row_pass(T, p->d_work, p->d_trans + (size_t)j * XY, nb, p->stream));
       if (j + 1 < nslices) {
@@ -518,6 +522,12 @@ lma_status lma_build_basis(const lma_optics* optics, const lma_lattice* lattice,
     };
     to_f2T(h.spec, 1.0 / (double)XY);
     if ((s = upload(p, &p->d_specT, v.data(), v.size())) != LMA_OK) { release(p); return s; }
+    if (h.lat.basis_kind == LMA_BASIS_PROBE) {
+      p->d_uspecT = p->d_specT;
+    } else {
+      to_f2T(h.uspec, 1.0 / (double)XY);
+      if ((s = upload(p, &p->d_uspecT, v.data(), v.size())) != LMA_OK) { release(p); return s; }
+    }
     to_f2T(h.prop, 1.0);
     if ((s = upload(p, &p->d_propT, v.data(), v.size())) != LMA_OK) { release(p); return s; }
     auto twx = twiddles(nx), twy = twiddles(ny);
@@ -889,6 +899,15 @@ lma_status lma_get_probe_spectrum(const lma_plan* p, double* spec) {
   for (size_t i = 0; i < p->h.spec.size(); ++i) {
     spec[2 * i] = p->h.spec[i].real();
     spec[2 * i + 1] = p->h.spec[i].imag();
+  }
+  return LMA_OK;
+}
+
+lma_status lma_get_input_wave_spectrum(const lma_plan* p, double* spec) {
+  if (!p || !spec) return fail(LMA_ERR_ARG, "null argument");
+  for (size_t i = 0; i < p->h.uspec.size(); ++i) {
+    spec[2 * i] = p->h.uspec[i].real();
+    spec[2 * i + 1] = p->h.uspec[i].imag();
   }
   return LMA_OK;
 }

@@ -68,7 +68,11 @@ lma_status check_arguments(const lma_optics* op, const lma_lattice* lat, const l
   if ((int64_t)rfx * rfy > (int64_t)1 << 28) { *err = "too many translates"; return LMA_ERR_UNSUPPORTED; }
   if (lat->L < 1 || (int64_t)lat->L > (int64_t)rfx * rfy) { *err = "L must be in [1, |I_f|]"; return LMA_ERR_ARG; }
   if (lat->L > 2048) { *err = "L above 2048"; return LMA_ERR_UNSUPPORTED; }
-  if (lat->basis_kind != LMA_BASIS_PROBE) { *err = "only the probe input wave is implemented"; return LMA_ERR_UNSUPPORTED; }
+  if (lat->basis_kind != LMA_BASIS_PROBE && lat->basis_kind != LMA_BASIS_GAUSSIAN) {
+    *err = "unknown input wave kind";
+    return LMA_ERR_UNSUPPORTED;
+  }
+  if (!std::isfinite(lat->basis_param) || lat->basis_param < 0.0) { *err = "basis_param must be >= 0"; return LMA_ERR_ARG; }
   if (lat->precision != LMA_GEMM_FP32 && lat->precision != LMA_GEMM_SPLIT_BF16) { *err = "unknown precision"; return LMA_ERR_ARG; }
   const int32_t* w = lat->window;
   bool whole = w[0] == 0 && w[1] == 0 && w[2] == 0 && w[3] == 0;
@@ -168,6 +172,29 @@ lma_status build_host_plan(const lma_optics* op, const lma_lattice* lat, const l
   const double norm = std::sqrt(XY / nap);
   for (auto& s : h.spec) s *= norm;
 
+  // ---- input wave u (Sec. 4.2.3) ----------------------------------------------------------------
+  if (lat->basis_kind == LMA_BASIS_GAUSSIAN) {
+    // g_sigma sampled on the grid: its DFT is the continuous transform, a Gaussian
+    // exp(-2 pi^2 sigma^2 |k|^2) up to a constant, as long as sigma is well above the pixel
+    // and well below the cell (aliasing and wrap-around below 1e-30 for the paper's sigma)
+    const double sg = lat->basis_param > 0.0 ? lat->basis_param : lam / (2.0 * op->alpha_max);
+    h.uspec.assign((size_t)nx * ny, cd(0.0));
+    double s2 = 0.0;
+    for (int my = 0; my < ny; ++my) {
+      const double ky = (double)freq_index(my, ny) / op->ly;
+      for (int mx = 0; mx < nx; ++mx) {
+        const double kx = (double)freq_index(mx, nx) / op->lx;
+        const double g = std::exp(-2.0 * kPi * kPi * sg * sg * (kx * kx + ky * ky));
+        h.uspec[(size_t)my * nx + mx] = cd(g, 0.0);
+        s2 += g * g;
+      }
+    }
+    const double un = std::sqrt(XY / s2);
+    for (auto& u : h.uspec) u *= un;
+  } else {
+    h.uspec = h.spec;
+  }
+
   // ---- detector pixel list: sorted by (ring mask, flat index), cut into uniform chunks --------
   std::vector<int32_t> pix;
   for (int i = 0; i < nx * ny; ++i)
@@ -223,11 +250,15 @@ lma_status build_host_plan(const lma_optics* op, const lma_lattice* lat, const l
   h.alpha.assign((size_t)h.nsets * L, cd(0.0));
   h.residual.assign(h.nsets, 0.0);
 
-  // aperture frequencies for the least-squares system (exact in Fourier space: u = psi_0 and
-  // every probe vanish outside the aperture, and the DFT preserves the residual up to XY)
+  // frequencies of the least-squares system: the DFT preserves the residual up to XY, so the
+  // residual runs over every frequency where the probe or u is non-zero (for u = psi_0 the
+  // aperture; frequencies where u is below 1e-18 of its peak and the probe vanishes add
+  // nothing at FP64 precision)
   std::vector<int32_t> kidx;
+  double umax = 0.0;
+  for (const cd& u : h.uspec) umax = std::max(umax, std::abs(u));
   for (int i = 0; i < nx * ny; ++i)
-    if (std::abs(h.spec[i]) > 0.0) kidx.push_back(i);
+    if (std::abs(h.spec[i]) > 0.0 || std::abs(h.uspec[i]) > 1e-18 * umax) kidx.push_back(i);
   const int m = (int)kidx.size();
 
   struct Key { long double d2; int64_t i2; int64_t dy, dx; int32_t t; };
@@ -262,7 +293,7 @@ lma_status build_host_plan(const lma_optics* op, const lma_lattice* lat, const l
         h.set_dx[(size_t)s * L + j] = keys[j].t % h.Rfx;
         h.set_dy[(size_t)s * L + j] = keys[j].t / h.Rfx;
       }
-      // least squares over the aperture frequencies (Sec. 4.2.2):
+      // least squares over those frequencies (Sec. 4.2.2):
       //   min || psi_hat_p - sum_j alpha_j u_hat e^{-2 pi i k.i_j} ||
       std::vector<cd> A((size_t)m * L), b(m);
       auto phase = [&](int k, int64_t xu, int64_t yu) {
@@ -277,7 +308,7 @@ lma_status build_host_plan(const lma_optics* op, const lma_lattice* lat, const l
         int t = h.set_nbr[(size_t)s * L + j];
         int64_t txu = ((t % h.Rfx) * h.stepTx + h.oxu) % h.Qx;
         int64_t tyu = ((t / h.Rfx) * h.stepTy + h.oyu) % h.Qy;
-        for (int r = 0; r < m; ++r) A[(size_t)j * m + r] = h.spec[kidx[r]] * phase(kidx[r], txu, tyu);
+        for (int r = 0; r < m; ++r) A[(size_t)j * m + r] = h.uspec[kidx[r]] * phase(kidx[r], txu, tyu);
       }
       double bn2 = 0.0;
       for (int r = 0; r < m; ++r) {

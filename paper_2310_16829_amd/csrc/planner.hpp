@@ -31,6 +31,7 @@ struct HostPlan {
 
   // ---- probe, propagator, detectors ------------------------------------------------------
   std::vector<cd> spec;          // normalised probe spectrum [ny][nx], sum |.|^2 = XY
+  std::vector<cd> uspec;         // normalised spectrum of the input wave u, sum |.|^2 = XY
   int n_aperture = 0;
   std::vector<cd> prop;          // P(k) / (XY) with the band limit [ny][nx]
   std::vector<uint32_t> detmask; // ring bits per frequency [ny][nx]

@@ -32,7 +32,7 @@ def say(*a):
 
 
 def build(w, L=None, scan=None, R=None, f=1, offset=None, window=(0, 0, 0, 0), precision=0, batch=0, nx=None,
-          ny=None, lx=None, ly=None, detectors=None, budget=0):
+          ny=None, lx=None, ly=None, detectors=None, budget=0, basis_kind=0, basis_param=0.0):
     lam, sig = lma.electron_constants(w.kv)
     nx, ny = nx or w.nx, ny or w.ny
     lx, ly = lx or w.lx, ly or w.ly
@@ -43,7 +43,8 @@ def build(w, L=None, scan=None, R=None, f=1, offset=None, window=(0, 0, 0, 0), p
     L = w.L if L is None else L
     offset = offset or w.offset_frac
     rings = detectors or det_rad(w)
-    lat = lma.lattice(scan[0], scan[1], R[0], R[1], f, offset, L, precision, window, batch, hbm_budget_bytes=budget)
+    lat = lma.lattice(scan[0], scan[1], R[0], R[1], f, offset, L, precision, window, batch, hbm_budget_bytes=budget,
+                      basis_kind=basis_kind, basis_param=basis_param)
     plan = lma.Plan(opt, lat, lma.detectors(rings))
     st = Setup(nx, ny, lx, ly, lam, sig, w.dz, w.bandlimit, w.alpha_mrad * 1e-3, w.defocus, w.cs, scan, rings)
     ol = Lattice(st, R, f, offset, L)
@@ -223,6 +224,23 @@ def test_partitioned_image_case2_three_sets():
     img = pplan.image(v)
     assert np.allclose(img, ref, rtol=1e-12, atol=0)
     image_errors(img, crop(LMA(st, ol).image(v, window_probes(plan)), plan), TOL32)
+
+
+def test_gaussian_input_wave(tiny):
+    # u = g_sigma with the paper's sigma = lambda / (2 alpha_max) (Sec. 4.2.3): the translates
+    # start from the Gaussian, the probes of the plain path from psi_0
+    say("tiny: Gaussian input wave")
+    w = tiny["w"]
+    plan, st, ol = build(w, L=100, basis_kind=lma.LMA_BASIS_GAUSSIAN)
+    plan.propagate(tiny["v"])
+    img = plan.probe_image()
+    sg = st.wavelength / (2 * st.alpha_max)
+    om = LMA(st, ol, spec_u=ph.gaussian_spectrum(st.nx, st.ny, st.lx, st.ly, sg))
+    ref = om.image(tiny["v"])
+    e = image_errors(img, ref, TOL32)
+    say(f"  vs oracle, per-detector rel L2 {e}; probe residual {plan.info().max_residual:.3e}")
+    say("  LMA(Gaussian) vs plain, per-detector rel L2", per_det(img, tiny["img_plain"]))
+    image_errors(plan.plain_image(tiny["v"]), tiny["img_plain"], TOL32)
 
 
 def test_tiny_split_bf16_image(tiny):

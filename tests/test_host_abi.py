@@ -46,7 +46,7 @@ def test_product_does_not_import_the_oracle():
 
 
 def _plan_args(w, L=None, scan=None, R=None, f=1, offset=None, window=(0, 0, 0, 0), precision=0, nx=None, ny=None,
-               lx=None, ly=None, batch=0):
+               lx=None, ly=None, batch=0, basis_kind=0, basis_param=0.0):
     lam, sig = lma.electron_constants(w.kv)
     opt = lma.optics(nx or w.nx, ny or w.ny, lx or w.lx, ly or w.ly, lam, sig, w.dz, w.bandlimit,
                      w.alpha_mrad * 1e-3, w.defocus, w.cs)
@@ -54,7 +54,7 @@ def _plan_args(w, L=None, scan=None, R=None, f=1, offset=None, window=(0, 0, 0, 
     if R is None:
         R = ((nx or w.nx) // w.basis_px * f, (ny or w.ny) // w.basis_px * f)
     lat = lma.lattice(scan[0], scan[1], R[0], R[1], f, offset or w.offset_frac, w.L if L is None else L, precision,
-                      window, batch)
+                      window, batch, basis_kind=basis_kind, basis_param=basis_param)
     det = lma.detectors(det_rad(w))
     return opt, lat, det
 
@@ -68,12 +68,16 @@ def test_electron_constants_match_oracle():
         lma.electron_constants(-1.0)
 
 
-@pytest.mark.parametrize("case", ["tiny", "case2", "nonsquare", "f2_paper_style"])
+@pytest.mark.parametrize("case", ["tiny", "case2", "nonsquare", "f2_paper_style", "gaussian", "gaussian_sigma"])
 def test_host_plan_matches_oracle(case):
     w = WORKLOADS["tiny"]
     kw = {}
     okw = {}
-    if case == "case2":          # P = 2 R_f: four coefficient sets
+    if case == "gaussian":       # u = g_sigma with the paper's sigma = lambda / (2 alpha_max)
+        kw = dict(L=100, basis_kind=lma.LMA_BASIS_GAUSSIAN)
+    elif case == "gaussian_sigma":   # an explicit sigma, Case 2 lattice
+        kw = dict(scan=(16, 16), R=(8, 8), L=16, basis_kind=lma.LMA_BASIS_GAUSSIAN, basis_param=0.9)
+    elif case == "case2":        # P = 2 R_f: four coefficient sets
         kw = dict(scan=(16, 16), R=(8, 8), L=16)
     elif case == "nonsquare":    # nx != ny, lx != ly, Case 1 with c = 2 along x and 1 along y
         kw = dict(nx=128, ny=64, lx=12.8, ly=7.2, scan=(16, 16), R=(32, 16), L=24)
@@ -87,8 +91,14 @@ def test_host_plan_matches_oracle(case):
     ol = Lattice(st, (lat.rx, lat.ry), lat.f, (lat.offset_x, lat.offset_y), lat.L)
     assert (info.ncls_x, info.ncls_y) == (ol.ncls_x, ol.ncls_y)
     assert info.n_translates == ol.n_translates
-    # probe spectrum
+    # probe spectrum, and the input wave's
     assert np.abs(plan.probe_spectrum() - st.spec0).max() < 1e-12
+    if kw.get("basis_kind"):
+        sg = kw.get("basis_param") or st.wavelength / (2 * st.alpha_max)
+        spec_u = ph.gaussian_spectrum(st.nx, st.ny, st.lx, st.ly, sg)
+    else:
+        spec_u = st.spec0
+    assert np.abs(plan.input_wave_spectrum() - spec_u).max() < 1e-10 * np.abs(spec_u).max()
     # detector pixels and ring masks: bit-exact
     flat, mask = plan.detector_pixels()
     om = np.zeros(opt.nx * opt.ny, np.uint32)
@@ -104,13 +114,13 @@ def test_host_plan_matches_oracle(case):
         assert abs(pos[t, 0] - float(ex[0])) < 1e-12 and abs(pos[t, 1] - float(ex[1])) < 1e-12
     # neighbour lists (ordered, exact) and approximants of every coefficient set
     tr, al = plan.coefficients()
-    lm = LMA(st, ol)
+    lm = LMA(st, ol, spec_u=spec_u)
     for sy in range(ol.ncls_y):
         for sx in range(ol.ncls_x):
             s = sy * ol.ncls_x + sx
             want = [tb * ol.Rfx + ta for ta, tb in ol.nearest(sx, sy)]
             assert list(tr[s]) == want
-            appr = sum(a * translate_wave(st, st.spec0, ol.translate_position(t % ol.Rfx, t // ol.Rfx))
+            appr = sum(a * translate_wave(st, spec_u, ol.translate_position(t % ol.Rfx, t // ol.Rfx))
                        for a, t in zip(al[s], tr[s]))
             assert rel_l2(appr, lm.approximant(sx, sy)) < 1e-8
     assert info.max_residual == pytest.approx(max(lm.residual.values()), rel=1e-6)

@@ -35,6 +35,22 @@ def test_gaussian_width_matches_printed_value():
     assert round(ph.electron_wavelength(200.0) / (2 * 0.026), 3) == 0.482
 
 
+def test_gaussian_input_wave_spectrum_closed_form():
+    # the Fourier transform of exp(-|x|^2 / (2 s^2)) is proportional to exp(-2 pi^2 s^2 |k|^2);
+    # sampled on a grid much finer than s in a cell much larger than s, the DFT of the samples
+    # agrees with it (aliasing and wrap-around far below 1e-12); non-square grid and cell
+    nx, ny, lx, ly, s = 96, 64, 12.0, 9.6, 0.6
+    got = ph.gaussian_spectrum(nx, ny, lx, ly, s)
+    kx = np.fft.fftfreq(nx, d=lx / nx)[None, :]
+    ky = np.fft.fftfreq(ny, d=ly / ny)[:, None]
+    want = np.exp(-2 * np.pi ** 2 * s * s * (kx ** 2 + ky ** 2))
+    want = want * np.sqrt(nx * ny / (np.abs(want) ** 2).sum())
+    assert rel_l2(got, want) < 1e-12
+    # centred at the origin: real spectrum; unit norm in real space
+    assert np.abs(got.imag).max() < 1e-12 * np.abs(got).max()
+    assert abs(np.linalg.norm(np.fft.ifft2(got)) - 1.0) < 1e-12
+
+
 def test_interaction_constant_si_route():
     # sigma = 2 pi m e lambda / h^2 with the relativistic mass, in SI, then per V*Angstrom
     m0, e, h, c = 9.1093837015e-31, 1.602176634e-19, 6.62607015e-34, 299792458.0
