@@ -375,6 +375,110 @@ def paper_shaped():
         "lma_vs_plain_rel_l2_on_window": err}), flush=True)
 
 
+def uneven(n_specimens=64):
+    """The uneven batch: n independent specimens of mixed grid sizes, slice counts and scans
+    (synth.specimen.uneven_batch). Each forms the LMA image of a window of its scan: 16 x 16
+    probes, or fewer when probes are sparser than translates (16 P / R per side, at least 2),
+    so that every specimen propagates a few hundred translates. Timed with potentials
+    resident in HBM, host planning excluded: (a) plan after plan, eager launches; (b) the
+    same plans as one lma_batch graph launch; (c) plans built with LMA_AUTOTUNE | LMA_GRAPH,
+    plan after plan from captured graphs; (d) those plans as one lma_batch launch. Each
+    image is checked against (a)."""
+    from concurrent.futures import ProcessPoolExecutor
+    import numpy as np
+    import torch
+    import paper_2310_16829_amd as lma
+    from synth.specimen import potential_slices, uneven_batch
+
+    ws = uneven_batch(n_specimens)
+    log(f"uneven: generating {len(ws)} specimens")
+    with ProcessPoolExecutor(max_workers=max(1, min(16, os.cpu_count() or 1))) as ex:
+        pots = [torch.from_numpy(v).cuda() for v in ex.map(potential_slices, ws)]
+    sides = sorted({w.nx for w in ws})
+    tuning = {}
+    for n in sides:
+        tuning[n] = lma.autotune(n, n)
+        log(f"uneven: autotune {n}^2 -> {tuning[n]}")
+
+    def window_of(w):
+        R = w.nx // w.basis_px
+        side = max(2, min(16, (16 * w.scan[0]) // R))
+        return (0, 0, side, side)
+
+    def build(flags):
+        plans = []
+        for w in ws:
+            lam, sig = lma.electron_constants(w.kv)
+            opt = lma.optics(w.nx, w.ny, w.lx, w.ly, lam, sig, w.dz, w.bandlimit, w.alpha_mrad * 1e-3, w.defocus, w.cs)
+            (Rx, Ry), f = w.lattice_size()
+            lat = lma.lattice(w.scan[0], w.scan[1], Rx, Ry, f, w.offset_frac, w.L, window=window_of(w))
+            rings = [(a * 1e-3, b * 1e-3) for _, a, b in w.detectors]
+            plans.append(lma.Plan(opt, lat, lma.detectors(rings), flags=flags))
+        return plans
+
+    def images(plans, imgs):
+        for p, im in zip(plans, imgs):
+            p.probe_image(im)
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    nsl = [w.nslices for w in ws]
+    log("uneven: building plans (eager layout)")
+    plans = build(0)
+    rows = sum(p.n_rows for p in plans)
+    pixels = sum(int(np.prod(p.image_shape()[1:])) for p in plans)
+    wave_slices = sum(p.n_rows * w.nslices for p, w in zip(plans, ws))
+    imgs = [torch.zeros(p.image_shape(), dtype=torch.float64, device="cuda") for p in plans]
+
+    def eager_round():
+        for p, v in zip(plans, pots):
+            p.propagate(v)
+        images(plans, imgs)
+
+    eager_round()                                   # first launches of every kernel shape
+    t_eager = timed(eager_round)
+    ref = [im.cpu().numpy() for im in imgs]
+    batch = lma.Batch(plans, nsl)
+    batch.propagate(pots)                           # capture
+    images(plans, imgs)
+    t_batch = timed(lambda: (batch.propagate(pots), images(plans, imgs)))
+    err_batch = max(float(np.abs(im.cpu().numpy() - r).max() / np.abs(r).max()) for im, r in zip(imgs, ref))
+    batch.close()
+    for p in plans:
+        p.close()
+    del plans
+    log("uneven: building plans (autotuned layout, captured graphs)")
+    plans = build(lma.LMA_AUTOTUNE | lma.LMA_GRAPH)
+    for _ in range(2):                              # eager, then captured
+        eager_round()
+    t_graph = timed(eager_round)
+    batch = lma.Batch(plans, nsl)
+    batch.propagate(pots)
+    images(plans, imgs)
+    t_tuned_batch = timed(lambda: (batch.propagate(pots), images(plans, imgs)))
+    err_tuned = max(float(np.abs(im.cpu().numpy() - r).max() / np.abs(r).max()) for im, r in zip(imgs, ref))
+    batch.close()
+    for p in plans:
+        p.close()
+    res = {"eager": t_eager, "batch_graph": t_batch, "tuned_plan_graphs": t_graph, "tuned_batch_graph": t_tuned_batch}
+    print(json.dumps({
+        "study": f"uneven batch: {len(ws)} specimens, sides {sides} at 0.1 A/px, 20-200 slices of 2 A, FCC "
+                 "{14,29,79} V*A, 200 kV, 20 mrad, translates every 4 px, L=144, scans 32-128 per side; "
+                 "LMA image of a scan window per specimen",
+        "specimens_by_side": {str(n): sum(1 for w in ws if w.nx == n) for n in sides},
+        "translates": rows, "probes": pixels, "translate_slices": wave_slices,
+        "autotune": {str(n): tuning[n] for n in sides},
+        "seconds": res,
+        "stem_pixels_per_s": {k: pixels / t for k, t in res.items()},
+        "translate_slices_per_s": {k: wave_slices / t for k, t in res.items()},
+        "max_rel_diff_vs_eager": {"batch_graph": err_batch, "tuned_batch_graph": err_tuned}}), flush=True)
+
+
 def contraction_roofline(plan, info, kt):
     """Flop rate of the contraction launch. Algorithmic: 8 real flops per complex multiply-add,
     |P| L D of them. Implemented (MFMA kernel): every 4 x 4-probe sub-block multiplies a 16 x K
@@ -428,6 +532,8 @@ def main():
                     help="p50/p99 latency of the request loop under Poisson arrivals of image and local-edit requests")
     ap.add_argument("--paper-shaped", action="store_true",
                     help="LMA against plain multislice in the paper's regime (1024^2, 424x400 scan, f=2)")
+    ap.add_argument("--uneven", action="store_true",
+                    help="64 specimens of mixed sizes: eager, one batch graph, autotuned plans with graphs")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device-to-device copy kernel (HBM counter calibration)")
     args = ap.parse_args()
@@ -460,6 +566,9 @@ def main():
         return
     if args.serve:
         serve()
+        return
+    if args.uneven:
+        uneven()
         return
     if args.spacing_study:
         spacing_study(w)

@@ -62,14 +62,20 @@ enum {
   LMA_HOST_ONLY = 4,         /* lma_build_basis: plan on the host, no device work     */
   LMA_CONTRACT_PER_PIXEL = 8,/* lma_probe_image: per-pixel VALU contraction even where  */
                              /* the banded MFMA GEMM applies (a cross-check)          */
-  LMA_OWN_STREAM = 16        /* lma_build_basis: the plan creates its own non-blocking */
+  LMA_OWN_STREAM = 16,       /* lma_build_basis: the plan creates its own non-blocking */
                              /* stream (default priority) and destroys it with the plan */
+  LMA_AUTOTUNE = 32,         /* lma_build_basis: tile width (and the batch, if         */
+                             /* lattice.batch is 0) from lma_autotune for this grid    */
+  LMA_GRAPH = 64             /* lma_build_basis: a wave sequence (the slice loop of a  */
+                             /* batch list) seen a second time with the same buffers is */
+                             /* captured into a HIP graph and replayed from then on; a  */
+                             /* plan given no stream gets its own (LMA_OWN_STREAM)      */
 };
 
 /* Microscope and grid: eqs. probe_wave_function, aberration_function, aperture_function,
  * schroedinger_equation and Sec. 3.2 of the paper. */
 typedef struct {
-  int32_t nx, ny;            /* X x Y grid; powers of two in [16, 2048]               */
+  int32_t nx, ny;            /* X x Y grid: powers of two in [16, 2048], or 96, 192, 384, 640 */
   double lx, ly;             /* periodic cell lx x ly (lx != ly allowed)             */
   double wavelength;         /* lambda                                               */
   double sigma;              /* interaction constant                                 */
@@ -133,7 +139,17 @@ typedef struct {
   int32_t part_w, part_h;    /* rectangle size in probes (edge ones clipped)           */
   int64_t resident_rows;     /* basis rows held on the device                         */
   int64_t multislice_calls;  /* translates propagated per image: T_{P_1..P_l}         */
+  int32_t tile_width;        /* waves are stored in tile_width^2-pixel tiles          */
+  int32_t graphs;            /* wave sequences captured as HIP graphs so far          */
 } lma_info;
+
+/* Result of lma_autotune for one grid. */
+typedef struct {
+  int32_t tile_width;        /* fastest tile width of the wave layout (4, 8 or 16)    */
+  int32_t batch;             /* fastest waves per propagation batch                  */
+  double us_per_wave_slice;  /* its time for one slice (row + column pass) per wave  */
+  int32_t candidates;        /* (tile width, batch) pairs timed                      */
+} lma_tuning;
 
 /* Per-kernel timing of the last timed calls (enable with lma_set_timing). */
 typedef struct {
@@ -208,6 +224,38 @@ lma_status lma_recompute_local(lma_plan* plan, const float* potential_new, int32
 
 /* Blocks until every piece of work the plan has queued on its stream has finished. */
 lma_status lma_synchronize(lma_plan* plan);
+
+/* Picks the slice-pass schedule for an nx x ny grid by measurement: times one slice (row
+ * pass, then column pass, the multislice step of Fig. multislice_pseudocode) on synthetic
+ * waves for every tile width the passes are built for and every batch of 64..4096 waves
+ * that fits max_bytes (0: 1 GiB), and returns the fastest. Results are kept per device and
+ * grid for the life of the process; later calls return them without measuring. Allocates
+ * and frees its own scratch memory; work runs on hip_stream (may be NULL) and is finished
+ * on return. LMA_ERR_UNSUPPORTED for a grid the passes are not built for. */
+lma_status lma_autotune(int32_t nx, int32_t ny, int64_t max_bytes, void* hip_stream, lma_tuning* out);
+
+/* ------------------------------------------------------------------------------------------
+ * Uneven batch: the translate propagation (step 1 of Fig. lma_pseudocode) of several plans,
+ * of any grid sizes, slice counts and scans, as one HIP graph launch. The graph holds every
+ * plan's slice loop (its passes over all its wave batches) on one of four branches; plans on
+ * different branches run concurrently on the device. The graph is captured at the first
+ * lma_batch_propagate and replayed afterwards.
+ * ---------------------------------------------------------------------------------------- */
+typedef struct lma_batch lma_batch;
+
+/* plans[n]: device plans on the current device, none partitioned, each at most once;
+ * nslices[n] >= 1 slices per plan. hip_stream: the stream the graph is launched on (NULL:
+ * the batch creates its own). Reserves each plan's transmission tables for its nslices. The
+ * plans must outlive the batch. */
+lma_status lma_batch_create(lma_plan* const* plans, int32_t n, const int32_t* nslices, void* hip_stream,
+                            lma_batch** out);
+/* potentials[n]: [nslices[i]][ny_i][nx_i] each (device pointers with LMA_PTR_DEVICE, else
+ * host; host ones are read before the call returns). Forms every plan's transmission tables
+ * on the plan's stream, then launches the graph; afterwards each plan's stream is ordered
+ * after the graph, so lma_probe_image on a plan sees its new basis. With host potentials the
+ * call returns when the propagation has finished. */
+lma_status lma_batch_propagate(lma_batch* batch, const float* const* potentials, int32_t flags);
+void lma_batch_destroy(lma_batch* batch);
 
 /* Device bytes a plan with these arguments would hold for nslices slices. */
 lma_status lma_footprint(const lma_optics* optics, const lma_lattice* lattice,

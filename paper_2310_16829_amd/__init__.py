@@ -12,14 +12,15 @@ import ctypes as C
 import numpy as np
 
 from . import _lib
-from ._lib import (LMA_ACCUMULATE, LMA_BASIS_GAUSSIAN, LMA_BASIS_PROBE, LMA_CONTRACT_PER_PIXEL, LMA_GEMM_FP32, LMA_GEMM_SPLIT_BF16,
-                   LMA_HOST_ONLY, LMA_OWN_STREAM, LMA_PTR_DEVICE, LMA_REQ_BUILD, LMA_REQ_EDIT, LMA_REQ_IMAGE,
-                   LMA_REQ_PLAIN, LMA_REQ_RELEASE, lma_detectors, lma_info, lma_kernel_time, lma_lattice, lma_optics,
-                   lma_request)
+from ._lib import (LMA_ACCUMULATE, LMA_AUTOTUNE, LMA_BASIS_GAUSSIAN, LMA_BASIS_PROBE, LMA_CONTRACT_PER_PIXEL,
+                   LMA_GEMM_FP32, LMA_GEMM_SPLIT_BF16, LMA_GRAPH, LMA_HOST_ONLY, LMA_OWN_STREAM, LMA_PTR_DEVICE,
+                   LMA_REQ_BUILD, LMA_REQ_EDIT, LMA_REQ_IMAGE, LMA_REQ_PLAIN, LMA_REQ_RELEASE, lma_detectors,
+                   lma_info, lma_kernel_time, lma_lattice, lma_optics, lma_request, lma_tuning)
 
 __all__ = ["LmaError", "Plan", "electron_constants", "footprint", "optics", "lattice", "detectors",
            "LMA_ACCUMULATE", "LMA_PTR_DEVICE", "LMA_HOST_ONLY", "LMA_GEMM_FP32", "LMA_GEMM_SPLIT_BF16",
-           "LMA_BASIS_PROBE", "LMA_BASIS_GAUSSIAN", "LMA_CONTRACT_PER_PIXEL", "LMA_OWN_STREAM", "Server", "lib"]
+           "LMA_BASIS_PROBE", "LMA_BASIS_GAUSSIAN", "LMA_CONTRACT_PER_PIXEL", "LMA_OWN_STREAM", "LMA_AUTOTUNE",
+           "LMA_GRAPH", "Server", "Batch", "autotune", "lib"]
 
 
 class LmaError(RuntimeError):
@@ -80,6 +81,15 @@ def footprint(opt: lma_optics, lat: lma_lattice, det: _Detectors, nslices: int) 
     b = C.c_int64()
     _check(lib().lma_footprint(C.byref(opt), C.byref(lat), C.byref(det.s), int(nslices), C.byref(b)))
     return b.value
+
+
+def autotune(nx: int, ny: int, max_bytes: int = 0, stream=None) -> dict:
+    """lma_autotune: the fastest (tile width, batch) of the slice passes for an nx x ny grid."""
+    t = lma_tuning()
+    st = _current_stream() if stream is None else C.c_void_p(stream)
+    _check(lib().lma_autotune(int(nx), int(ny), int(max_bytes), st, C.byref(t)))
+    return dict(tile_width=t.tile_width, batch=t.batch, us_per_wave_slice=t.us_per_wave_slice,
+                candidates=t.candidates)
 
 
 def _is_torch(x) -> bool:
@@ -247,6 +257,44 @@ class Plan:
         n = C.c_int32()
         _check(lib().lma_get_timing(self._h, arr, 32, C.byref(n), int(bool(reset))))
         return {arr[i].name.decode(): (arr[i].launches, arr[i].total_ms) for i in range(n.value)}
+
+
+class Batch:
+    """An lma_batch: the translate propagation of several plans as one graph launch."""
+
+    def __init__(self, plans, nslices, stream=None):
+        self._plans = list(plans)
+        n = len(self._plans)
+        hs = (C.c_void_p * n)(*[p._h.value for p in self._plans])
+        ns = (C.c_int32 * n)(*[int(x) for x in nslices])
+        self._h = C.c_void_p()
+        st = C.c_void_p(None) if stream is None else C.c_void_p(stream)
+        _check(lib().lma_batch_create(hs, n, ns, st, C.byref(self._h)))
+
+    def propagate(self, potentials, flags: int = 0):
+        ptrs, fl = [], set()
+        for v in potentials:
+            p, f = _ptr(v, np.float32)
+            ptrs.append(p.value)
+            fl.add(f)
+        if len(fl) != 1:
+            raise ValueError("potentials must all be host or all be device")
+        if fl == {LMA_PTR_DEVICE}:
+            import torch
+            torch.cuda.current_stream().synchronize()
+        arr = (C.c_void_p * len(ptrs))(*ptrs)
+        _check(lib().lma_batch_propagate(self._h, arr, int(flags) | fl.pop()))
+
+    def close(self):
+        if self._h:
+            lib().lma_batch_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Server:

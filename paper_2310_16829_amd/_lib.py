@@ -11,6 +11,7 @@ LMA_OK, LMA_ERR_ARG, LMA_ERR_OOM, LMA_ERR_DEVICE, LMA_ERR_STATE, LMA_ERR_UNSUPPO
 LMA_BASIS_PROBE, LMA_BASIS_GAUSSIAN = 0, 1
 LMA_GEMM_FP32, LMA_GEMM_SPLIT_BF16 = 0, 1
 LMA_PTR_DEVICE, LMA_ACCUMULATE, LMA_HOST_ONLY, LMA_CONTRACT_PER_PIXEL, LMA_OWN_STREAM = 1, 2, 4, 8, 16
+LMA_AUTOTUNE, LMA_GRAPH = 32, 64
 LMA_REQ_BUILD, LMA_REQ_IMAGE, LMA_REQ_EDIT, LMA_REQ_PLAIN, LMA_REQ_RELEASE = 1, 2, 3, 4, 5
 
 
@@ -40,7 +41,13 @@ class lma_info(C.Structure):
                 ("basis_valid", C.c_int32), ("host_only", C.c_int32), ("max_residual", C.c_double),
                 ("device_bytes", C.c_int64), ("contract_kernel", C.c_int32), ("contract_k", C.c_int32),
                 ("partitioned", C.c_int32), ("n_parts", C.c_int32), ("part_w", C.c_int32), ("part_h", C.c_int32),
-                ("resident_rows", C.c_int64), ("multislice_calls", C.c_int64)]
+                ("resident_rows", C.c_int64), ("multislice_calls", C.c_int64), ("tile_width", C.c_int32),
+                ("graphs", C.c_int32)]
+
+
+class lma_tuning(C.Structure):
+    _fields_ = [("tile_width", C.c_int32), ("batch", C.c_int32), ("us_per_wave_slice", C.c_double),
+                ("candidates", C.c_int32)]
 
 
 class lma_request(C.Structure):
@@ -80,6 +87,10 @@ SIGNATURES = {
     "lma_get_timing": (C.c_int, [P, C.POINTER(lma_kernel_time), C.c_int32, C.POINTER(C.c_int32), C.c_int32]),
     "lma_destroy": (None, [P]),
     "lma_synchronize": (C.c_int, [P]),
+    "lma_autotune": (C.c_int, [C.c_int32, C.c_int32, C.c_int64, P, C.POINTER(lma_tuning)]),
+    "lma_batch_create": (C.c_int, [C.POINTER(P), C.c_int32, C.POINTER(C.c_int32), P, C.POINTER(P)]),
+    "lma_batch_propagate": (C.c_int, [P, C.POINTER(P), C.c_int32]),
+    "lma_batch_destroy": (None, [P]),
     "lma_server_create": (C.c_int, [C.c_int32, C.c_int32, C.c_int64, C.POINTER(P)]),
     "lma_server_submit": (C.c_int, [P, C.POINTER(lma_request), C.POINTER(C.c_int64)]),
     "lma_server_wait": (C.c_int, [P, C.c_int64, C.POINTER(C.c_double), C.POINTER(C.c_double)]),

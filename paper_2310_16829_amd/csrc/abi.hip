@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -48,7 +49,16 @@ struct lma_plan {
   bool own_stream = false;           // created by lma_build_basis (LMA_OWN_STREAM)
   int device = 0;
   int B = 1;                         // waves per batch
+  int tw = 0;                        // tile width of the wave layout
   bool basis_valid = false;
+  // LMA_GRAPH: wave sequences by their buffers; a sequence seen twice is captured and replayed
+  bool use_graph = false;
+  struct Captured {
+    std::vector<int64_t> key;
+    hipGraphExec_t exec = nullptr;
+  };
+  std::vector<Captured> graphs;      // most recent last
+  int n_captured = 0;
   int64_t dev_bytes = 0;
   std::vector<void*> allocs;
 
@@ -138,6 +148,7 @@ lma::dev::Tables tables(const lma_plan* p) {
   lma::dev::Tables t;
   t.nx = p->h.op.nx;
   t.ny = p->h.op.ny;
+  t.tw = p->tw;
   t.Qx = p->h.Qx;
   t.Qy = p->h.Qy;
   t.specT = p->d_specT;
@@ -223,8 +234,8 @@ void collect_timing(lma_plan* p) {
     if (e_ != hipSuccess) return fail(LMA_ERR_DEVICE, std::string(name) + ": " + hipGetErrorString(e_)); \
   } while (0)
 
-// transmission tables t_j = exp(i sigma v_j) for the given potential
-lma_status prepare_transmission(lma_plan* p, const float* potential, int nslices, int32_t flags) {
+// room for nslices transmission tables
+lma_status ensure_trans(lma_plan* p, int nslices) {
   const int64_t XY = (int64_t)p->h.op.nx * p->h.op.ny;
   if (nslices > p->trans_cap) {
     free_one(p, p->d_trans, (size_t)p->trans_cap * XY * sizeof(float2));
@@ -234,6 +245,13 @@ lma_status prepare_transmission(lma_plan* p, const float* potential, int nslices
     if (s != LMA_OK) return s;
     p->trans_cap = nslices;
   }
+  return LMA_OK;
+}
+
+// transmission tables t_j = exp(i sigma v_j) for the given potential
+lma_status prepare_transmission(lma_plan* p, const float* potential, int nslices, int32_t flags) {
+  const int64_t XY = (int64_t)p->h.op.nx * p->h.op.ny;
+  if (lma_status s = ensure_trans(p, nslices); s != LMA_OK) return s;
   const float* src = potential;
   if (!(flags & LMA_PTR_DEVICE)) {
     if (nslices > p->pot_cap) {
@@ -275,6 +293,45 @@ lma_status run_waves(lma_plan* p, const int64_t* d_u, const int32_t* d_row, cons
       }
     }
   }
+  return LMA_OK;
+}
+
+// run_waves through a HIP graph (LMA_GRAPH): the first call of a sequence runs eagerly and
+// records its key (every buffer and size its kernels take); the second captures it and
+// every later one replays the graph. Graphs hold kernel launches only.
+constexpr size_t kMaxGraphs = 8;
+lma_status waves(lma_plan* p, const int64_t* d_u, const int32_t* d_row, const int32_t* d_out, int n, int nslices) {
+  if (!p->use_graph || p->timing || !p->stream) return run_waves(p, d_u, d_row, d_out, n, nslices);
+  std::vector<int64_t> key = {(int64_t)(intptr_t)d_u, (int64_t)(intptr_t)d_row, (int64_t)(intptr_t)d_out, n, nslices,
+                              (int64_t)(intptr_t)p->d_trans, (int64_t)(intptr_t)p->d_work,
+                              (int64_t)(intptr_t)p->d_basis, (int64_t)(intptr_t)p->d_img, p->B};
+  auto it = std::find_if(p->graphs.begin(), p->graphs.end(), [&](const lma_plan::Captured& c) { return c.key == key; });
+  if (it == p->graphs.end()) {
+    if (p->graphs.size() >= kMaxGraphs) {
+      if (p->graphs.front().exec) (void)hipGraphExecDestroy(p->graphs.front().exec);
+      p->graphs.erase(p->graphs.begin());
+    }
+    p->graphs.push_back({key, nullptr});
+    return run_waves(p, d_u, d_row, d_out, n, nslices);
+  }
+  if (!it->exec) {
+    hipGraph_t g = nullptr;
+    HIP_TRY(hipStreamBeginCapture(p->stream, hipStreamCaptureModeRelaxed));
+    lma_status s = run_waves(p, d_u, d_row, d_out, n, nslices);
+    hipError_t e = hipStreamEndCapture(p->stream, &g);
+    if (s != LMA_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return s;
+    }
+    if (e != hipSuccess) return fail(LMA_ERR_DEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+    hipGraphExec_t x = nullptr;
+    e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return fail(LMA_ERR_DEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    it->exec = x;
+    ++p->n_captured;
+  }
+  HIP_TRY(hipGraphLaunch(it->exec, p->stream));
   return LMA_OK;
 }
 
@@ -439,6 +496,8 @@ static void release(lma_plan* p) {
     (void)hipEventDestroy(t.b);
   }
   for (auto e : p->event_pool) (void)hipEventDestroy(e);
+  for (auto& g : p->graphs)
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
   for (void* a : p->allocs) (void)hipFree(a);
   if (p->own_stream && p->stream) (void)hipStreamDestroy(p->stream);
   delete p;
@@ -472,7 +531,7 @@ lma_status lma_build_basis(const lma_optics* optics, const lma_lattice* lattice,
       delete p;
       return fail(LMA_ERR_DEVICE, "no HIP device");
     }
-    if (!p->host_only && (flags & LMA_OWN_STREAM)) {
+    if (!p->host_only && ((flags & LMA_OWN_STREAM) || ((flags & LMA_GRAPH) && !p->stream))) {
       // non-blocking: the plan's work never waits for, or holds up, the legacy default stream
       if (hipStreamCreateWithFlags(&p->stream, hipStreamNonBlocking) != hipSuccess) {
         (void)hipGetLastError();
@@ -480,6 +539,19 @@ lma_status lma_build_basis(const lma_optics* optics, const lma_lattice* lattice,
         return fail(LMA_ERR_DEVICE, "stream creation failed");
       }
       p->own_stream = true;
+    }
+    p->use_graph = (flags & LMA_GRAPH) != 0;
+    if (const char* e = std::getenv("LMA_TILE_WIDTH")) lma::dev::set_tile_width(std::atoi(e));
+    p->tw = lma::dev::tile_width(h.op.nx, h.op.ny);
+    if (!p->host_only && (flags & LMA_AUTOTUNE)) {
+      lma_tuning t{};
+      if (lma_status ts = lma_autotune(h.op.nx, h.op.ny, 0, p->stream, &t); ts != LMA_OK) {
+        release(p);
+        return ts;
+      }
+      p->tw = t.tile_width;
+      if (h.lat.batch <= 0)
+        p->B = std::max(1, std::min<int>(t.batch, (int)std::max<int64_t>(std::max<int64_t>((int64_t)h.rows.size(), h.n_probes()), 1)));
     }
     // residency (Sec. 4.2.4): the whole window's basis, or a rectangle partition when it needs
     // more than M = budget / (D x 8 B) propagated translates
@@ -542,7 +614,6 @@ lma_status lma_build_basis(const lma_optics* optics, const lma_lattice* lattice,
       }
     if ((s = upload(p, &p->d_compT, compT.data(), compT.size())) != LMA_OK) { release(p); return s; }
     if ((s = upload(p, &p->d_maskT, maskT.data(), maskT.size())) != LMA_OK) { release(p); return s; }
-    if (const char* e = std::getenv("LMA_TILE_WIDTH")) lma::dev::set_tile_width(std::atoi(e));
     if ((s = upload(p, &p->d_row_of, h.row_of.data(), h.row_of.size())) != LMA_OK) { release(p); return s; }
     if ((s = upload(p, &p->d_set_dx, h.set_dx.data(), h.set_dx.size())) != LMA_OK) { release(p); return s; }
     if ((s = upload(p, &p->d_set_dy, h.set_dy.data(), h.set_dy.size())) != LMA_OK) { release(p); return s; }
@@ -641,7 +712,7 @@ lma_status lma_propagate(lma_plan* plan, const float* potential, int32_t nslices
   plan->basis_valid = false;
   try {
     if ((s = prepare_transmission(plan, potential, nslices, flags)) != LMA_OK) return s;
-    if ((s = run_waves(plan, plan->d_row_u, plan->d_row_id, nullptr, (int)plan->h.rows.size(), nslices)) != LMA_OK) return s;
+    if ((s = waves(plan, plan->d_row_u, plan->d_row_id, nullptr, (int)plan->h.rows.size(), nslices)) != LMA_OK) return s;
     if (!(flags & LMA_PTR_DEVICE)) HIP_TRY(hipStreamSynchronize(plan->stream));
     plan->basis_valid = true;
     return LMA_OK;
@@ -687,7 +758,7 @@ lma_status lma_image(lma_plan* plan, const float* potential, int32_t nslices, do
       const lma::PartPlan::Part& q = plan->pp.parts[j];
       const int64_t f0 = plan->part_fresh_off[j], nf = plan->part_fresh_off[j + 1] - f0;
       // step 1 for the translates this rectangle adds to the resident set
-      if (nf > 0 && (s = run_waves(plan, plan->d_part_u + 2 * f0, plan->d_part_slot + f0, nullptr, (int)nf, nslices)) != LMA_OK)
+      if (nf > 0 && (s = waves(plan, plan->d_part_u + 2 * f0, plan->d_part_slot + f0, nullptr, (int)nf, nslices)) != LMA_OK)
         return s;
       // step 2 and the detector for the rectangle's probes
       if (plan->st.ok) {
@@ -721,7 +792,7 @@ lma_status lma_plain_image(lma_plan* plan, const float* potential, int32_t nslic
   try {
     if ((s = prepare_transmission(plan, potential, nslices, flags)) != LMA_OK) return s;
     HIP_TRY(hipMemsetAsync(plan->d_img, 0, (size_t)plan->h.ndet * plan->h.n_probes() * sizeof(double), plan->stream));
-    if ((s = run_waves(plan, plan->d_probe_u, nullptr, plan->d_probe_out, (int)plan->h.n_probes(), nslices)) != LMA_OK) return s;
+    if ((s = waves(plan, plan->d_probe_u, nullptr, plan->d_probe_out, (int)plan->h.n_probes(), nslices)) != LMA_OK) return s;
     return write_image(plan, image, flags, weight);
   } catch (const std::exception& e) {
     return fail(LMA_ERR_DEVICE, e.what());
@@ -795,7 +866,7 @@ lma_status lma_recompute_local(lma_plan* plan, const float* potential_new, int32
     }
     HIP_TRY(hipMemcpy(plan->d_list_u, u.data(), u.size() * sizeof(int64_t), hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(plan->d_list, redo_rows.data(), redo_rows.size() * sizeof(int32_t), hipMemcpyHostToDevice));
-    if ((s = run_waves(plan, plan->d_list_u, plan->d_list, nullptr, (int)redo_rows.size(), nslices)) != LMA_OK) return s;
+    if ((s = waves(plan, plan->d_list_u, plan->d_list, nullptr, (int)redo_rows.size(), nslices)) != LMA_OK) return s;
     plan->basis_valid = true;
     HIP_TRY(hipStreamSynchronize(plan->stream));
     // re-form the affected probes
@@ -856,6 +927,8 @@ lma_status lma_plan_info(const lma_plan* p, lma_info* out) {
   out->multislice_calls = p->partitioned ? p->pp.multislice_calls : (int64_t)h.rows.size();
   out->contract_kernel = p->st.ok ? 1 : 0;
   out->contract_k = p->st.ok ? 4 * p->st.nks : (int32_t)h.lat.L;
+  out->tile_width = p->tw;
+  out->graphs = p->n_captured;
   return LMA_OK;
 }
 
@@ -970,6 +1043,291 @@ lma_status lma_get_timing(lma_plan* p, lma_kernel_time* out, int32_t max, int32_
   *n = k;
   if (reset) p->totals.clear();
   return LMA_OK;
+}
+
+// ---- autotuner ------------------------------------------------------------------------------
+namespace {
+struct TuneEntry {
+  int device, nx, ny;
+  int64_t max_bytes;
+  lma_tuning t;
+};
+std::mutex g_tune_mu;
+std::vector<TuneEntry> g_tune;
+
+// times one slice (row pass + column pass) per candidate on synthetic waves
+lma_status measure_tuning(int nx, int ny, int64_t max_bytes, hipStream_t st, lma_tuning* out) {
+  const int64_t XY = (int64_t)nx * ny, wave = XY * (int64_t)sizeof(float2);
+  std::vector<int> batches;
+  for (int b = 64; b <= 4096; b *= 2)
+    if ((int64_t)b * wave <= max_bytes) batches.push_back(b);
+  if (batches.empty()) batches.push_back((int)std::max<int64_t>(1, max_bytes / wave));
+  std::vector<int> widths;
+  for (int tw : {4, 8, 16})
+    if (lma::dev::tile_width_ok(nx, ny, tw)) widths.push_back(tw);
+  if (widths.empty()) return fail(LMA_ERR_UNSUPPORTED, "no tile width fits this grid");
+  std::vector<void*> bufs;
+  auto cleanup = [&]() {
+    for (void* b : bufs) (void)hipFree(b);
+  };
+  auto alloc = [&](size_t bytes) -> void* {
+    void* q = nullptr;
+    if (hipMalloc(&q, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    bufs.push_back(q);
+    return q;
+  };
+  float2* work = (float2*)alloc((size_t)batches.back() * wave);
+  float2* trans = (float2*)alloc((size_t)wave);
+  float2* prop = (float2*)alloc((size_t)wave);
+  float2* twx = (float2*)alloc((size_t)nx * sizeof(float2));
+  float2* twy = (float2*)alloc((size_t)ny * sizeof(float2));
+  hipEvent_t ea = nullptr, eb = nullptr;
+  if (!work || !trans || !prop || !twx || !twy) {
+    cleanup();
+    return fail(LMA_ERR_OOM, "autotune scratch allocation failed");
+  }
+  std::vector<float2> ones((size_t)XY, make_float2(1.f, 0.f)), scaled((size_t)XY, make_float2(1.f / (float)XY, 0.f));
+  auto tx = twiddles(nx), ty = twiddles(ny);
+  hipError_t e = hipMemcpy(trans, ones.data(), (size_t)wave, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(prop, scaled.data(), (size_t)wave, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(twx, tx.data(), tx.size() * sizeof(float2), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(twy, ty.data(), ty.size() * sizeof(float2), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemsetAsync(work, 0, (size_t)batches.back() * wave, st);
+  if (e == hipSuccess) e = hipEventCreate(&ea);
+  if (e == hipSuccess) e = hipEventCreate(&eb);
+  lma_tuning best{};
+  best.us_per_wave_slice = 1e300;
+  int tried = 0;
+  for (int tw : widths) {
+    for (int B : batches) {
+      if (e != hipSuccess) break;
+      lma::dev::Tables T;
+      T.nx = nx;
+      T.ny = ny;
+      T.tw = tw;
+      T.propT = prop;
+      T.twx = twx;
+      T.twy = twy;
+      const int reps = 3;
+      e = lma::dev::row_pass(T, work, trans, B, st);                 // warm-up
+      if (e == hipSuccess) e = lma::dev::col_pass(T, work, B, st);
+      if (e == hipSuccess) e = hipEventRecord(ea, st);
+      for (int r = 0; r < reps && e == hipSuccess; ++r) {
+        e = lma::dev::row_pass(T, work, trans, B, st);
+        if (e == hipSuccess) e = lma::dev::col_pass(T, work, B, st);
+      }
+      if (e == hipSuccess) e = hipEventRecord(eb, st);
+      if (e == hipSuccess) e = hipEventSynchronize(eb);
+      float ms = 0.f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, ea, eb);
+      if (e != hipSuccess) break;
+      ++tried;
+      const double us = 1e3 * (double)ms / ((double)reps * B);
+      if (us < best.us_per_wave_slice) {
+        best.us_per_wave_slice = us;
+        best.tile_width = tw;
+        best.batch = B;
+      }
+    }
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (ea) (void)hipEventDestroy(ea);
+  if (eb) (void)hipEventDestroy(eb);
+  cleanup();
+  if (e != hipSuccess) return fail(LMA_ERR_DEVICE, std::string("autotune: ") + hipGetErrorString(e));
+  best.candidates = tried;
+  *out = best;
+  return LMA_OK;
+}
+}  // namespace
+
+lma_status lma_autotune(int32_t nx, int32_t ny, int64_t max_bytes, void* hip_stream, lma_tuning* out) {
+  if (!out) return fail(LMA_ERR_ARG, "out is null");
+  if (!lma::dev::supported(nx, ny)) return fail(LMA_ERR_UNSUPPORTED, "the passes are not built for this grid");
+  if (max_bytes < 0) return fail(LMA_ERR_ARG, "max_bytes must be >= 0");
+  if (max_bytes == 0) max_bytes = (int64_t)1 << 30;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(LMA_ERR_DEVICE, "no HIP device");
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  for (const TuneEntry& t : g_tune)
+    if (t.device == dev && t.nx == nx && t.ny == ny && t.max_bytes == max_bytes) {
+      *out = t.t;
+      return LMA_OK;
+    }
+  lma_tuning t{};
+  lma_status s = measure_tuning(nx, ny, max_bytes, reinterpret_cast<hipStream_t>(hip_stream), &t);
+  if (s != LMA_OK) return s;
+  g_tune.push_back({dev, nx, ny, max_bytes, t});
+  *out = t;
+  return LMA_OK;
+}
+
+}  // extern "C"
+
+// ---- uneven batch ---------------------------------------------------------------------------
+struct lma_batch {
+  std::vector<lma_plan*> plans;
+  std::vector<int32_t> nslices;
+  hipStream_t origin = nullptr;
+  bool own_origin = false;
+  std::vector<hipStream_t> branch;   // capture branches
+  std::vector<hipEvent_t> plan_ev;   // per plan: its transmission tables are ready
+  hipEvent_t fork = nullptr, done = nullptr;
+  std::vector<hipEvent_t> join;
+  hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+constexpr int kBatchBranches = 4;
+
+void batch_release(lma_batch* b) {
+  if (!b) return;
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  for (hipEvent_t e : b->plan_ev) (void)hipEventDestroy(e);
+  for (hipEvent_t e : b->join) (void)hipEventDestroy(e);
+  if (b->fork) (void)hipEventDestroy(b->fork);
+  if (b->done) (void)hipEventDestroy(b->done);
+  for (hipStream_t s : b->branch) (void)hipStreamDestroy(s);
+  if (b->own_origin && b->origin) (void)hipStreamDestroy(b->origin);
+  delete b;
+}
+
+// captures every plan's slice loop, plan i on branch i % kBatchBranches
+lma_status batch_capture(lma_batch* b) {
+  hipGraph_t g = nullptr;
+  HIP_TRY(hipStreamBeginCapture(b->origin, hipStreamCaptureModeRelaxed));
+  lma_status s = LMA_OK;
+  hipError_t e = hipEventRecord(b->fork, b->origin);
+  for (hipStream_t br : b->branch)
+    if (e == hipSuccess) e = hipStreamWaitEvent(br, b->fork, 0);
+  for (size_t i = 0; i < b->plans.size() && e == hipSuccess && s == LMA_OK; ++i) {
+    lma_plan* p = b->plans[i];
+    const hipStream_t keep = p->stream;
+    const bool timing = p->timing;
+    p->stream = b->branch[i % b->branch.size()];
+    p->timing = false;
+    s = run_waves(p, p->d_row_u, p->d_row_id, nullptr, (int)p->h.rows.size(), b->nslices[i]);
+    p->stream = keep;
+    p->timing = timing;
+  }
+  for (size_t k = 0; k < b->branch.size() && e == hipSuccess; ++k) {
+    e = hipEventRecord(b->join[k], b->branch[k]);
+    if (e == hipSuccess) e = hipStreamWaitEvent(b->origin, b->join[k], 0);
+  }
+  hipError_t ee = hipStreamEndCapture(b->origin, &g);
+  if (s != LMA_OK || e != hipSuccess || ee != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    if (s != LMA_OK) return s;
+    return fail(LMA_ERR_DEVICE, std::string("batch capture: ") + hipGetErrorString(e != hipSuccess ? e : ee));
+  }
+  e = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) {
+    b->exec = nullptr;
+    return fail(LMA_ERR_DEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+  }
+  return LMA_OK;
+}
+}  // namespace
+
+extern "C" {
+
+lma_status lma_batch_create(lma_plan* const* plans, int32_t n, const int32_t* nslices, void* hip_stream,
+                            lma_batch** out) {
+  if (!out) return fail(LMA_ERR_ARG, "out is null");
+  *out = nullptr;
+  if (!plans || !nslices || n < 1) return fail(LMA_ERR_ARG, "plans, nslices and n >= 1 required");
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(LMA_ERR_DEVICE, "no HIP device");
+  for (int32_t i = 0; i < n; ++i) {
+    lma_plan* p = plans[i];
+    if (!p) return fail(LMA_ERR_ARG, "null plan");
+    if (p->host_only) return fail(LMA_ERR_STATE, "host-only plan has no device state");
+    if (p->partitioned) return fail(LMA_ERR_STATE, "partitioned plans are formed rectangle by rectangle (lma_image)");
+    if (p->device != dev) return fail(LMA_ERR_ARG, "every plan must live on the current device");
+    if (nslices[i] < 1) return fail(LMA_ERR_ARG, "nslices must be >= 1");
+    for (int32_t k = 0; k < i; ++k)
+      if (plans[k] == p) return fail(LMA_ERR_ARG, "a plan appears twice");
+  }
+  lma_batch* b = new lma_batch();
+  b->plans.assign(plans, plans + n);
+  b->nslices.assign(nslices, nslices + n);
+  b->origin = reinterpret_cast<hipStream_t>(hip_stream);
+  hipError_t e = hipSuccess;
+  if (!b->origin) {
+    e = hipStreamCreateWithFlags(&b->origin, hipStreamNonBlocking);
+    b->own_origin = e == hipSuccess;
+  }
+  for (int k = 0; k < std::min<int>(kBatchBranches, n) && e == hipSuccess; ++k) {
+    hipStream_t s = nullptr;
+    e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+    if (e == hipSuccess) b->branch.push_back(s);
+  }
+  for (int32_t i = 0; i < n && e == hipSuccess; ++i) {
+    hipEvent_t ev = nullptr;
+    e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (e == hipSuccess) b->plan_ev.push_back(ev);
+  }
+  for (size_t k = 0; k < b->branch.size() && e == hipSuccess; ++k) {
+    hipEvent_t ev = nullptr;
+    e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (e == hipSuccess) b->join.push_back(ev);
+  }
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&b->done, hipEventDisableTiming);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    batch_release(b);
+    return fail(LMA_ERR_DEVICE, std::string("batch streams and events: ") + hipGetErrorString(e));
+  }
+  for (int32_t i = 0; i < n; ++i) {
+    lma_status s = ensure_trans(plans[i], nslices[i]);
+    if (s != LMA_OK) {
+      batch_release(b);
+      return s;
+    }
+  }
+  *out = b;
+  return LMA_OK;
+}
+
+lma_status lma_batch_propagate(lma_batch* b, const float* const* potentials, int32_t flags) {
+  if (!b || !potentials) return fail(LMA_ERR_ARG, "null argument");
+  for (size_t i = 0; i < b->plans.size(); ++i)
+    if (!potentials[i]) return fail(LMA_ERR_ARG, "null potential");
+  try {
+    lma_status s;
+    for (size_t i = 0; i < b->plans.size(); ++i) {
+      lma_plan* p = b->plans[i];
+      p->basis_valid = false;
+      if (b->nslices[i] > p->trans_cap) return fail(LMA_ERR_STATE, "transmission tables were released");
+      const float2* keep = p->d_trans;
+      if ((s = prepare_transmission(p, potentials[i], b->nslices[i], flags)) != LMA_OK) return s;
+      if (p->d_trans != keep) return fail(LMA_ERR_STATE, "transmission tables moved");
+      HIP_TRY(hipEventRecord(b->plan_ev[i], p->stream));
+      HIP_TRY(hipStreamWaitEvent(b->origin, b->plan_ev[i], 0));
+    }
+    if (!b->exec && (s = batch_capture(b)) != LMA_OK) return s;
+    HIP_TRY(hipGraphLaunch(b->exec, b->origin));
+    HIP_TRY(hipEventRecord(b->done, b->origin));
+    for (lma_plan* p : b->plans) {
+      HIP_TRY(hipStreamWaitEvent(p->stream, b->done, 0));
+      p->basis_valid = true;
+    }
+    if (!(flags & LMA_PTR_DEVICE)) HIP_TRY(hipStreamSynchronize(b->origin));
+    return LMA_OK;
+  } catch (const std::exception& e) {
+    return fail(LMA_ERR_DEVICE, e.what());
+  }
+}
+
+void lma_batch_destroy(lma_batch* b) {
+  if (!b) return;
+  if (b->origin) (void)hipStreamSynchronize(b->origin);
+  batch_release(b);
 }
 
 }  // extern "C"

@@ -7,10 +7,11 @@
 // Between passes a wave lives in HBM in the mixed domain (x transformed, y spatial), so each
 // step reads and writes every pixel twice: 32 bytes per pixel per slice per wave.
 //
-// Transforms are Stockham radix-8/4/2 FFTs with 8 elements per thread: N/8 threads per
-// transform, each holding elements j + (N/8) m for m = 0..7 before every stage and after
-// the last one, so consecutive transforms need no exchange; stages in between exchange
-// through LDS. Twiddles come from FP64-computed tables rounded to FP32.
+// Transforms are Stockham FFTs: lengths 2^a run radix 8 (then 4 or 2) with E = 8 elements
+// per thread, lengths 3 * 2^a and 5 * 2^a run the odd radix first, then radix 4 (then 2), with
+// E = 12 or 20. N/E threads per transform each hold elements j + (N/E) m for m < E before
+// every stage and after the last one, so consecutive transforms need no exchange; stages in
+// between exchange through LDS. Twiddles come from FP64-computed tables rounded to FP32.
 #include <hip/hip_runtime.h>
 #include <hip/hip_bf16.h>
 
@@ -73,44 +74,104 @@ __device__ __forceinline__ void dft8(float2* a) {
   a[3] = cadd(e3, o3); a[7] = csub(e3, o3);
 }
 
+// 3-point DFT: X0 = a0 + (a1 + a2), X1,2 = a0 - (a1 + a2)/2 +- DIR i sin(2 pi/3) (a1 - a2)
+template <int DIR>
+__device__ __forceinline__ void dft3(float2* a) {
+  const float s3 = 0.86602540378443864676f;   // sin(2 pi / 3)
+  const float2 t1 = cadd(a[1], a[2]);
+  const float2 t2 = make_float2(a[0].x - 0.5f * t1.x, a[0].y - 0.5f * t1.y);
+  const float2 d = mul_unit_i<DIR>(csub(a[1], a[2]));
+  a[0] = cadd(a[0], t1);
+  a[1] = make_float2(t2.x + s3 * d.x, t2.y + s3 * d.y);
+  a[2] = make_float2(t2.x - s3 * d.x, t2.y - s3 * d.y);
+}
+// 5-point DFT from the symmetric sums t1 = a1 + a4, t2 = a2 + a3 and differences
+// t3 = a1 - a4, t4 = a2 - a3 (w = exp(DIR 2 pi i / 5); c_k, s_k = cos, sin of 2 pi k / 5):
+//   X1,4 = a0 + c1 t1 + c2 t2 +- DIR i (s1 t3 + s2 t4)
+//   X2,3 = a0 + c2 t1 + c1 t2 +- DIR i (s2 t3 - s1 t4)
+template <int DIR>
+__device__ __forceinline__ void dft5(float2* a) {
+  const float c1 = 0.30901699437494742410f, c2 = -0.80901699437494742410f;
+  const float s1 = 0.95105651629515357212f, s2 = 0.58778525229247312917f;
+  const float2 t1 = cadd(a[1], a[4]), t2 = cadd(a[2], a[3]);
+  const float2 t3 = csub(a[1], a[4]), t4 = csub(a[2], a[3]);
+  const float2 r1 = make_float2(a[0].x + c1 * t1.x + c2 * t2.x, a[0].y + c1 * t1.y + c2 * t2.y);
+  const float2 r2 = make_float2(a[0].x + c2 * t1.x + c1 * t2.x, a[0].y + c2 * t1.y + c1 * t2.y);
+  const float2 i1 = mul_unit_i<DIR>(make_float2(s1 * t3.x + s2 * t4.x, s1 * t3.y + s2 * t4.y));
+  const float2 i2 = mul_unit_i<DIR>(make_float2(s2 * t3.x - s1 * t4.x, s2 * t3.y - s1 * t4.y));
+  a[0] = cadd(a[0], cadd(t1, t2));
+  a[1] = cadd(r1, i1);
+  a[4] = csub(r1, i1);
+  a[2] = cadd(r2, i2);
+  a[3] = csub(r2, i2);
+}
+
 template <int R, int DIR>
 __device__ __forceinline__ void dft_r(float2* a) {
   if constexpr (R == 8) dft8<DIR>(a);
+  else if constexpr (R == 5) dft5<DIR>(a);
   else if constexpr (R == 4) dft4<DIR>(a[0], a[1], a[2], a[3]);
+  else if constexpr (R == 3) dft3<DIR>(a);
   else if constexpr (R == 2) dft2<DIR>(a[0], a[1]);
 }
 
 // ------------------------------------------------------------------------------------------
-// stage schedule: radix 8 while possible, the remaining factor (2 or 4) last
+// stage schedule. 2^a: radix 8 while possible, the remaining factor (2 or 4) last, E = 8.
+// 3 * 2^a and 5 * 2^a: the odd radix, then radix 4, then a 2 if needed, E = 4 x the odd factor
+// (every radix of the schedule divides E).
 // ------------------------------------------------------------------------------------------
+__host__ __device__ constexpr int fft_odd(int n) { while (n > 1 && n % 2 == 0) n /= 2; return n; }
+__host__ __device__ constexpr bool fft_pow2(int n) { return fft_odd(n) == 1; }
+__host__ __device__ constexpr int fft_elems(int n) { return fft_pow2(n) ? 8 : 4 * fft_odd(n); }
+__host__ __device__ constexpr int fft_log2(int n) { int a = 0; while (n > 1) { n /= 2; ++a; } return a; }
 __host__ __device__ constexpr int fft_full8(int n) { int s = 0; while (n >= 8) { n /= 8; ++s; } return s; }
 __host__ __device__ constexpr int fft_rest(int n) { while (n >= 8) n /= 8; return n; }
-__host__ __device__ constexpr int fft_nstages(int n) { return fft_full8(n) + (fft_rest(n) > 1 ? 1 : 0); }
-__host__ __device__ constexpr int fft_radix(int n, int s) { return s < fft_full8(n) ? 8 : fft_rest(n); }
+__host__ __device__ constexpr int fft_nstages(int n) {
+  return fft_pow2(n) ? fft_full8(n) + (fft_rest(n) > 1 ? 1 : 0)
+                     : 1 + fft_log2(n / fft_odd(n)) / 2 + fft_log2(n / fft_odd(n)) % 2;
+}
+__host__ __device__ constexpr int fft_radix(int n, int s) {
+  if (fft_pow2(n)) return s < fft_full8(n) ? 8 : fft_rest(n);
+  return s == 0 ? fft_odd(n) : (s <= fft_log2(n / fft_odd(n)) / 2 ? 4 : 2);
+}
 __host__ __device__ constexpr int fft_span(int n, int s) {  // product of the radices before stage s
   int p = 1;
   for (int i = 0; i < s; ++i) p *= fft_radix(n, i);
   return p;
 }
+// b mod NS and b / NS for b >= 0 (masks and shifts when NS is a power of two)
+template <int NS>
+__device__ __forceinline__ int mod_c(int b) { return fft_pow2(NS) ? (b & (NS - 1)) : (int)((unsigned)b % (unsigned)NS); }
+template <int NS>
+__device__ __forceinline__ int div_c(int b) { return (int)((unsigned)b / (unsigned)NS); }
+// transform lengths the passes are built for
+__host__ __device__ constexpr bool fft_length_ok(int n) {
+  return (fft_pow2(n) && n >= 16 && n <= 2048) || n == 96 || n == 192 || n == 384 || n == 640;
+}
 
 // ------------------------------------------------------------------------------------------
-// twiddles held in registers: for every stage after the first, the r-1 factors of each of
-// the thread's 8/r butterflies
+// twiddles: for every stage after the first, the r-1 factors of each of the thread's E/r
+// butterflies. Power-of-two lengths hold them in registers for the whole pass; the others
+// (12 or 20 elements per thread) read them from the table at each stage.
 // ------------------------------------------------------------------------------------------
+__host__ __device__ constexpr bool tw_in_regs(int n) { return fft_pow2(n); }
 __host__ __device__ constexpr int tw_off(int n, int s) {
   int o = 0;
-  for (int i = 1; i < s; ++i) o += 8 - 8 / fft_radix(n, i);
+  for (int i = 1; i < s; ++i) o += fft_elems(n) - fft_elems(n) / fft_radix(n, i);
   return o;
 }
-__host__ __device__ constexpr int tw_count(int n) { return tw_off(n, fft_nstages(n)) > 0 ? tw_off(n, fft_nstages(n)) : 1; }
+__host__ __device__ constexpr int tw_count(int n) {
+  return tw_in_regs(n) && tw_off(n, fft_nstages(n)) > 0 ? tw_off(n, fft_nstages(n)) : 1;
+}
 
 template <int N, int S>
 __device__ __forceinline__ void tw_load_stage(float2* w, const float2* __restrict__ tab, int j) {
-  constexpr int r = fft_radix(N, S), Ns = fft_span(N, S), Q = 8 / r, T = N / 8;
+  constexpr int E = fft_elems(N);
+  constexpr int r = fft_radix(N, S), Ns = fft_span(N, S), Q = E / r, T = N / E;
   constexpr int off = tw_off(N, S);
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
-    const int k = (j + T * q) & (Ns - 1);
+    const int k = mod_c<Ns>(j + T * q);
 #pragma unroll
     for (int m = 1; m < r; ++m) w[off + q * (r - 1) + (m - 1)] = tab[m * k * (N / (Ns * r))];
   }
@@ -119,6 +180,7 @@ __device__ __forceinline__ void tw_load_stage(float2* w, const float2* __restric
 template <int N>
 __device__ __forceinline__ void tw_load(float2* w, const float2* __restrict__ tab, int j) {
   constexpr int ns = fft_nstages(N);
+  if constexpr (!tw_in_regs(N)) return;
   if constexpr (ns > 1) tw_load_stage<N, 1>(w, tab, j);
   if constexpr (ns > 2) tw_load_stage<N, (ns > 2 ? 2 : 1)>(w, tab, j);
   if constexpr (ns > 3) tw_load_stage<N, (ns > 3 ? 3 : 1)>(w, tab, j);
@@ -150,11 +212,13 @@ __device__ __forceinline__ void exchange_sync() {
 }
 
 template <int N, int DIR, int S, bool WL>
-__device__ __forceinline__ void fft_stage(float2 (&v)[8], int j, const float2* w, const Slot& slot) {
+__device__ __forceinline__ void fft_stage(float2 (&v)[fft_elems(N)], int j, const float2* w,
+                                          const float2* __restrict__ twg, const Slot& slot) {
+  constexpr int E = fft_elems(N);
   constexpr int r = fft_radix(N, S);
   constexpr int Ns = fft_span(N, S);
-  constexpr int Q = 8 / r;
-  constexpr int T = N / 8;
+  constexpr int Q = E / r;
+  constexpr int T = N / E;
   constexpr bool last = (S == fft_nstages(N) - 1);
   constexpr int off = tw_off(N, S);
 #pragma unroll
@@ -163,17 +227,20 @@ __device__ __forceinline__ void fft_stage(float2 (&v)[8], int j, const float2* w
 #pragma unroll
     for (int m = 0; m < r; ++m) a[m] = v[q + m * Q];
     const int b = j + T * q;
-    const int k = b & (Ns - 1);
+    const int k = mod_c<Ns>(b);
     if constexpr (Ns > 1) {
 #pragma unroll
-      for (int m = 1; m < r; ++m) a[m] = cmul(a[m], conj_if_inv<DIR>(w[off + q * (r - 1) + (m - 1)]));
+      for (int m = 1; m < r; ++m) {
+        const float2 t = tw_in_regs(N) ? w[off + q * (r - 1) + (m - 1)] : twg[m * k * (N / (Ns * r))];
+        a[m] = cmul(a[m], conj_if_inv<DIR>(t));
+      }
     }
     dft_r<r, DIR>(a);
     if constexpr (last) {
 #pragma unroll
       for (int m = 0; m < r; ++m) v[q + m * Q] = a[m];
     } else {
-      const int base = (b / Ns) * Ns * r + k;
+      const int base = div_c<Ns>(b) * Ns * r + k;
 #pragma unroll
       for (int m = 0; m < r; ++m) slot.put(base + m * Ns, a[m]);
     }
@@ -181,20 +248,24 @@ __device__ __forceinline__ void fft_stage(float2 (&v)[8], int j, const float2* w
   if constexpr (!last) {
     exchange_sync<WL>();
 #pragma unroll
-    for (int m = 0; m < 8; ++m) v[m] = slot.get(j + T * m);
+    for (int m = 0; m < E; ++m) v[m] = slot.get(j + T * m);
     exchange_sync<WL>();
   }
 }
 
-// N-point transform of the 8 values held by thread j (of N/8); input and output at
-// positions j + (N/8) m, natural order.
+// N-point transform of the E values held by thread j (of N/E); input and output at
+// positions j + (N/E) m, natural order. w: register twiddles (powers of two), twg: the table.
 template <int N, int DIR, bool WL>
-__device__ __forceinline__ void fft(float2 (&v)[8], int j, const float2* w, const Slot& slot) {
+__device__ __forceinline__ void fft(float2 (&v)[fft_elems(N)], int j, const float2* w, const float2* twg,
+                                    const Slot& slot) {
   constexpr int ns = fft_nstages(N);
-  fft_stage<N, DIR, 0, WL>(v, j, w, slot);
-  if constexpr (ns > 1) fft_stage<N, DIR, (ns > 1 ? 1 : 0), WL>(v, j, w, slot);
-  if constexpr (ns > 2) fft_stage<N, DIR, (ns > 2 ? 2 : 0), WL>(v, j, w, slot);
-  if constexpr (ns > 3) fft_stage<N, DIR, (ns > 3 ? 3 : 0), WL>(v, j, w, slot);
+  static_assert(ns <= 6, "at most six stages");
+  fft_stage<N, DIR, 0, WL>(v, j, w, twg, slot);
+  if constexpr (ns > 1) fft_stage<N, DIR, (ns > 1 ? 1 : 0), WL>(v, j, w, twg, slot);
+  if constexpr (ns > 2) fft_stage<N, DIR, (ns > 2 ? 2 : 0), WL>(v, j, w, twg, slot);
+  if constexpr (ns > 3) fft_stage<N, DIR, (ns > 3 ? 3 : 0), WL>(v, j, w, twg, slot);
+  if constexpr (ns > 4) fft_stage<N, DIR, (ns > 4 ? 4 : 0), WL>(v, j, w, twg, slot);
+  if constexpr (ns > 5) fft_stage<N, DIR, (ns > 5 ? 5 : 0), WL>(v, j, w, twg, slot);
 }
 
 // Blocks are dispatched round-robin over the 8 XCDs; give each XCD a contiguous range of
@@ -241,7 +312,8 @@ enum { PASS_ROW = 0, PASS_COL = 1, PASS_INIT = 2, PASS_GATHER = 3, PASS_REDUCE =
 #endif
 template <int N, int TW, int WLW = LMA_WL_WAVES>
 struct PassCfg {
-  static constexpr int T = N / 8;                                   // threads per transform
+  static constexpr int E = fft_elems(N);                            // elements per thread
+  static constexpr int T = N / E;                                   // threads per transform
   static constexpr bool WL = T <= 64;                               // transform inside one wavefront
   static constexpr int S = WL ? ((64 / T) < TW ? 64 / T : TW) : 1;  // transforms per wavefront
   static constexpr int WPT = WL ? 1 : T / 64;                       // wavefronts per transform
@@ -375,6 +447,14 @@ struct ItemWalk {
   __device__ __forceinline__ bool valid(int i) const { return i < end; }
 };
 
+// elements a thread stages per step when the item is not prefetched: the largest divisor of
+// the per-thread count up to 16
+constexpr int stage_chunk(int ept) {
+  for (int c = 16; c > 1; --c)
+    if (ept % c == 0) return c;
+  return 1;
+}
+
 template <int MODE>
 constexpr int pass_waves() { return MODE == PASS_ROW ? LMA_WL_WAVES_ROW : LMA_WL_WAVES; }
 
@@ -390,7 +470,7 @@ __global__ __launch_bounds__((PassCfg<N, TW, pass_waves<MODE>()>::WAVES * 64)) v
 #define LMA_PREFETCH 1
 #endif
   constexpr bool PREF = LMA_PREFETCH && EPT <= 16;         // next item prefetched into registers
-  constexpr int CHUNK = 16;                                // staging step otherwise
+  constexpr int CHUNK = stage_chunk(EPT);                  // staging step otherwise
   static_assert(TOTAL % NT == 0, "work item must split evenly over the threads");
   __shared__ float2 tile[(TW + (C::WL ? 1 : 0)) * RS];     // extra line: scratch of idle lanes
   [[maybe_unused]] __shared__ double part[C::WAVES][8];
@@ -493,7 +573,7 @@ __global__ __launch_bounds__((PassCfg<N, TW, pass_waves<MODE>()>::WAVES * 64)) v
       const int line = g * TW + r;                          // y (row pass) or x (column passes)
       const Slot slot{tile + (active ? r : TW) * RS};
       const float2* tab = a.table + (size_t)line * N;
-      float2 v[8];
+      float2 v[C::E];
       if constexpr (MODE == PASS_INIT) {
         // u(. - pos_w): spectrum times exp(-2 pi i (mx ux / Qx + my uy / Qy)), reduced exactly
         // in lattice units, phase in FP64; lines are kx, positions ky
@@ -501,7 +581,7 @@ __global__ __launch_bounds__((PassCfg<N, TW, pass_waves<MODE>()>::WAVES * 64)) v
         const int64_t ux = a.wave_u[2 * w], uy = a.wave_u[2 * w + 1];
         const int64_t ax = (((int64_t)mx * ux) % a.Qx + a.Qx) % a.Qx;
 #pragma unroll
-        for (int m = 0; m < 8; ++m) {
+        for (int m = 0; m < C::E; ++m) {
           const int ky = j + T * m;
           const int my = freq_index(ky, N);
           const int64_t ay = (((int64_t)my * uy) % a.Qy + a.Qy) % a.Qy;
@@ -509,29 +589,29 @@ __global__ __launch_bounds__((PassCfg<N, TW, pass_waves<MODE>()>::WAVES * 64)) v
           sincospi(-2.0 * ((double)ax / (double)a.Qx + (double)ay / (double)a.Qy), &sn, &cs);
           v[m] = cmul(tab[ky], make_float2((float)cs, (float)sn));
         }
-        fft<N, +1, C::WL>(v, j, tw, slot);
+        fft<N, +1, C::WL>(v, j, tw, a.tw, slot);
       } else {
 #pragma unroll
-        for (int m = 0; m < 8; ++m) v[m] = slot.get(j + T * m);
+        for (int m = 0; m < C::E; ++m) v[m] = slot.get(j + T * m);
         // the first stage overwrites the line: every thread of the transform must have read it
         exchange_sync<C::WL>();
         if constexpr (MODE == PASS_ROW) {
-          fft<N, +1, C::WL>(v, j, tw, slot);
+          fft<N, +1, C::WL>(v, j, tw, a.tw, slot);
 #pragma unroll
-          for (int m = 0; m < 8; ++m) v[m] = cmul(v[m], tab[j + T * m]);
-          fft<N, -1, C::WL>(v, j, tw, slot);
+          for (int m = 0; m < C::E; ++m) v[m] = cmul(v[m], tab[j + T * m]);
+          fft<N, -1, C::WL>(v, j, tw, a.tw, slot);
         } else {
-          fft<N, -1, C::WL>(v, j, tw, slot);
+          fft<N, -1, C::WL>(v, j, tw, a.tw, slot);
 #pragma unroll
-          for (int m = 0; m < 8; ++m) v[m] = cmul(v[m], tab[j + T * m]);
+          for (int m = 0; m < C::E; ++m) v[m] = cmul(v[m], tab[j + T * m]);
           if constexpr (MODE == PASS_COL) {
-            fft<N, +1, C::WL>(v, j, tw, slot);
+            fft<N, +1, C::WL>(v, j, tw, a.tw, slot);
           } else if constexpr (MODE == PASS_GATHER) {
             if (active) {
               const int64_t brow = a.wave_row[w];
               const int32_t* cm = a.comp + (size_t)line * N;
 #pragma unroll
-              for (int m = 0; m < 8; ++m) {
+              for (int m = 0; m < C::E; ++m) {
                 const int d = cm[j + T * m];
                 if (d >= 0) {
                   if (a.split_bf16) {
@@ -549,7 +629,7 @@ __global__ __launch_bounds__((PassCfg<N, TW, pass_waves<MODE>()>::WAVES * 64)) v
             if (active) {
               const uint32_t* mk = a.mask + (size_t)line * N;
 #pragma unroll
-              for (int m = 0; m < 8; ++m) {
+              for (int m = 0; m < C::E; ++m) {
                 const uint32_t bits = mk[j + T * m];
                 const double p = (double)v[m].x * v[m].x + (double)v[m].y * v[m].y;
 #pragma unroll
@@ -563,7 +643,7 @@ __global__ __launch_bounds__((PassCfg<N, TW, pass_waves<MODE>()>::WAVES * 64)) v
       if constexpr (MODE == PASS_ROW || MODE == PASS_COL || MODE == PASS_INIT) {
         if (active) {
 #pragma unroll
-          for (int m = 0; m < 8; ++m) slot.put(j + T * m, v[m]);
+          for (int m = 0; m < C::E; ++m) slot.put(j + T * m, v[m]);
         }
       }
     }
@@ -801,10 +881,7 @@ __global__ void k_scale_out(double* out, const double* img, int64_t n, double w,
 // ------------------------------------------------------------------------------------------
 // launchers
 // ------------------------------------------------------------------------------------------
-bool supported(int nx, int ny) {
-  auto ok = [](int n) { return n >= 16 && n <= 2048 && (n & (n - 1)) == 0; };
-  return ok(nx) && ok(ny);
-}
+bool supported(int nx, int ny) { return fft_length_ok(nx) && fft_length_ok(ny); }
 
 hipError_t transmission(const float* v, float2* t, int64_t n, double sigma, hipStream_t s) {
   if (n <= 0) return hipSuccess;
@@ -864,6 +941,10 @@ static hipError_t pass_dispatch(int N, int TW, int lines, const PassArgs& a, int
       case 512: return pass_launch<512, 4, MODE>(a, lines, B, s);
       case 1024: return pass_launch<1024, 4, MODE>(a, lines, B, s);
       case 2048: return pass_launch<2048, 4, MODE>(a, lines, B, s);
+      case 96: return pass_launch<96, 4, MODE>(a, lines, B, s);
+      case 192: return pass_launch<192, 4, MODE>(a, lines, B, s);
+      case 384: return pass_launch<384, 4, MODE>(a, lines, B, s);
+      case 640: return pass_launch<640, 4, MODE>(a, lines, B, s);
     }
   } else if (TW == 8) {
     switch (N) {
@@ -875,6 +956,10 @@ static hipError_t pass_dispatch(int N, int TW, int lines, const PassArgs& a, int
       case 512: return pass_launch<512, 8, MODE>(a, lines, B, s);
       case 1024: return pass_launch<1024, 8, MODE>(a, lines, B, s);
       case 2048: return pass_launch<2048, 8, MODE>(a, lines, B, s);
+      case 96: return pass_launch<96, 8, MODE>(a, lines, B, s);
+      case 192: return pass_launch<192, 8, MODE>(a, lines, B, s);
+      case 384: return pass_launch<384, 8, MODE>(a, lines, B, s);
+      case 640: return pass_launch<640, 8, MODE>(a, lines, B, s);
     }
   }
   return hipErrorInvalidValue;
@@ -891,6 +976,16 @@ int tile_width(int nx, int ny) {
   return g_tile_width ? g_tile_width : 8;
 }
 
+bool tile_width_ok(int nx, int ny, int tw) {
+  auto side = [tw](int n) {
+    if (n % tw) return false;
+    if (tw == 16) return fft_pow2(n) && n <= 512;
+    return tw == 4 || tw == 8;
+  };
+  return fft_length_ok(nx) && fft_length_ok(ny) && side(nx) && side(ny);
+}
+static int tw_of(const Tables& T) { return T.tw ? T.tw : tile_width(T.nx, T.ny); }
+
 static PassArgs pass_args(const Tables& T, float2* work) {
   PassArgs a{};
   a.work = work;
@@ -906,21 +1001,21 @@ hipError_t init_waves(const Tables& T, float2* work, const int64_t* wave_u, int 
   a.table = T.specT;
   a.tw = T.twy;
   a.wave_u = wave_u;
-  return pass_dispatch<PASS_INIT>(T.ny, tile_width(T.nx, T.ny), T.nx, a, B, s);
+  return pass_dispatch<PASS_INIT>(T.ny, tw_of(T), T.nx, a, B, s);
 }
 
 hipError_t row_pass(const Tables& T, float2* work, const float2* trans_j, int B, hipStream_t s) {
   PassArgs a = pass_args(T, work);
   a.table = trans_j;
   a.tw = T.twx;
-  return pass_dispatch<PASS_ROW>(T.nx, tile_width(T.nx, T.ny), T.ny, a, B, s);
+  return pass_dispatch<PASS_ROW>(T.nx, tw_of(T), T.ny, a, B, s);
 }
 
 hipError_t col_pass(const Tables& T, float2* work, int B, hipStream_t s) {
   PassArgs a = pass_args(T, work);
   a.table = T.propT;
   a.tw = T.twy;
-  return pass_dispatch<PASS_COL>(T.ny, tile_width(T.nx, T.ny), T.nx, a, B, s);
+  return pass_dispatch<PASS_COL>(T.ny, tw_of(T), T.nx, a, B, s);
 }
 
 hipError_t col_gather(const Tables& T, float2* work, int B, void* basis, int D, const int32_t* wave_row, int split,
@@ -933,7 +1028,7 @@ hipError_t col_gather(const Tables& T, float2* work, int B, void* basis, int D, 
   a.comp = T.compT;
   a.wave_row = wave_row;
   a.split_bf16 = split;
-  return pass_dispatch<PASS_GATHER>(T.ny, tile_width(T.nx, T.ny), T.nx, a, B, s);
+  return pass_dispatch<PASS_GATHER>(T.ny, tw_of(T), T.nx, a, B, s);
 }
 
 hipError_t col_reduce(const Tables& T, float2* work, int B, const int32_t* wave_out, double* img, int ndet,
@@ -947,7 +1042,7 @@ hipError_t col_reduce(const Tables& T, float2* work, int B, const int32_t* wave_
   a.ndet = ndet;
   a.img_stride = img_stride;
   a.scale = scale;
-  return pass_dispatch<PASS_REDUCE>(T.ny, tile_width(T.nx, T.ny), T.nx, a, B, s);
+  return pass_dispatch<PASS_REDUCE>(T.ny, tw_of(T), T.nx, a, B, s);
 }
 
 template <int SPLIT, int PT>

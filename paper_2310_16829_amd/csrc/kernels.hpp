@@ -10,6 +10,7 @@ namespace dev {
 // transposed, [kx][ky].
 struct Tables {
   int nx = 0, ny = 0;
+  int tw = 0;                        // tile width of the wave layout (0: tile_width(nx, ny))
   int64_t Qx = 1, Qy = 1;            // lattice units per cell (wave positions are in units)
   const float2* specT = nullptr;     // probe spectrum / (XY)          [nx][ny]
   const float2* propT = nullptr;     // propagator * band limit / (XY) [nx][ny]
@@ -74,8 +75,10 @@ hipError_t transmission(const float* v, float2* t, int64_t n, double sigma, hipS
 // A wave batch is stored [B][ny/TW][nx/TW][TW][TW] (TW x TW tiles, TW = tile_width) and every
 // pass updates it in place. Between passes a wave is in the mixed domain (y spatial, x frequency).
 int tile_width(int nx, int ny);
-// forces the tile width (8 or 16; anything else restores the default), a tuning knob
+// forces the tile width (4, 8 or 16; anything else restores the default), a tuning knob
 void set_tile_width(int tw);
+// whether the passes are built for this grid with tile width tw
+bool tile_width_ok(int nx, int ny, int tw);
 // initial waves u(. - pos_w): column IFFT of spectrum * modulation
 hipError_t init_waves(const Tables& T, float2* work, const int64_t* wave_u, int B, hipStream_t s);
 // row pass of slice j: row IFFT, * t_j, row FFT

@@ -19,6 +19,9 @@ constexpr double kM0c2Ev = 510998.95;   // electron rest energy, eV
 constexpr int kChunk = 256;             // detector pixels per contraction chunk
 
 bool pow2_in(int n, int lo, int hi) { return n >= lo && n <= hi && (n & (n - 1)) == 0; }
+// grid sides the slice passes are built for: powers of two, and 96, 192, 384 (3 x 2^a) and
+// 640 (5 x 2^7)
+bool grid_side_ok(int n) { return pow2_in(n, 16, 2048) || n == 96 || n == 192 || n == 384 || n == 640; }
 
 // spatial frequency index in FFT order
 inline int freq_index(int m, int n) { return m < (n + 1) / 2 ? m : m - n; }
@@ -46,8 +49,8 @@ void electron_constants(double kv, double* lambda, double* sigma) {
 lma_status check_arguments(const lma_optics* op, const lma_lattice* lat, const lma_detectors* det,
                            std::string* err) {
   if (!op || !lat || !det) { *err = "null argument"; return LMA_ERR_ARG; }
-  if (!pow2_in(op->nx, 16, 2048) || !pow2_in(op->ny, 16, 2048)) {
-    *err = "nx and ny must be powers of two in [16, 2048]";
+  if (!grid_side_ok(op->nx) || !grid_side_ok(op->ny)) {
+    *err = "nx and ny must be powers of two in [16, 2048] or one of 96, 192, 384, 640";
     return LMA_ERR_UNSUPPORTED;
   }
   if (!(op->lx > 0) || !(op->ly > 0) || !finite(op->lx) || !finite(op->ly)) { *err = "cell size must be positive"; return LMA_ERR_ARG; }

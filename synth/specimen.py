@@ -91,6 +91,30 @@ WORKLOADS = {
 }
 
 
+# Uneven batch: independent specimens of mixed grid sizes (0.1 A/px), slice counts and scans.
+UNEVEN_SIDES = (96, 128, 192, 256, 384, 512, 640)
+
+
+def uneven_batch(n: int = 64, seed: int = 0):
+    """n specimens with square grids whose sides are drawn uniformly from UNEVEN_SIDES at
+    0.1 A/px, slice counts uniform in 20..200 (2 A each), the medium workload's FCC
+    specimen and optics, translates every 4 px, L = 144, and a scan of 32..128 positions
+    per side drawn from those for which the coefficient sets per axis number 1 or 2
+    (P divides R, or P = 2R, with R = side / 4). Seeds: default_rng([5, 3, seed])."""
+    rng = np.random.default_rng([5, 3, seed])
+    out = []
+    for i in range(n):
+        side = int(rng.choice(UNEVEN_SIDES))
+        nsl = int(rng.integers(20, 201))
+        R = side // 4
+        scans = [P for P in range(32, 129) if R % P == 0 or P == 2 * R]
+        P = int(rng.choice(scans))
+        out.append(Workload(f"uneven{i}", 1000 + i, side, side, side * 0.1, side * 0.1, nsl, 2.0, "fcc", 4.05,
+                            (14.0, 29.0, 79.0), (1 / 3, 1 / 3, 1 / 3), 0.08, 200.0, 20.0, 0.0, 0.0, 2.0 / 3.0,
+                            (P, P), 4, (0.5, 0.5), 144, 1, _STD_DET))
+    return out
+
+
 def _basis(lattice: str) -> np.ndarray:
     if lattice == "sc":
         return np.zeros((1, 3))

@@ -32,7 +32,7 @@ def say(*a):
 
 
 def build(w, L=None, scan=None, R=None, f=1, offset=None, window=(0, 0, 0, 0), precision=0, batch=0, nx=None,
-          ny=None, lx=None, ly=None, detectors=None, budget=0, basis_kind=0, basis_param=0.0):
+          ny=None, lx=None, ly=None, detectors=None, budget=0, basis_kind=0, basis_param=0.0, flags=0):
     lam, sig = lma.electron_constants(w.kv)
     nx, ny = nx or w.nx, ny or w.ny
     lx, ly = lx or w.lx, ly or w.ly
@@ -45,7 +45,7 @@ def build(w, L=None, scan=None, R=None, f=1, offset=None, window=(0, 0, 0, 0), p
     rings = detectors or det_rad(w)
     lat = lma.lattice(scan[0], scan[1], R[0], R[1], f, offset, L, precision, window, batch, hbm_budget_bytes=budget,
                       basis_kind=basis_kind, basis_param=basis_param)
-    plan = lma.Plan(opt, lat, lma.detectors(rings))
+    plan = lma.Plan(opt, lat, lma.detectors(rings), flags=flags)
     st = Setup(nx, ny, lx, ly, lam, sig, w.dz, w.bandlimit, w.alpha_mrad * 1e-3, w.defocus, w.cs, scan, rings)
     ol = Lattice(st, R, f, offset, L)
     return plan, st, ol
@@ -296,8 +296,9 @@ def test_case2_nonsquare_f2():
     image_errors(plan.plain_image(v), crop(plain_image(st, v, probes), plan), TOL32)
 
 
-@pytest.mark.parametrize("n", [16, 32, 256])
+@pytest.mark.parametrize("n", [16, 32, 256, 96, 192, 384, 640])
 def test_small_and_mid_grids(n):
+    # 96, 192, 384 = 3 x 2^a and 640 = 5 x 2^7 run the mixed-radix transforms
     say(f"grid {n}^2")
     w = WORKLOADS["tiny"]
     l = n * 0.1
@@ -337,6 +338,23 @@ def test_mixed_grid_1024_by_256():
     v = rng.uniform(0, 40, size=(3, ny, nx)).astype(np.float32)
     plan, st, ol = build(w, nx=nx, ny=ny, lx=lx, ly=ly, scan=(128, 32), R=(256, 64), L=9,
                          window=(60, 3, 3, 2), batch=3)
+    plan.propagate(v)
+    probes = window_probes(plan)
+    ref = crop(LMA(st, ol).image(v, probes), plan)
+    image_errors(plan.probe_image(), ref, TOL32)
+    image_errors(plan.plain_image(v), crop(plain_image(st, v, probes), plan), TOL32)
+
+
+def test_mixed_radix_grid_640_by_96():
+    # 640 x 96: radix-5 rows over several tile columns, radix-3 columns, 4 x 4 tiles (a side
+    # above 512), a ragged last batch
+    say("grid 640 x 96, 4 slices")
+    w = WORKLOADS["tiny"]
+    nx, ny, lx, ly = 640, 96, 64.0, 9.6
+    rng = np.random.default_rng(640)
+    v = rng.uniform(0, 40, size=(4, ny, nx)).astype(np.float32)
+    plan, st, ol = build(w, nx=nx, ny=ny, lx=lx, ly=ly, scan=(80, 12), R=(160, 24), L=9,
+                         window=(76, 9, 4, 3), batch=5)
     plan.propagate(v)
     probes = window_probes(plan)
     ref = crop(LMA(st, ol).image(v, probes), plan)

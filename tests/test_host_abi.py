@@ -68,7 +68,8 @@ def test_electron_constants_match_oracle():
         lma.electron_constants(-1.0)
 
 
-@pytest.mark.parametrize("case", ["tiny", "case2", "nonsquare", "f2_paper_style", "gaussian", "gaussian_sigma"])
+@pytest.mark.parametrize("case", ["tiny", "case2", "nonsquare", "f2_paper_style", "gaussian", "gaussian_sigma",
+                                  "grid_96_by_640"])
 def test_host_plan_matches_oracle(case):
     w = WORKLOADS["tiny"]
     kw = {}
@@ -77,6 +78,8 @@ def test_host_plan_matches_oracle(case):
         kw = dict(L=100, basis_kind=lma.LMA_BASIS_GAUSSIAN)
     elif case == "gaussian_sigma":   # an explicit sigma, Case 2 lattice
         kw = dict(scan=(16, 16), R=(8, 8), L=16, basis_kind=lma.LMA_BASIS_GAUSSIAN, basis_param=0.9)
+    elif case == "grid_96_by_640":   # mixed-radix sides
+        kw = dict(nx=96, ny=640, lx=9.6, ly=64.0, scan=(12, 80), R=(24, 160), L=16)
     elif case == "case2":        # P = 2 R_f: four coefficient sets
         kw = dict(scan=(16, 16), R=(8, 8), L=16)
     elif case == "nonsquare":    # nx != ny, lx != ly, Case 1 with c = 2 along x and 1 along y
@@ -141,7 +144,7 @@ def test_window_rows_are_the_union_of_neighbour_sets():
 
 
 @pytest.mark.parametrize("bad", [
-    dict(nx=96), dict(nx=4096), dict(scan=(12, 16)), dict(L=0), dict(L=5000), dict(offset=(0.3, 0.5)),
+    dict(nx=80), dict(nx=100), dict(nx=4096), dict(scan=(12, 16)), dict(L=0), dict(L=5000), dict(offset=(0.3, 0.5)),
     dict(window=(10, 0, 8, 4)), dict(f=3, R=(32, 32)), dict(batch=-1),
 ])
 def test_invalid_arguments_are_rejected(bad):
