@@ -150,11 +150,13 @@ __host__ __device__ constexpr bool fft_length_ok(int n) {
 }
 
 // ------------------------------------------------------------------------------------------
-// twiddles: for every stage after the first, the r-1 factors of each of the thread's E/r
-// butterflies. Power-of-two lengths hold them in registers for the whole pass; the others
-// (12 or 20 elements per thread) read them from the table at each stage.
+// twiddles: for every stage after the first, the factors w^m (m = 1..r-1) of each of the
+// thread's E/r butterflies, from the FP64-derived table. Lengths 2^a and 3 * 2^a hold all of
+// them in registers for the whole pass. Lengths 5 * 2^a (20 elements per thread) would need
+// 55 registers pairs; they read w from the table at each stage (one load per butterfly) and
+// form w^2, w^3 by complex products (FP32, a few ulp).
 // ------------------------------------------------------------------------------------------
-__host__ __device__ constexpr bool tw_in_regs(int n) { return fft_pow2(n); }
+__host__ __device__ constexpr bool tw_in_regs(int n) { return fft_odd(n) != 5; }
 __host__ __device__ constexpr int tw_off(int n, int s) {
   int o = 0;
   for (int i = 1; i < s; ++i) o += fft_elems(n) - fft_elems(n) / fft_radix(n, i);
@@ -184,6 +186,8 @@ __device__ __forceinline__ void tw_load(float2* w, const float2* __restrict__ ta
   if constexpr (ns > 1) tw_load_stage<N, 1>(w, tab, j);
   if constexpr (ns > 2) tw_load_stage<N, (ns > 2 ? 2 : 1)>(w, tab, j);
   if constexpr (ns > 3) tw_load_stage<N, (ns > 3 ? 3 : 1)>(w, tab, j);
+  if constexpr (ns > 4) tw_load_stage<N, (ns > 4 ? 4 : 1)>(w, tab, j);
+  if constexpr (ns > 5) tw_load_stage<N, (ns > 5 ? 5 : 1)>(w, tab, j);
 }
 
 // One transform's exchange slot inside the pass tile: position p lives at p + p/2^PAD (one
@@ -212,8 +216,8 @@ __device__ __forceinline__ void exchange_sync() {
 }
 
 template <int N, int DIR, int S, bool WL>
-__device__ __forceinline__ void fft_stage(float2 (&v)[fft_elems(N)], int j, const float2* w,
-                                          const float2* __restrict__ twg, const Slot& slot) {
+__device__ __forceinline__ void fft_stage(float2 (&v)[fft_elems(N)], int j, const float2* w, const float2* twg,
+                                          const Slot& slot) {
   constexpr int E = fft_elems(N);
   constexpr int r = fft_radix(N, S);
   constexpr int Ns = fft_span(N, S);
@@ -229,10 +233,17 @@ __device__ __forceinline__ void fft_stage(float2 (&v)[fft_elems(N)], int j, cons
     const int b = j + T * q;
     const int k = mod_c<Ns>(b);
     if constexpr (Ns > 1) {
+      if constexpr (tw_in_regs(N)) {
 #pragma unroll
-      for (int m = 1; m < r; ++m) {
-        const float2 t = tw_in_regs(N) ? w[off + q * (r - 1) + (m - 1)] : twg[m * k * (N / (Ns * r))];
-        a[m] = cmul(a[m], conj_if_inv<DIR>(t));
+        for (int m = 1; m < r; ++m) a[m] = cmul(a[m], conj_if_inv<DIR>(w[off + q * (r - 1) + (m - 1)]));
+      } else {
+        const float2 w1 = conj_if_inv<DIR>(twg[k * (N / (Ns * r))]);
+        float2 wm = w1;
+#pragma unroll
+        for (int m = 1; m < r; ++m) {
+          a[m] = cmul(a[m], wm);
+          if (m + 1 < r) wm = cmul(wm, w1);
+        }
       }
     }
     dft_r<r, DIR>(a);
@@ -254,7 +265,8 @@ __device__ __forceinline__ void fft_stage(float2 (&v)[fft_elems(N)], int j, cons
 }
 
 // N-point transform of the E values held by thread j (of N/E); input and output at
-// positions j + (N/E) m, natural order. w: register twiddles (powers of two), twg: the table.
+// positions j + (N/E) m, natural order. w: the thread's register twiddles (tw_load); twg: the
+// twiddle table (lengths whose twiddles are not held in registers).
 template <int N, int DIR, bool WL>
 __device__ __forceinline__ void fft(float2 (&v)[fft_elems(N)], int j, const float2* w, const float2* twg,
                                     const Slot& slot) {
@@ -458,8 +470,12 @@ constexpr int stage_chunk(int ept) {
 template <int MODE>
 constexpr int pass_waves() { return MODE == PASS_ROW ? LMA_WL_WAVES_ROW : LMA_WL_WAVES; }
 
+// Register budget: lengths 5 * 2^a are held to two wavefronts per SIMD (at most 256 VGPRs;
+// unlimited they take 280-310 and run one wavefront per SIMD, measured 30 % slower at 640);
+// the others are not limited.
 template <int N, int TW, int MODE>
-__global__ __launch_bounds__((PassCfg<N, TW, pass_waves<MODE>()>::WAVES * 64)) void k_pass(PassArgs a) {
+__global__ __launch_bounds__((PassCfg<N, TW, pass_waves<MODE>()>::WAVES * 64))
+__attribute__((amdgpu_waves_per_eu(fft_odd(N) == 5 ? 2 : 1, 8))) void k_pass(PassArgs a) {
   using C = PassCfg<N, TW, pass_waves<MODE>()>;
   constexpr int T = C::T, S = C::S, RS = C::RS, TPB = C::TPB, RPW = C::RPW;
   constexpr int NT = C::WAVES * 64;
