@@ -228,7 +228,7 @@ lma_status lma_synchronize(lma_plan* plan);
 /* Picks the slice-pass schedule for an nx x ny grid by measurement: times one slice (row
  * pass, then column pass, the multislice step of Fig. multislice_pseudocode) on synthetic
  * waves for every tile width the passes are built for and every batch of 64..4096 waves
- * that fits max_bytes (0: 1 GiB), and returns the fastest. Results are kept per device and
+ * that fits max_bytes (0: 4 GiB), and returns the fastest. Results are kept per device and
  * grid for the life of the process; later calls return them without measuring. Allocates
  * and frees its own scratch memory; work runs on hip_stream (may be NULL) and is finished
  * on return. LMA_ERR_UNSUPPORTED for a grid the passes are not built for. */

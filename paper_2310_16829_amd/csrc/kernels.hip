@@ -116,13 +116,15 @@ __device__ __forceinline__ void dft_r(float2* a) {
 }
 
 // ------------------------------------------------------------------------------------------
-// stage schedule. 2^a: radix 8 while possible, the remaining factor (2 or 4) last, E = 8.
+// stage schedule. 2^a: radix 8 while possible, the remaining factor (2 or 4) last, E = 8
+// (E = 16 at 1024 points, so that a line is one wavefront's: 8.8.8.2, exchanges without
+// workgroup barriers; measured +17-23 % over two wavefronts per line).
 // 3 * 2^a and 5 * 2^a: the odd radix, then radix 4, then a 2 if needed, E = 4 x the odd factor
 // (every radix of the schedule divides E).
 // ------------------------------------------------------------------------------------------
 __host__ __device__ constexpr int fft_odd(int n) { while (n > 1 && n % 2 == 0) n /= 2; return n; }
 __host__ __device__ constexpr bool fft_pow2(int n) { return fft_odd(n) == 1; }
-__host__ __device__ constexpr int fft_elems(int n) { return fft_pow2(n) ? 8 : 4 * fft_odd(n); }
+__host__ __device__ constexpr int fft_elems(int n) { return fft_pow2(n) ? (n == 1024 ? 16 : 8) : 4 * fft_odd(n); }
 __host__ __device__ constexpr int fft_log2(int n) { int a = 0; while (n > 1) { n /= 2; ++a; } return a; }
 __host__ __device__ constexpr int fft_full8(int n) { int s = 0; while (n >= 8) { n /= 8; ++s; } return s; }
 __host__ __device__ constexpr int fft_rest(int n) { while (n >= 8) n /= 8; return n; }
