@@ -218,12 +218,25 @@ def summarize_counters(fetch_dir, write_dir, cal_fetch_dir, cal_write_dir):
 
 
 def serve(rates=(2.0, 10.0, 50.0, 200.0), n_requests=60, slots=4):
-    """Serving under Poisson arrivals: six resident specimens of mixed sizes (128^2 x 10 slices,
-    256^2 x 20 slices, the 512^2 x 100-slice medium specimen on a 16 x 16-probe window), 70 %
-    image requests (a new frozen-phonon configuration of a random specimen) and 30 % local edits
-    (one raised 12 x 12-pixel column patch of a random specimen, recomputed locally), run by
-    the library's request loop with `slots` worker slots. Reports p50 / p99 latency (arrival to
-    completion) and throughput per arrival rate."""
+    """Serving under Poisson arrivals, once with FP32 basis rows and contraction and once with
+    the basis stored as split BF16 (hi + lo): see serve_mode."""
+    import paper_2310_16829_amd as lma
+    out = {"study": "serving: Poisson arrivals over 6 resident specimens (2 x 128^2 x 10 slices, 2 x 256^2 x 20 "
+                    "slices, 2 x the medium 512^2 x 100-slice specimen on 16 x 16-probe windows), 70 % LMA "
+                    "images, 30 % local edits", "slots": slots}
+    for name, prec in (("fp32", lma.LMA_GEMM_FP32), ("split_bf16", lma.LMA_GEMM_SPLIT_BF16)):
+        log(f"serve: {name}")
+        out[name] = serve_mode(prec, rates, n_requests, slots)
+    print(json.dumps(out), flush=True)
+
+
+def serve_mode(precision, rates, n_requests, slots):
+    """Six resident specimens of mixed sizes (128^2 x 10 slices, 256^2 x 20 slices, the 512^2 x
+    100-slice medium specimen on a 16 x 16-probe window), 70 % image requests (a new
+    frozen-phonon configuration of a random specimen) and 30 % local edits (one raised 12 x
+    12-pixel column patch of a random specimen, recomputed locally), run by the library's
+    request loop with `slots` worker slots. Returns p50 / p99 latency (arrival to completion)
+    and throughput per arrival rate."""
     import numpy as np
     import torch
     import paper_2310_16829_amd as lma
@@ -240,19 +253,17 @@ def serve(rates=(2.0, 10.0, 50.0, 200.0), n_requests=60, slots=4):
         opt = lma.optics(n, n, l, l, lam, sig, 2.0, 2.0 / 3.0, 0.02)
         if kind == "medium":
             a0, b0 = (int(x) for x in rng.integers(0, 112, size=2))
-            lat = lma.lattice(128, 128, 128, 128, 1, (0.5, 0.5), 144, window=(a0, b0, 16, 16))
+            lat = lma.lattice(128, 128, 128, 128, 1, (0.5, 0.5), 144, precision, window=(a0, b0, 16, 16))
             pots = [potential_slices(wm, c) for c in range(2)]
         else:
-            lat = lma.lattice(n // 8, n // 8, n // 4, n // 4, 1, (0.5, 0.5), 36)
+            lat = lma.lattice(n // 8, n // 8, n // 4, n // 4, 1, (0.5, 0.5), 36, precision)
             pots = [rng.uniform(0, 40, size=(nsl, n, n)).astype(np.float32) for _ in range(2)]
         shape = (len(rings), lat.window[3] or lat.py, lat.window[2] or lat.px)
         specs.append(dict(opt=opt, lat=lat, det=lma.detectors(rings), pots=[torch.from_numpy(v).cuda() for v in pots],
                           host=pots[0], n=n, shape=shape, kind=kind))
     torch.cuda.synchronize()
     budget = 64 << 30
-    out = {"study": "serving: Poisson arrivals over 6 resident specimens (2 x 128^2 x 10 slices, 2 x 256^2 x 20 "
-                    "slices, 2 x the medium 512^2 x 100-slice specimen on 16 x 16-probe windows), 70 % LMA "
-                    "images, 30 % local edits", "slots": slots, "rates": []}
+    out = {"rates": []}
     with lma.Server(slots, len(specs), budget) as srv:
         t = [srv.build(k, s["opt"], s["lat"], s["det"], s["pots"][0].shape[0]) for k, s in enumerate(specs)]
         for x in t:
@@ -307,7 +318,7 @@ def serve(rates=(2.0, 10.0, 50.0, 200.0), n_requests=60, slots=4):
             log(f"serve: rate {rate}/s: p50 {row['p50_ms']:.1f} ms, p99 {row['p99_ms']:.1f} ms, "
                 f"{row['throughput_per_s']:.1f} req/s")
             out["rates"].append(row)
-    print(json.dumps(out), flush=True)
+    return out
 
 
 def paper_shaped():
