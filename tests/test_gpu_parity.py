@@ -509,6 +509,78 @@ def test_medium_full_size_sampled():
         assert e.max() < TOL32
 
 
+_LARGE = {}
+
+
+def _large_potential(args):
+    """Slices [lo, hi) of the large workload's configuration-0 potential (the generator's own
+    per-slice computation, split over processes)."""
+    from synth.specimen import atom_sites, phonon_positions
+    lo, hi = args
+    w = WORKLOADS["large"]
+    sites, amps = atom_sites(w)
+    return potential_from_atoms(w, phonon_positions(w, 0, sites), amps, range(lo, hi))
+
+
+def _large_job(job):
+    """Oracle work for the large workload in a worker (inherits _LARGE from the parent)."""
+    kind, arg = job
+    st, v = _LARGE["st"], _LARGE["v"]
+    if kind == "translate":
+        from oracle.lma import translate_wave
+        from oracle.multislice import multislice
+        return kind, np.fft.fft2(multislice(translate_wave(st, st.spec0, arg), v, st.sigma, st.prop))
+    return kind, plain_image(st, v, [arg])[:, arg[1], arg[0]]
+
+
+@pytest.mark.slow
+def test_large_full_size_sampled():
+    # the large precision workload at full size: 2048^2 over 204.8 A, 250 slices, 300 kV, 25 mrad,
+    # defocus -50 A, the 256 x 256 scan and translates every 4 px; a 4 x 4-probe window with the
+    # basis in FP32 and in split BF16 (hi + lo); one translate's exit wave and one plain pixel
+    # against the oracle (each about a minute of FP64 CPU time)
+    w = WORKLOADS["large"]
+    n_workers = max(1, min(16, len(os.sched_getaffinity(0))))
+    say(f"large: potential (250 x 2048^2) on {n_workers} processes")
+    step = -(-w.nslices // n_workers)
+    with ProcessPoolExecutor(n_workers) as ex:
+        v = np.concatenate(list(ex.map(_large_potential, [(lo, min(lo + step, w.nslices))
+                                                          for lo in range(0, w.nslices, step)])))
+    win = (100, 60, 4, 4)
+    plan, st, ol = build(w, window=win)
+    say(f"large: GPU propagate ({plan.info().n_rows} translates) + images")
+    plan.propagate(v)
+    img = plan.probe_image()
+    bplan, _, _ = build(w, window=win, precision=lma.LMA_GEMM_SPLIT_BF16)
+    bplan.propagate(v)
+    bimg = bplan.probe_image()
+    bplan.close()
+    for r in range(img.shape[0]):
+        e = rel_l2(bimg[r], img[r])
+        say(f"  ring {r}: split-BF16 vs FP32 basis rel L2 {e:.2e}")
+        assert e < TOL_BF16
+    pimg = plan.plain_image(v)
+    rows = plan.rows()
+    flat, _ = plan.detector_pixels()
+    t = int(rows[len(rows) // 2])
+    tpos = ol.translate_position(t % ol.Rfx, t // ol.Rfx)
+    probe = (win[0] + 1, win[1] + 2)
+    _LARGE.update(st=st, v=v)
+    say("large: oracle (one translate, one plain probe) on 2 processes")
+    with ProcessPoolExecutor(2) as ex:
+        res = dict(ex.map(_large_job, [("translate", (float(tpos[0]), float(tpos[1]))), ("plain", probe)]))
+    _LARGE.clear()
+    got = plan.basis_rows(int(np.nonzero(rows == t)[0][0]), 1)[0]
+    e = rel_l2(got, res["translate"].ravel()[flat])
+    say(f"  exit wave of translate {t}: rel L2 {e:.2e}")
+    assert e < TOL32
+    a, b = probe
+    e = np.abs(pimg[:, b - win[1], a - win[0]] - res["plain"]) / np.abs(res["plain"])
+    say(f"  plain pixel {probe} rel err", e)
+    assert e.max() < TOL32
+    plan.close()
+
+
 @pytest.mark.slow
 def test_paper_shaped_full_size_sampled():
     # the paper-shaped workload at full size: 1024^2 grid over a non-square cell, Case 2 with
