@@ -212,6 +212,30 @@ lma_status lma_image(lma_plan* plan, const float* potential, int32_t nslices, do
 lma_status lma_plain_image(lma_plan* plan, const float* potential, int32_t nslices,
                            double* image, int32_t flags, double weight);
 
+/* 4-D STEM output (Sec. 3.1, step 3, the pixelated detector): for every probe of the window,
+ * |F(psi_p^exit)(k)|^2 / (XY) (unit incident intensity) at each of the plan's D detector
+ * pixels k, the union of its rings in the order of lma_get_detector_pixels: out
+ * [wh][ww][D] float32, host (the call returns when it is written) or device with
+ * LMA_PTR_DEVICE. A plan whose rings include [0, a) with a at or beyond the band limit records
+ * every frequency of the band. Needs a propagated basis; LMA_ERR_STATE on a partitioned plan.
+ * Allocates a device buffer of the output's size for host output. */
+lma_status lma_probe_patterns(lma_plan* plan, float* out, int32_t flags);
+
+/* 3-D STEM output (Sec. 3.1, step 3, many small annuli): for every probe of the window and
+ * a = 0..nbins-1, the sum of |F(psi_p^exit)(k)|^2 / (XY) over the plan's detector pixels with
+ * a * width <= lambda |k| < (a + 1) * width (width in radians, 1 <= nbins <= 512): image
+ * [nbins][wh][ww] float64, image = weight * I, or image += weight * I with LMA_ACCUMULATE;
+ * host or device (LMA_PTR_DEVICE) as for lma_probe_image. Needs a propagated basis;
+ * LMA_ERR_STATE on a partitioned plan. */
+lma_status lma_probe_radial(lma_plan* plan, double width, int32_t nbins, double* image, int32_t flags,
+                            double weight);
+
+/* The plain-multislice 4-D output: every probe of the window propagated directly (Sec. 3.1
+ * steps 1-3), out as for lma_probe_patterns. Does not touch the resident basis. Allocates a
+ * device buffer of n_probes x D complex values for the call. */
+lma_status lma_plain_patterns(lma_plan* plan, const float* potential, int32_t nslices, float* out,
+                              int32_t flags);
+
 /* Local recompute after a specimen edit (Sec. 4.2.6): re-propagate the resident translates
  * whose centre lies within radius_A of the edited pixel box, with the new potential, and
  * re-form the probes whose translate set meets them; their image values are replaced in

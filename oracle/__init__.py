@@ -9,7 +9,7 @@ Contents (paper: Doberstein & Binev, "Lattice Multislice Algorithm for Fast Simu
 of Scanning Transmission Electron Microscopy Images"):
   physics     electron constants, frequency grid, probe (eqs. probe_wave_function,
               aberration_function, aperture_function), transmission and Fresnel
-              propagator (Sec. 3.2), detector rings (Sec. 3.1, step 3)
+              propagator (Sec. 3.2), 2-D, 3-D and 4-D STEM outputs (Sec. 3.1, step 3)
   multislice  the multislice loop (Fig. multislice_pseudocode) and the plain STEM image
   lma         lattices (Sec. 4.2.1), nearest-translate sets and least-squares
               coefficients (Sec. 4.2.2), the LMA image (Fig. lma_pseudocode), local

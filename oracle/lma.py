@@ -183,12 +183,18 @@ class LMA:
             basis = self.propagate(potential, self.needed_translates(probes))
         img = np.full((len(st.detectors), st.Py, st.Px), np.nan)
         for a, b in probes:
-            al = self.alpha[self.lat.coefficient_class(a, b)]
-            spec = np.zeros((st.ny, st.nx), dtype=np.complex128)
-            for c, t in zip(al, self.lat.nearest(a, b)):
-                spec += c * basis[t]
-            img[:, b, a] = ph.detector_values(spec, st.masks)
+            img[:, b, a] = ph.detector_values(self.exit_spectrum(a, b, basis), st.masks)
         return img
+
+    def exit_spectrum(self, a: int, b: int, basis: dict) -> np.ndarray:
+        """Step 2 in Fourier space: sum_j alpha_j F(U_{i_j}) for probe (a, b), from the
+        propagated translates ``basis`` ({(ta, tb): F(U_i)}, as returned by propagate)."""
+        st = self.setup
+        al = self.alpha[self.lat.coefficient_class(a, b)]
+        spec = np.zeros((st.ny, st.nx), dtype=np.complex128)
+        for c, t in zip(al, self.lat.nearest(a, b)):
+            spec += c * basis[t]
+        return spec
 
 
 def phonon_average(images) -> np.ndarray:

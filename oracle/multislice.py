@@ -53,6 +53,20 @@ class Setup:
         return ph.probe_wave(self.spec0, self.lx, self.ly, self.probe_position(a, b))
 
 
+def plain_exit_spectra(setup: Setup, potential: np.ndarray, probes, batch: int = 16) -> dict:
+    """F(psi_p^exit) of every probe (a, b) in ``probes``, each propagated directly (Sec. 3.1
+    steps 1-2)."""
+    out = {}
+    probes = list(probes)
+    for s in range(0, len(probes), batch):
+        chunk = probes[s:s + batch]
+        psi0 = np.stack([setup.probe(a, b) for a, b in chunk])
+        spec = np.fft.fft2(multislice(psi0, potential, setup.sigma, setup.prop))
+        for p, sp in zip(chunk, spec):
+            out[p] = sp
+    return out
+
+
 def plain_image(setup: Setup, potential: np.ndarray, probes=None, batch: int = 16) -> np.ndarray:
     """Plain multislice STEM image: every probe propagated directly (Sec. 3.1 steps 1-3).
 
@@ -61,14 +75,8 @@ def plain_image(setup: Setup, potential: np.ndarray, probes=None, batch: int = 1
     img = np.full((len(setup.detectors), setup.Py, setup.Px), np.nan)
     if probes is None:
         probes = [(a, b) for b in range(setup.Py) for a in range(setup.Px)]
-    probes = list(probes)
-    for s in range(0, len(probes), batch):
-        chunk = probes[s:s + batch]
-        psi0 = np.stack([setup.probe(a, b) for a, b in chunk])
-        exit_ = multislice(psi0, potential, setup.sigma, setup.prop)
-        spec = np.fft.fft2(exit_)
-        for (a, b), sp in zip(chunk, spec):
-            img[:, b, a] = ph.detector_values(sp, setup.masks)
+    for (a, b), sp in plain_exit_spectra(setup, potential, probes, batch).items():
+        img[:, b, a] = ph.detector_values(sp, setup.masks)
     return img
 
 

@@ -144,6 +144,26 @@ def ring_masks(nx, ny, lx, ly, wavelength, bandlimit, detectors) -> np.ndarray:
     return out
 
 
+def detector_pattern(exit_spectrum: np.ndarray, pixels: np.ndarray) -> np.ndarray:
+    """4-D STEM output of one exit wave (Sec. 3.1, step 3, pixelated detector): |F(psi_exit)|^2
+    / (XY) at the pixels where the boolean (ny, nx) mask ``pixels`` holds, in row-major order."""
+    ny, nx = exit_spectrum.shape
+    return (np.abs(exit_spectrum) ** 2)[pixels] / (nx * ny)
+
+
+def annulus_values(exit_spectrum: np.ndarray, lx: float, ly: float, wavelength: float, width: float,
+                   nbins: int, pixels: np.ndarray) -> np.ndarray:
+    """3-D STEM output of one exit wave (Sec. 3.1, step 3, many small annuli): for a = 0..nbins-1
+    the sum of |F(psi_exit)|^2 / (XY) over the pixels of ``pixels`` whose scattering angle
+    theta = lambda |k| satisfies a * width <= theta < (a + 1) * width (annulus index taken as
+    floor(theta / width) in float64)."""
+    ny, nx = exit_spectrum.shape
+    kx, ky, _ = k_grid(nx, ny, lx, ly)
+    a = np.floor(wavelength * np.sqrt(kx * kx + ky * ky) / width)
+    inten = np.abs(exit_spectrum) ** 2 / (nx * ny)
+    return np.array([inten[pixels & (a == b)].sum() for b in range(nbins)])
+
+
 def detector_values(exit_spectrum: np.ndarray, masks: np.ndarray) -> np.ndarray:
     """I_r = sum over ring r of |F(psi_exit)|^2 / (XY) for one exit wave (its DFT given)."""
     ny, nx = exit_spectrum.shape

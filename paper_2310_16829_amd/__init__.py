@@ -193,6 +193,46 @@ class Plan:
         _check(lib().lma_plain_image(self._h, pp, int(potential.shape[0]), pi, int(flags) | fi, float(weight)))
         return image
 
+    def _pattern_out(self, out, device):
+        shape = (self.window[3], self.window[2], self.n_pix)
+        if out is None:
+            if device:
+                import torch
+                out = torch.zeros(shape, dtype=torch.float32, device="cuda")
+            else:
+                out = np.zeros(shape, dtype=np.float32)
+        return out
+
+    def probe_patterns(self, out=None, flags: int = 0, device: bool = False):
+        """4-D STEM: [wh][ww][D] float32 at the plan's detector pixels."""
+        out = self._pattern_out(out, device)
+        p, f = _ptr(out, np.float32)
+        _check(lib().lma_probe_patterns(self._h, p, int(flags) | f))
+        return out
+
+    def plain_patterns(self, potential, out=None, flags: int = 0, device: bool = False):
+        pp, fp = _ptr(potential, np.float32)
+        out = self._pattern_out(out, device)
+        po, fo = _ptr(out, np.float32)
+        if fp != fo:
+            raise ValueError("potential and output must both be host or both be device")
+        _check(lib().lma_plain_patterns(self._h, pp, int(potential.shape[0]), po, int(flags) | fo))
+        return out
+
+    def probe_radial(self, width: float, nbins: int, image=None, flags: int = 0, weight: float = 1.0,
+                     device: bool = False):
+        """3-D STEM: [nbins][wh][ww] float64 sums over annuli a*width <= lambda|k| < (a+1)*width."""
+        shape = (int(nbins), self.window[3], self.window[2])
+        if image is None:
+            if device:
+                import torch
+                image = torch.zeros(shape, dtype=torch.float64, device="cuda")
+            else:
+                image = np.zeros(shape, dtype=np.float64)
+        p, f = _ptr(image, np.float64)
+        _check(lib().lma_probe_radial(self._h, float(width), int(nbins), p, int(flags) | f, float(weight)))
+        return image
+
     def recompute_local(self, potential_new, bbox, radius: float, image):
         pp, fp = _ptr(potential_new, np.float32)
         pi, fi = _ptr(image, np.float64)

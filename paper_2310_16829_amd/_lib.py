@@ -71,6 +71,9 @@ SIGNATURES = {
     "lma_probe_image": (C.c_int, [P, P, C.c_int32, C.c_double]),
     "lma_plain_image": (C.c_int, [P, P, C.c_int32, P, C.c_int32, C.c_double]),
     "lma_image": (C.c_int, [P, P, C.c_int32, P, C.c_int32, C.c_double]),
+    "lma_probe_patterns": (C.c_int, [P, P, C.c_int32]),
+    "lma_probe_radial": (C.c_int, [P, C.c_double, C.c_int32, P, C.c_int32, C.c_double]),
+    "lma_plain_patterns": (C.c_int, [P, P, C.c_int32, P, C.c_int32]),
     "lma_recompute_local": (C.c_int, [P, P, C.c_int32, C.POINTER(C.c_int32), C.c_double, P,
                                       C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
     "lma_footprint": (C.c_int, [C.POINTER(lma_optics), C.POINTER(lma_lattice), C.POINTER(lma_detectors),

@@ -94,6 +94,9 @@ struct lma_plan {
   float* d_pot = nullptr;            // staging for host potentials
   int pot_cap = 0;
   double* d_img = nullptr;           // [ndet][n_probes]
+  int32_t* d_bin_of = nullptr;       // 3-D output: annulus of each detector pixel
+  double bin_width = 0.0;
+  int bin_count = 0;
   int32_t* d_list = nullptr;         // scratch index list (recompute)
   int64_t* d_list_u = nullptr;
   int list_cap = 0;
@@ -273,23 +276,27 @@ lma_status prepare_transmission(lma_plan* p, const float* potential, int nslices
 }
 
 // multislice of waves [first, first + n) of a position list; the last column pass either
-// gathers basis rows (wave_row != null) or reduces into the image (wave_out != null)
-lma_status run_waves(lma_plan* p, const int64_t* d_u, const int32_t* d_row, const int32_t* d_out, int n, int nslices) {
+// gathers the detector pixels into rows of `target` (wave_row != null; the resident basis
+// unless given) or reduces into the image (wave_out != null). Probe waves (no wave_row) start
+// from psi_0, translates from u.
+lma_status run_waves(lma_plan* p, const int64_t* d_u, const int32_t* d_row, const int32_t* d_out, int n, int nslices,
+                     void* target = nullptr, bool probes = false) {
   const lma::dev::Tables T = tables(p);
   const int64_t XY = (int64_t)p->h.op.nx * p->h.op.ny;
-  const int split = p->h.lat.precision == LMA_GEMM_SPLIT_BF16;
+  const int split = target ? 0 : p->h.lat.precision == LMA_GEMM_SPLIT_BF16;
   for (int first = 0; first < n; first += p->B) {
     const int nb = std::min(p->B, n - first);
     // translates start from u, probes from psi_0
     lma::dev::Tables Ti = T;
-    if (d_row) Ti.specT = p->d_uspecT;
+    if (d_row && !probes) Ti.specT = p->d_uspecT;
     LAUNCH(p, "init", lma::dev::init_waves(Ti, p->d_work, d_u + 2 * (int64_t)first, nb, p->stream));
     for (int j = 0; j < nslices; ++j) {
       LAUNCH(p, "row_pass", lma::dev::row_pass(T, p->d_work, p->d_trans + (size_t)j * XY, nb, p->stream));
       if (j + 1 < nslices) {
         LAUNCH(p, "col_pass", lma::dev::col_pass(T, p->d_work, nb, p->stream));
       } else if (d_row) {
-        LAUNCH(p, "col_gather", lma::dev::col_gather(T, p->d_work, nb, p->d_basis, p->h.D(), d_row + first, split, p->stream));
+        LAUNCH(p, "col_gather", lma::dev::col_gather(T, p->d_work, nb, target ? target : p->d_basis, p->h.D(), d_row + first,
+                                                     split, p->stream));
       } else {
         LAUNCH(p, "col_reduce", lma::dev::col_reduce(T, p->d_work, nb, d_out + first, p->d_img, p->h.ndet,
                                                      p->h.n_probes(), (double)XY, p->stream));
@@ -797,6 +804,122 @@ lma_status lma_plain_image(lma_plan* plan, const float* potential, int32_t nslic
     HIP_TRY(hipMemsetAsync(plan->d_img, 0, (size_t)plan->h.ndet * plan->h.n_probes() * sizeof(double), plan->stream));
     if ((s = waves(plan, plan->d_probe_u, nullptr, plan->d_probe_out, (int)plan->h.n_probes(), nslices)) != LMA_OK) return s;
     return write_image(plan, image, flags, weight);
+  } catch (const std::exception& e) {
+    return fail(LMA_ERR_DEVICE, e.what());
+  }
+}
+
+lma_status lma_probe_patterns(lma_plan* plan, float* out, int32_t flags) {
+  lma_status s = check_device_call(plan, out, 1);
+  if (s != LMA_OK) return s;
+  if (plan->partitioned) return fail(LMA_ERR_STATE, "the plan is partitioned: its basis is never resident whole");
+  if (!plan->basis_valid) return fail(LMA_ERR_STATE, "no valid propagated basis (call lma_propagate)");
+  const int64_t n = plan->h.n_probes() * (int64_t)plan->h.D();
+  try {
+    float* dst = out;
+    if (!(flags & LMA_PTR_DEVICE) && (s = dalloc(plan, (void**)&dst, (size_t)n * sizeof(float))) != LMA_OK) return s;
+    lma::dev::Contraction c = contraction(plan);
+    c.patterns = dst;
+    Launch l(plan, "contract_pattern");
+    hipError_t e = lma::dev::contract(c, plan->stream);
+    l.done();
+    if (e == hipSuccess && !(flags & LMA_PTR_DEVICE)) {
+      e = hipMemcpyAsync(out, dst, (size_t)n * sizeof(float), hipMemcpyDeviceToHost, plan->stream);
+      if (e == hipSuccess) e = hipStreamSynchronize(plan->stream);
+    }
+    if (dst != out) free_one(plan, dst, (size_t)n * sizeof(float));
+    if (e != hipSuccess) return fail(LMA_ERR_DEVICE, std::string("patterns: ") + hipGetErrorString(e));
+    return LMA_OK;
+  } catch (const std::exception& e) {
+    return fail(LMA_ERR_DEVICE, e.what());
+  }
+}
+
+lma_status lma_probe_radial(lma_plan* plan, double width, int32_t nbins, double* image, int32_t flags, double weight) {
+  lma_status s = check_device_call(plan, image, 1);
+  if (s != LMA_OK) return s;
+  if (!(width > 0) || !std::isfinite(width)) return fail(LMA_ERR_ARG, "annulus width must be positive");
+  if (nbins < 1 || nbins > lma::dev::kMaxRadialBins) return fail(LMA_ERR_ARG, "nbins must be in [1, 512]");
+  if (!std::isfinite(weight)) return fail(LMA_ERR_ARG, "weight must be finite");
+  if (plan->partitioned) return fail(LMA_ERR_STATE, "the plan is partitioned: its basis is never resident whole");
+  if (!plan->basis_valid) return fail(LMA_ERR_STATE, "no valid propagated basis (call lma_propagate)");
+  const HostPlan& h = plan->h;
+  const int D = h.D();
+  const int64_t n = (int64_t)nbins * h.n_probes();
+  try {
+    if (!plan->d_bin_of || plan->bin_width != width || plan->bin_count != nbins) {
+      // annulus of every detector pixel: a = floor(lambda |k| / width) while below nbins
+      std::vector<int32_t> bin(D);
+      for (int d = 0; d < D; ++d) {
+        const int f = h.comp_flat[d];
+        const int mx = f % h.op.nx, my = f / h.op.nx;
+        const double kx = (double)(mx < (h.op.nx + 1) / 2 ? mx : mx - h.op.nx) / h.op.lx;
+        const double ky = (double)(my < (h.op.ny + 1) / 2 ? my : my - h.op.ny) / h.op.ly;
+        const double a = std::floor(h.op.wavelength * std::sqrt(kx * kx + ky * ky) / width);
+        bin[d] = a < (double)nbins ? (int32_t)a : -1;
+      }
+      if (!plan->d_bin_of && (s = dalloc(plan, (void**)&plan->d_bin_of, (size_t)D * sizeof(int32_t))) != LMA_OK) return s;
+      HIP_TRY(hipMemcpy(plan->d_bin_of, bin.data(), (size_t)D * sizeof(int32_t), hipMemcpyHostToDevice));
+      plan->bin_width = width;
+      plan->bin_count = nbins;
+    }
+    double* acc = nullptr;
+    if ((s = dalloc(plan, (void**)&acc, (size_t)n * sizeof(double))) != LMA_OK) return s;
+    lma::dev::Contraction c = contraction(plan);
+    c.bin_of = plan->d_bin_of;
+    c.nbins = nbins;
+    c.radial = acc;
+    hipError_t e = hipMemsetAsync(acc, 0, (size_t)n * sizeof(double), plan->stream);
+    if (e == hipSuccess) {
+      Launch l(plan, "contract_radial");
+      e = lma::dev::contract(c, plan->stream);
+      l.done();
+    }
+    if (e == hipSuccess && (flags & LMA_PTR_DEVICE)) {
+      e = lma::dev::scale_out(image, acc, n, weight, (flags & LMA_ACCUMULATE) ? 1 : 0, plan->stream);
+      if (e == hipSuccess) e = hipStreamSynchronize(plan->stream);
+    } else if (e == hipSuccess) {
+      std::vector<double> tmp((size_t)n);
+      e = hipMemcpyAsync(tmp.data(), acc, (size_t)n * sizeof(double), hipMemcpyDeviceToHost, plan->stream);
+      if (e == hipSuccess) e = hipStreamSynchronize(plan->stream);
+      if (e == hipSuccess)
+        for (int64_t i = 0; i < n; ++i) image[i] = (flags & LMA_ACCUMULATE) ? image[i] + weight * tmp[i] : weight * tmp[i];
+    }
+    free_one(plan, acc, (size_t)n * sizeof(double));
+    if (e != hipSuccess) return fail(LMA_ERR_DEVICE, std::string("radial: ") + hipGetErrorString(e));
+    return LMA_OK;
+  } catch (const std::exception& e) {
+    return fail(LMA_ERR_DEVICE, e.what());
+  }
+}
+
+lma_status lma_plain_patterns(lma_plan* plan, const float* potential, int32_t nslices, float* out, int32_t flags) {
+  lma_status s = check_device_call(plan, potential, nslices);
+  if (s != LMA_OK) return s;
+  if (!out) return fail(LMA_ERR_ARG, "out is null");
+  const int64_t np = plan->h.n_probes(), D = plan->h.D(), n = np * D;
+  try {
+    if ((s = prepare_transmission(plan, potential, nslices, flags)) != LMA_OK) return s;
+    float2* spec = nullptr;
+    float* dst = out;
+    if ((s = dalloc(plan, (void**)&spec, (size_t)n * sizeof(float2))) != LMA_OK) return s;
+    if (!(flags & LMA_PTR_DEVICE) && (s = dalloc(plan, (void**)&dst, (size_t)n * sizeof(float))) != LMA_OK) {
+      free_one(plan, spec, (size_t)n * sizeof(float2));
+      return s;
+    }
+    s = run_waves(plan, plan->d_probe_u, plan->d_probe_out, nullptr, (int)np, nslices, spec, true);
+    hipError_t e = hipSuccess;
+    if (s == LMA_OK) {
+      e = lma::dev::intensity(spec, dst, n, (double)plan->h.op.nx * plan->h.op.ny, plan->stream);
+      if (e == hipSuccess && !(flags & LMA_PTR_DEVICE))
+        e = hipMemcpyAsync(out, dst, (size_t)n * sizeof(float), hipMemcpyDeviceToHost, plan->stream);
+      if (e == hipSuccess) e = hipStreamSynchronize(plan->stream);
+    }
+    free_one(plan, spec, (size_t)n * sizeof(float2));
+    if (dst != out) free_one(plan, dst, (size_t)n * sizeof(float));
+    if (s != LMA_OK) return s;
+    if (e != hipSuccess) return fail(LMA_ERR_DEVICE, std::string("plain patterns: ") + hipGetErrorString(e));
+    return LMA_OK;
   } catch (const std::exception& e) {
     return fail(LMA_ERR_DEVICE, e.what());
   }

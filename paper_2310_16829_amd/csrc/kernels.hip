@@ -723,11 +723,16 @@ __device__ __forceinline__ float2 load_basis(const void* basis, int64_t i) {
   }
 }
 
-template <int SPLIT, int kPT>
+// OUT: 0 ring sums (2-D STEM), 1 the pattern |psi_hat|^2 at every detector pixel (4-D STEM),
+// 2 sums over annuli of scattering angle (3-D STEM)
+enum { OUT_RINGS = 0, OUT_PATTERN = 1, OUT_RADIAL = 2 };
+
+template <int SPLIT, int kPT, int OUT>
 __global__ __launch_bounds__(kCT) void k_contract(Contraction c) {
   extern __shared__ unsigned char dyn[];
   int64_t* rows = reinterpret_cast<int64_t*>(dyn);                        // [kPT][L]
   float2* al = reinterpret_cast<float2*>(rows + (size_t)kPT * c.L);       // [kPT][L]
+  [[maybe_unused]] double* bins = reinterpret_cast<double*>(al + (size_t)kPT * c.L);  // [kPT][nbins]
   __shared__ double part[kCT / 64][kPT];
   const int chunk = blockIdx.x;
   const int p0 = blockIdx.y * kPT;
@@ -748,6 +753,9 @@ __global__ __launch_bounds__(kCT) void k_contract(Contraction c) {
     rows[pi * c.L + jj] = row >= 0 ? (int64_t)row * c.D : 0;
     al[pi * c.L + jj] = row >= 0 ? c.alpha[s * c.L + jj] : make_float2(0.f, 0.f);
   }
+  if constexpr (OUT == OUT_RADIAL) {
+    for (int i = threadIdx.x; i < kPT * c.nbins; i += kCT) bins[i] = 0.0;
+  }
   __syncthreads();
   const int start = c.chunk_start[chunk], len = c.chunk_len[chunk];
   const uint32_t mask = c.chunk_mask[chunk];
@@ -767,6 +775,36 @@ __global__ __launch_bounds__(kCT) void k_contract(Contraction c) {
       }
       val[pi] = (double)acc.x * acc.x + (double)acc.y * acc.y;
     }
+  }
+  if constexpr (OUT == OUT_PATTERN) {
+    if (t < len) {
+#pragma unroll
+      for (int pi = 0; pi < kPT; ++pi)
+        if (pi < npb) {
+          const int p = c.probe_list ? c.probe_list[p0 + pi] : p0 + pi;
+          c.patterns[(int64_t)p * c.D + start + t] = (float)(val[pi] * c.scale);
+        }
+    }
+    return;
+  }
+  if constexpr (OUT == OUT_RADIAL) {
+    const int bin = t < len ? c.bin_of[start + t] : -1;
+    if (bin >= 0) {
+#pragma unroll
+      for (int pi = 0; pi < kPT; ++pi)
+        if (pi < npb) atomicAdd(&bins[pi * c.nbins + bin], val[pi]);
+    }
+    __syncthreads();
+    const int64_t stride = c.probe_list ? c.n_list : (int64_t)c.ww * c.wh;
+    for (int i = t; i < npb * c.nbins; i += kCT) {
+      const double x = bins[i];
+      if (x != 0.0) {
+        const int pi = i / c.nbins, b = i % c.nbins;
+        const int p = c.probe_list ? c.probe_list[p0 + pi] : p0 + pi;
+        atomicAdd(c.radial + (int64_t)b * stride + p, x * c.scale);
+      }
+    }
+    return;
   }
   const int lane = t & 63, wv = t >> 6;
 #pragma unroll
@@ -1063,21 +1101,51 @@ hipError_t col_reduce(const Tables& T, float2* work, int B, const int32_t* wave_
   return pass_dispatch<PASS_REDUCE>(T.ny, tw_of(T), T.nx, a, B, s);
 }
 
-template <int SPLIT, int PT>
+static size_t contract_shm(const Contraction& c, int pt, int out) {
+  return (size_t)pt * c.L * (sizeof(int64_t) + sizeof(float2)) +
+         (out == OUT_RADIAL ? (size_t)pt * c.nbins * sizeof(double) : 0);
+}
+
+template <int SPLIT, int PT, int OUT>
 static hipError_t contract_pt(const Contraction& c, int np, hipStream_t s) {
   dim3 grid((unsigned)c.nchunks, (unsigned)((np + PT - 1) / PT));
-  const size_t shm = (size_t)PT * c.L * (sizeof(int64_t) + sizeof(float2));
-  k_contract<SPLIT, PT><<<grid, kCT, shm, s>>>(c);
+  k_contract<SPLIT, PT, OUT><<<grid, kCT, contract_shm(c, PT, OUT), s>>>(c);
   return hipGetLastError();
+}
+
+template <int OUT>
+static hipError_t contract_out(const Contraction& c, int np, hipStream_t s) {
+  // per-block tables of PT probes x L neighbours (and PT x nbins annulus sums) must fit
+  // 64 KiB of LDS
+  const bool wide = contract_shm(c, 8, OUT) <= 60 * 1024;
+  if (!wide && contract_shm(c, 1, OUT) > 60 * 1024) return hipErrorInvalidValue;
+  if (c.split_bf16) return wide ? contract_pt<1, 8, OUT>(c, np, s) : contract_pt<1, 1, OUT>(c, np, s);
+  return wide ? contract_pt<0, 8, OUT>(c, np, s) : contract_pt<0, 1, OUT>(c, np, s);
 }
 
 hipError_t contract(const Contraction& c, hipStream_t s) {
   const int np = c.probe_list ? c.n_list : c.ww * c.wh;
   if (np <= 0 || c.nchunks <= 0) return hipSuccess;
-  // per-block tables of PT probes x L neighbours must fit 64 KiB of LDS
-  const bool wide = (size_t)8 * c.L * (sizeof(int64_t) + sizeof(float2)) <= 60 * 1024;
-  if (c.split_bf16) return wide ? contract_pt<1, 8>(c, np, s) : contract_pt<1, 1>(c, np, s);
-  return wide ? contract_pt<0, 8>(c, np, s) : contract_pt<0, 1>(c, np, s);
+  if (c.patterns) return contract_out<OUT_PATTERN>(c, np, s);
+  if (c.radial) {
+    if (!c.bin_of || c.nbins < 1 || c.nbins > kMaxRadialBins) return hipErrorInvalidValue;
+    return contract_out<OUT_RADIAL>(c, np, s);
+  }
+  return contract_out<OUT_RINGS>(c, np, s);
+}
+
+__global__ void k_intensity(const float2* __restrict__ in, float* __restrict__ out, int64_t n, double scale) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float2 v = in[i];
+  out[i] = (float)(scale * ((double)v.x * v.x + (double)v.y * v.y));
+}
+
+hipError_t intensity(const float2* in, float* out, int64_t n, double scale, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int th = 256;
+  k_intensity<<<(unsigned)((n + th - 1) / th), th, 0, s>>>(in, out, n, scale);
+  return hipGetLastError();
 }
 
 // The same contraction with the K-steps of every sub-block split over two wavefronts (8 per

@@ -39,6 +39,11 @@ struct Contraction {
   double* img = nullptr;             // [ndet][wh][ww]
   const int32_t* probe_list = nullptr;  // optional subset of window probes (index b*ww + a)
   int n_list = 0;
+  // instead of the ring sums (at most one of them):
+  float* patterns = nullptr;         // 4-D STEM: [probe][D] |psi_hat|^2 / (XY)
+  const int32_t* bin_of = nullptr;   // 3-D STEM: annulus of each detector pixel, or -1
+  int nbins = 0;
+  double* radial = nullptr;          // 3-D STEM: [nbins][probe] annulus sums of |psi_hat|^2 / (XY)
 };
 
 // The contraction of a whole window as a banded complex GEMM on MFMA (layout built on the host
@@ -91,8 +96,12 @@ hipError_t col_gather(const Tables& T, float2* work, int B, void* basis, int D, 
 // last column pass, plain: column FFT, * P, ring sums of |.|^2 added to img[r][wave_out[w]]
 hipError_t col_reduce(const Tables& T, float2* work, int B, const int32_t* wave_out, double* img, int ndet,
                       int64_t img_stride, double scale, hipStream_t s);
-// probe-coefficient contraction and detector reduction
+// probe-coefficient contraction and detector reduction (ring sums, or the 4-D / 3-D outputs)
 hipError_t contract(const Contraction& c, hipStream_t s);
+// largest annulus count of the 3-D output
+constexpr int kMaxRadialBins = 512;
+// out[i] = scale * |in[i]|^2 as float, n values
+hipError_t intensity(const float2* in, float* out, int64_t n, double scale, hipStream_t s);
 // the same contraction for a whole window on MFMA
 hipError_t contract_stencil(const Stencil& c, hipStream_t s);
 // out = (acc ? out : 0) + w * img, n doubles, device memory

@@ -127,6 +127,54 @@ def test_tiny_plain_image(tiny):
     say("  per-detector rel L2", e)
 
 
+def _pattern_ref(spec, pixels, flat):
+    """The oracle's 4-D pattern in the GPU's detector-pixel order (flat indices ``flat``)."""
+    full = np.zeros(pixels.size)
+    full[pixels.ravel()] = ph.detector_pattern(spec, pixels)
+    return full[flat]
+
+
+def test_4d_and_3d_outputs(tiny):
+    say("tiny: 4-D and 3-D STEM outputs (LMA and plain)")
+    plan, st, om, basis, v = tiny["plan"], tiny["st"], tiny["om"], tiny["basis"], tiny["v"]
+    plan.propagate(v)
+    pat = plan.probe_patterns()
+    flat, bits = plan.detector_pixels()
+    pixels = st.masks.any(axis=0)
+    assert pat.shape == (16, 16, len(flat)) and pat.dtype == np.float32
+    from oracle.multislice import plain_exit_spectra
+    probes = [(a, b) for b in range(16) for a in range(16)]
+    pspec = plain_exit_spectra(st, v, probes)
+    ppat = plan.plain_patterns(v)
+    width, nbins = 0.005, 17
+    rad = plan.probe_radial(width, nbins)
+    ref_rad = np.zeros((nbins, 16, 16))
+    worst = [0.0, 0.0]
+    for a, b in probes:
+        spec = om.exit_spectrum(a, b, basis)
+        e = rel_l2(pat[b, a], _pattern_ref(spec, pixels, flat))
+        ep = rel_l2(ppat[b, a], _pattern_ref(pspec[(a, b)], pixels, flat))
+        worst = [max(worst[0], e), max(worst[1], ep)]
+        ref_rad[:, b, a] = ph.annulus_values(spec, st.lx, st.ly, st.wavelength, width, nbins, pixels)
+    say(f"  4-D patterns, worst probe rel L2: LMA {worst[0]:.2e}, plain {worst[1]:.2e}")
+    assert worst[0] < TOL32 and worst[1] < TOL32
+    errs = image_errors(rad, ref_rad, TOL32)
+    say("  3-D annuli rel L2", ["%.1e" % x for x in errs])
+    # a pattern summed over a ring's pixels gives that ring's 2-D value
+    img = plan.probe_image()
+    for r in range(img.shape[0]):
+        on = ((bits >> r) & 1).astype(bool)
+        assert rel_l2(pat[:, :, on].sum(axis=2, dtype=np.float64), img[r]) < 1e-5
+    # weight and accumulation, device output
+    import torch
+    dev = torch.zeros((nbins, 16, 16), dtype=torch.float64, device="cuda")
+    plan.probe_radial(width, nbins, dev, weight=0.25)
+    plan.probe_radial(width, nbins, dev, flags=lma.LMA_ACCUMULATE, weight=0.75)
+    assert rel_l2(dev.cpu().numpy(), rad) < 1e-12
+    dpat = plan.probe_patterns(device=True)
+    assert np.array_equal(dpat.cpu().numpy(), pat)
+
+
 def test_mfma_and_per_pixel_contractions(tiny):
     # the window contraction as a banded complex GEMM on MFMA and as per-pixel vector sums,
     # on the same resident basis: both against the oracle, and against each other

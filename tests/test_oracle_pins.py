@@ -227,6 +227,60 @@ def test_detector_ring_inner_edge_inclusive_outer_exclusive():
     assert masks[0][0, 1] and not masks[1][0, 1]
 
 
+def test_4d_output_of_a_probe_in_vacuum_is_the_aperture():
+    # no specimen: the exit spectrum is the probe's times unit-modulus propagators inside the
+    # band, so the pattern is 1/|K| on the aperture pixels (unit incident intensity) and 0 off it
+    from oracle.multislice import plain_exit_spectra
+    st = _setup(nx=64, ny=64, lx=12.8, ly=12.8, defocus=40.0, cs=1e4, scan=(8, 8))
+    spec = plain_exit_spectra(st, np.zeros((3, 64, 64), np.float32), [(3, 5)])[(3, 5)]
+    pixels = st.masks.any(axis=0)
+    pat = ph.detector_pattern(spec, pixels)
+    ap = (np.abs(st.spec0) > 0)[pixels]
+    n_ap = int((np.abs(st.spec0) > 0).sum())
+    assert np.abs(pat[ap] - 1.0 / n_ap).max() < 1e-14
+    assert np.abs(pat[~ap]).max() < 1e-28
+    # pixel order: row-major over the frequency grid
+    ky, kx = np.nonzero(pixels)
+    assert np.array_equal(ky * 64 + kx, np.sort(ky * 64 + kx))
+
+
+def test_3d_output_of_a_probe_in_vacuum_counts_aperture_pixels():
+    # annulus a collects the aperture pixels with a w <= lambda |k| < (a + 1) w, each 1/|K|;
+    # counted here pixel by pixel from the frequency definition k_m = m / l (m in FFT order)
+    from oracle.multislice import plain_exit_spectra
+    st = _setup(nx=64, ny=64, lx=12.8, ly=12.8, scan=(8, 8), detectors=((0.0, 0.2),))
+    spec = plain_exit_spectra(st, np.zeros((2, 64, 64), np.float32), [(0, 0)])[(0, 0)]
+    pixels = st.masks.any(axis=0)
+    w, nb = 0.0025, 10
+    got = ph.annulus_values(spec, st.lx, st.ly, st.wavelength, w, nb, pixels)
+    counts = [0] * nb
+    n_ap = 0
+    for my in range(64):
+        for mx in range(64):
+            fx = (mx if mx < 32 else mx - 64) / 12.8
+            fy = (my if my < 32 else my - 64) / 12.8
+            if (st.wavelength ** 2) * (fx * fx + fy * fy) < 0.02 ** 2:
+                n_ap += 1
+                a = math.floor(st.wavelength * math.sqrt(fx * fx + fy * fy) / w)
+                if a < nb:
+                    counts[a] += 1
+    assert np.abs(got - np.array(counts) / n_ap).max() < 1e-14
+    assert abs(got.sum() - 1.0) < 1e-12          # 10 x 2.5 mrad cover the 20 mrad aperture
+
+
+def test_3d_and_4d_outputs_agree_with_the_2d_rings():
+    # a 2-D ring [w, 2w) equals annulus 1 of width w over the same pixels, and the sum of a
+    # ring's 4-D pattern
+    rng = np.random.default_rng(12)
+    st = _setup(detectors=((0.01, 0.02),))
+    spec = np.fft.fft2(rng.standard_normal((32, 32)) + 1j * rng.standard_normal((32, 32)))
+    pixels = st.masks.any(axis=0)
+    ring = ph.detector_values(spec, st.masks)[0]
+    ann = ph.annulus_values(spec, st.lx, st.ly, st.wavelength, 0.01, 4, pixels)
+    assert abs(ann[1] - ring) < 1e-12 * ring and ann[0] == 0 and ann[2] == 0 and ann[3] == 0
+    assert abs(ph.detector_pattern(spec, pixels).sum() - ring) < 1e-12 * ring
+
+
 # ---------------------------------------------------------------------------------------
 # LMA: special cases, error bound, staircase, coefficient reuse
 # ---------------------------------------------------------------------------------------
