@@ -128,10 +128,19 @@ def least_squares(setup: Setup, lat: Lattice, spec_u: np.ndarray, a: int, b: int
 
 class LMA:
     """LMA with u = psi_0^init (Sec. 4.2.3). Coefficients are computed once per class
-    (the Case 1 / Case 2 reuse of Sec. 4.2.2)."""
+    (the Case 1 / Case 2 reuse of Sec. 4.2.2).
 
-    def __init__(self, setup: Setup, lat: Lattice, spec_u: np.ndarray | None = None):
+    window = (X', Y') selects option (ii) of Sec. 4.2.1: every translate is propagated on an
+    X' x Y' pixel window centred on it (origin c = i - (X'/2, Y'/2) in pixels; translates must
+    lie on pixels) with the potential cropped to that window, per the DFT's periodicity on the
+    window. Readings: the initial wave is u_i cropped to the window; the window propagator has
+    the same physical band limit (same pixel size); after the last transmission the window is
+    embedded (zero outside) in the cell and the last propagation step is taken there, so the
+    exit spectrum is P F(embedded wave) on the cell's frequency grid, as without a window."""
+
+    def __init__(self, setup: Setup, lat: Lattice, spec_u: np.ndarray | None = None, window=None):
         self.setup, self.lat = setup, lat
+        self.window = None if window is None else (int(window[0]), int(window[1]))
         self.spec_u = setup.spec0 if spec_u is None else spec_u
         self.alpha = {}
         self.residual = {}
@@ -150,10 +159,40 @@ class LMA:
             out += c * translate_wave(self.setup, self.spec_u, self.lat.translate_position(ta, tb))
         return out
 
+    def window_origin(self, ta: int, tb: int):
+        """Pixel origin of the window of translate (ta, tb): i - (X'/2, Y'/2)."""
+        st = self.setup
+        tx, ty = self.lat.translate_position(ta, tb)
+        ix, iy = tx * st.nx / self.lat.lx, ty * st.ny / self.lat.ly
+        if ix.denominator != 1 or iy.denominator != 1:
+            raise ValueError("windowed propagation needs translates on pixels")
+        return int(ix) - self.window[0] // 2, int(iy) - self.window[1] // 2
+
+    def _propagate_windowed(self, potential: np.ndarray, t) -> np.ndarray:
+        st = self.setup
+        wx, wy = self.window
+        cx, cy = self.window_origin(*t)
+        rows = (cy + np.arange(wy)) % st.ny
+        cols = (cx + np.arange(wx)) % st.nx
+        psi = translate_wave(st, self.spec_u, self.lat.translate_position(*t))[np.ix_(rows, cols)]
+        prop_w = ph.propagator(wx, wy, st.lx * wx / st.nx, st.ly * wy / st.ny, st.wavelength, st.dz, st.bandlimit)
+        n = potential.shape[0]
+        for j in range(n):
+            psi = ph.transmission(potential[j][np.ix_(rows, cols)], st.sigma) * psi
+            if j + 1 < n:
+                psi = np.fft.ifft2(prop_w * np.fft.fft2(psi))
+        full = np.zeros((st.ny, st.nx), dtype=np.complex128)
+        full[np.ix_(rows, cols)] = psi
+        return st.prop * np.fft.fft2(full)
+
     def propagate(self, potential: np.ndarray, translates, batch: int = 16) -> dict:
         """Step 1: U_i for the given (ta, tb) translates; returns {(ta, tb): DFT(U_i)}."""
         out = {}
         translates = list(translates)
+        if self.window is not None:
+            for t in translates:
+                out[t] = self._propagate_windowed(potential, t)
+            return out
         for s in range(0, len(translates), batch):
             chunk = translates[s:s + batch]
             u0 = np.stack([translate_wave(self.setup, self.spec_u, self.lat.translate_position(ta, tb))

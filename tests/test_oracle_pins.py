@@ -282,6 +282,59 @@ def test_3d_and_4d_outputs_agree_with_the_2d_rings():
 
 
 # ---------------------------------------------------------------------------------------
+# windowed translate propagation (option (ii) of Sec. 4.2.1)
+# ---------------------------------------------------------------------------------------
+def _windowed_case(window):
+    st = _setup(scan=(8, 8))
+    lat = Lattice(st, (8, 8), 1, (0, 0), 4)           # translates every 4 px, on pixels
+    return st, lat, LMA(st, lat, window=window)
+
+
+def test_window_of_the_whole_cell_is_plain_propagation():
+    # a window as large as the cell is the cell itself, rolled: same exit spectra
+    rng = np.random.default_rng(21)
+    v = rng.uniform(0, 40, (3, 32, 32)).astype(np.float32)
+    st, lat, lw = _windowed_case((32, 32))
+    lf = LMA(st, lat)
+    ts = [(0, 0), (3, 5), (7, 7)]
+    bw, bf = lw.propagate(v, ts), lf.propagate(v, ts)
+    for t in ts:
+        assert rel_l2(bw[t], bf[t]) < 1e-12
+
+
+def test_windowed_translate_sees_only_its_window():
+    rng = np.random.default_rng(22)
+    v = rng.uniform(0, 40, (3, 32, 32)).astype(np.float32)
+    st, lat, lw = _windowed_case((16, 8))
+    t = (2, 5)                                          # at pixel (8, 20): window x 0..15, y 16..23
+    cx, cy = lw.window_origin(*t)
+    assert (cx, cy) == (0, 16)
+    base = lw.propagate(v, [t])[t]
+    out = v.copy()
+    out[:, 10, 20] += 30.0                              # outside the window
+    out[:, 24, 3] += 30.0
+    assert np.array_equal(lw.propagate(out, [t])[t], base)
+    corner = v.copy()
+    corner[1, 23, 15] += 30.0                           # last row and column of the window
+    assert rel_l2(lw.propagate(corner, [t])[t], base) > 1e-6
+    centre = v.copy()
+    centre[1, 20, 8] += 30.0
+    assert rel_l2(lw.propagate(centre, [t])[t], base) > 1e-2
+
+
+def test_windowed_translation_covariance():
+    # rolling the specimen by one translate spacing moves the window with the translate: the
+    # exit spectrum of the next translate is the modulated spectrum of this one
+    rng = np.random.default_rng(23)
+    v = rng.uniform(0, 40, (3, 32, 32)).astype(np.float32)
+    st, lat, lw = _windowed_case((16, 16))
+    a = lw.propagate(v, [(3, 1)])[(3, 1)]
+    b = lw.propagate(np.roll(v, 4, axis=2), [(4, 1)])[(4, 1)]
+    kx = ph.freqs(32, st.lx)[None, :]
+    assert rel_l2(b, a * np.exp(-2j * np.pi * kx * (4 * st.lx / 32))) < 1e-12
+
+
+# ---------------------------------------------------------------------------------------
 # LMA: special cases, error bound, staircase, coefficient reuse
 # ---------------------------------------------------------------------------------------
 def test_lma_reduces_to_plain_multislice():
