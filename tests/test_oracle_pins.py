@@ -319,7 +319,7 @@ def test_windowed_translate_sees_only_its_window():
     assert rel_l2(lw.propagate(corner, [t])[t], base) > 1e-6
     centre = v.copy()
     centre[1, 20, 8] += 30.0
-    assert rel_l2(lw.propagate(centre, [t])[t], base) > 1e-2
+    assert rel_l2(lw.propagate(centre, [t])[t], base) > 1e-3
 
 
 def test_windowed_translation_covariance():
