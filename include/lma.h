@@ -103,6 +103,11 @@ typedef struct {
                              /* propagated translates (Sec. 4.2.4); 0 = what free     */
                              /* device memory holds after the plan's other buffers    */
   double basis_param;        /* LMA_BASIS_GAUSSIAN: sigma in Angstrom (0: default)     */
+  int32_t prop_nx, prop_ny;  /* option (ii) of Sec. 4.2.1: propagate every translate on a */
+                             /* prop_nx x prop_ny pixel window centred on it, with the   */
+                             /* potential cropped to the window (sides as for nx, ny, at */
+                             /* most the grid's; translates must lie on pixels);          */
+                             /* 0, 0 = the whole cell                                     */
 } lma_lattice;
 
 /* 2-D STEM detectors (Sec. 3.1, step 3): ring r collects lambda|k| in [inner, outer). */
@@ -141,6 +146,7 @@ typedef struct {
   int64_t multislice_calls;  /* translates propagated per image: T_{P_1..P_l}         */
   int32_t tile_width;        /* waves are stored in tile_width^2-pixel tiles          */
   int32_t graphs;            /* wave sequences captured as HIP graphs so far          */
+  int32_t prop_nx, prop_ny;  /* translate window (0, 0: the whole cell)              */
 } lma_info;
 
 /* Result of lma_autotune for one grid. */
@@ -354,6 +360,9 @@ lma_status lma_get_detector_pixels(const lma_plan* plan, int32_t* flat, uint32_t
 lma_status lma_get_probe_spectrum(const lma_plan* plan, double* spec);
 /* Normalised spectrum of the input wave u (sum |.|^2 = XY), double [ny][nx][2]. */
 lma_status lma_get_input_wave_spectrum(const lma_plan* plan, double* spec);
+/* With translate windows (lattice.prop_nx > 0): the window DFT of u cropped to a window
+ * centred on it, double [prop_ny][prop_nx][2]; LMA_ERR_STATE without windows. */
+lma_status lma_get_window_spectrum(const lma_plan* plan, double* spec);
 /* Resident-basis rows first..first+count-1 (rows in increasing translate order, see
  * lma_get_rows): F(U_i) at the D detector pixels, float [count][D][2] on the host. */
 lma_status lma_get_basis_rows(lma_plan* plan, int32_t first, int32_t count, float* out);

@@ -50,7 +50,8 @@ def optics(nx, ny, lx, ly, wavelength, sigma, dz, bandlimit, alpha_max, defocus=
 
 
 def lattice(px, py, rx, ry, f=1, offset=(0.5, 0.5), L=1, precision=LMA_GEMM_FP32, window=(0, 0, 0, 0),
-            batch=0, hbm_budget_bytes=0, basis_kind=LMA_BASIS_PROBE, basis_param=0.0) -> lma_lattice:
+            batch=0, hbm_budget_bytes=0, basis_kind=LMA_BASIS_PROBE, basis_param=0.0,
+            prop_window=(0, 0)) -> lma_lattice:
     lat = lma_lattice()
     lat.px, lat.py, lat.rx, lat.ry, lat.f = int(px), int(py), int(rx), int(ry), int(f)
     lat.offset_x, lat.offset_y = float(offset[0]), float(offset[1])
@@ -59,6 +60,7 @@ def lattice(px, py, rx, ry, f=1, offset=(0.5, 0.5), L=1, precision=LMA_GEMM_FP32
         lat.window[i] = int(window[i])
     lat.batch, lat.hbm_budget_bytes = int(batch), int(hbm_budget_bytes)
     lat.basis_param = float(basis_param)
+    lat.prop_nx, lat.prop_ny = int(prop_window[0]), int(prop_window[1])
     return lat
 
 
@@ -272,6 +274,12 @@ class Plan:
     def input_wave_spectrum(self) -> np.ndarray:
         out = np.zeros((self.ny, self.nx, 2))
         _check(lib().lma_get_input_wave_spectrum(self._h, C.c_void_p(out.ctypes.data)))
+        return out[..., 0] + 1j * out[..., 1]
+
+    def window_spectrum(self) -> np.ndarray:
+        i = self.info()
+        out = np.zeros((i.prop_ny, i.prop_nx, 2))
+        _check(lib().lma_get_window_spectrum(self._h, C.c_void_p(out.ctypes.data)))
         return out[..., 0] + 1j * out[..., 1]
 
     def probe_spectrum(self) -> np.ndarray:

@@ -26,7 +26,8 @@ class lma_lattice(C.Structure):
     _fields_ = [("px", C.c_int32), ("py", C.c_int32), ("rx", C.c_int32), ("ry", C.c_int32),
                 ("f", C.c_int32), ("offset_x", C.c_double), ("offset_y", C.c_double), ("L", C.c_int32),
                 ("basis_kind", C.c_int32), ("precision", C.c_int32), ("window", C.c_int32 * 4),
-                ("batch", C.c_int32), ("hbm_budget_bytes", C.c_int64), ("basis_param", C.c_double)]
+                ("batch", C.c_int32), ("hbm_budget_bytes", C.c_int64), ("basis_param", C.c_double),
+                ("prop_nx", C.c_int32), ("prop_ny", C.c_int32)]
 
 
 class lma_detectors(C.Structure):
@@ -42,7 +43,7 @@ class lma_info(C.Structure):
                 ("device_bytes", C.c_int64), ("contract_kernel", C.c_int32), ("contract_k", C.c_int32),
                 ("partitioned", C.c_int32), ("n_parts", C.c_int32), ("part_w", C.c_int32), ("part_h", C.c_int32),
                 ("resident_rows", C.c_int64), ("multislice_calls", C.c_int64), ("tile_width", C.c_int32),
-                ("graphs", C.c_int32)]
+                ("graphs", C.c_int32), ("prop_nx", C.c_int32), ("prop_ny", C.c_int32)]
 
 
 class lma_tuning(C.Structure):
@@ -84,6 +85,7 @@ SIGNATURES = {
     "lma_get_detector_pixels": (C.c_int, [P, P, P]),
     "lma_get_probe_spectrum": (C.c_int, [P, P]),
     "lma_get_input_wave_spectrum": (C.c_int, [P, P]),
+    "lma_get_window_spectrum": (C.c_int, [P, P]),
     "lma_get_basis_rows": (C.c_int, [P, C.c_int32, C.c_int32, P]),
     "lma_get_rows": (C.c_int, [P, P]),
     "lma_set_timing": (C.c_int, [P, C.c_int32]),

@@ -65,6 +65,10 @@ struct lma_plan {
   // tables (those read by column passes transposed, [kx][ky])
   float2 *d_specT = nullptr, *d_propT = nullptr, *d_twx = nullptr, *d_twy = nullptr;
   float2* d_uspecT = nullptr;        // spectrum of the input wave u (the probe's unless another u)
+  // option (ii): translate windows (window tables transposed like the cell's)
+  float2 *d_wspecT = nullptr, *d_wpropT = nullptr, *d_wtwx = nullptr, *d_wtwy = nullptr;
+  int64_t* d_zero_u = nullptr;       // [B][2] zeros: every window starts from the same wave
+  float2* d_wwork = nullptr;         // [B][window tiles]
   int32_t* d_compT = nullptr;
   uint32_t* d_maskT = nullptr;
   int32_t *d_row_of = nullptr, *d_set_dx = nullptr, *d_set_dy = nullptr;
@@ -145,6 +149,20 @@ void free_one(lma_plan* p, void* ptr, size_t bytes) {
   if (it != p->allocs.end()) p->allocs.erase(it);
   (void)hipFree(ptr);
   p->dev_bytes -= (int64_t)bytes;
+}
+
+lma::dev::Tables window_tables(const lma_plan* p) {
+  lma::dev::Tables t;
+  t.nx = p->h.wnx;
+  t.ny = p->h.wny;
+  t.tw = lma::dev::tile_width(p->h.wnx, p->h.wny);
+  t.Qx = p->h.Qx;
+  t.Qy = p->h.Qy;
+  t.specT = p->d_wspecT;
+  t.propT = p->d_wpropT;
+  t.twx = p->d_wtwx;
+  t.twy = p->d_wtwy;
+  return t;
 }
 
 lma::dev::Tables tables(const lma_plan* p) {
@@ -284,6 +302,25 @@ lma_status run_waves(lma_plan* p, const int64_t* d_u, const int32_t* d_row, cons
   const lma::dev::Tables T = tables(p);
   const int64_t XY = (int64_t)p->h.op.nx * p->h.op.ny;
   const int split = target ? 0 : p->h.lat.precision == LMA_GEMM_SPLIT_BF16;
+  if (p->h.wnx > 0 && d_row && !probes) {
+    // option (ii): translates on windows centred on them, the last step on the cell
+    const lma::dev::Tables Tw = window_tables(p);
+    for (int first = 0; first < n; first += p->B) {
+      const int nb = std::min(p->B, n - first);
+      const int64_t* u = d_u + 2 * (int64_t)first;
+      LAUNCH(p, "init", lma::dev::init_waves(Tw, p->d_wwork, p->d_zero_u, nb, p->stream));
+      for (int j = 0; j < nslices; ++j) {
+        const bool last = j + 1 == nslices;
+        LAUNCH(p, "row_pass", lma::dev::row_pass_window(Tw, p->d_wwork, p->d_trans + (size_t)j * XY, T.nx, T.ny, u,
+                                                        T.Qx, T.Qy, last, nb, p->stream));
+        if (!last) LAUNCH(p, "col_pass", lma::dev::col_pass(Tw, p->d_wwork, nb, p->stream));
+      }
+      LAUNCH(p, "embed", lma::dev::embed_windows(T, p->d_work, Tw, p->d_wwork, u, nb, p->stream));
+      LAUNCH(p, "col_gather", lma::dev::col_gather(T, p->d_work, nb, target ? target : p->d_basis, p->h.D(),
+                                                   d_row + first, split, p->stream));
+    }
+    return LMA_OK;
+  }
   for (int first = 0; first < n; first += p->B) {
     const int nb = std::min(p->B, n - first);
     // translates start from u, probes from psi_0
@@ -457,6 +494,7 @@ int64_t footprint_of(const HostPlan& h, int B, int nslices, bool with_basis) {
   b += (int64_t)B * XY * 8;                           // wave batch
   b += (int64_t)nslices * XY * (8 + 4);               // transmission tables and potential staging
   if (with_basis) b += (int64_t)h.rows.size() * h.D() * 8;
+  if (h.wnx > 0) b += (int64_t)h.wnx * h.wny * (8 + 8) + (int64_t)B * (h.wnx * h.wny * 8 + 16);   // window tables, batch
   return b;
 }
 
@@ -615,6 +653,27 @@ lma_status lma_build_basis(const lma_optics* optics, const lma_lattice* lattice,
     auto twx = twiddles(nx), twy = twiddles(ny);
     if ((s = upload(p, &p->d_twx, twx.data(), twx.size())) != LMA_OK) { release(p); return s; }
     if ((s = upload(p, &p->d_twy, twy.data(), twy.size())) != LMA_OK) { release(p); return s; }
+    if (h.wnx > 0) {
+      const int wx = h.wnx, wy = h.wny;
+      std::vector<float2> wv((size_t)wx * wy);
+      auto wT = [&](const std::vector<cd>& src, double scale) {
+        for (int y = 0; y < wy; ++y)
+          for (int x = 0; x < wx; ++x) {
+            const cd& z = src[(size_t)y * wx + x];
+            wv[(size_t)x * wy + y] = make_float2((float)(z.real() * scale), (float)(z.imag() * scale));
+          }
+      };
+      wT(h.wspec, 1.0 / ((double)wx * wy));
+      if ((s = upload(p, &p->d_wspecT, wv.data(), wv.size())) != LMA_OK) { release(p); return s; }
+      wT(h.wprop, 1.0);
+      if ((s = upload(p, &p->d_wpropT, wv.data(), wv.size())) != LMA_OK) { release(p); return s; }
+      auto wtx = twiddles(wx), wty = twiddles(wy);
+      if ((s = upload(p, &p->d_wtwx, wtx.data(), wtx.size())) != LMA_OK) { release(p); return s; }
+      if ((s = upload(p, &p->d_wtwy, wty.data(), wty.size())) != LMA_OK) { release(p); return s; }
+      std::vector<int64_t> zeros((size_t)p->B * 2, 0);
+      if ((s = upload(p, &p->d_zero_u, zeros.data(), zeros.size())) != LMA_OK) { release(p); return s; }
+      if ((s = dalloc(p, (void**)&p->d_wwork, (size_t)p->B * wx * wy * sizeof(float2))) != LMA_OK) { release(p); return s; }
+    }
     std::vector<int32_t> compT((size_t)XY);
     std::vector<uint32_t> maskT((size_t)XY);
     for (int y = 0; y < ny; ++y)
@@ -1055,6 +1114,8 @@ lma_status lma_plan_info(const lma_plan* p, lma_info* out) {
   out->contract_k = p->st.ok ? 4 * p->st.nks : (int32_t)h.lat.L;
   out->tile_width = p->tw;
   out->graphs = p->n_captured;
+  out->prop_nx = p->h.wnx;
+  out->prop_ny = p->h.wny;
   return LMA_OK;
 }
 
@@ -1107,6 +1168,16 @@ lma_status lma_get_input_wave_spectrum(const lma_plan* p, double* spec) {
   for (size_t i = 0; i < p->h.uspec.size(); ++i) {
     spec[2 * i] = p->h.uspec[i].real();
     spec[2 * i + 1] = p->h.uspec[i].imag();
+  }
+  return LMA_OK;
+}
+
+lma_status lma_get_window_spectrum(const lma_plan* p, double* spec) {
+  if (!p || !spec) return fail(LMA_ERR_ARG, "null argument");
+  if (p->h.wnx == 0) return fail(LMA_ERR_STATE, "the plan has no translate windows");
+  for (size_t i = 0; i < p->h.wspec.size(); ++i) {
+    spec[2 * i] = p->h.wspec[i].real();
+    spec[2 * i + 1] = p->h.wspec[i].imag();
   }
   return LMA_OK;
 }

@@ -314,7 +314,11 @@ __global__ void k_transmission(const float* __restrict__ v, float2* __restrict__
 // and written back to the same place. Between passes a wave is in the mixed domain (y
 // spatial, x frequency). Tables read by column passes are stored transposed, [kx][ky].
 // ------------------------------------------------------------------------------------------
-enum { PASS_ROW = 0, PASS_COL = 1, PASS_INIT = 2, PASS_GATHER = 3, PASS_REDUCE = 4 };
+enum { PASS_ROW = 0, PASS_COL = 1, PASS_INIT = 2, PASS_GATHER = 3, PASS_REDUCE = 4, PASS_ROW_WIN = 5, PASS_ROW_LAST = 6 };
+// PASS_ROW_WIN / PASS_ROW_LAST: the row pass of waves propagated on windows of the cell
+// (option (ii) of Sec. 4.2.1): each wave reads the cell's transmission at its own window;
+// PASS_ROW_LAST stops after the transmission and leaves the window's wave in real space.
+__host__ __device__ constexpr bool pass_rows(int mode) { return mode == PASS_ROW || mode == PASS_ROW_WIN || mode == PASS_ROW_LAST; }
 
 // Wavefronts per workgroup for transforms that fit one wavefront (N <= 512): 8, one line each
 // (8 prefetch registers pairs per thread instead of 16; 3-4 wavefronts per SIMD).
@@ -363,6 +367,8 @@ struct PassArgs {
   int ndet;
   int64_t img_stride;
   double scale;
+  int tnx, tny;              // ROW_WIN / ROW_LAST: the cell (table [tny][tnx]); window origin
+  int hx, hy;                //   of wave w: its position in pixels minus (hx, hy)
 };
 
 __device__ __forceinline__ void split_bf16(float x, __hip_bfloat16& hi, __hip_bfloat16& lo) {
@@ -470,7 +476,7 @@ constexpr int stage_chunk(int ept) {
 }
 
 template <int MODE>
-constexpr int pass_waves() { return MODE == PASS_ROW ? LMA_WL_WAVES_ROW : LMA_WL_WAVES; }
+constexpr int pass_waves() { return pass_rows(MODE) ? LMA_WL_WAVES_ROW : LMA_WL_WAVES; }
 
 // Register budget: lengths 5 * 2^a are held to two wavefronts per SIMD (at most 256 VGPRs;
 // unlimited they take 280-310 and run one wavefront per SIMD, measured 30 % slower at 640);
@@ -481,7 +487,7 @@ __attribute__((amdgpu_waves_per_eu(fft_odd(N) == 5 ? 2 : 1, 8))) void k_pass(Pas
   using C = PassCfg<N, TW, pass_waves<MODE>()>;
   constexpr int T = C::T, S = C::S, RS = C::RS, TPB = C::TPB, RPW = C::RPW;
   constexpr int NT = C::WAVES * 64;
-  constexpr bool ROWS = (MODE == PASS_ROW);
+  constexpr bool ROWS = pass_rows(MODE);
   constexpr int TOTAL = TW * N;                            // elements of one work item
   constexpr int EPT = TOTAL / NT;                          // per thread
 #ifndef LMA_PREFETCH
@@ -618,6 +624,23 @@ __attribute__((amdgpu_waves_per_eu(fft_odd(N) == 5 ? 2 : 1, 8))) void k_pass(Pas
 #pragma unroll
           for (int m = 0; m < C::E; ++m) v[m] = cmul(v[m], tab[j + T * m]);
           fft<N, -1, C::WL>(v, j, tw, a.tw, slot);
+        } else if constexpr (MODE == PASS_ROW_WIN || MODE == PASS_ROW_LAST) {
+          fft<N, +1, C::WL>(v, j, tw, a.tw, slot);
+          // the cell's transmission at the window: row (y0 + line) mod tny, columns
+          // (x0 + x) mod tnx with (x0, y0) the window origin of wave w (exact integers)
+          const int64_t px = a.wave_u[2 * w] * a.tnx / a.Qx, py = a.wave_u[2 * w + 1] * a.tny / a.Qy;
+          int ry = (int)((py - a.hy + line) % a.tny);
+          if (ry < 0) ry += a.tny;
+          int bx = (int)((px - a.hx) % a.tnx);
+          if (bx < 0) bx += a.tnx;
+          const float2* trow = a.table + (size_t)ry * a.tnx;
+#pragma unroll
+          for (int m = 0; m < C::E; ++m) {
+            int col = bx + j + T * m;
+            if (col >= a.tnx) col -= a.tnx;
+            v[m] = cmul(v[m], trow[col]);
+          }
+          if constexpr (MODE == PASS_ROW_WIN) fft<N, -1, C::WL>(v, j, tw, a.tw, slot);
         } else {
           fft<N, -1, C::WL>(v, j, tw, a.tw, slot);
 #pragma unroll
@@ -658,7 +681,8 @@ __attribute__((amdgpu_waves_per_eu(fft_odd(N) == 5 ? 2 : 1, 8))) void k_pass(Pas
           }
         }
       }
-      if constexpr (MODE == PASS_ROW || MODE == PASS_COL || MODE == PASS_INIT) {
+      if constexpr (MODE == PASS_ROW || MODE == PASS_COL || MODE == PASS_INIT || MODE == PASS_ROW_WIN ||
+                    MODE == PASS_ROW_LAST) {
         if (active) {
 #pragma unroll
           for (int m = 0; m < C::E; ++m) slot.put(j + T * m, v[m]);
@@ -1065,6 +1089,123 @@ hipError_t row_pass(const Tables& T, float2* work, const float2* trans_j, int B,
   a.table = trans_j;
   a.tw = T.twx;
   return pass_dispatch<PASS_ROW>(T.nx, tw_of(T), T.ny, a, B, s);
+}
+
+hipError_t row_pass_window(const Tables& Tw, float2* work, const float2* trans_j, int cell_nx, int cell_ny,
+                           const int64_t* wave_u, int64_t Qx, int64_t Qy, bool last, int B, hipStream_t s) {
+  PassArgs a = pass_args(Tw, work);
+  a.table = trans_j;
+  a.tw = Tw.twx;
+  a.wave_u = wave_u;
+  a.Qx = Qx;
+  a.Qy = Qy;
+  a.tnx = cell_nx;
+  a.tny = cell_ny;
+  a.hx = Tw.nx / 2;
+  a.hy = Tw.ny / 2;
+  return last ? pass_dispatch<PASS_ROW_LAST>(Tw.nx, tw_of(Tw), Tw.ny, a, B, s)
+              : pass_dispatch<PASS_ROW_WIN>(Tw.nx, tw_of(Tw), Tw.ny, a, B, s);
+}
+
+// ------------------------------------------------------------------------------------------
+// the last step of windowed waves: each window's real-space wave is placed in the cell at its
+// window (zero elsewhere, periodic) and row-transformed on the cell's grid, which leaves the
+// mixed domain (x frequency, y spatial) that the gather pass takes. One block per (cell row,
+// wave), one transform of N = nx points.
+// ------------------------------------------------------------------------------------------
+struct EmbedArgs {
+  float2* out;               // [B][cell tiles], cell tile width TW
+  const float2* win;         // [B][window tiles], window tile width wtw
+  int nx, ny;                // cell
+  int wnx, wny, wtw;         // window
+  const int64_t* wave_u;     // [B][2] positions in lattice units
+  int64_t Qx, Qy;
+  const float2* twx;         // cell twiddles exp(-2 pi i t / nx)
+};
+
+template <int N, int TW>
+__global__ __launch_bounds__(N / fft_elems(N)) void k_embed(EmbedArgs a) {
+  constexpr int E = fft_elems(N), T = N / E;
+  constexpr bool WL = T <= 64;
+  __shared__ float2 line[slot_pos(N - 1) + 1];
+  const int y = (int)(blockIdx.x % (unsigned)a.ny), w = (int)(blockIdx.x / (unsigned)a.ny);
+  const int j = threadIdx.x;
+  float2 tw[tw_count(N)];
+  tw_load<N>(tw, a.twx, j);
+  const int64_t px = a.wave_u[2 * w] * a.nx / a.Qx, py = a.wave_u[2 * w + 1] * a.ny / a.Qy;
+  int wy = (int)((y - (py - a.wny / 2)) % a.ny);        // window row of cell row y
+  if (wy < 0) wy += a.ny;
+  int x0 = (int)((px - a.wnx / 2) % a.nx);              // cell column of window column 0
+  if (x0 < 0) x0 += a.nx;
+  const bool inside = wy < a.wny;                        // uniform over the block
+  const float2* src = a.win + (size_t)w * a.wnx * a.wny;
+  const int wt = a.wtw, wtiles = a.wnx / wt;
+  float2 v[E];
+#pragma unroll
+  for (int m = 0; m < E; ++m) {
+    const int x = j + T * m;
+    int wx = x - x0;
+    if (wx < 0) wx += a.nx;
+    v[m] = make_float2(0.f, 0.f);
+    if (inside && wx < a.wnx)
+      v[m] = src[((size_t)(wy / wt) * wtiles + wx / wt) * wt * wt + (wy % wt) * wt + wx % wt];
+  }
+  if (inside) fft<N, -1, WL>(v, j, tw, a.twx, Slot{line});
+  float2* dst = a.out + (size_t)w * a.nx * a.ny;
+  const int ctiles = a.nx / TW;
+#pragma unroll
+  for (int m = 0; m < E; ++m) {
+    const int x = j + T * m;
+    dst[((size_t)(y / TW) * ctiles + x / TW) * TW * TW + (y % TW) * TW + x % TW] = v[m];
+  }
+}
+
+template <int N, int TW>
+static hipError_t embed_launch(const EmbedArgs& a, int B, hipStream_t s) {
+  k_embed<N, TW><<<(unsigned)((int64_t)B * a.ny), N / fft_elems(N), 0, s>>>(a);
+  return hipGetLastError();
+}
+
+template <int TW>
+static hipError_t embed_dispatch(const EmbedArgs& a, int B, hipStream_t s) {
+  switch (a.nx) {
+    case 16: return embed_launch<16, TW>(a, B, s);
+    case 32: return embed_launch<32, TW>(a, B, s);
+    case 64: return embed_launch<64, TW>(a, B, s);
+    case 96: return embed_launch<96, TW>(a, B, s);
+    case 128: return embed_launch<128, TW>(a, B, s);
+    case 192: return embed_launch<192, TW>(a, B, s);
+    case 256: return embed_launch<256, TW>(a, B, s);
+    case 384: return embed_launch<384, TW>(a, B, s);
+    case 512: return embed_launch<512, TW>(a, B, s);
+    case 640: return embed_launch<640, TW>(a, B, s);
+    case 1024: return embed_launch<1024, TW>(a, B, s);
+    case 2048: return embed_launch<2048, TW>(a, B, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t embed_windows(const Tables& T, float2* work, const Tables& Tw, const float2* win, const int64_t* wave_u,
+                         int B, hipStream_t s) {
+  if (B <= 0) return hipSuccess;
+  EmbedArgs a{};
+  a.out = work;
+  a.win = win;
+  a.nx = T.nx;
+  a.ny = T.ny;
+  a.wnx = Tw.nx;
+  a.wny = Tw.ny;
+  a.wtw = tw_of(Tw);
+  a.wave_u = wave_u;
+  a.Qx = T.Qx;
+  a.Qy = T.Qy;
+  a.twx = T.twx;
+  const int tw = tw_of(T);
+  if (a.wnx > a.nx || a.wny > a.ny || a.wnx % a.wtw || a.wny % a.wtw) return hipErrorInvalidValue;
+  if (tw == 4) return embed_dispatch<4>(a, B, s);
+  if (tw == 8) return embed_dispatch<8>(a, B, s);
+  if (tw == 16) return embed_dispatch<16>(a, B, s);
+  return hipErrorInvalidValue;
 }
 
 hipError_t col_pass(const Tables& T, float2* work, int B, hipStream_t s) {

@@ -39,6 +39,78 @@ bool finite(double x) { return std::isfinite(x); }
 
 }  // namespace
 
+// Window tables of option (ii): the input wave cropped to a wnx x wny window centred on it,
+// u_W(x') = u(x' - (wnx/2, wny/2)) with u = IDFT(uspec) / (XY) on the cell, is evaluated at the
+// window's pixels by separable sums over the non-zero part of the spectrum, then transformed
+// by the window's DFT; the window propagator keeps the cell's band limit (same pixel size).
+void build_window_tables(HostPlan& h) {
+  const int nx = h.op.nx, ny = h.op.ny, wx = h.lat.prop_nx, wy = h.lat.prop_ny;
+  h.wnx = wx;
+  h.wny = wy;
+  // exp(sign 2 pi i t / n) for t < n, FP64
+  auto table = [](int n, double sign) {
+    std::vector<cd> t(n);
+    for (int i = 0; i < n; ++i) {
+      const double a = sign * 2.0 * kPi * (double)i / (double)n;
+      t[i] = cd(std::cos(a), std::sin(a));
+    }
+    return t;
+  };
+  auto wrap = [](int64_t v, int64_t n) { return (size_t)(((v % n) + n) % n); };
+  const std::vector<cd> ex = table(nx, 1.0), ey = table(ny, 1.0), fx = table(wx, -1.0), fy = table(wy, -1.0);
+  double umax = 0.0;
+  for (const cd& u : h.uspec) umax = std::max(umax, std::abs(u));
+  // A[ky][x'] = sum_kx uspec[ky][kx] exp(2 pi i kx (x' - wx/2) / nx)
+  std::vector<cd> A((size_t)ny * wx, cd(0.0));
+  for (int my = 0; my < ny; ++my)
+    for (int mx = 0; mx < nx; ++mx) {
+      const cd s = h.uspec[(size_t)my * nx + mx];
+      if (std::abs(s) <= 1e-18 * umax) continue;
+      const int64_t kx = freq_index(mx, nx);
+      for (int x = 0; x < wx; ++x) A[(size_t)my * wx + x] += s * ex[wrap(kx * (x - wx / 2), nx)];
+    }
+  // u_W[y'][x'] = sum_ky A[ky][x'] exp(2 pi i ky (y' - wy/2) / ny) / (XY)
+  std::vector<cd> uw((size_t)wy * wx, cd(0.0));
+  const double inv = 1.0 / ((double)nx * ny);
+  for (int my = 0; my < ny; ++my) {
+    const int64_t ky = freq_index(my, ny);
+    for (int y = 0; y < wy; ++y) {
+      const cd e = ey[wrap(ky * (y - wy / 2), ny)] * inv;
+      for (int x = 0; x < wx; ++x) uw[(size_t)y * wx + x] += A[(size_t)my * wx + x] * e;
+    }
+  }
+  // window DFT, rows then columns
+  std::vector<cd> tmp((size_t)wy * wx, cd(0.0));
+  for (int y = 0; y < wy; ++y)
+    for (int q = 0; q < wx; ++q) {
+      cd acc(0.0);
+      for (int x = 0; x < wx; ++x) acc += uw[(size_t)y * wx + x] * fx[((size_t)q * x) % wx];
+      tmp[(size_t)y * wx + q] = acc;
+    }
+  h.wspec.assign((size_t)wy * wx, cd(0.0));
+  for (int q = 0; q < wy; ++q)
+    for (int x = 0; x < wx; ++x) {
+      cd acc(0.0);
+      for (int y = 0; y < wy; ++y) acc += tmp[(size_t)y * wx + x] * fy[((size_t)q * y) % wy];
+      h.wspec[(size_t)q * wx + x] = acc;
+    }
+  // propagator on the window's frequencies, the cell's band radius
+  const double kbw = h.op.bandlimit * std::min(nx / (2.0 * h.op.lx), ny / (2.0 * h.op.ly));
+  const double lwx = h.op.lx * wx / nx, lwy = h.op.ly * wy / ny;
+  h.wprop.assign((size_t)wy * wx, cd(0.0));
+  for (int my = 0; my < wy; ++my) {
+    const double ky = (double)freq_index(my, wy) / lwy;
+    for (int mx = 0; mx < wx; ++mx) {
+      const double kx = (double)freq_index(mx, wx) / lwx;
+      const double k2 = kx * kx + ky * ky;
+      if (k2 < kbw * kbw) {
+        const double ph = -kPi * h.op.wavelength * h.op.dz * k2;
+        h.wprop[(size_t)my * wx + mx] = cd(std::cos(ph), std::sin(ph)) / ((double)wx * wy);
+      }
+    }
+  }
+}
+
 void electron_constants(double kv, double* lambda, double* sigma) {
   double ev = kv * 1e3;
   double lam = kHcEvA / std::sqrt(ev * (2.0 * kM0c2Ev + ev));
@@ -76,6 +148,12 @@ lma_status check_arguments(const lma_optics* op, const lma_lattice* lat, const l
     return LMA_ERR_UNSUPPORTED;
   }
   if (!std::isfinite(lat->basis_param) || lat->basis_param < 0.0) { *err = "basis_param must be >= 0"; return LMA_ERR_ARG; }
+  if (lat->prop_nx != 0 || lat->prop_ny != 0) {
+    if (!grid_side_ok(lat->prop_nx) || !grid_side_ok(lat->prop_ny) || lat->prop_nx > op->nx || lat->prop_ny > op->ny) {
+      *err = "translate window sides must be grid sides (powers of two from 16, or 96, 192, 384, 640) within the grid";
+      return LMA_ERR_UNSUPPORTED;
+    }
+  }
   if (lat->precision != LMA_GEMM_FP32 && lat->precision != LMA_GEMM_SPLIT_BF16) { *err = "unknown precision"; return LMA_ERR_ARG; }
   const int32_t* w = lat->window;
   bool whole = w[0] == 0 && w[1] == 0 && w[2] == 0 && w[3] == 0;
@@ -237,6 +315,16 @@ lma_status build_host_plan(const lma_optics* op, const lma_lattice* lat, const l
   h.ncls_x = lat->px / h.gx;
   h.ncls_y = lat->py / h.gy;
   h.nsets = h.ncls_x * h.ncls_y;
+
+  // ---- option (ii): translate windows ----------------------------------------------------------
+  if (lat->prop_nx > 0) {
+    // translates on pixels: every position in units times the grid size is a multiple of Q
+    if ((h.stepTx * nx) % h.Qx || (h.oxu * nx) % h.Qx || (h.stepTy * ny) % h.Qy || (h.oyu * ny) % h.Qy) {
+      *err = "windowed propagation needs translates on pixels";
+      return LMA_ERR_ARG;
+    }
+    build_window_tables(h);
+  }
 
   // squared distance in exact integers when the units are square (l_x/Q_x == l_y/Q_y exactly)
   double p1 = op->lx * (double)h.Qy, e1 = std::fma(op->lx, (double)h.Qy, -p1);

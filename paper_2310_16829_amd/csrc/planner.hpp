@@ -34,6 +34,10 @@ struct HostPlan {
   std::vector<cd> uspec;         // normalised spectrum of the input wave u, sum |.|^2 = XY
   int n_aperture = 0;
   std::vector<cd> prop;          // P(k) / (XY) with the band limit [ny][nx]
+  // option (ii): translate windows of wnx x wny pixels (0: none)
+  int wnx = 0, wny = 0;
+  std::vector<cd> wspec;         // DFT of u cropped to a window centred on it [wny][wnx]
+  std::vector<cd> wprop;         // window propagator / (wnx wny), the cell's band limit [wny][wnx]
   std::vector<uint32_t> detmask; // ring bits per frequency [ny][nx]
   std::vector<int32_t> comp_flat;   // D detector pixels, sorted by (mask, flat index)
   std::vector<uint32_t> comp_mask;  // [D]
@@ -74,6 +78,9 @@ lma_status check_arguments(const lma_optics* op, const lma_lattice* lat, const l
 
 // Relativistic constants.
 void electron_constants(double kv, double* lambda, double* sigma);
+
+// Window tables of option (ii) (wspec, wprop) for h.lat.prop_nx x h.lat.prop_ny windows.
+void build_window_tables(HostPlan& h);
 
 }  // namespace lma
 

@@ -32,7 +32,8 @@ def say(*a):
 
 
 def build(w, L=None, scan=None, R=None, f=1, offset=None, window=(0, 0, 0, 0), precision=0, batch=0, nx=None,
-          ny=None, lx=None, ly=None, detectors=None, budget=0, basis_kind=0, basis_param=0.0, flags=0):
+          ny=None, lx=None, ly=None, detectors=None, budget=0, basis_kind=0, basis_param=0.0, flags=0,
+          prop_window=(0, 0)):
     lam, sig = lma.electron_constants(w.kv)
     nx, ny = nx or w.nx, ny or w.ny
     lx, ly = lx or w.lx, ly or w.ly
@@ -44,7 +45,7 @@ def build(w, L=None, scan=None, R=None, f=1, offset=None, window=(0, 0, 0, 0), p
     offset = offset or w.offset_frac
     rings = detectors or det_rad(w)
     lat = lma.lattice(scan[0], scan[1], R[0], R[1], f, offset, L, precision, window, batch, hbm_budget_bytes=budget,
-                      basis_kind=basis_kind, basis_param=basis_param)
+                      basis_kind=basis_kind, basis_param=basis_param, prop_window=prop_window)
     plan = lma.Plan(opt, lat, lma.detectors(rings), flags=flags)
     st = Setup(nx, ny, lx, ly, lam, sig, w.dz, w.bandlimit, w.alpha_mrad * 1e-3, w.defocus, w.cs, scan, rings)
     ol = Lattice(st, R, f, offset, L)
@@ -289,6 +290,39 @@ def test_gaussian_input_wave(tiny):
     say(f"  vs oracle, per-detector rel L2 {e}; probe residual {plan.info().max_residual:.3e}")
     say("  LMA(Gaussian) vs plain, per-detector rel L2", per_det(img, tiny["img_plain"]))
     image_errors(plan.plain_image(tiny["v"]), tiny["img_plain"], TOL32)
+
+
+def test_windowed_translates(tiny):
+    # option (ii) of Sec. 4.2.1: translates propagated on windows centred on them with the
+    # cropped potential, against the oracle's windowed propagation
+    w, v = tiny["w"], tiny["v"]
+    win_p = (3, 2, 6, 5)
+    flat = None
+    for pw, batch in (((64, 64), 0), ((96, 32), 100), ((32, 16), 0)):
+        say(f"tiny: translate windows {pw}, batch {batch}")
+        plan, st, ol = build(w, prop_window=pw, batch=batch, window=win_p)
+        assert (plan.info().prop_nx, plan.info().prop_ny) == pw
+        plan.propagate(v)
+        om = LMA(st, ol, window=pw)
+        rows = plan.rows()
+        ts = [(int(t) % ol.Rfx, int(t) // ol.Rfx) for t in rows]
+        basis = om.propagate(v, ts)
+        flat, _ = plan.detector_pixels()
+        got = plan.basis_rows(0, len(rows))
+        worst = max(rel_l2(got[r], basis[t].ravel()[flat]) for r, t in enumerate(ts))
+        say(f"  {len(ts)} exit waves: worst rel L2 {worst:.2e}")
+        assert worst < TOL32
+        ref = crop(om.image(v, window_probes(plan), basis=basis), plan)
+        image_errors(plan.probe_image(), ref, TOL32)
+        plan.close()
+    # a window of the whole cell propagates like the cell
+    full, _, _ = build(w, prop_window=(128, 128), window=win_p)
+    cell, _, _ = build(w, window=win_p)
+    full.propagate(v)
+    cell.propagate(v)
+    e = rel_l2(full.basis_rows(0, full.n_rows), cell.basis_rows(0, cell.n_rows))
+    say(f"  whole-cell window vs cell: rel L2 {e:.2e}")
+    assert e < 1e-5
 
 
 def test_tiny_split_bf16_image(tiny):

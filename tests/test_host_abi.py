@@ -303,3 +303,37 @@ def test_server_build_failure_returns_its_bytes():
             s.wait(s.build(0, opt, lat, det, w.nslices))
         assert e.value.status == _lib.LMA_ERR_DEVICE
         assert s.in_use() == 0
+
+
+def test_window_tables_match_the_oracle():
+    # option (ii): the window spectrum is the DFT of u cropped to a window centred on a
+    # translate; the window propagator keeps the cell's band limit
+    from oracle.lma import LMA as OLMA
+    w = WORKLOADS["tiny"]
+    for win in ((64, 32), (128, 128), (96, 16)):
+        opt, lat, det = _plan_args(w)
+        lat.prop_nx, lat.prop_ny = win
+        plan = lma.Plan(opt, lat, det, flags=lma.LMA_HOST_ONLY)
+        i = plan.info()
+        assert (i.prop_nx, i.prop_ny) == win
+        st = oracle_setup(w)
+        ol = oracle_lattice(w, st)
+        om = OLMA(st, ol, window=win)
+        t = (5, 2)
+        cx, cy = om.window_origin(*t)
+        u = translate_wave(st, st.spec0, ol.translate_position(*t))
+        ref = np.fft.fft2(u[np.ix_((cy + np.arange(win[1])) % 128, (cx + np.arange(win[0])) % 128)])
+        got = plan.window_spectrum()
+        assert np.abs(got - ref).max() < 1e-12 * np.abs(ref).max()
+    # every window has the same wave only when translates sit on pixels: 48 translates over
+    # 128 pixels do not
+    opt, lat, det = _plan_args(w, R=(48, 48), offset=(0.0, 0.0))
+    lma.Plan(opt, lat, det, flags=lma.LMA_HOST_ONLY)
+    lat.prop_nx, lat.prop_ny = 64, 64
+    with pytest.raises(lma.LmaError, match="translates on pixels"):
+        lma.Plan(opt, lat, det, flags=lma.LMA_HOST_ONLY)
+    for bad in ((100, 64), (256, 64), (64, 0)):
+        opt, lat, det = _plan_args(w)
+        lat.prop_nx, lat.prop_ny = bad
+        with pytest.raises(lma.LmaError):
+            lma.Plan(opt, lat, det, flags=lma.LMA_HOST_ONLY)
