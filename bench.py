@@ -159,12 +159,60 @@ def spacing_study(w):
                       "rows": rows}), flush=True)
 
 
+def window_study(w):
+    """Option (ii): the medium workload (configuration 0, translates every 4 px, L = 144) with
+    every translate propagated on a window of 64, 128 or 256 pixels centred on it, and on the
+    whole cell: LMA time (propagation + contraction), speed-up
+    over plain multislice of the whole cell, and the LMA-vs-plain image error per detector."""
+    import numpy as np
+    import torch
+    import paper_2310_16829_amd as lma
+    from synth import potential_slices
+    v = torch.from_numpy(potential_slices(w, 0)).cuda()
+    lam, sig = lma.electron_constants(w.kv)
+    rings = [(a * 1e-3, b * 1e-3) for _, a, b in w.detectors]
+    opt = lma.optics(w.nx, w.ny, w.lx, w.ly, lam, sig, w.dz, w.bandlimit, w.alpha_mrad * 1e-3, w.defocus, w.cs)
+
+    def run(fn):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = fn()
+        torch.cuda.synchronize()
+        return out, time.perf_counter() - t0
+
+    base = lma.Plan(opt, lma.lattice(w.scan[0], w.scan[1], 128, 128, 1, (0.5, 0.5), w.L), lma.detectors(rings))
+    plain, t_plain = run(lambda: base.plain_image(v, device=True))
+    plain = plain.cpu().numpy()
+    base.close()
+    rows = []
+    for side in (64, 128, 256, 0):
+        plan = lma.Plan(opt, lma.lattice(w.scan[0], w.scan[1], 128, 128, 1, (0.5, 0.5), w.L, prop_window=(side, side)),
+                        lma.detectors(rings))
+
+        def step():
+            plan.propagate(v)
+            return plan.probe_image(device=True)
+        img, t = run(step)
+        img = img.cpu().numpy()
+        err = [float(np.linalg.norm(img[r] - plain[r]) / np.linalg.norm(plain[r])) for r in range(len(rings))]
+        rows.append({"window_px": side or w.nx, "window_A": (side or w.nx) * w.lx / w.nx, "seconds": t,
+                     "speedup_vs_plain": t_plain / t,
+                     "lma_vs_plain_rel_l2": dict(zip([d[0] for d in w.detectors], err))})
+        log(f"window {side or w.nx}: {t:.3f} s, errors {err}")
+        plan.close()
+    print(json.dumps({"study": "translate windows (option (ii)), medium workload, configuration 0",
+                      "plain_seconds": t_plain, "rows": rows}), flush=True)
+
+
 # ------------------------------------------------------------------------------------------
 FP32_MFMA_PEAK_TFLOPS = 157.3
 
 KERNEL_NAMES = (("k_contract_mfma2", "contract_mfma"), ("k_contract_mfma", "contract_mfma"), ("k_contract", "contract"),
-                ("k_transmission", "transmission"), ("k_scale_out", "scale_out"))
-PASS_MODES = {"0": "row_pass", "1": "col_pass", "2": "init", "3": "col_gather", "4": "col_reduce"}
+                ("k_transmission", "transmission"), ("k_scale_out", "scale_out"), ("k_embed", "embed"),
+                ("k_intensity", "intensity"))
+PASS_MODES = {"0": "row_pass", "1": "col_pass", "2": "init", "3": "col_gather", "4": "col_reduce", "5": "row_pass",
+              "6": "row_pass"}
 
 
 def _short_name(kernel: str):
@@ -543,6 +591,8 @@ def main():
                     help="p50/p99 latency of the request loop under Poisson arrivals of image and local-edit requests")
     ap.add_argument("--paper-shaped", action="store_true",
                     help="LMA against plain multislice in the paper's regime (1024^2, 424x400 scan, f=2)")
+    ap.add_argument("--window-study", action="store_true",
+                    help="LMA with translates propagated on 64, 128, 256 px windows against plain multislice")
     ap.add_argument("--uneven", action="store_true",
                     help="64 specimens of mixed sizes: eager, one batch graph, autotuned plans with graphs")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -583,6 +633,9 @@ def main():
         return
     if args.spacing_study:
         spacing_study(w)
+        return
+    if args.window_study:
+        window_study(w)
         return
     K, W = args.steps, args.warmup
     n_cfg = w.n_phonons

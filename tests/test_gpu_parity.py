@@ -664,6 +664,28 @@ def test_large_full_size_sampled():
 
 
 @pytest.mark.slow
+def test_medium_windowed_full_size_sampled():
+    # option (ii) on the medium workload at full size: 256 x 256-pixel translate windows over
+    # the 512^2 cell, 100 slices; three translates' exit waves against the oracle
+    w = WORKLOADS["medium"]
+    say("medium, 256^2 translate windows: potential")
+    v = potential_slices(w, 0)
+    plan, st, ol = build(w, prop_window=(256, 256), window=(60, 70, 4, 4))
+    plan.propagate(v)
+    rows = plan.rows()
+    flat, _ = plan.detector_pixels()
+    pick = [0, len(rows) // 2, len(rows) - 1]
+    om = LMA(st, ol, window=(256, 256))
+    for r in pick:
+        t = int(rows[r])
+        ref = om.propagate(v, [(t % ol.Rfx, t // ol.Rfx)])[(t % ol.Rfx, t // ol.Rfx)]
+        e = rel_l2(plan.basis_rows(r, 1)[0], ref.ravel()[flat])
+        say(f"  exit wave of translate {t}: rel L2 {e:.2e}")
+        assert e < TOL32
+    plan.close()
+
+
+@pytest.mark.slow
 def test_paper_shaped_full_size_sampled():
     # the paper-shaped workload at full size: 1024^2 grid over a non-square cell, Case 2 with
     # four coefficient sets (I = P + p/2, f = 2), defocus and C_s; one LMA pixel (with the
