@@ -247,7 +247,10 @@ lma_status lma_plain_patterns(lma_plan* plan, const float* potential, int32_t ns
  * re-form the probes whose translate set meets them; their image values are replaced in
  * `image` (host, the layout of lma_probe_image, holding the previous image). bbox_px:
  * x0, y0, x1, y1, half-open, periodic. radius_A <= 0 selects every translate (the full
- * recompute). Outputs: counts of re-propagated translates and re-formed probes. */
+ * recompute). With translate windows (lattice.prop_nx > 0) a translate depends on the
+ * potential inside its window only: a radius of half the window's diagonal makes the local
+ * recompute equal to a full one. Outputs: counts of re-propagated translates and re-formed
+ * probes. */
 lma_status lma_recompute_local(lma_plan* plan, const float* potential_new, int32_t nslices,
                                const int32_t bbox_px[4], double radius_A, double* image,
                                int32_t* n_translates_redone, int32_t* n_probes_redone);
