@@ -217,7 +217,7 @@ __device__ __forceinline__ void exchange_sync() {
   else __syncthreads();
 }
 
-template <int N, int DIR, int S, bool WL>
+template <int N, int DIR, int S, bool WL, int TAG = 0>
 __device__ __forceinline__ void fft_stage(float2 (&v)[fft_elems(N)], int j, const float2* w, const float2* twg,
                                           const Slot& slot) {
   constexpr int E = fft_elems(N);
@@ -268,18 +268,20 @@ __device__ __forceinline__ void fft_stage(float2 (&v)[fft_elems(N)], int j, cons
 
 // N-point transform of the E values held by thread j (of N/E); input and output at
 // positions j + (N/E) m, natural order. w: the thread's register twiddles (tw_load); twg: the
-// twiddle table (lengths whose twiddles are not held in registers).
-template <int N, int DIR, bool WL>
+// twiddle table (lengths whose twiddles are not held in registers). TAG gives a kernel its
+// own instantiation: the embedding kernel sharing the passes' changed their register
+// allocation (640 points: 33-58 spilled registers).
+template <int N, int DIR, bool WL, int TAG = 0>
 __device__ __forceinline__ void fft(float2 (&v)[fft_elems(N)], int j, const float2* w, const float2* twg,
                                     const Slot& slot) {
   constexpr int ns = fft_nstages(N);
   static_assert(ns <= 6, "at most six stages");
-  fft_stage<N, DIR, 0, WL>(v, j, w, twg, slot);
-  if constexpr (ns > 1) fft_stage<N, DIR, (ns > 1 ? 1 : 0), WL>(v, j, w, twg, slot);
-  if constexpr (ns > 2) fft_stage<N, DIR, (ns > 2 ? 2 : 0), WL>(v, j, w, twg, slot);
-  if constexpr (ns > 3) fft_stage<N, DIR, (ns > 3 ? 3 : 0), WL>(v, j, w, twg, slot);
-  if constexpr (ns > 4) fft_stage<N, DIR, (ns > 4 ? 4 : 0), WL>(v, j, w, twg, slot);
-  if constexpr (ns > 5) fft_stage<N, DIR, (ns > 5 ? 5 : 0), WL>(v, j, w, twg, slot);
+  fft_stage<N, DIR, 0, WL, TAG>(v, j, w, twg, slot);
+  if constexpr (ns > 1) fft_stage<N, DIR, (ns > 1 ? 1 : 0), WL, TAG>(v, j, w, twg, slot);
+  if constexpr (ns > 2) fft_stage<N, DIR, (ns > 2 ? 2 : 0), WL, TAG>(v, j, w, twg, slot);
+  if constexpr (ns > 3) fft_stage<N, DIR, (ns > 3 ? 3 : 0), WL, TAG>(v, j, w, twg, slot);
+  if constexpr (ns > 4) fft_stage<N, DIR, (ns > 4 ? 4 : 0), WL, TAG>(v, j, w, twg, slot);
+  if constexpr (ns > 5) fft_stage<N, DIR, (ns > 5 ? 5 : 0), WL, TAG>(v, j, w, twg, slot);
 }
 
 // Blocks are dispatched round-robin over the 8 XCDs; give each XCD a contiguous range of
@@ -1150,7 +1152,7 @@ __global__ __launch_bounds__(N / fft_elems(N)) void k_embed(EmbedArgs a) {
     if (inside && wx < a.wnx)
       v[m] = src[((size_t)(wy / wt) * wtiles + wx / wt) * wt * wt + (wy % wt) * wt + wx % wt];
   }
-  if (inside) fft<N, -1, WL>(v, j, tw, a.twx, Slot{line});
+  if (inside) fft<N, -1, WL, 1>(v, j, tw, a.twx, Slot{line});
   float2* dst = a.out + (size_t)w * a.nx * a.ny;
   const int ctiles = a.nx / TW;
 #pragma unroll
