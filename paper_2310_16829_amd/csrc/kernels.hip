@@ -16,6 +16,7 @@
 #include <hip/hip_bf16.h>
 
 #include <algorithm>
+#include <atomic>
 
 #include "kernels.hpp"
 
@@ -972,12 +973,15 @@ hipError_t transmission(const float* v, float2* t, int64_t n, double sigma, hipS
   return hipGetLastError();
 }
 
+// host-side caches below are filled on first use by any thread (same value from each)
 static int device_cus() {
-  static int cus = 0;
+  static std::atomic<int> cached{0};
+  int cus = cached.load(std::memory_order_relaxed);
   if (cus == 0) {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
       cus = 256;
+    cached.store(cus, std::memory_order_relaxed);
   }
   return cus;
 }
@@ -986,12 +990,13 @@ template <int N, int TW, int MODE>
 static hipError_t pass_launch(const PassArgs& a0, int lines, int B, hipStream_t s) {
   if (lines % TW) return hipErrorInvalidValue;
   constexpr int threads = PassCfg<N, TW, pass_waves<MODE>()>::WAVES * 64;
-  static int resident = 0;   // workgroups of this kernel resident per CU
+  static std::atomic<int> cached{0};   // workgroups of this kernel resident per CU
+  int resident = cached.load(std::memory_order_relaxed);
   if (resident == 0) {
-    int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)k_pass<N, TW, MODE>, threads, 0) != hipSuccess || nb <= 0)
-      nb = 1;
-    resident = nb;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&resident, (const void*)k_pass<N, TW, MODE>, threads, 0) != hipSuccess ||
+        resident <= 0)
+      resident = 1;
+    cached.store(resident, std::memory_order_relaxed);
   }
   PassArgs a = a0;
   a.B = B;
@@ -1051,11 +1056,12 @@ static hipError_t pass_dispatch(int N, int TW, int lines, const PassArgs& a, int
 // workgroups share a CU; grids with a side above 512 use 4 x 4 tiles (128 B), which halve the
 // LDS tile and prefetch registers of the long-line workgroups (measured +28 % at 1024^2);
 // 16 x 16 tiles (2 KB) measured slower and need N <= 512.
-static int g_tile_width = 0;   // 0: default; 4, 8 or 16 forces a tile width (tuning)
-void set_tile_width(int tw) { g_tile_width = (tw == 4 || tw == 8 || tw == 16) ? tw : 0; }
+static std::atomic<int> g_tile_width{0};   // 0: default; 4, 8 or 16 forces a tile width (tuning)
+void set_tile_width(int tw) { g_tile_width.store((tw == 4 || tw == 8 || tw == 16) ? tw : 0); }
 int tile_width(int nx, int ny) {
-  if (nx > 512 || ny > 512) return g_tile_width == 8 ? 8 : 4;
-  return g_tile_width ? g_tile_width : 8;
+  const int forced = g_tile_width.load();
+  if (nx > 512 || ny > 512) return forced == 8 ? 8 : 4;
+  return forced ? forced : 8;
 }
 
 bool tile_width_ok(int nx, int ny, int tw) {
