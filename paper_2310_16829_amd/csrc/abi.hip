@@ -91,7 +91,8 @@ struct lma_plan {
   int64_t* d_probe_u = nullptr;      // [n_probes][2]
   int32_t* d_probe_out = nullptr;    // [n_probes] image index
   // work
-  void* d_basis = nullptr;           // [n_rows][D] x 8 bytes
+  void* d_basis = nullptr;           // [n_rows][D] x 8 bytes, + 128 bytes of padding
+  float2* d_zeros = nullptr;         // 256 zero bytes
   float2* d_work = nullptr;          // [B][ny/TW][nx/TW][TW][TW] tiled waves
   float2* d_trans = nullptr;         // [cap][ny][nx]
   int trans_cap = 0;
@@ -462,6 +463,7 @@ lma::dev::Stencil stencil(const lma_plan* p) {
   c.ndet = h.ndet;
   c.scale = (double)h.op.nx * h.op.ny;
   c.img = p->d_img;
+  c.zeros = p->d_zeros;
   return c;
 }
 
@@ -493,7 +495,8 @@ int64_t footprint_of(const HostPlan& h, int B, int nslices, bool with_basis) {
   b += (int64_t)h.ndet * h.n_probes() * 8;            // image
   b += (int64_t)B * XY * 8;                           // wave batch
   b += (int64_t)nslices * XY * (8 + 4);               // transmission tables and potential staging
-  if (with_basis) b += (int64_t)h.rows.size() * h.D() * 8;
+  if (with_basis) b += (int64_t)h.rows.size() * h.D() * 8 + 128;
+  b += 256;                                           // zero bytes
   if (h.wnx > 0) b += (int64_t)h.wnx * h.wny * (8 + 8) + (int64_t)B * (h.wnx * h.wny * 8 + 16);   // window tables, batch
   return b;
 }
@@ -722,6 +725,10 @@ lma_status lma_build_basis(const lma_optics* optics, const lma_lattice* lattice,
     if ((s = upload(p, &p->d_probe_out, po.data(), po.size())) != LMA_OK) { release(p); return s; }
     // buffers
     if ((s = dalloc(p, (void**)&p->d_img, (size_t)h.ndet * h.n_probes() * sizeof(double))) != LMA_OK) { release(p); return s; }
+    {
+      const std::vector<float2> z(32, make_float2(0.f, 0.f));
+      if ((s = upload(p, &p->d_zeros, z.data(), z.size())) != LMA_OK) { release(p); return s; }
+    }
     if ((s = dalloc(p, (void**)&p->d_work, (size_t)p->B * XY * sizeof(float2))) != LMA_OK) { release(p); return s; }
     if (p->partitioned) {
       const lma::PartPlan& pp = p->pp;
@@ -749,9 +756,9 @@ lma_status lma_build_basis(const lma_optics* optics, const lma_lattice* lattice,
       if ((s = upload(p, &p->d_part_u, u.data(), u.size())) != LMA_OK) { release(p); return s; }
       if ((s = upload(p, &p->d_part_slot, slot.data(), slot.size())) != LMA_OK) { release(p); return s; }
       if ((s = upload(p, &p->d_part_probes, probes.data(), probes.size())) != LMA_OK) { release(p); return s; }
-      if ((s = dalloc(p, &p->d_basis, (size_t)pp.slots * h.D() * 8)) != LMA_OK) { release(p); return s; }
+      if ((s = dalloc(p, &p->d_basis, (size_t)pp.slots * h.D() * 8 + 128)) != LMA_OK) { release(p); return s; }
     } else {
-      if ((s = dalloc(p, &p->d_basis, (size_t)h.rows.size() * h.D() * 8)) != LMA_OK) { release(p); return s; }
+      if ((s = dalloc(p, &p->d_basis, (size_t)h.rows.size() * h.D() * 8 + 128)) != LMA_OK) { release(p); return s; }
     }
     *out = p;
     return LMA_OK;

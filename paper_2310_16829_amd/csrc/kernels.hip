@@ -1395,11 +1395,116 @@ __global__ __launch_bounds__(512) void k_contract_mfma2(Stencil c) {
   }
 }
 
+// The same with the slab copied from the basis straight into LDS (16 bytes per lane per
+// instruction, no registers in between): every wavefront copies 8 translate rows of 16 pixels
+// per instruction and all copies of a slab are in flight at once. FP32 basis only. Rows that
+// are absent and pixels past the chunk copy 16 zero bytes; a pixel pair that straddles the
+// chunk's end reads one value past it (inside the basis allocation, padded by 128 bytes),
+// which lands in a column the epilogue ignores.
+template <int KH>
+__global__ __launch_bounds__(512) void k_contract_mfma2_dma(Stencil c) {
+  extern __shared__ unsigned char dyn[];
+  const int nt = c.W * c.H;
+  const int ntp = (nt + 7) & ~7;                                          // whole 8-row copies
+  float2* slab = reinterpret_cast<float2*>(dyn);                          // [ntp][16]
+  int32_t* rowid = reinterpret_cast<int32_t*>(slab + (size_t)ntp * 16);   // [ntp]
+  __shared__ f32x4 part[4][2][64];
+  const int ti = c.tile_x0 + (int)blockIdx.x % c.tiles_x, tj = c.tile_y0 + (int)blockIdx.x / c.tiles_x;
+  const int chunk = blockIdx.y;
+  const int ox = (c.ox0 + ti * c.tile_dx) % c.Rfx;
+  const int oy = (c.oy0 + tj * c.tile_dy) % c.Rfy;
+  for (int t = threadIdx.x; t < ntp; t += 512) {
+    const int x = t % c.W, y = t / c.W;
+    rowid[t] = t < nt ? c.row_of[((oy + y) % c.Rfy) * c.Rfx + (ox + x) % c.Rfx] : -1;
+  }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int sb = wv & 3, kh = wv >> 2;
+  const int kk = lane >> 4, n = lane & 15;
+  const int k0 = kh * KH;
+  float2 A[KH];
+#pragma unroll
+  for (int q = 0; q < KH; ++q) A[q] = k0 + q < c.nks ? c.a[(k0 + q) * 64 + lane] : make_float2(0.f, 0.f);
+  const int base = (sb >> 1) * c.sub_dy * c.W + (sb & 1) * c.sub_dx + kk;
+  const int start = c.chunk_start[chunk], len = c.chunk_len[chunk];
+  const uint32_t mask = c.chunk_mask[chunk];
+  const float2* basis = reinterpret_cast<const float2*>(c.basis);
+  const int rr = lane >> 3, q0 = (lane & 7) * 2;       // row within the copy, first pixel of the pair
+  double val[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int d0 = 0; d0 < len; d0 += 16) {
+    __syncthreads();  // row ids written, previous slab and partial sums consumed
+    const int rem = len - d0;
+    for (int t0 = wv * 8; t0 < ntp; t0 += 64) {
+      const int r = rowid[t0 + rr];
+      const float2* src = (r >= 0 && q0 < rem) ? basis + (int64_t)r * c.D + start + d0 + q0 : c.zeros;
+      __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)(slab + (size_t)t0 * 16), 16, 0, 0);
+    }
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): this wavefront's copies are in LDS
+    __syncthreads();
+    f32x4 cre = {0.f, 0.f, 0.f, 0.f}, cim = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int q = 0; q < KH; ++q) {
+      if (k0 + q < c.nks) {
+        const float2 b = slab[(base + c.ks_off[k0 + q]) * 16 + n];
+        cre = __builtin_amdgcn_mfma_f32_16x16x4f32(A[q].x, b.x, cre, 0, 0, 0);
+        cim = __builtin_amdgcn_mfma_f32_16x16x4f32(A[q].x, b.y, cim, 0, 0, 0);
+        cre = __builtin_amdgcn_mfma_f32_16x16x4f32(-A[q].y, b.y, cre, 0, 0, 0);
+        cim = __builtin_amdgcn_mfma_f32_16x16x4f32(A[q].y, b.x, cim, 0, 0, 0);
+      }
+    }
+    if (kh == 1) {
+      part[sb][0][lane] = cre;
+      part[sb][1][lane] = cim;
+    }
+    __syncthreads();
+    if (kh == 0 && n < rem) {
+      cre += part[sb][0][lane];
+      cim += part[sb][1][lane];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) val[r] += (double)cre[r] * cre[r] + (double)cim[r] * cim[r];
+    }
+  }
+  if (kh != 0) return;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    double x = val[r];
+#pragma unroll
+    for (int o = 8; o > 0; o >>= 1) x += __shfl_xor(x, o);
+    val[r] = x;
+  }
+  if (n == 0) {
+    const int by = tj * 8 + (sb >> 1) * 4 + kk;
+    const int64_t stride = (int64_t)c.ww * c.wh;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int bx = ti * 8 + (sb & 1) * 4 + r;
+      if (bx < c.ww && by < c.wh) {
+        const double v = val[r] * c.scale;
+        for (int d = 0; d < c.ndet; ++d)
+          if (mask & (1u << d)) atomicAdd(c.img + (int64_t)d * stride + (int64_t)by * c.ww + bx, v);
+      }
+    }
+  }
+}
+
+#ifndef LMA_CONTRACT_DMA
+#define LMA_CONTRACT_DMA 1
+#endif
+
 template <int SPLIT, int KS>
 static hipError_t stencil_ks(const Stencil& c, hipStream_t s) {
   const size_t shm = (size_t)c.W * c.H * (16 * sizeof(float2) + sizeof(int32_t));
   // split K over two wavefronts while each half keeps 4 wavefronts per SIMD (up to 80 K-steps)
   if constexpr (KS <= 80) {
+    if (LMA_CONTRACT_DMA && !SPLIT && c.zeros) {
+      const int ntp = (c.W * c.H + 7) & ~7;
+      const size_t shd = (size_t)ntp * (16 * sizeof(float2) + sizeof(int32_t));
+      const void* fd = reinterpret_cast<const void*>(&k_contract_mfma2_dma<KS / 2>);
+      hipError_t e = hipFuncSetAttribute(fd, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shd);
+      if (e != hipSuccess) return e;
+      dim3 grid((unsigned)(c.tiles_x * c.tiles_y), (unsigned)c.nchunks);
+      k_contract_mfma2_dma<KS / 2><<<grid, 512, shd, s>>>(c);
+      return hipGetLastError();
+    }
     const void* fn = reinterpret_cast<const void*>(&k_contract_mfma2<SPLIT, KS / 2>);
     hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
     if (e != hipSuccess) return e;

@@ -69,6 +69,7 @@ struct Stencil {
   int ndet = 0;
   double scale = 1.0;
   double* img = nullptr;             // [ndet][wh][ww]
+  const float2* zeros = nullptr;     // 16 zero bytes (copies of absent rows and pixels)
 };
 // largest K-step count and translate rectangle the MFMA contraction accepts
 constexpr int kStencilMaxKs = 96;
