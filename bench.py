@@ -208,7 +208,7 @@ def window_study(w):
 # ------------------------------------------------------------------------------------------
 FP32_MFMA_PEAK_TFLOPS = 157.3
 
-KERNEL_NAMES = (("k_contract_mfma2", "contract_mfma"), ("k_contract_mfma", "contract_mfma"), ("k_contract", "contract"),
+KERNEL_NAMES = (("k_contract_mfma2_dma", "contract_mfma"), ("k_contract_mfma2", "contract_mfma"), ("k_contract_mfma", "contract_mfma"), ("k_contract", "contract"),
                 ("k_transmission", "transmission"), ("k_scale_out", "scale_out"), ("k_embed", "embed"),
                 ("k_intensity", "intensity"))
 PASS_MODES = {"0": "row_pass", "1": "col_pass", "2": "init", "3": "col_gather", "4": "col_reduce", "5": "row_pass",
