@@ -337,3 +337,35 @@ def test_window_tables_match_the_oracle():
         lat.prop_nx, lat.prop_ny = bad
         with pytest.raises(lma.LmaError):
             lma.Plan(opt, lat, det, flags=lma.LMA_HOST_ONLY)
+
+
+def test_autotune_and_batch_argument_checks():
+    # checked before any device work, so these run without a GPU
+    with pytest.raises(lma.LmaError) as e:
+        lma.autotune(100, 100)
+    assert e.value.status == _lib.LMA_ERR_UNSUPPORTED
+    t = _lib.lma_tuning()
+    assert lma.lib().lma_autotune(128, 128, -1, None, ctypes.byref(t)) != 0
+    w = WORKLOADS["tiny"]
+    opt, lat, det = _plan_args(w)
+    plan = lma.Plan(opt, lat, det, flags=lma.LMA_HOST_ONLY)
+    out = ctypes.c_void_p()
+    one = (ctypes.c_int32 * 1)(10)
+    assert lma.lib().lma_batch_create(None, 1, one, None, ctypes.byref(out)) == _lib.LMA_ERR_ARG
+    hs = (ctypes.c_void_p * 1)(plan._h.value)
+    assert lma.lib().lma_batch_create(hs, 0, one, None, ctypes.byref(out)) == _lib.LMA_ERR_ARG
+    # a host-only plan has no device state (or, without a GPU, there is no device at all)
+    assert lma.lib().lma_batch_create(hs, 1, one, None, ctypes.byref(out)) in (_lib.LMA_ERR_STATE, _lib.LMA_ERR_DEVICE)
+    assert not out.value
+
+
+def test_3d_4d_outputs_refuse_host_only_plans():
+    w = WORKLOADS["tiny"]
+    opt, lat, det = _plan_args(w)
+    plan = lma.Plan(opt, lat, det, flags=lma.LMA_HOST_ONLY)
+    with pytest.raises(lma.LmaError):
+        plan.probe_patterns()
+    with pytest.raises(lma.LmaError):
+        plan.probe_radial(0.005, 10)
+    img = np.zeros((10, 16, 16))
+    assert lma.lib().lma_probe_radial(plan._h, 0.0, 10, ctypes.c_void_p(img.ctypes.data), 0, 1.0) != 0
