@@ -325,6 +325,34 @@ def test_windowed_translates(tiny):
     assert e < 1e-5
 
 
+def test_single_slice_and_vacuum(tiny):
+    # one slice: the first row pass is also the last (no column pass before the gather)
+    w = tiny["w"]
+    rng = np.random.default_rng(31)
+    v1 = rng.uniform(0, 40, size=(1, 128, 128)).astype(np.float32)
+    win = (4, 9, 5, 4)
+    for pw in ((0, 0), (64, 64)):
+        say(f"tiny: one slice, translate windows {pw}")
+        plan, st, ol = build(w, window=win, prop_window=pw)
+        plan.propagate(v1)
+        om = LMA(st, ol, window=None if pw == (0, 0) else pw)
+        ref = crop(om.image(v1, window_probes(plan)), plan)
+        image_errors(plan.probe_image(), ref, TOL32)
+        if pw == (0, 0):
+            image_errors(plan.plain_image(v1), crop(plain_image(st, v1, window_probes(plan)), plan), TOL32)
+        plan.close()
+    # vacuum: every probe keeps its spectrum (unit-modulus propagators inside the band), so a
+    # ring holds the fraction of aperture pixels whose angle it covers, counted here
+    say("tiny: vacuum, 3 slices")
+    plan, st, ol = build(w, window=win)
+    img = plan.plain_image(np.zeros((3, 128, 128), np.float32))
+    ap = np.abs(st.spec0) > 0
+    for r in range(img.shape[0]):
+        want = (ap & st.masks[r]).sum() / ap.sum()
+        assert np.abs(img[r] - want).max() < 2e-6, (r, want, img[r].min(), img[r].max())
+    plan.close()
+
+
 def test_tiny_split_bf16_image(tiny):
     say("tiny split-bf16 LMA image")
     plan, _, _ = build(tiny["w"], precision=lma.LMA_GEMM_SPLIT_BF16)
