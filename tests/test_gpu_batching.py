@@ -82,9 +82,10 @@ def test_uneven_batch_matches_each_plan_alone():
     specs = [dict(nx=96, ny=96, lx=9.6, ly=9.6, scan=(12, 12), R=(24, 24), L=9, window=(1, 2, 5, 4), batch=50),
              dict(window=(3, 3, 6, 5)),
              dict(nx=192, ny=64, lx=19.2, ly=6.4, scan=(24, 8), R=(48, 16), L=9, window=(20, 5, 4, 3)),
-             dict(nx=640, ny=96, lx=64.0, ly=9.6, scan=(80, 12), R=(160, 24), L=9, window=(40, 7, 4, 3))]
-    nsl = [3, 10, 7, 2]
-    pots = [potential_slices(w, 0) if i == 1 else
+             dict(nx=640, ny=96, lx=64.0, ly=9.6, scan=(80, 12), R=(160, 24), L=9, window=(40, 7, 4, 3)),
+             dict(window=(8, 1, 5, 6), prop_window=(64, 32))]     # translates on windows
+    nsl = [3, 10, 7, 2, 10]
+    pots = [potential_slices(w, 0) if i in (1, 4) else
             rng.uniform(0, 40, size=(nsl[i], s["ny"], s["nx"])).astype(np.float32) for i, s in enumerate(specs)]
     alone = [_plan(w, **s)[0] for s in specs]
     refs = []

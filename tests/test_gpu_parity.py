@@ -535,6 +535,31 @@ def test_local_recompute(tiny):
     image_errors(img, full_ref, TOL32)
 
 
+def test_local_recompute_with_translate_windows(tiny):
+    # with 32 x 32-pixel windows a translate depends on the potential inside its window only:
+    # a radius of half the window's diagonal (plus the edit's own extent, which the box
+    # carries) recomputes exactly what a full propagation would change
+    say("local recompute, 32 x 32 translate windows")
+    w, v0 = tiny["w"], tiny["v"]
+    win = (2, 3, 6, 5)
+    plan, st, ol = build(w, window=win, prop_window=(32, 32))
+    pos, amps, bbox = edit_column(w, 0, (4.0, 8.0), seed=1)
+    v1 = potential_from_atoms(w, pos, amps)
+    plan.propagate(v0)
+    img = plan.probe_image()
+    rho = 32 * st.lx / st.nx * np.sqrt(2) / 2 + 0.1
+    nt, npr = plan.recompute_local(v1, bbox, rho, img)
+    say(f"  {nt} translates, {npr} probes redone")
+    fresh, _, _ = build(w, window=win, prop_window=(32, 32))
+    fresh.propagate(v1)
+    ref = fresh.probe_image()
+    e = per_det(img, ref)
+    say("  local vs full recompute (GPU), per-detector rel L2", e)
+    assert max(e) < 1e-6
+    fresh.close()
+    plan.close()
+
+
 # ------------------------------------------------------------------------------------------
 # medium workload at full size, in the benchmark's launch configuration, on sampled outputs
 # ------------------------------------------------------------------------------------------
