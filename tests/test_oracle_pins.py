@@ -10,7 +10,7 @@ import pytest
 from oracle import physics as ph
 from oracle import costs
 from oracle.dft import dft2
-from oracle.lma import LMA, Lattice, least_squares, translate_wave
+from oracle.lma import LMA, Lattice, least_squares, recompute_sets, translate_wave
 from oracle.multislice import Setup, multislice, plain_image
 from oracle.partition import multislice_calls, union
 from tests._cases import rel_l2
@@ -468,6 +468,34 @@ def test_cost_model_log_base_two():
     assert math.ceil(costs.realspace_breakeven_f(2048, 2048, 25, 25)) == 4
     assert math.ceil(costs.realspace_breakeven_f(2048, 2048, 25, 25, log=math.log)) != 4
     assert costs.t_multislice(1, 4, 4) == 2 * 16 + 2 * 16 * 4
+
+
+def test_recompute_sets_distance_rule():
+    # Sec. 4.2.6 selection (reading: Euclidean distance from a translate's centre to the span of
+    # edited pixel positions, periodic, inclusive): checked on a single edited pixel whose
+    # distances to the translates are known exactly
+    st = _setup(scan=(8, 8))                             # 32 px over 6.4 A: 0.2 A per pixel
+    lat = Lattice(st, (8, 8), 1, (0, 0), 4)              # translates every 4 px = 0.8 A, at (0, 0) + k
+    box = (8, 8, 9, 9)                                   # pixel (8, 8) = (1.6, 1.6) A = translate (2, 2)
+    R0, _ = recompute_sets(lat, box, 1e-9)
+    assert R0 == {(2, 2)}
+    # the four neighbours at 0.8 A (the cell length 6.4 is a binary double, so the distances
+    # are 0.8 to within 1e-15, and rho is read to 1/2^24, hence the tolerance), the diagonals at 1.13 A
+    R1, _ = recompute_sets(lat, box, 0.8 + 1e-6)
+    assert R1 == {(2, 2), (1, 2), (3, 2), (2, 1), (2, 3)}
+    R2, _ = recompute_sets(lat, box, 0.8 * math.sqrt(2) - 1e-6)
+    assert R2 == R1
+    R2b, _ = recompute_sets(lat, box, 0.8 * math.sqrt(2) + 1e-6)
+    assert R2b == R1 | {(1, 1), (3, 1), (1, 3), (3, 3)}
+    # periodic: a box at the cell's last pixel reaches translate (0, 0) across the edge
+    R3, _ = recompute_sets(lat, (31, 31, 32, 32), 0.2 * math.sqrt(2) + 1e-6)
+    assert (0, 0) in R3
+    # every translate for rho <= 0; the probes are those whose neighbour sets meet R
+    Rall, Pall = recompute_sets(lat, box, 0.0)
+    assert len(Rall) == 64 and len(Pall) == 64
+    _, P1 = recompute_sets(lat, box, 0.8 + 1e-6)
+    assert P1 == {(a, b) for b in range(8) for a in range(8) if set(lat.nearest(a, b)) & R1}
+    assert (2, 2) in P1 and (6, 6) not in P1
 
 
 def test_phonon_average_linear():
