@@ -78,6 +78,7 @@ struct lma_plan {
   lma::StencilPlan st;               // the window's contraction as a banded GEMM (if it applies)
   int32_t* d_ks_off = nullptr;
   float2* d_stencil_a = nullptr;
+  uint16_t* d_stencil_abf = nullptr; // split-BF16 A fragments of the bf16 MFMA (split basis)
   // rectangle partition when the window's basis exceeds the residency budget
   bool partitioned = false;
   lma::PartPlan pp;
@@ -190,6 +191,21 @@ std::vector<float2> twiddles(int n) {
     w[t] = make_float2((float)std::cos(a), (float)std::sin(a));
   }
   return w;
+}
+
+// bf16 of a float, rounded to nearest even (the device's conversion), and back
+uint16_t bf16_round(float f) {
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  if ((u & 0x7FFFFFFFu) > 0x7F800000u) return (uint16_t)((u >> 16) | 0x40u);   // NaN stays NaN
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+float bf16_value(uint16_t h) {
+  const uint32_t u = (uint32_t)h << 16;
+  float f;
+  std::memcpy(&f, &u, 4);
+  return f;
 }
 
 int64_t wave_bytes(const lma_optics& op) { return (int64_t)op.nx * op.ny * (int64_t)sizeof(float2); }
@@ -454,6 +470,7 @@ lma::dev::Stencil stencil(const lma_plan* p) {
   c.tile_y0 = 0;
   c.ks_off = p->d_ks_off;
   c.a = p->d_stencil_a;
+  c.abf = p->d_stencil_abf;
   c.ww = h.ww;
   c.wh = h.wh;
   c.chunk_start = p->d_chunk_start;
@@ -700,6 +717,27 @@ lma_status lma_build_basis(const lma_optics* optics, const lma_lattice* lattice,
       for (size_t i = 0; i < sa.size(); ++i) sa[i] = make_float2(p->st.a[i].real(), p->st.a[i].imag());
       if ((s = upload(p, &p->d_stencil_a, sa.data(), sa.size())) != LMA_OK) { release(p); return s; }
       if ((s = upload(p, &p->d_ks_off, p->st.ks_off.data(), p->st.ks_off.size())) != LMA_OK) { release(p); return s; }
+      if (h.lat.precision == LMA_GEMM_SPLIT_BF16) {
+        // A fragments of the bf16 MFMA: group G of 4 K-steps, lane l = m + 16 g holds the
+        // coefficients of probe m for the 4 translates of K-step 4 G + g, each split into hi
+        // and lo bf16 (Re hi x4, Re lo x4, Im hi x4, Im lo x4)
+        const int nks = p->st.nks, ng = (nks + 3) / 4;
+        std::vector<uint16_t> abf((size_t)ng * 64 * 16, 0);
+        for (int G = 0; G < ng; ++G)
+          for (int l = 0; l < 64; ++l) {
+            const int m = l % 16, g = l / 16, ks = 4 * G + g;
+            uint16_t* o = &abf[((size_t)G * 64 + l) * 16];
+            for (int i = 0; i < 4 && ks < nks; ++i) {
+              const std::complex<float> z = p->st.a[(size_t)ks * 64 + m + 16 * i];
+              const uint16_t rh = bf16_round(z.real()), ih = bf16_round(z.imag());
+              o[i] = rh;
+              o[4 + i] = bf16_round(z.real() - bf16_value(rh));
+              o[8 + i] = ih;
+              o[12 + i] = bf16_round(z.imag() - bf16_value(ih));
+            }
+          }
+        if ((s = upload(p, &p->d_stencil_abf, abf.data(), abf.size())) != LMA_OK) { release(p); return s; }
+      }
     }
     // wave position lists
     std::vector<int64_t> ru(h.rows.size() * 2);

@@ -1486,6 +1486,145 @@ __global__ __launch_bounds__(512) void k_contract_mfma2_dma(Stencil c) {
   }
 }
 
+// The contraction of a split-BF16 basis on the bf16 MFMA (v_mfma_f32_16x16x16_bf16, FP32
+// accumulation). Basis values are stored as (hi, lo) bf16 pairs, x = hi + lo; the
+// coefficients are split the same way on the host. A product of two split values keeps the
+// three terms hi hi + hi lo + lo hi (the lo lo term is below 2^-16 of it), so each complex
+// product takes 12 bf16 MFMAs: Re += Re A Re B - Im A Im B and Im += Re A Im B + Im A Re B, three
+// terms each. One instruction covers 16 translates (4 K-steps): lane l holds, for lane group
+// g = l / 16, the 4 translates of K-step 4 G + g at its pixel (B) and its probe's coefficients
+// for them (A), so the slab rows are read 4 at a time. Slabs are the raw 8-byte split values,
+// copied straight into LDS as for FP32.
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+struct SplitA {
+  bf16x4 rh, rl, ih, il;             // Re and Im of 4 coefficients, hi and lo parts
+};
+
+// the 4 bf16 at half `h` (0: low 16 bits, 1: high) of word w of 4 rows
+__device__ __forceinline__ bf16x4 gather4(uint32_t a, uint32_t b, uint32_t c, uint32_t d, int h) {
+  uint2 r;
+  if (h == 0) {
+    r.x = (a & 0xFFFFu) | (b << 16);
+    r.y = (c & 0xFFFFu) | (d << 16);
+  } else {
+    r.x = (a >> 16) | (b & 0xFFFF0000u);
+    r.y = (c >> 16) | (d & 0xFFFF0000u);
+  }
+  return __builtin_bit_cast(bf16x4, r);
+}
+
+template <int GH>
+__global__ __launch_bounds__(512) void k_contract_bf16(Stencil c) {
+  extern __shared__ unsigned char dyn[];
+  const int nt = c.W * c.H;
+  const int ntp = (nt + 7) & ~7;
+  float2* slab = reinterpret_cast<float2*>(dyn);                          // [ntp][16] raw split values
+  int32_t* rowid = reinterpret_cast<int32_t*>(slab + (size_t)ntp * 16);   // [ntp]
+  __shared__ f32x4 part[4][2][64];
+  const int ti = c.tile_x0 + (int)blockIdx.x % c.tiles_x, tj = c.tile_y0 + (int)blockIdx.x / c.tiles_x;
+  const int chunk = blockIdx.y;
+  const int ox = (c.ox0 + ti * c.tile_dx) % c.Rfx;
+  const int oy = (c.oy0 + tj * c.tile_dy) % c.Rfy;
+  for (int t = threadIdx.x; t < ntp; t += 512) {
+    const int x = t % c.W, y = t / c.W;
+    rowid[t] = t < nt ? c.row_of[((oy + y) % c.Rfy) * c.Rfx + (ox + x) % c.Rfx] : -1;
+  }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int sb = wv & 3, kh = wv >> 2;
+  const int g = lane >> 4, n = lane & 15, kk = lane >> 4;
+  const int ng = (c.nks + 3) / 4;
+  const int g0 = kh * GH;
+  const SplitA* abf = reinterpret_cast<const SplitA*>(c.abf);
+  SplitA A[GH];
+#pragma unroll
+  for (int q = 0; q < GH; ++q) {
+    if (g0 + q < ng) {
+      A[q] = abf[(g0 + q) * 64 + lane];
+    } else {
+      const bf16x4 z = {0, 0, 0, 0};
+      A[q] = SplitA{z, z, z, z};
+    }
+  }
+  const bf16x4 sign = {(short)0x8000, (short)0x8000, (short)0x8000, (short)0x8000};
+  const int base0 = (sb >> 1) * c.sub_dy * c.W + (sb & 1) * c.sub_dx;
+  const int start = c.chunk_start[chunk], len = c.chunk_len[chunk];
+  const uint32_t mask = c.chunk_mask[chunk];
+  const float2* basis = reinterpret_cast<const float2*>(c.basis);
+  const int rr = lane >> 3, q0 = (lane & 7) * 2;
+  double val[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int d0 = 0; d0 < len; d0 += 16) {
+    __syncthreads();  // row ids written, previous slab and partial sums consumed
+    const int rem = len - d0;
+    for (int t0 = wv * 8; t0 < ntp; t0 += 64) {
+      const int r = rowid[t0 + rr];
+      const float2* src = (r >= 0 && q0 < rem) ? basis + (int64_t)r * c.D + start + d0 + q0 : c.zeros;
+      __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)(slab + (size_t)t0 * 16), 16, 0, 0);
+    }
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): this wavefront's copies are in LDS
+    __syncthreads();
+    f32x4 cre = {0.f, 0.f, 0.f, 0.f}, cim = {0.f, 0.f, 0.f, 0.f};
+    const uint2* raw = reinterpret_cast<const uint2*>(slab);
+#pragma unroll
+    for (int q = 0; q < GH; ++q) {
+      if (g0 + q < ng) {
+        const int ks = 4 * (g0 + q) + g;
+        const int row = base0 + (ks < c.nks ? c.ks_off[ks] : 0);
+        const uint2 r0 = raw[(row + 0) * 16 + n], r1 = raw[(row + 1) * 16 + n];
+        const uint2 r2 = raw[(row + 2) * 16 + n], r3 = raw[(row + 3) * 16 + n];
+        // word x: hi_re | lo_re << 16, word y: hi_im | lo_im << 16
+        const bf16x4 brh = gather4(r0.x, r1.x, r2.x, r3.x, 0), brl = gather4(r0.x, r1.x, r2.x, r3.x, 1);
+        const bf16x4 bih = gather4(r0.y, r1.y, r2.y, r3.y, 0), bil = gather4(r0.y, r1.y, r2.y, r3.y, 1);
+        const SplitA& a = A[q];
+        const bf16x4 nih = a.ih ^ sign, nil = a.il ^ sign;
+        cre = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a.rh, brh, cre, 0, 0, 0);
+        cim = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a.rh, bih, cim, 0, 0, 0);
+        cre = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a.rh, brl, cre, 0, 0, 0);
+        cim = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a.rh, bil, cim, 0, 0, 0);
+        cre = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a.rl, brh, cre, 0, 0, 0);
+        cim = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a.rl, bih, cim, 0, 0, 0);
+        cre = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(nih, bih, cre, 0, 0, 0);
+        cim = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a.ih, brh, cim, 0, 0, 0);
+        cre = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(nih, bil, cre, 0, 0, 0);
+        cim = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a.ih, brl, cim, 0, 0, 0);
+        cre = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(nil, bih, cre, 0, 0, 0);
+        cim = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a.il, brh, cim, 0, 0, 0);
+      }
+    }
+    if (kh == 1) {
+      part[sb][0][lane] = cre;
+      part[sb][1][lane] = cim;
+    }
+    __syncthreads();
+    if (kh == 0 && n < rem) {
+      cre += part[sb][0][lane];
+      cim += part[sb][1][lane];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) val[r] += (double)cre[r] * cre[r] + (double)cim[r] * cim[r];
+    }
+  }
+  if (kh != 0) return;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    double x = val[r];
+#pragma unroll
+    for (int o = 8; o > 0; o >>= 1) x += __shfl_xor(x, o);
+    val[r] = x;
+  }
+  if (n == 0) {
+    const int by = tj * 8 + (sb >> 1) * 4 + kk;
+    const int64_t stride = (int64_t)c.ww * c.wh;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int bx = ti * 8 + (sb & 1) * 4 + r;
+      if (bx < c.ww && by < c.wh) {
+        const double v = val[r] * c.scale;
+        for (int d = 0; d < c.ndet; ++d)
+          if (mask & (1u << d)) atomicAdd(c.img + (int64_t)d * stride + (int64_t)by * c.ww + bx, v);
+      }
+    }
+  }
+}
+
 #ifndef LMA_CONTRACT_DMA
 #define LMA_CONTRACT_DMA 1
 #endif
@@ -1495,6 +1634,17 @@ static hipError_t stencil_ks(const Stencil& c, hipStream_t s) {
   const size_t shm = (size_t)c.W * c.H * (16 * sizeof(float2) + sizeof(int32_t));
   // split K over two wavefronts while each half keeps 4 wavefronts per SIMD (up to 80 K-steps)
   if constexpr (KS <= 80) {
+    if (SPLIT && c.abf && c.zeros) {
+      const int ntp = (c.W * c.H + 7) & ~7;
+      const size_t shd = (size_t)ntp * (16 * sizeof(float2) + sizeof(int32_t));
+      constexpr int GH = (KS / 2 + 3) / 4;   // 4-K-step groups per half
+      const void* fb = reinterpret_cast<const void*>(&k_contract_bf16<GH>);
+      hipError_t e = hipFuncSetAttribute(fb, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shd);
+      if (e != hipSuccess) return e;
+      dim3 grid((unsigned)(c.tiles_x * c.tiles_y), (unsigned)c.nchunks);
+      k_contract_bf16<GH><<<grid, 512, shd, s>>>(c);
+      return hipGetLastError();
+    }
     if (LMA_CONTRACT_DMA && !SPLIT && c.zeros) {
       const int ntp = (c.W * c.H + 7) & ~7;
       const size_t shd = (size_t)ntp * (16 * sizeof(float2) + sizeof(int32_t));

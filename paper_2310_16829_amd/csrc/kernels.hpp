@@ -70,6 +70,9 @@ struct Stencil {
   double scale = 1.0;
   double* img = nullptr;             // [ndet][wh][ww]
   const float2* zeros = nullptr;     // 16 zero bytes (copies of absent rows and pixels)
+  // split-BF16 basis: A fragments of the bf16 MFMA, [ceil(nks/4)][64] x 32 bytes (see
+  // k_contract_bf16); null: the FP32 MFMA on converted values
+  const void* abf = nullptr;
 };
 // largest K-step count and translate rectangle the MFMA contraction accepts
 constexpr int kStencilMaxKs = 96;

@@ -218,6 +218,29 @@ def test_mfma_contraction_k_steps(tiny, L, ks_template):
             assert rel_l2(a[r], b[r]) < 1e-5
 
 
+@pytest.mark.parametrize("L", [4, 25, 60, 100, 150])
+def test_split_bf16_contraction_k_steps(tiny, L):
+    # the split-BF16 basis on the bf16 MFMA (groups of 4 K-steps, K-step counts that are not
+    # multiples of 4, every register capacity up to 80 K-steps, the FP32-MFMA fallback past 80)
+    # against the FP32 basis on the same propagation, and against the oracle at the split-BF16
+    # tolerance
+    say(f"tiny, L = {L}: split-BF16 contraction")
+    w = tiny["w"]
+    plan, st, ol = build(w, L=L)
+    bplan, _, _ = build(w, L=L, precision=lma.LMA_GEMM_SPLIT_BF16)
+    plan.propagate(tiny["v"])
+    bplan.propagate(tiny["v"])
+    a, b = plan.probe_image(), bplan.probe_image()
+    for r in range(a.shape[0]):
+        if np.mean(a[r]) >= RESOLVABLE:
+            e = rel_l2(b[r], a[r])
+            say(f"  ring {r}: split vs FP32 rel L2 {e:.2e}")
+            assert e < 1e-5
+    image_errors(b, LMA(st, ol).image(tiny["v"], basis=tiny["basis"]), TOL_BF16)
+    plan.close()
+    bplan.close()
+
+
 def test_case2_three_sets_per_axis():
     # P = 3 R_f: nine coefficient sets; 3 does not divide the 4 x 4 sub-blocks of the MFMA
     # contraction, so the window uses the per-pixel kernel
