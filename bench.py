@@ -207,8 +207,9 @@ def window_study(w):
 
 # ------------------------------------------------------------------------------------------
 FP32_MFMA_PEAK_TFLOPS = 157.3
+BF16_MFMA_PEAK_TFLOPS = 2500.0   # dense
 
-KERNEL_NAMES = (("k_contract_mfma2_dma", "contract_mfma"), ("k_contract_mfma2", "contract_mfma"), ("k_contract_mfma", "contract_mfma"), ("k_contract", "contract"),
+KERNEL_NAMES = (("k_contract_bf16", "contract_bf16"), ("k_contract_mfma2_dma", "contract_mfma"), ("k_contract_mfma2", "contract_mfma"), ("k_contract_mfma", "contract_mfma"), ("k_contract", "contract"),
                 ("k_transmission", "transmission"), ("k_scale_out", "scale_out"), ("k_embed", "embed"),
                 ("k_intensity", "intensity"))
 PASS_MODES = {"0": "row_pass", "1": "col_pass", "2": "init", "3": "col_gather", "4": "col_reduce", "5": "row_pass",
@@ -538,11 +539,13 @@ def uneven(n_specimens=64):
         "max_rel_diff_vs_eager": {"batch_graph": err_batch, "tuned_batch_graph": err_tuned}}), flush=True)
 
 
-def contraction_roofline(plan, info, kt):
+def contraction_roofline(plan, info, kt, split=False):
     """Flop rate of the contraction launch. Algorithmic: 8 real flops per complex multiply-add,
     |P| L D of them. Implemented (MFMA kernel): every 4 x 4-probe sub-block multiplies a 16 x K
     coefficient block (K = contract_k translates, zero where a translate is not a neighbour)
-    into 16-pixel slabs of each detector-pixel chunk, four real 16x16x4 products per K-step of 4."""
+    into 16-pixel slabs of each detector-pixel chunk: FP32, four real 16x16x4 products per K-step
+    of 4 translates; split BF16 (K up to 320), twelve bf16 16x16x16 products per 16 translates,
+    against the dense bf16 MFMA peak."""
     name = "contract_mfma" if info.contract_kernel else "contract"
     if name not in kt:
         return None
@@ -566,10 +569,16 @@ def contraction_roofline(plan, info, kt):
     if info.contract_kernel:
         ww, wh = plan.window[2], plan.window[3]
         sub_blocks = 4 * (-(-ww // 8)) * (-(-wh // 8))
-        impl = sub_blocks * slabs * (info.contract_k // 4) * 4 * (2 * 16 * 16 * 4)
-        out.update({"bound": "mfma", "implemented_tflop": impl / 1e12,
-                    "achieved": impl / avg_s / 1e12, "peak": FP32_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
-                    "frac": impl / avg_s / 1e12 / FP32_MFMA_PEAK_TFLOPS, "density": info.L / info.contract_k})
+        nks = info.contract_k // 4
+        if split and nks <= 80:
+            impl = sub_blocks * slabs * (-(-nks // 4)) * 12 * (2 * 16 * 16 * 16)
+            peak, dt = BF16_MFMA_PEAK_TFLOPS, "bf16"
+        else:
+            impl = sub_blocks * slabs * nks * 4 * (2 * 16 * 16 * 4)
+            peak, dt = FP32_MFMA_PEAK_TFLOPS, "f32"
+        out.update({"bound": "mfma", "mfma_dtype": dt, "implemented_tflop": impl / 1e12,
+                    "achieved": impl / avg_s / 1e12, "peak": peak, "unit": "TFLOP/s",
+                    "frac": impl / avg_s / 1e12 / peak, "density": info.L / info.contract_k})
     return out
 
 
@@ -716,6 +725,28 @@ def main():
     achieved = bytes_per_launch / avg_s / 1e9
     traffic = load_traffic(dom)
     contraction = contraction_roofline(plan, info, kt)
+    # the precision mode: the same configuration with the basis stored as split BF16 and the
+    # contraction on the bf16 MFMA (propagation untimed), its launch time and its image error
+    # against the FP32 basis
+    split = None
+    if not args.no_kernel_timing:
+        ref = torch.zeros_like(img)
+        plan.propagate(pots[0])
+        plan.probe_image(ref)
+        slat = lma.lattice(w.scan[0], w.scan[1], R[0], R[1], 1, w.offset_frac, w.L, lma.LMA_GEMM_SPLIT_BF16,
+                           batch=args.batch)
+        with lma.Plan(opt, slat, lma.detectors(rings)) as sp:
+            simg = torch.zeros_like(img)
+            sp.propagate(pots[0])
+            sp.probe_image(simg)
+            sp.set_timing(True)
+            for _ in range(3):
+                sp.probe_image(simg)
+            skt = sp.timing(reset=True)
+            split = contraction_roofline(sp, sp.info(), skt, split=True)
+        r, s_ = ref.cpu().numpy(), simg.cpu().numpy()
+        split["image_rel_l2_vs_fp32_basis"] = [float(np.linalg.norm(s_[i] - r[i]) / np.linalg.norm(r[i]))
+                                               for i in range(r.shape[0])]
     out = {
         "metric": "STEM pixels/s, LMA vs plain multislice, same GPU at <=1e-4 rel err; p99 latency",
         "value": value,
@@ -746,6 +777,7 @@ def main():
                      "algorithmic_bytes_per_launch": bytes_per_launch,
                      "avg_launch_ms": avg_s * 1e3},
         "contraction": contraction,
+        "contraction_split_bf16": split,
         "plan_build_s": t_build,
     }
     if not args.no_cpu_baseline:

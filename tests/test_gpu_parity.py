@@ -218,6 +218,14 @@ def test_mfma_contraction_k_steps(tiny, L, ks_template):
             assert rel_l2(a[r], b[r]) < 1e-5
 
 
+# Split BF16 against the FP32 basis: bf16 rounds to nearest with an 8-bit significand, so
+# x = hi + lo leaves at most 2^-16 |x|, and the three products drop lo_a lo_b, another 2^-16 |a b|:
+# at most 3 * 2^-16 relative per complex product, 6 * 2^-16 once the amplitude is squared. That
+# bounds the sum over translates relative to sum |c_l| |u_l|; the tiny workload's coefficient sums
+# cancel little (the nearest translate dominates), so the bound is applied to the image itself.
+SPLIT_VS_FP32 = 6 * 2.0 ** -16
+
+
 @pytest.mark.parametrize("L", [4, 25, 60, 100, 150])
 def test_split_bf16_contraction_k_steps(tiny, L):
     # the split-BF16 basis on the bf16 MFMA (groups of 4 K-steps, K-step counts that are not
@@ -235,7 +243,7 @@ def test_split_bf16_contraction_k_steps(tiny, L):
         if np.mean(a[r]) >= RESOLVABLE:
             e = rel_l2(b[r], a[r])
             say(f"  ring {r}: split vs FP32 rel L2 {e:.2e}")
-            assert e < 1e-5
+            assert e < SPLIT_VS_FP32
     image_errors(b, LMA(st, ol).image(tiny["v"], basis=tiny["basis"]), TOL_BF16)
     plan.close()
     bplan.close()
