@@ -75,17 +75,37 @@ def _oracle_init(spec):
                             [(a * 1e-3, b * 1e-3) for _, a, b in w.detectors])
 
 
-def cpu_baseline(w, n_translates, n_probes):
+def sample_translates(w, plan, n):
+    """n translates spread over the plan's rows: (row, exact position) from the oracle's lattice."""
+    import numpy as np
+    from oracle.lma import Lattice
+    if not hasattr(_oracle_wave, "st"):
+        _oracle_init(WORKLOAD)
+    R = (w.nx // w.basis_px, w.ny // w.basis_px)
+    ol = Lattice(_oracle_wave.st, R, 1, w.offset_frac, w.L)
+    rows = plan.rows()
+    pick = np.linspace(0, len(rows) - 1, n).round().astype(int)
+    return [(int(r), tuple(float(c) for c in ol.translate_position(int(rows[r]) % ol.Rfx, int(rows[r]) // ol.Rfx)))
+            for r in pick]
+
+
+def cpu_baseline(w, n_translates, n_probes, plan=None):
     """Times the oracle on a sample (waves propagated in parallel, one process per core, then
     the per-probe combination and detector sums) and scales to one full image of one phonon
-    configuration: T = |I_f| t_wave + |P| t_probe."""
+    configuration: T = |I_f| t_wave + |P| t_probe. The sample waves are translates of the plan's
+    lattice: with `plan` holding the basis of phonon configuration 0, their exit waves at the
+    detector pixels are also compared with the GPU's (relative L2 per translate)."""
     import numpy as np
     from concurrent.futures import ProcessPoolExecutor
     from oracle import physics as ph
     cores = max(1, min(16, len(os.sched_getaffinity(0))))
     n_waves = cores
-    rng = np.random.default_rng(0)
-    positions = [(float(x), float(y)) for x, y in rng.uniform(0, w.lx, size=(n_waves, 2))]
+    if plan is not None:
+        sample = sample_translates(w, plan, n_waves)
+        positions = [p for _, p in sample]
+    else:
+        rng = np.random.default_rng(0)
+        positions = [(float(x), float(y)) for x, y in rng.uniform(0, w.lx, size=(n_waves, 2))]
     with ProcessPoolExecutor(cores, initializer=_oracle_init, initargs=(WORKLOAD,)) as ex:
         list(ex.map(_oracle_wave, positions[:cores]))          # start-up and potential generation
         t0 = time.perf_counter()
@@ -93,7 +113,8 @@ def cpu_baseline(w, n_translates, n_probes):
         t_waves = time.perf_counter() - t0
     t_wave = t_waves / n_waves                                  # wall time per wave at `cores` workers
     # combination of L translates and the detector sums for a few probes (single process)
-    _oracle_init(WORKLOAD)
+    if not hasattr(_oracle_wave, "st"):
+        _oracle_init(WORKLOAD)
     st = _oracle_wave.st
     n_p = 2
     t0 = time.perf_counter()
@@ -105,6 +126,14 @@ def cpu_baseline(w, n_translates, n_probes):
     t_probe = (time.perf_counter() - t0) / n_p / cores          # probes spread over the same cores
     t_image = n_translates * t_wave + n_probes * t_probe
     t_plain = n_probes * t_wave
+    errors = None
+    if plan is not None:
+        flat, _ = plan.detector_pixels()
+        errors = []
+        for (r, _), ref in zip(sample, spectra):
+            ref = ref.ravel()[flat]
+            got = plan.basis_rows(r, 1)[0]
+            errors.append(float(np.linalg.norm(got - ref) / np.linalg.norm(ref)))
     return {
         "value": n_probes / t_image, "unit": "STEM pixels/s", "cores": cores, "kind": "oracle",
         "plain_value": n_probes / t_plain,
@@ -112,6 +141,7 @@ def cpu_baseline(w, n_translates, n_probes):
                    f"{cores} processes ({t_wave:.3f} s wall per wave) plus {n_p} probe combinations of "
                    f"L={w.L} translates ({t_probe * cores:.3f} s each); scaled to one phonon image: "
                    f"{n_translates} translates + {n_probes} probes"),
+        "exit_wave_rel_l2_vs_oracle": errors,
     }
 
 
@@ -782,7 +812,14 @@ def main():
     }
     if not args.no_cpu_baseline:
         log("bench: oracle CPU baseline")
-        out["cpu_baseline"] = cpu_baseline(w, n_waves, n_probes)
+        if split is None:
+            plan.propagate(pots[0])
+        torch.cuda.synchronize()
+        out["cpu_baseline"] = cpu_baseline(w, n_waves, n_probes, plan)
+        e = out["cpu_baseline"]["exit_wave_rel_l2_vs_oracle"]
+        out["error_vs_oracle"] = {"exit_wave_rel_l2_max": max(e), "translates": len(e),
+                                  "what": "FP32 GPU exit waves at the detector pixels against the FP64 oracle, "
+                                          "phonon configuration 0, translates spread over the lattice"}
     plan.close()
     print(json.dumps(out), flush=True)
 
