@@ -743,14 +743,23 @@ def main():
         plain = {"value": n_probes * K / pel, "ms_per_step": 1e3 * pel / K,
                  "p50_ms": float(np.percentile(plat_ms, 50)), "p99_ms": float(np.percentile(plat_ms, 99))}
     # roofline of the dominant kernel: a slice pass reads and writes every pixel of every wave
-    # of its launch once (16 B per pixel per wave) and reads one 8 B/pixel table
+    # of its launch once (16 B per pixel per wave) and reads one 8 B/pixel table, except in the
+    # band gap (kx columns that the band-limited propagator zeroes): column passes skip its tile
+    # columns, row passes write none of it and read none of it after the first slice
     dom = max(("row_pass", "col_pass"), key=lambda k: kt.get(k, (0, 0.0))[1])
     launches, total_ms = kt.get(dom, (1, float("nan")))
     XY = w.nx * w.ny
     n_waves = info.n_rows
     batches = -(-n_waves // info.batch)
     waves_per_launch = n_waves / batches
-    bytes_per_launch = waves_per_launch * XY * 16 + XY * 8
+    tw = info.tile_width
+    gap_tiles = max(0, info.gap_hi // tw - (-(-info.gap_lo // tw)))
+    kept = 1.0 - gap_tiles * tw / w.nx
+    if dom == "row_pass":
+        read = ((w.nslices - 1) * kept + 1.0) / w.nslices
+        bytes_per_launch = waves_per_launch * XY * 8 * (read + kept) + XY * 8
+    else:
+        bytes_per_launch = (waves_per_launch * XY * 16 + XY * 8) * kept
     avg_s = total_ms / launches * 1e-3
     achieved = bytes_per_launch / avg_s / 1e9
     traffic = load_traffic(dom)
@@ -805,6 +814,7 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic,
                      "algorithmic_bytes_per_launch": bytes_per_launch,
+                     "band_gap_columns": [info.gap_lo, info.gap_hi], "kept_fraction": kept,
                      "avg_launch_ms": avg_s * 1e3},
         "contraction": contraction,
         "contraction_split_bf16": split,

@@ -147,6 +147,11 @@ typedef struct {
   int32_t tile_width;        /* waves are stored in tile_width^2-pixel tiles          */
   int32_t graphs;            /* wave sequences captured as HIP graphs so far          */
   int32_t prop_nx, prop_ny;  /* translate window (0, 0: the whole cell)              */
+  int32_t gap_lo, gap_hi;    /* kx columns [gap_lo, gap_hi) where the propagator with  */
+                             /* its band limit (Fig. multislice_pseudocode) vanishes  */
+                             /* for every ky and no detector pixel lies: waves are    */
+                             /* exactly zero there after every propagator multiply,   */
+                             /* and the slice passes skip the tile columns inside it  */
 } lma_info;
 
 /* Result of lma_autotune for one grid. */

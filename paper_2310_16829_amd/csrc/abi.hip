@@ -71,6 +71,7 @@ struct lma_plan {
   float2* d_wwork = nullptr;         // [B][window tiles]
   int32_t* d_compT = nullptr;
   uint32_t* d_maskT = nullptr;
+  int zc0 = 0, zc1 = 0;              // kx columns zero after every column pass (band gap)
   int32_t *d_row_of = nullptr, *d_set_dx = nullptr, *d_set_dy = nullptr;
   int32_t *d_chunk_start = nullptr, *d_chunk_len = nullptr;
   uint32_t* d_chunk_mask = nullptr;
@@ -180,6 +181,8 @@ lma::dev::Tables tables(const lma_plan* p) {
   t.twy = p->d_twy;
   t.compT = p->d_compT;
   t.maskT = p->d_maskT;
+  t.zc0 = p->zc0;
+  t.zc1 = p->zc1;
   return t;
 }
 
@@ -345,7 +348,7 @@ lma_status run_waves(lma_plan* p, const int64_t* d_u, const int32_t* d_row, cons
     if (d_row && !probes) Ti.specT = p->d_uspecT;
     LAUNCH(p, "init", lma::dev::init_waves(Ti, p->d_work, d_u + 2 * (int64_t)first, nb, p->stream));
     for (int j = 0; j < nslices; ++j) {
-      LAUNCH(p, "row_pass", lma::dev::row_pass(T, p->d_work, p->d_trans + (size_t)j * XY, nb, p->stream));
+      LAUNCH(p, "row_pass", lma::dev::row_pass(T, p->d_work, p->d_trans + (size_t)j * XY, nb, j > 0, p->stream));
       if (j + 1 < nslices) {
         LAUNCH(p, "col_pass", lma::dev::col_pass(T, p->d_work, nb, p->stream));
       } else if (d_row) {
@@ -702,6 +705,27 @@ lma_status lma_build_basis(const lma_optics* optics, const lma_lattice* lattice,
         maskT[(size_t)x * ny + y] = h.detmask[(size_t)y * nx + x];
       }
     if ((s = upload(p, &p->d_compT, compT.data(), compT.size())) != LMA_OK) { release(p); return s; }
+    // the band gap: the longest run of kx columns where the propagator table (as uploaded) is
+    // exactly zero and no detector pixel lies; a column pass leaves exact zeros there
+    {
+      int best0 = 0, best1 = 0;
+      for (int x = 0; x < nx;) {
+        auto zero_col = [&](int c) {
+          for (int y = 0; y < ny; ++y) {
+            const float2 q = v[(size_t)c * ny + y];
+            if (q.x != 0.f || q.y != 0.f || compT[(size_t)c * ny + y] >= 0) return false;
+          }
+          return true;
+        };
+        if (!zero_col(x)) { ++x; continue; }
+        int e = x;
+        while (e < nx && zero_col(e)) ++e;
+        if (e - x > best1 - best0) { best0 = x; best1 = e; }
+        x = e;
+      }
+      p->zc0 = best0;
+      p->zc1 = best1;
+    }
     if ((s = upload(p, &p->d_maskT, maskT.data(), maskT.size())) != LMA_OK) { release(p); return s; }
     if ((s = upload(p, &p->d_row_of, h.row_of.data(), h.row_of.size())) != LMA_OK) { release(p); return s; }
     if ((s = upload(p, &p->d_set_dx, h.set_dx.data(), h.set_dx.size())) != LMA_OK) { release(p); return s; }
@@ -1160,6 +1184,8 @@ lma_status lma_plan_info(const lma_plan* p, lma_info* out) {
   out->tile_width = p->tw;
   out->graphs = p->n_captured;
   out->prop_nx = p->h.wnx;
+  out->gap_lo = p->zc0;
+  out->gap_hi = p->zc1;
   out->prop_ny = p->h.wny;
   return LMA_OK;
 }
@@ -1354,11 +1380,11 @@ lma_status measure_tuning(int nx, int ny, int64_t max_bytes, hipStream_t st, lma
       T.twx = twx;
       T.twy = twy;
       const int reps = 3;
-      e = lma::dev::row_pass(T, work, trans, B, st);                 // warm-up
+      e = lma::dev::row_pass(T, work, trans, B, true, st);           // warm-up
       if (e == hipSuccess) e = lma::dev::col_pass(T, work, B, st);
       if (e == hipSuccess) e = hipEventRecord(ea, st);
       for (int r = 0; r < reps && e == hipSuccess; ++r) {
-        e = lma::dev::row_pass(T, work, trans, B, st);
+        e = lma::dev::row_pass(T, work, trans, B, true, st);
         if (e == hipSuccess) e = lma::dev::col_pass(T, work, B, st);
       }
       if (e == hipSuccess) e = hipEventRecord(eb, st);

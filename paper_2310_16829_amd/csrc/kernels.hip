@@ -372,6 +372,8 @@ struct PassArgs {
   double scale;
   int tnx, tny;              // ROW_WIN / ROW_LAST: the cell (table [tny][tnx]); window origin
   int hx, hy;                //   of wave w: its position in pixels minus (hx, hy)
+  int zlo, zhi;              // tile columns [zlo, zhi) stay zero between passes (kx band gap)
+  int zread;                 // ROW: the input comes from a column pass; skip reading the gap
 };
 
 __device__ __forceinline__ void split_bf16(float x, __hip_bfloat16& hi, __hip_bfloat16& lo) {
@@ -507,10 +509,27 @@ __attribute__((amdgpu_waves_per_eu(fft_odd(N) == 5 ? 2 : 1, 8))) void k_pass(Pas
   const int j = C::WL ? lane % T : tid % T;                // thread within the transform
   const int tslot = C::WL ? (tid >> 6) * S + sub : tid / T;  // transform slot within the block
   const bool active = !C::WL || sub < S;
-  const int ngroups = (ROWS ? a.ny : a.nx) / TW;
+  // column passes after the first skip the tile columns of the band gap: item group g' maps
+  // to tile column g' below the gap and g' + (zhi - zlo) above it
+  constexpr bool kGapItems = MODE == PASS_COL || MODE == PASS_GATHER || MODE == PASS_REDUCE;
+  const int gap = kGapItems ? a.zhi - a.zlo : 0;
+  const int ngroups = (ROWS ? a.ny : a.nx) / TW - gap;
   const int B = a.B;
   const int ntx = a.nx / TW;
   const ItemWalk walk(B * ngroups);
+  auto group_of = [&](int l) -> int {
+    const int gg = l / B;
+    return (kGapItems && gg >= a.zlo) ? gg + gap : gg;
+  };
+  // row passes: tile q of a row item lies in the gap
+  auto in_gap = [&](int c) -> bool {
+    if constexpr (MODE == PASS_ROW) {
+      const int q = c / (TW * TW);
+      return q >= a.zlo && q < a.zhi;
+    } else {
+      return false;
+    }
+  };
 
   float2 tw[C::NTW];
   tw_load<N>(tw, a.tw, j);
@@ -518,7 +537,7 @@ __attribute__((amdgpu_waves_per_eu(fft_odd(N) == 5 ? 2 : 1, 8))) void k_pass(Pas
   using M = TileMap<N, TW, ROWS>;
   const int stride_q = ntx * M::TT;                        // column items: tile-to-tile stride
   auto item_ptr = [&](int l) -> float2* {
-    const int g = l / B, w = l % B;
+    const int g = group_of(l), w = l % B;
     return a.work + (size_t)w * a.nx * a.ny + M::item_base(g, a.nx);
   };
   [[maybe_unused]] float2 buf[PREF ? EPT : 1];
@@ -534,14 +553,14 @@ __attribute__((amdgpu_waves_per_eu(fft_odd(N) == 5 ? 2 : 1, 8))) void k_pass(Pas
       for (int k = 0; k < EPT; ++k) {
         int lds, off;
         M::at(k * NT + tid, stride_q, lds, off);
-        buf[k] = load_item_elem(r, off);
+        buf[k] = (a.zread && in_gap(k * NT + tid)) ? make_float2(0.f, 0.f) : load_item_elem(r, off);
       }
     } else {
 #pragma unroll
       for (int k = 0; k < EPT; ++k) {
         int lds, off;
         M::at(k * NT + tid, stride_q, lds, off);
-        buf[k] = load_stream(src + off);
+        buf[k] = (a.zread && in_gap(k * NT + tid)) ? make_float2(0.f, 0.f) : load_stream(src + off);
       }
     }
     memory_phase_end();
@@ -552,7 +571,7 @@ __attribute__((amdgpu_waves_per_eu(fft_odd(N) == 5 ? 2 : 1, 8))) void k_pass(Pas
 
 #pragma unroll 1
   for (int l = walk.l; walk.valid(l); l += walk.step) {
-    const int g = l / B, w = l % B;
+    const int g = group_of(l), w = l % B;
     float2* item = item_ptr(l);
     __syncthreads();                                       // the previous item is out of LDS
 
@@ -575,7 +594,7 @@ __attribute__((amdgpu_waves_per_eu(fft_odd(N) == 5 ? 2 : 1, 8))) void k_pass(Pas
           for (int k = 0; k < CHUNK; ++k) {
             int lds, off;
             M::at(c0 + k * NT + tid, stride_q, lds, off);
-            st[k] = load_stream(item + off);
+            st[k] = (a.zread && in_gap(c0 + k * NT + tid)) ? make_float2(0.f, 0.f) : load_stream(item + off);
           }
 #pragma unroll
           for (int k = 0; k < CHUNK; ++k) {
@@ -718,14 +737,14 @@ __attribute__((amdgpu_waves_per_eu(fft_odd(N) == 5 ? 2 : 1, 8))) void k_pass(Pas
         for (int k = 0; k < EPT; ++k) {
           int lds, off;
           M::at(k * NT + tid, stride_q, lds, off);
-          store_item_elem(r, off, tile[lds]);
+          if (!in_gap(k * NT + tid)) store_item_elem(r, off, tile[lds]);
         }
       } else {
 #pragma unroll
         for (int k = 0; k < EPT; ++k) {
           int lds, off;
           M::at(k * NT + tid, stride_q, lds, off);
-          store_stream(item + off, tile[lds]);
+          if (!in_gap(k * NT + tid)) store_stream(item + off, tile[lds]);
         }
       }
       memory_phase_end();
@@ -1000,7 +1019,10 @@ static hipError_t pass_launch(const PassArgs& a0, int lines, int B, hipStream_t 
   }
   PassArgs a = a0;
   a.B = B;
-  const int64_t items = (int64_t)B * (lines / TW);
+  if (a.zlo < 0 || a.zhi < a.zlo || a.zhi > a.nx / TW) return hipErrorInvalidValue;
+  constexpr bool kGapItems = MODE == PASS_COL || MODE == PASS_GATHER || MODE == PASS_REDUCE;
+  const int64_t items = (int64_t)B * (lines / TW - (kGapItems ? a.zhi - a.zlo : 0));
+  if (items <= 0) return hipSuccess;
   int64_t grid = std::min<int64_t>(items, (int64_t)resident * device_cus());
   if (grid >= 8) grid &= ~(int64_t)7;
   k_pass<N, TW, MODE><<<(unsigned)grid, threads, 0, s>>>(a);
@@ -1081,19 +1103,28 @@ static PassArgs pass_args(const Tables& T, float2* work) {
   a.ny = T.ny;
   a.Qx = T.Qx;
   a.Qy = T.Qy;
+  // tile columns wholly inside the band gap
+  const int tw = tw_of(T);
+  const int lo = (T.zc0 + tw - 1) / tw, hi = T.zc1 / tw;
+  if (T.zc0 >= 0 && T.zc1 <= T.nx && hi > lo) {
+    a.zlo = lo;
+    a.zhi = hi;
+  }
   return a;
 }
 
 hipError_t init_waves(const Tables& T, float2* work, const int64_t* wave_u, int B, hipStream_t s) {
   PassArgs a = pass_args(T, work);
+  a.zlo = a.zhi = 0;                 // the input wave need not vanish in the gap
   a.table = T.specT;
   a.tw = T.twy;
   a.wave_u = wave_u;
   return pass_dispatch<PASS_INIT>(T.ny, tw_of(T), T.nx, a, B, s);
 }
 
-hipError_t row_pass(const Tables& T, float2* work, const float2* trans_j, int B, hipStream_t s) {
+hipError_t row_pass(const Tables& T, float2* work, const float2* trans_j, int B, bool after_column, hipStream_t s) {
   PassArgs a = pass_args(T, work);
+  a.zread = after_column ? 1 : 0;
   a.table = trans_j;
   a.tw = T.twx;
   return pass_dispatch<PASS_ROW>(T.nx, tw_of(T), T.ny, a, B, s);
@@ -1102,6 +1133,7 @@ hipError_t row_pass(const Tables& T, float2* work, const float2* trans_j, int B,
 hipError_t row_pass_window(const Tables& Tw, float2* work, const float2* trans_j, int cell_nx, int cell_ny,
                            const int64_t* wave_u, int64_t Qx, int64_t Qy, bool last, int B, hipStream_t s) {
   PassArgs a = pass_args(Tw, work);
+  a.zlo = a.zhi = 0;
   a.table = trans_j;
   a.tw = Tw.twx;
   a.wave_u = wave_u;

@@ -18,6 +18,11 @@ struct Tables {
   const float2* twy = nullptr;       // exp(-2 pi i t / ny)            [ny]
   const int32_t* compT = nullptr;    // frequency -> detector pixel or -1 [nx][ny]
   const uint32_t* maskT = nullptr;   // ring bits per frequency        [nx][ny]
+  // kx columns [zc0, zc1) are zero after every column pass: the band-limited propagator
+  // vanishes on all of them and they hold no detector pixel. Column passes skip the tile
+  // columns inside the range; row passes write only the others, and read only the others
+  // when their input comes from a column pass.
+  int zc0 = 0, zc1 = 0;
 };
 
 struct Contraction {
@@ -91,7 +96,9 @@ bool tile_width_ok(int nx, int ny, int tw);
 // initial waves u(. - pos_w): column IFFT of spectrum * modulation
 hipError_t init_waves(const Tables& T, float2* work, const int64_t* wave_u, int B, hipStream_t s);
 // row pass of slice j: row IFFT, * t_j, row FFT
-hipError_t row_pass(const Tables& T, float2* work, const float2* trans_j, int B, hipStream_t s);
+// after_column: the waves come from a column pass (every slice but the first), so their
+// zero kx columns need not be read
+hipError_t row_pass(const Tables& T, float2* work, const float2* trans_j, int B, bool after_column, hipStream_t s);
 // row pass of slice j for waves propagated on windows (Tw: the window's tables): row IFFT,
 // * t_j of the cell at each wave's window (origin: its position in pixels minus half the
 // window), row FFT; with last, no row FFT (the window's wave is left in real space)

@@ -128,6 +128,38 @@ def test_tiny_plain_image(tiny):
     say("  per-detector rel L2", e)
 
 
+def longest_zero_run(zero):
+    best, x, n = (0, 0), 0, len(zero)
+    while x < n:
+        if not zero[x]:
+            x += 1
+            continue
+        e = x
+        while e < n and zero[e]:
+            e += 1
+        if e - x > best[1] - best[0]:
+            best = (x, e)
+        x = e
+    return best
+
+
+@pytest.mark.parametrize("side", [128, 96, 640])
+def test_band_gap_columns(tiny, side):
+    # the kx columns the passes skip: the longest run where the oracle's band-limited
+    # propagator is zero for every ky and no detector ring has a pixel; the parity tests of
+    # this file run with the skip (the tiny grid keeps 12 of its 16 tile columns)
+    w = tiny["w"]
+    lx = w.lx * side / w.nx
+    plan, st, _ = build(w, nx=side, ny=side, lx=lx, ly=lx, scan=(16, 16), R=(16, 16))
+    i = plan.info()
+    zero = np.all(st.prop == 0, axis=0) & ~np.any([m.any(axis=0) for m in st.masks], axis=0)
+    want = longest_zero_run(zero)
+    say(f"  {side}^2: gap {i.gap_lo}..{i.gap_hi} (oracle {want}), tile width {i.tile_width}")
+    assert (i.gap_lo, i.gap_hi) == want
+    assert i.gap_hi // i.tile_width > -(-i.gap_lo // i.tile_width)
+    plan.close()
+
+
 def _pattern_ref(spec, pixels, flat):
     """The oracle's 4-D pattern in the GPU's detector-pixel order (flat indices ``flat``)."""
     full = np.zeros(pixels.size)
