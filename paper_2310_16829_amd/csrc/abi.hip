@@ -72,6 +72,7 @@ struct lma_plan {
   int32_t* d_compT = nullptr;
   uint32_t* d_maskT = nullptr;
   int zc0 = 0, zc1 = 0;              // kx columns zero after every column pass (band gap)
+  int wzc0 = 0, wzc1 = 0;            // the same on the translate windows
   int32_t *d_row_of = nullptr, *d_set_dx = nullptr, *d_set_dy = nullptr;
   int32_t *d_chunk_start = nullptr, *d_chunk_len = nullptr;
   uint32_t* d_chunk_mask = nullptr;
@@ -154,6 +155,29 @@ void free_one(lma_plan* p, void* ptr, size_t bytes) {
   p->dev_bytes -= (int64_t)bytes;
 }
 
+// The band gap of a transposed propagator table propT [nx][ny] (as uploaded): the longest run
+// of kx columns where it is exactly zero for every ky and no detector pixel lies (compT, if
+// given); a column pass leaves exact zeros there.
+void band_gap(const std::vector<float2>& propT, int nx, int ny, const int32_t* compT, int* c0, int* c1) {
+  auto zero_col = [&](int c) {
+    for (int y = 0; y < ny; ++y) {
+      const float2 q = propT[(size_t)c * ny + y];
+      if (q.x != 0.f || q.y != 0.f || (compT && compT[(size_t)c * ny + y] >= 0)) return false;
+    }
+    return true;
+  };
+  int best0 = 0, best1 = 0;
+  for (int x = 0; x < nx;) {
+    if (!zero_col(x)) { ++x; continue; }
+    int e = x;
+    while (e < nx && zero_col(e)) ++e;
+    if (e - x > best1 - best0) { best0 = x; best1 = e; }
+    x = e;
+  }
+  *c0 = best0;
+  *c1 = best1;
+}
+
 lma::dev::Tables window_tables(const lma_plan* p) {
   lma::dev::Tables t;
   t.nx = p->h.wnx;
@@ -165,6 +189,8 @@ lma::dev::Tables window_tables(const lma_plan* p) {
   t.propT = p->d_wpropT;
   t.twx = p->d_wtwx;
   t.twy = p->d_wtwy;
+  t.zc0 = p->wzc0;
+  t.zc1 = p->wzc1;
   return t;
 }
 
@@ -332,7 +358,7 @@ lma_status run_waves(lma_plan* p, const int64_t* d_u, const int32_t* d_row, cons
       for (int j = 0; j < nslices; ++j) {
         const bool last = j + 1 == nslices;
         LAUNCH(p, "row_pass", lma::dev::row_pass_window(Tw, p->d_wwork, p->d_trans + (size_t)j * XY, T.nx, T.ny, u,
-                                                        T.Qx, T.Qy, last, nb, p->stream));
+                                                        T.Qx, T.Qy, last, j > 0, nb, p->stream));
         if (!last) LAUNCH(p, "col_pass", lma::dev::col_pass(Tw, p->d_wwork, nb, p->stream));
       }
       LAUNCH(p, "embed", lma::dev::embed_windows(T, p->d_work, Tw, p->d_wwork, u, nb, p->stream));
@@ -690,6 +716,7 @@ lma_status lma_build_basis(const lma_optics* optics, const lma_lattice* lattice,
       if ((s = upload(p, &p->d_wspecT, wv.data(), wv.size())) != LMA_OK) { release(p); return s; }
       wT(h.wprop, 1.0);
       if ((s = upload(p, &p->d_wpropT, wv.data(), wv.size())) != LMA_OK) { release(p); return s; }
+      band_gap(wv, wx, wy, nullptr, &p->wzc0, &p->wzc1);
       auto wtx = twiddles(wx), wty = twiddles(wy);
       if ((s = upload(p, &p->d_wtwx, wtx.data(), wtx.size())) != LMA_OK) { release(p); return s; }
       if ((s = upload(p, &p->d_wtwy, wty.data(), wty.size())) != LMA_OK) { release(p); return s; }
@@ -705,27 +732,7 @@ lma_status lma_build_basis(const lma_optics* optics, const lma_lattice* lattice,
         maskT[(size_t)x * ny + y] = h.detmask[(size_t)y * nx + x];
       }
     if ((s = upload(p, &p->d_compT, compT.data(), compT.size())) != LMA_OK) { release(p); return s; }
-    // the band gap: the longest run of kx columns where the propagator table (as uploaded) is
-    // exactly zero and no detector pixel lies; a column pass leaves exact zeros there
-    {
-      int best0 = 0, best1 = 0;
-      for (int x = 0; x < nx;) {
-        auto zero_col = [&](int c) {
-          for (int y = 0; y < ny; ++y) {
-            const float2 q = v[(size_t)c * ny + y];
-            if (q.x != 0.f || q.y != 0.f || compT[(size_t)c * ny + y] >= 0) return false;
-          }
-          return true;
-        };
-        if (!zero_col(x)) { ++x; continue; }
-        int e = x;
-        while (e < nx && zero_col(e)) ++e;
-        if (e - x > best1 - best0) { best0 = x; best1 = e; }
-        x = e;
-      }
-      p->zc0 = best0;
-      p->zc1 = best1;
-    }
+    band_gap(v, nx, ny, compT.data(), &p->zc0, &p->zc1);
     if ((s = upload(p, &p->d_maskT, maskT.data(), maskT.size())) != LMA_OK) { release(p); return s; }
     if ((s = upload(p, &p->d_row_of, h.row_of.data(), h.row_of.size())) != LMA_OK) { release(p); return s; }
     if ((s = upload(p, &p->d_set_dx, h.set_dx.data(), h.set_dx.size())) != LMA_OK) { release(p); return s; }

@@ -521,15 +521,18 @@ __attribute__((amdgpu_waves_per_eu(fft_odd(N) == 5 ? 2 : 1, 8))) void k_pass(Pas
     const int gg = l / B;
     return (kGapItems && gg >= a.zlo) ? gg + gap : gg;
   };
-  // row passes: tile q of a row item lies in the gap
+  // row passes: tile q of a row item lies in the gap. Every row pass may skip reading it
+  // (zread: its input comes from a column pass); those whose output goes to a column pass
+  // skip writing it (not PASS_ROW_LAST, which leaves its wave in real space).
   auto in_gap = [&](int c) -> bool {
-    if constexpr (MODE == PASS_ROW) {
+    if constexpr (ROWS) {
       const int q = c / (TW * TW);
       return q >= a.zlo && q < a.zhi;
     } else {
       return false;
     }
   };
+  constexpr bool kGapStores = MODE == PASS_ROW || MODE == PASS_ROW_WIN;
 
   float2 tw[C::NTW];
   tw_load<N>(tw, a.tw, j);
@@ -737,14 +740,14 @@ __attribute__((amdgpu_waves_per_eu(fft_odd(N) == 5 ? 2 : 1, 8))) void k_pass(Pas
         for (int k = 0; k < EPT; ++k) {
           int lds, off;
           M::at(k * NT + tid, stride_q, lds, off);
-          if (!in_gap(k * NT + tid)) store_item_elem(r, off, tile[lds]);
+          if (!kGapStores || !in_gap(k * NT + tid)) store_item_elem(r, off, tile[lds]);
         }
       } else {
 #pragma unroll
         for (int k = 0; k < EPT; ++k) {
           int lds, off;
           M::at(k * NT + tid, stride_q, lds, off);
-          if (!in_gap(k * NT + tid)) store_stream(item + off, tile[lds]);
+          if (!kGapStores || !in_gap(k * NT + tid)) store_stream(item + off, tile[lds]);
         }
       }
       memory_phase_end();
@@ -1131,9 +1134,10 @@ hipError_t row_pass(const Tables& T, float2* work, const float2* trans_j, int B,
 }
 
 hipError_t row_pass_window(const Tables& Tw, float2* work, const float2* trans_j, int cell_nx, int cell_ny,
-                           const int64_t* wave_u, int64_t Qx, int64_t Qy, bool last, int B, hipStream_t s) {
+                           const int64_t* wave_u, int64_t Qx, int64_t Qy, bool last, bool after_column, int B,
+                           hipStream_t s) {
   PassArgs a = pass_args(Tw, work);
-  a.zlo = a.zhi = 0;
+  a.zread = after_column ? 1 : 0;
   a.table = trans_j;
   a.tw = Tw.twx;
   a.wave_u = wave_u;

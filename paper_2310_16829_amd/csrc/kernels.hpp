@@ -103,7 +103,8 @@ hipError_t row_pass(const Tables& T, float2* work, const float2* trans_j, int B,
 // * t_j of the cell at each wave's window (origin: its position in pixels minus half the
 // window), row FFT; with last, no row FFT (the window's wave is left in real space)
 hipError_t row_pass_window(const Tables& Tw, float2* work, const float2* trans_j, int cell_nx, int cell_ny,
-                           const int64_t* wave_u, int64_t Qx, int64_t Qy, bool last, int B, hipStream_t s);
+                           const int64_t* wave_u, int64_t Qx, int64_t Qy, bool last, bool after_column, int B,
+                           hipStream_t s);
 // places each window's real-space wave in the cell (zero elsewhere) and row-transforms it
 // on the cell's grid (T: the cell's tables, work: the cell's wave batch)
 hipError_t embed_windows(const Tables& T, float2* work, const Tables& Tw, const float2* win, const int64_t* wave_u,
