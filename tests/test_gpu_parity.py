@@ -33,11 +33,12 @@ def say(*a):
 
 def build(w, L=None, scan=None, R=None, f=1, offset=None, window=(0, 0, 0, 0), precision=0, batch=0, nx=None,
           ny=None, lx=None, ly=None, detectors=None, budget=0, basis_kind=0, basis_param=0.0, flags=0,
-          prop_window=(0, 0)):
+          prop_window=(0, 0), bandlimit=None):
     lam, sig = lma.electron_constants(w.kv)
     nx, ny = nx or w.nx, ny or w.ny
     lx, ly = lx or w.lx, ly or w.ly
-    opt = lma.optics(nx, ny, lx, ly, lam, sig, w.dz, w.bandlimit, w.alpha_mrad * 1e-3, w.defocus, w.cs)
+    bandlimit = bandlimit or w.bandlimit
+    opt = lma.optics(nx, ny, lx, ly, lam, sig, w.dz, bandlimit, w.alpha_mrad * 1e-3, w.defocus, w.cs)
     scan = scan or w.scan
     if R is None:
         R = (nx // w.basis_px * f, ny // w.basis_px * f)
@@ -47,7 +48,7 @@ def build(w, L=None, scan=None, R=None, f=1, offset=None, window=(0, 0, 0, 0), p
     lat = lma.lattice(scan[0], scan[1], R[0], R[1], f, offset, L, precision, window, batch, hbm_budget_bytes=budget,
                       basis_kind=basis_kind, basis_param=basis_param, prop_window=prop_window)
     plan = lma.Plan(opt, lat, lma.detectors(rings), flags=flags)
-    st = Setup(nx, ny, lx, ly, lam, sig, w.dz, w.bandlimit, w.alpha_mrad * 1e-3, w.defocus, w.cs, scan, rings)
+    st = Setup(nx, ny, lx, ly, lam, sig, w.dz, bandlimit, w.alpha_mrad * 1e-3, w.defocus, w.cs, scan, rings)
     ol = Lattice(st, R, f, offset, L)
     return plan, st, ol
 
@@ -157,6 +158,38 @@ def test_band_gap_columns(tiny, side):
     say(f"  {side}^2: gap {i.gap_lo}..{i.gap_hi} (oracle {want}), tile width {i.tile_width}")
     assert (i.gap_lo, i.gap_hi) == want
     assert i.gap_hi // i.tile_width > -(-i.gap_lo // i.tile_width)
+    plan.close()
+
+
+@pytest.mark.parametrize("bandlimit", [1.0, 0.3])
+def test_band_gap_extremes(tiny, bandlimit):
+    # band limit at the Nyquist edge: at most the one column kx = -X/2 vanishes, no tile is
+    # skipped; band limit 0.3: kx 20..108 vanish, 10 of the 16 tile columns are skipped. Exit
+    # waves and plain pixels against the oracle with the same band limit.
+    w, v = tiny["w"], tiny["v"]
+    plan, st, ol = build(w, bandlimit=bandlimit, L=16)
+    i = plan.info()
+    skipped = max(0, i.gap_hi // i.tile_width - (-(-i.gap_lo // i.tile_width)))
+    say(f"  band limit {bandlimit}: gap {i.gap_lo}..{i.gap_hi}, {skipped} tile columns skipped")
+    assert skipped == (0 if bandlimit == 1.0 else 10)
+    plan.propagate(v)
+    rows = plan.rows()
+    flat, _ = plan.detector_pixels()
+    pick = [0, len(rows) // 3, len(rows) - 1]
+    ts = [(int(rows[r]) % ol.Rfx, int(rows[r]) // ol.Rfx) for r in pick]
+    ref = LMA(st, ol).propagate(v, ts)
+    got = plan.basis_rows(0, len(rows))
+    for r, t in zip(pick, ts):
+        e = rel_l2(got[r], ref[t].ravel()[flat])
+        say(f"    exit wave of translate {t}: rel L2 {e:.2e}")
+        assert e < TOL32
+    probes = [(0, 0), (7, 11), (15, 15)]
+    pimg = plan.plain_image(v)
+    pref = plain_image(st, v, probes)
+    for a, b in probes:
+        for r in range(pref.shape[0]):
+            want, have = pref[r, b, a], pimg[r, b, a]
+            assert abs(have - want) <= TOL32 * abs(want) + 2e-4 * np.sqrt(abs(want)) + 1e-8, (a, b, r)
     plan.close()
 
 
