@@ -296,6 +296,41 @@ def summarize_counters(fetch_dir, write_dir, cal_fetch_dir, cal_write_dir):
                       "kernels": kernels}, indent=1))
 
 
+def summarize_pmc(run_dirs, n_cu=256):
+    """Per-kernel means per dispatch of every counter in rocprofv3 --pmc runs, with the
+    utilisations they give. SQ_BUSY_CU_CYCLES sums busy cycles over the CUs (256 x the kernel's
+    duration x 2.4 GHz, within a few percent); per SIMD: MFMA busy = SQ_VALU_MFMA_BUSY_CYCLES /
+    (SQ_BUSY_CU_CYCLES x 4 SIMDs); VALU issue = SQ_INSTS_VALU x 4 cycles (a 64-wide wavefront
+    on a 16-lane SIMD) / (SQ_BUSY_CU_CYCLES x 4 SIMDs); MFMA flops = MOPS x 512."""
+    import csv
+    import glob
+    per = {}
+    for d in run_dirs:
+        for path in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            with open(path) as fh:
+                for r in csv.DictReader(fh):
+                    name = _short_name(r["Kernel_Name"])
+                    if name is None:
+                        continue
+                    c = per.setdefault(name, {}).setdefault(r["Counter_Name"], {})
+                    c[r["Dispatch_Id"]] = c.get(r["Dispatch_Id"], 0.0) + float(r["Counter_Value"])
+    out = {}
+    for k, cs in sorted(per.items()):
+        m = {c: sum(v.values()) / len(v) for c, v in cs.items()}
+        m["dispatches"] = max(len(v) for v in cs.values())
+        if "SQ_BUSY_CU_CYCLES" in m:
+            m["busy_us"] = m["SQ_BUSY_CU_CYCLES"] / n_cu / 2.4e3
+            if "SQ_VALU_MFMA_BUSY_CYCLES" in m:
+                m["mfma_busy"] = m["SQ_VALU_MFMA_BUSY_CYCLES"] / (m["SQ_BUSY_CU_CYCLES"] * 4)
+            if "SQ_INSTS_VALU" in m:
+                m["valu_issue"] = m["SQ_INSTS_VALU"] * 4 / (m["SQ_BUSY_CU_CYCLES"] * 4)
+        for dt in ("F32", "BF16"):
+            if f"SQ_INSTS_VALU_MFMA_MOPS_{dt}" in m:
+                m[f"mfma_tflop_{dt.lower()}"] = m[f"SQ_INSTS_VALU_MFMA_MOPS_{dt}"] * 512 / 1e12
+        out[k] = m
+    print(json.dumps({"kernel_source_hash": kernel_source_hash(), "workload": WORKLOAD, "kernels": out}, indent=1))
+
+
 def serve(rates=(2.0, 10.0, 50.0, 200.0), n_requests=60, slots=4):
     """Serving under Poisson arrivals, once with FP32 basis rows and contraction and once with
     the basis stored as split BF16 (hi + lo): see serve_mode."""
@@ -634,11 +669,16 @@ def main():
                     help="LMA with translates propagated on 64, 128, 256 px windows against plain multislice")
     ap.add_argument("--uneven", action="store_true",
                     help="64 specimens of mixed sizes: eager, one batch graph, autotuned plans with graphs")
+    ap.add_argument("--summarize-pmc", nargs="+", metavar="RUN_DIR",
+                    help="per-kernel means and utilisations from rocprofv3 --pmc runs")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device-to-device copy kernel (HBM counter calibration)")
     args = ap.parse_args()
     if args.summarize_counters:
         summarize_counters(*args.summarize_counters)
+        return
+    if args.summarize_pmc:
+        summarize_pmc(args.summarize_pmc)
         return
     if args.copy_calibration:
         import torch
