@@ -503,6 +503,10 @@ __attribute__((amdgpu_waves_per_eu(fft_odd(N) == 5 ? 2 : 1, 8))) void k_pass(Pas
   static_assert(TOTAL % NT == 0, "work item must split evenly over the threads");
   __shared__ float2 tile[(TW + (C::WL ? 1 : 0)) * RS];     // extra line: scratch of idle lanes
   [[maybe_unused]] __shared__ double part[C::WAVES][8];
+  // PASS_INIT: exp(-2 pi i my uy / Qy) at every ky of the item's wave, shared by its lines
+  // (when the LDS has room next to the tile: not for 2048-point lines in 8 x 8 tiles)
+  constexpr bool kYfac = MODE == PASS_INIT && sizeof(tile) + sizeof(part) + (size_t)N * 16 <= 160 * 1024;
+  [[maybe_unused]] __shared__ double2 yfac[kYfac ? N : 1];
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int sub = C::WL ? lane / T : 0;                    // transform within the wavefront
@@ -610,6 +614,19 @@ __attribute__((amdgpu_waves_per_eu(fft_odd(N) == 5 ? 2 : 1, 8))) void k_pass(Pas
       }
     }
 
+    if constexpr (kYfac) {
+      // the translate modulation factors over ky: one FP64 phase per position, reduced exactly
+      // in lattice units (my uy mod Qy), for all the item's lines
+      const int64_t uy = a.wave_u[2 * w + 1];
+      for (int i = tid; i < N; i += NT) {
+        const int64_t ay = (((int64_t)freq_index(i, N) * uy) % a.Qy + a.Qy) % a.Qy;
+        double sn, cs;
+        sincospi(-2.0 * (double)ay / (double)a.Qy, &sn, &cs);
+        yfac[i] = make_double2(cs, sn);
+      }
+      __syncthreads();
+    }
+
     [[maybe_unused]] double acc[8];
     if constexpr (MODE == PASS_REDUCE) {
 #pragma unroll
@@ -624,18 +641,25 @@ __attribute__((amdgpu_waves_per_eu(fft_odd(N) == 5 ? 2 : 1, 8))) void k_pass(Pas
       const float2* tab = a.table + (size_t)line * N;
       float2 v[C::E];
       if constexpr (MODE == PASS_INIT) {
-        // u(. - pos_w): spectrum times exp(-2 pi i (mx ux / Qx + my uy / Qy)), reduced exactly
-        // in lattice units, phase in FP64; lines are kx, positions ky
+        // u(. - pos_w): spectrum times exp(-2 pi i mx ux / Qx) exp(-2 pi i my uy / Qy), each
+        // phase reduced exactly in lattice units and evaluated in FP64, their product in FP64;
+        // lines are kx, positions ky
         const int mx = freq_index(line, a.nx);
-        const int64_t ux = a.wave_u[2 * w], uy = a.wave_u[2 * w + 1];
+        const int64_t ux = a.wave_u[2 * w];
         const int64_t ax = (((int64_t)mx * ux) % a.Qx + a.Qx) % a.Qx;
+        double xs, xc;
+        sincospi(-2.0 * (double)ax / (double)a.Qx, &xs, &xc);
 #pragma unroll
         for (int m = 0; m < C::E; ++m) {
           const int ky = j + T * m;
-          const int my = freq_index(ky, N);
-          const int64_t ay = (((int64_t)my * uy) % a.Qy + a.Qy) % a.Qy;
-          double sn, cs;
-          sincospi(-2.0 * ((double)ax / (double)a.Qx + (double)ay / (double)a.Qy), &sn, &cs);
+          double2 yf;
+          if constexpr (kYfac) {
+            yf = yfac[ky];
+          } else {
+            const int64_t ay = (((int64_t)freq_index(ky, N) * a.wave_u[2 * w + 1]) % a.Qy + a.Qy) % a.Qy;
+            sincospi(-2.0 * (double)ay / (double)a.Qy, &yf.y, &yf.x);
+          }
+          const double cs = xc * yf.x - xs * yf.y, sn = xc * yf.y + xs * yf.x;
           v[m] = cmul(tab[ky], make_float2((float)cs, (float)sn));
         }
         fft<N, +1, C::WL>(v, j, tw, a.tw, slot);
