@@ -371,6 +371,19 @@ lma_status lma_get_input_wave_spectrum(const lma_plan* plan, double* spec);
 /* With translate windows (lattice.prop_nx > 0): the window DFT of u cropped to a window
  * centred on it, double [prop_ny][prop_nx][2]; LMA_ERR_STATE without windows. */
 lma_status lma_get_window_spectrum(const lma_plan* plan, double* spec);
+/* The resident basis (the propagated translates kept for reuse, Sec. 4.2.4) written to a file
+ * and read back, so that a specimen's propagation outlives the process that computed it.
+ * The file holds a header and the rows in the device's encoding; its fingerprint covers the
+ * optics, the input wave and translate lattice, the element encoding, the translate windows,
+ * the detector pixels and the resident translates (not the potential, which the caller
+ * pairs with the file). lma_save_basis needs a valid basis; lma_load_basis checks the header
+ * and the file's length against the plan before it copies anything to the device
+ * (LMA_ERR_ARG, basis unchanged, on a mismatch) and leaves the basis valid on success.
+ * Both stream through 64 MiB of host memory and synchronise the plan's stream.
+ * LMA_ERR_STATE on host-only and partitioned plans. */
+lma_status lma_save_basis(lma_plan* plan, const char* path);
+lma_status lma_load_basis(lma_plan* plan, const char* path);
+
 /* Resident-basis rows first..first+count-1 (rows in increasing translate order, see
  * lma_get_rows): F(U_i) at the D detector pixels, float [count][D][2] on the host. */
 lma_status lma_get_basis_rows(lma_plan* plan, int32_t first, int32_t count, float* out);

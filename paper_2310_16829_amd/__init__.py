@@ -8,6 +8,7 @@ this directory and there is no fallback when it is missing.
 from __future__ import annotations
 
 import ctypes as C
+import os
 
 import numpy as np
 
@@ -291,6 +292,14 @@ class Plan:
         out = np.zeros(self.info().n_rows, dtype=np.int32)
         _check(lib().lma_get_rows(self._h, C.c_void_p(out.ctypes.data)))
         return out
+
+    def save_basis(self, path: str):
+        """Writes the resident basis to `path` (lma_save_basis)."""
+        _check(lib().lma_save_basis(self._h, os.fsencode(path)))
+
+    def load_basis(self, path: str):
+        """Reads a basis written by a plan of the same layout (lma_load_basis)."""
+        _check(lib().lma_load_basis(self._h, os.fsencode(path)))
 
     def basis_rows(self, first: int, count: int) -> np.ndarray:
         out = np.zeros((count, self.n_pix, 2), dtype=np.float32)

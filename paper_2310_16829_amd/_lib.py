@@ -88,6 +88,8 @@ SIGNATURES = {
     "lma_get_input_wave_spectrum": (C.c_int, [P, P]),
     "lma_get_window_spectrum": (C.c_int, [P, P]),
     "lma_get_basis_rows": (C.c_int, [P, C.c_int32, C.c_int32, P]),
+    "lma_save_basis": (C.c_int, [P, C.c_char_p]),
+    "lma_load_basis": (C.c_int, [P, C.c_char_p]),
     "lma_get_rows": (C.c_int, [P, P]),
     "lma_set_timing": (C.c_int, [P, C.c_int32]),
     "lma_get_timing": (C.c_int, [P, C.POINTER(lma_kernel_time), C.c_int32, C.POINTER(C.c_int32), C.c_int32]),

@@ -1266,6 +1266,132 @@ lma_status lma_get_rows(const lma_plan* p, int32_t* translate) {
   return LMA_OK;
 }
 
+// ---- the resident basis as a file --------------------------------------------------------
+// Layout: a fixed header, then the rows exactly as the device holds them ([n_rows][D] x 8
+// bytes: complex64 scaled by 1/(XY), or four bf16 hi/lo words). The header's fingerprint covers
+// everything the rows' values and order depend on besides the potential: the optics, the input
+// wave and its translate lattice, the element encoding, the translate windows, the detector
+// pixels in compacted order and the resident translates in row order.
+namespace {
+struct BasisFileHeader {
+  char magic[8];
+  uint32_t version;
+  uint32_t elem_bytes;
+  int32_t nx, ny, D, n_rows, precision, reserved;
+  uint64_t fingerprint;
+  uint64_t payload_bytes;
+};
+constexpr char kBasisMagic[8] = {'L', 'M', 'A', 'B', 'A', 'S', 'I', 'S'};
+
+struct Fnv {
+  uint64_t h = 1469598103934665603ull;
+  void bytes(const void* p, size_t n) {
+    const unsigned char* c = static_cast<const unsigned char*>(p);
+    for (size_t i = 0; i < n; ++i) h = (h ^ c[i]) * 1099511628211ull;
+  }
+  void put(int32_t v) { bytes(&v, sizeof(v)); }
+  void put(double v) { bytes(&v, sizeof(v)); }
+};
+
+uint64_t basis_fingerprint(const lma_plan* p) {
+  const HostPlan& h = p->h;
+  Fnv f;
+  f.put(h.op.nx); f.put(h.op.ny); f.put(h.op.lx); f.put(h.op.ly); f.put(h.op.wavelength);
+  f.put(h.op.sigma); f.put(h.op.dz); f.put(h.op.bandlimit); f.put(h.op.alpha_max);
+  f.put(h.op.defocus); f.put(h.op.cs);
+  f.put(h.lat.rx); f.put(h.lat.ry); f.put(h.lat.f); f.put(h.lat.offset_x); f.put(h.lat.offset_y);
+  f.put(h.lat.basis_kind); f.put(h.lat.basis_param); f.put(h.lat.precision);
+  f.put(h.lat.prop_nx); f.put(h.lat.prop_ny);
+  f.bytes(h.comp_flat.data(), h.comp_flat.size() * sizeof(int32_t));
+  f.bytes(h.rows.data(), h.rows.size() * sizeof(h.rows[0]));
+  return f.h;
+}
+
+lma_status basis_file_state(const lma_plan* p) {
+  if (p->host_only) return fail(LMA_ERR_STATE, "host-only plan has no device state");
+  if (p->partitioned) return fail(LMA_ERR_STATE, "a partitioned plan keeps no whole basis");
+  return LMA_OK;
+}
+
+constexpr size_t kBasisChunk = (size_t)64 << 20;   // bytes staged through host memory at a time
+}  // namespace
+
+lma_status lma_save_basis(lma_plan* p, const char* path) {
+  if (!p || !path) return fail(LMA_ERR_ARG, "null argument");
+  if (lma_status s = basis_file_state(p); s != LMA_OK) return s;
+  if (!p->basis_valid) return fail(LMA_ERR_STATE, "no valid propagated basis");
+  BasisFileHeader hd{};
+  std::memcpy(hd.magic, kBasisMagic, 8);
+  hd.version = 1;
+  hd.elem_bytes = 8;
+  hd.nx = p->h.op.nx;
+  hd.ny = p->h.op.ny;
+  hd.D = p->h.D();
+  hd.n_rows = (int32_t)p->h.rows.size();
+  hd.precision = p->h.lat.precision;
+  hd.fingerprint = basis_fingerprint(p);
+  hd.payload_bytes = (uint64_t)hd.n_rows * hd.D * hd.elem_bytes;
+  FILE* fp = std::fopen(path, "wb");
+  if (!fp) return fail(LMA_ERR_ARG, std::string("cannot open for writing: ") + path);
+  bool ok = std::fwrite(&hd, sizeof(hd), 1, fp) == 1;
+  std::vector<char> buf(std::min<size_t>(kBasisChunk, std::max<uint64_t>(hd.payload_bytes, 1)));
+  hipError_t e = hipSuccess;
+  for (uint64_t off = 0; ok && off < hd.payload_bytes; off += buf.size()) {
+    const size_t n = (size_t)std::min<uint64_t>(buf.size(), hd.payload_bytes - off);
+    e = hipMemcpyAsync(buf.data(), (const char*)p->d_basis + off, n, hipMemcpyDeviceToHost, p->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+    ok = e == hipSuccess && std::fwrite(buf.data(), 1, n, fp) == n;
+  }
+  ok = (std::fclose(fp) == 0) && ok;
+  if (e != hipSuccess) return fail(LMA_ERR_DEVICE, std::string("lma_save_basis: ") + hipGetErrorString(e));
+  if (!ok) return fail(LMA_ERR_ARG, std::string("write failed: ") + path);
+  return LMA_OK;
+}
+
+lma_status lma_load_basis(lma_plan* p, const char* path) {
+  if (!p || !path) return fail(LMA_ERR_ARG, "null argument");
+  if (lma_status s = basis_file_state(p); s != LMA_OK) return s;
+  FILE* fp = std::fopen(path, "rb");
+  if (!fp) return fail(LMA_ERR_ARG, std::string("cannot open for reading: ") + path);
+  BasisFileHeader hd{};
+  std::string why;
+  if (std::fread(&hd, sizeof(hd), 1, fp) != 1 || std::memcmp(hd.magic, kBasisMagic, 8) != 0)
+    why = "not a basis file";
+  else if (hd.version != 1 || hd.elem_bytes != 8)
+    why = "unsupported basis file version";
+  else if (hd.nx != p->h.op.nx || hd.ny != p->h.op.ny || hd.D != p->h.D() ||
+           hd.n_rows != (int32_t)p->h.rows.size() || hd.precision != p->h.lat.precision ||
+           hd.fingerprint != basis_fingerprint(p) || hd.payload_bytes != (uint64_t)hd.n_rows * hd.D * 8)
+    why = "the basis file was written by a plan with another layout (grid, detector pixels, translates, optics or encoding)";
+  if (why.empty()) {
+    // the payload must be whole before any of it reaches the device
+    const long here = std::ftell(fp);
+    if (here < 0 || std::fseek(fp, 0, SEEK_END) != 0 || std::ftell(fp) - here != (long)hd.payload_bytes ||
+        std::fseek(fp, here, SEEK_SET) != 0)
+      why = "the basis file is truncated or has trailing bytes";
+  }
+  if (!why.empty()) {
+    std::fclose(fp);
+    return fail(LMA_ERR_ARG, why + ": " + path);
+  }
+  p->basis_valid = false;
+  std::vector<char> buf(std::min<size_t>(kBasisChunk, std::max<uint64_t>(hd.payload_bytes, 1)));
+  hipError_t e = hipSuccess;
+  bool ok = true;
+  for (uint64_t off = 0; off < hd.payload_bytes; off += buf.size()) {
+    const size_t n = (size_t)std::min<uint64_t>(buf.size(), hd.payload_bytes - off);
+    if (std::fread(buf.data(), 1, n, fp) != n) { ok = false; break; }
+    e = hipMemcpyAsync((char*)p->d_basis + off, buf.data(), n, hipMemcpyHostToDevice, p->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+    if (e != hipSuccess) break;
+  }
+  std::fclose(fp);
+  if (e != hipSuccess) return fail(LMA_ERR_DEVICE, std::string("lma_load_basis: ") + hipGetErrorString(e));
+  if (!ok) return fail(LMA_ERR_ARG, std::string("read failed: ") + path);
+  p->basis_valid = true;
+  return LMA_OK;
+}
+
 lma_status lma_get_basis_rows(lma_plan* p, int32_t first, int32_t count, float* out) {
   if (!p || !out) return fail(LMA_ERR_ARG, "null argument");
   if (p->host_only) return fail(LMA_ERR_STATE, "host-only plan has no device state");

@@ -19,6 +19,51 @@ def say(*a):
     sys.stdout.flush()
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_basis_save_and_load(tmp_path, precision):
+    # a propagated basis written to a file and read by a fresh plan of the same layout gives the
+    # same rows bit for bit and the same images; a plan of another layout (detectors, encoding), a
+    # truncated file and a file of another kind are refused before anything reaches the device
+    from paper_2310_16829_amd import _lib
+    prec = (lma.LMA_GEMM_FP32, lma.LMA_GEMM_SPLIT_BF16)[precision]
+    w = WORKLOADS["tiny"]
+    lam, sig = lma.electron_constants(w.kv)
+    opt = lma.optics(w.nx, w.ny, w.lx, w.ly, lam, sig, w.dz, w.bandlimit, w.alpha_mrad * 1e-3)
+    det = lma.detectors(det_rad(w))
+    lat = lma.lattice(16, 16, 32, 32, 1, (0.5, 0.5), 36, prec)
+    v = potential_slices(w, 0)
+    say(f"basis file, precision {prec}")
+    a = lma.Plan(opt, lat, det)
+    a.propagate(v)
+    img, rows = a.probe_image(), a.basis_rows(0, a.n_rows)
+    path = str(tmp_path / "tiny.basis")
+    a.save_basis(path)
+    a.close()
+    b = lma.Plan(opt, lat, det)
+    with pytest.raises(lma.LmaError):
+        b.probe_image()                                   # nothing propagated or loaded yet
+    b.load_basis(path)
+    assert np.array_equal(b.basis_rows(0, b.n_rows), rows)
+    assert np.allclose(b.probe_image(), img, rtol=1e-12, atol=0)   # FP64 atomics: sum order varies
+    b.close()
+    data = open(path, "rb").read()
+    cut, junk = str(tmp_path / "cut.basis"), str(tmp_path / "junk.basis")
+    open(cut, "wb").write(data[:-8])
+    open(junk, "wb").write(b"not a basis" * 16)
+    other_prec = lma.lattice(16, 16, 32, 32, 1, (0.5, 0.5), 36,
+                             lma.LMA_GEMM_FP32 if precision else lma.LMA_GEMM_SPLIT_BF16)
+    for o_lat, o_det, f in ((lat, lma.detectors([(0.0, 0.01)]), path), (other_prec, det, path),
+                            (lat, det, cut), (lat, det, junk), (lat, det, str(tmp_path / "missing.basis"))):
+        c = lma.Plan(opt, o_lat, o_det)
+        with pytest.raises(lma.LmaError) as e:
+            c.load_basis(f)
+        assert e.value.status == _lib.LMA_ERR_ARG
+        with pytest.raises(lma.LmaError) as e:
+            c.probe_image()                               # still no basis
+        assert e.value.status == _lib.LMA_ERR_STATE
+        c.close()
+
+
 def _specimens():
     """Three specimens: the tiny workload, the tiny geometry with another potential, and a
     256^2 grid; each with an edited potential (a raised 12 x 12-pixel patch)."""

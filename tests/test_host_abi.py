@@ -180,7 +180,8 @@ def test_host_only_plan_refuses_device_work():
     plan = lma.Plan(opt, lat, det, flags=lma.LMA_HOST_ONLY)
     v = np.zeros((2, w.ny, w.nx), np.float32)
     for call in (lambda: plan.propagate(v), lambda: plan.probe_image(), lambda: plan.plain_image(v),
-                 lambda: plan.basis_rows(0, 1)):
+                 lambda: plan.basis_rows(0, 1), lambda: plan.save_basis(os.devnull),
+                 lambda: plan.load_basis(os.devnull)):
         with pytest.raises(lma.LmaError) as e:
             call()
         assert e.value.status == _lib.LMA_ERR_STATE
