@@ -42,7 +42,7 @@ typedef enum {
   LMA_ERR_OOM = -2,          /* device or host allocation failed / over the budget   */
   LMA_ERR_DEVICE = -3,       /* a HIP call failed                                    */
   LMA_ERR_STATE = -4,        /* the plan cannot do this now (no valid basis, host-only plan) */
-  LMA_ERR_UNSUPPORTED = -5   /* valid request outside what this build implements     */
+  LMA_ERR_UNSUPPORTED = -5   /* valid request outside what the library implements    */
 } lma_status;
 
 typedef struct lma_plan lma_plan;   /* opaque */
