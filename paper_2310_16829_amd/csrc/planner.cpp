@@ -276,10 +276,13 @@ lma_status build_host_plan(const lma_optics* op, const lma_lattice* lat, const l
     h.uspec = h.spec;
   }
 
-  // ---- detector pixel list: sorted by (ring mask, flat index), cut into uniform chunks --------
+  // ---- detector pixel list: sorted by (ring mask, kx, ky), cut into uniform chunks -----------
+  // Within one ring mask the pixels of a kx column are consecutive, so the last column pass,
+  // whose lanes hold consecutive ky of one kx, writes runs of neighbouring basis entries.
   std::vector<int32_t> pix;
-  for (int i = 0; i < nx * ny; ++i)
-    if (h.detmask[i]) pix.push_back(i);
+  for (int x = 0; x < nx; ++x)
+    for (int y = 0; y < ny; ++y)
+      if (h.detmask[(size_t)y * nx + x]) pix.push_back(y * nx + x);
   if (pix.empty()) { *err = "no detector pixel lies inside the band limit"; return LMA_ERR_ARG; }
   std::stable_sort(pix.begin(), pix.end(), [&](int32_t a, int32_t b) { return h.detmask[a] < h.detmask[b]; });
   h.comp_flat = pix;

@@ -39,7 +39,7 @@ struct HostPlan {
   std::vector<cd> wspec;         // DFT of u cropped to a window centred on it [wny][wnx]
   std::vector<cd> wprop;         // window propagator / (wnx wny), the cell's band limit [wny][wnx]
   std::vector<uint32_t> detmask; // ring bits per frequency [ny][nx]
-  std::vector<int32_t> comp_flat;   // D detector pixels, sorted by (mask, flat index)
+  std::vector<int32_t> comp_flat;   // D detector pixels (flat index), sorted by (mask, kx, ky)
   std::vector<uint32_t> comp_mask;  // [D]
   std::vector<int32_t> comp_map;    // [ny][nx] -> compacted index or -1
   std::vector<int32_t> chunk_start; // chunks of compacted pixels with one ring mask
