@@ -795,8 +795,10 @@ def main():
     tw = info.tile_width
     gap_tiles = max(0, info.gap_hi // tw - (-(-info.gap_lo // tw)))
     kept = 1.0 - gap_tiles * tw / w.nx
+    # the first row pass reads what the initial waves wrote: all but the input spectrum's gap
+    first_read = 1.0 - max(0, info.input_gap_hi // tw - (-(-info.input_gap_lo // tw))) * tw / w.nx
     if dom == "row_pass":
-        read = ((w.nslices - 1) * kept + 1.0) / w.nslices
+        read = ((w.nslices - 1) * kept + first_read) / w.nslices
         bytes_per_launch = waves_per_launch * XY * 8 * (read + kept) + XY * 8
     else:
         bytes_per_launch = (waves_per_launch * XY * 16 + XY * 8) * kept
@@ -855,6 +857,7 @@ def main():
                      "traffic": traffic,
                      "algorithmic_bytes_per_launch": bytes_per_launch,
                      "band_gap_columns": [info.gap_lo, info.gap_hi], "kept_fraction": kept,
+                     "input_gap_columns": [info.input_gap_lo, info.input_gap_hi],
                      "avg_launch_ms": avg_s * 1e3},
         "contraction": contraction,
         "contraction_split_bf16": split,

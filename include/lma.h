@@ -152,6 +152,9 @@ typedef struct {
                              /* for every ky and no detector pixel lies: waves are    */
                              /* exactly zero there after every propagator multiply,   */
                              /* and the slice passes skip the tile columns inside it  */
+  int32_t input_gap_lo, input_gap_hi; /* kx columns where the input wave u's spectrum     */
+                             /* vanishes for every ky: the initial-wave pass skips    */
+                             /* their tile columns and the first row pass reads none  */
 } lma_info;
 
 /* Result of lma_autotune for one grid. */

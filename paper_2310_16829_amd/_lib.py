@@ -44,7 +44,8 @@ class lma_info(C.Structure):
                 ("partitioned", C.c_int32), ("n_parts", C.c_int32), ("part_w", C.c_int32), ("part_h", C.c_int32),
                 ("resident_rows", C.c_int64), ("multislice_calls", C.c_int64), ("tile_width", C.c_int32),
                 ("graphs", C.c_int32), ("prop_nx", C.c_int32), ("prop_ny", C.c_int32),
-                ("gap_lo", C.c_int32), ("gap_hi", C.c_int32)]
+                ("gap_lo", C.c_int32), ("gap_hi", C.c_int32), ("input_gap_lo", C.c_int32),
+                ("input_gap_hi", C.c_int32)]
 
 
 class lma_tuning(C.Structure):

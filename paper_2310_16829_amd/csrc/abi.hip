@@ -73,6 +73,8 @@ struct lma_plan {
   uint32_t* d_maskT = nullptr;
   int zc0 = 0, zc1 = 0;              // kx columns zero after every column pass (band gap)
   int wzc0 = 0, wzc1 = 0;            // the same on the translate windows
+  int sc0 = 0, sc1 = 0;              // kx columns where the probe spectrum vanishes
+  int uc0 = 0, uc1 = 0;              // ... and where the input wave u's spectrum does
   int32_t *d_row_of = nullptr, *d_set_dx = nullptr, *d_set_dy = nullptr;
   int32_t *d_chunk_start = nullptr, *d_chunk_len = nullptr;
   uint32_t* d_chunk_mask = nullptr;
@@ -176,6 +178,36 @@ void band_gap(const std::vector<float2>& propT, int nx, int ny, const int32_t* c
   }
   *c0 = best0;
   *c1 = best1;
+}
+
+// The kx-column gaps of a plan from its tables as the device holds them (FP32, transposed):
+// the band gap of the propagator (no detector pixel inside), the gaps of the probe spectrum and
+// of u's, and the band gap of the translate windows' propagator.
+void compute_gaps(lma_plan* p) {
+  const HostPlan& h = p->h;
+  const int nx = h.op.nx, ny = h.op.ny;
+  const double XY = (double)nx * ny;
+  auto f2T = [](const std::vector<cd>& src, int w, int hh, double scale) {
+    std::vector<float2> t((size_t)w * hh);
+    for (int y = 0; y < hh; ++y)
+      for (int x = 0; x < w; ++x) {
+        const cd& z = src[(size_t)y * w + x];
+        t[(size_t)x * hh + y] = make_float2((float)(z.real() * scale), (float)(z.imag() * scale));
+      }
+    return t;
+  };
+  std::vector<int32_t> compT((size_t)nx * ny);
+  for (int y = 0; y < ny; ++y)
+    for (int x = 0; x < nx; ++x) compT[(size_t)x * ny + y] = h.comp_map[(size_t)y * nx + x];
+  band_gap(f2T(h.prop, nx, ny, 1.0), nx, ny, compT.data(), &p->zc0, &p->zc1);
+  band_gap(f2T(h.spec, nx, ny, 1.0 / XY), nx, ny, nullptr, &p->sc0, &p->sc1);
+  if (h.lat.basis_kind == LMA_BASIS_PROBE) {
+    p->uc0 = p->sc0;
+    p->uc1 = p->sc1;
+  } else {
+    band_gap(f2T(h.uspec, nx, ny, 1.0 / XY), nx, ny, nullptr, &p->uc0, &p->uc1);
+  }
+  if (h.wnx > 0) band_gap(f2T(h.wprop, h.wnx, h.wny, 1.0), h.wnx, h.wny, nullptr, &p->wzc0, &p->wzc1);
 }
 
 lma::dev::Tables window_tables(const lma_plan* p) {
@@ -367,14 +399,18 @@ lma_status run_waves(lma_plan* p, const int64_t* d_u, const int32_t* d_row, cons
     }
     return LMA_OK;
   }
+  // translates start from u, probes from psi_0; the initial waves skip, and the first row
+  // pass does not read, the kx columns where that spectrum vanishes
+  lma::dev::Tables Ti = T;
+  const bool from_u = d_row && !probes;
+  if (from_u) Ti.specT = p->d_uspecT;
+  Ti.ic0 = from_u ? p->uc0 : p->sc0;
+  Ti.ic1 = from_u ? p->uc1 : p->sc1;
   for (int first = 0; first < n; first += p->B) {
     const int nb = std::min(p->B, n - first);
-    // translates start from u, probes from psi_0
-    lma::dev::Tables Ti = T;
-    if (d_row && !probes) Ti.specT = p->d_uspecT;
     LAUNCH(p, "init", lma::dev::init_waves(Ti, p->d_work, d_u + 2 * (int64_t)first, nb, p->stream));
     for (int j = 0; j < nslices; ++j) {
-      LAUNCH(p, "row_pass", lma::dev::row_pass(T, p->d_work, p->d_trans + (size_t)j * XY, nb, j > 0, p->stream));
+      LAUNCH(p, "row_pass", lma::dev::row_pass(Ti, p->d_work, p->d_trans + (size_t)j * XY, nb, j > 0, p->stream));
       if (j + 1 < nslices) {
         LAUNCH(p, "col_pass", lma::dev::col_pass(T, p->d_work, nb, p->stream));
       } else if (d_row) {
@@ -674,6 +710,7 @@ lma_status lma_build_basis(const lma_optics* optics, const lma_lattice* lattice,
         p->partitioned = true;
       }
     }
+    compute_gaps(p);
     if (p->host_only) {
       *out = p;
       return LMA_OK;
@@ -716,7 +753,6 @@ lma_status lma_build_basis(const lma_optics* optics, const lma_lattice* lattice,
       if ((s = upload(p, &p->d_wspecT, wv.data(), wv.size())) != LMA_OK) { release(p); return s; }
       wT(h.wprop, 1.0);
       if ((s = upload(p, &p->d_wpropT, wv.data(), wv.size())) != LMA_OK) { release(p); return s; }
-      band_gap(wv, wx, wy, nullptr, &p->wzc0, &p->wzc1);
       auto wtx = twiddles(wx), wty = twiddles(wy);
       if ((s = upload(p, &p->d_wtwx, wtx.data(), wtx.size())) != LMA_OK) { release(p); return s; }
       if ((s = upload(p, &p->d_wtwy, wty.data(), wty.size())) != LMA_OK) { release(p); return s; }
@@ -732,7 +768,6 @@ lma_status lma_build_basis(const lma_optics* optics, const lma_lattice* lattice,
         maskT[(size_t)x * ny + y] = h.detmask[(size_t)y * nx + x];
       }
     if ((s = upload(p, &p->d_compT, compT.data(), compT.size())) != LMA_OK) { release(p); return s; }
-    band_gap(v, nx, ny, compT.data(), &p->zc0, &p->zc1);
     if ((s = upload(p, &p->d_maskT, maskT.data(), maskT.size())) != LMA_OK) { release(p); return s; }
     if ((s = upload(p, &p->d_row_of, h.row_of.data(), h.row_of.size())) != LMA_OK) { release(p); return s; }
     if ((s = upload(p, &p->d_set_dx, h.set_dx.data(), h.set_dx.size())) != LMA_OK) { release(p); return s; }
@@ -1193,6 +1228,8 @@ lma_status lma_plan_info(const lma_plan* p, lma_info* out) {
   out->prop_nx = p->h.wnx;
   out->gap_lo = p->zc0;
   out->gap_hi = p->zc1;
+  out->input_gap_lo = p->uc0;
+  out->input_gap_hi = p->uc1;
   out->prop_ny = p->h.wny;
   return LMA_OK;
 }

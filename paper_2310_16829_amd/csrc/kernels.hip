@@ -372,8 +372,10 @@ struct PassArgs {
   double scale;
   int tnx, tny;              // ROW_WIN / ROW_LAST: the cell (table [tny][tnx]); window origin
   int hx, hy;                //   of wave w: its position in pixels minus (hx, hy)
-  int zlo, zhi;              // tile columns [zlo, zhi) stay zero between passes (kx band gap)
-  int zread;                 // ROW: the input comes from a column pass; skip reading the gap
+  int zlo, zhi;              // tile columns [zlo, zhi) stay zero between passes (kx band gap);
+                             //   INIT: the tile columns of the input spectrum's gap
+  int zread;                 // ROW: skip reading tile columns [rlo, rhi), which hold zeros
+  int rlo, rhi;
 };
 
 __device__ __forceinline__ void split_bf16(float x, __hip_bfloat16& hi, __hip_bfloat16& lo) {
@@ -515,7 +517,7 @@ __attribute__((amdgpu_waves_per_eu(fft_odd(N) == 5 ? 2 : 1, 8))) void k_pass(Pas
   const bool active = !C::WL || sub < S;
   // column passes after the first skip the tile columns of the band gap: item group g' maps
   // to tile column g' below the gap and g' + (zhi - zlo) above it
-  constexpr bool kGapItems = MODE == PASS_COL || MODE == PASS_GATHER || MODE == PASS_REDUCE;
+  constexpr bool kGapItems = MODE == PASS_COL || MODE == PASS_GATHER || MODE == PASS_REDUCE || MODE == PASS_INIT;
   const int gap = kGapItems ? a.zhi - a.zlo : 0;
   const int ngroups = (ROWS ? a.ny : a.nx) / TW - gap;
   const int B = a.B;
@@ -532,6 +534,14 @@ __attribute__((amdgpu_waves_per_eu(fft_odd(N) == 5 ? 2 : 1, 8))) void k_pass(Pas
     if constexpr (ROWS) {
       const int q = c / (TW * TW);
       return q >= a.zlo && q < a.zhi;
+    } else {
+      return false;
+    }
+  };
+  auto in_rgap = [&](int c) -> bool {
+    if constexpr (ROWS) {
+      const int q = c / (TW * TW);
+      return q >= a.rlo && q < a.rhi;
     } else {
       return false;
     }
@@ -560,14 +570,14 @@ __attribute__((amdgpu_waves_per_eu(fft_odd(N) == 5 ? 2 : 1, 8))) void k_pass(Pas
       for (int k = 0; k < EPT; ++k) {
         int lds, off;
         M::at(k * NT + tid, stride_q, lds, off);
-        buf[k] = (a.zread && in_gap(k * NT + tid)) ? make_float2(0.f, 0.f) : load_item_elem(r, off);
+        buf[k] = (a.zread && in_rgap(k * NT + tid)) ? make_float2(0.f, 0.f) : load_item_elem(r, off);
       }
     } else {
 #pragma unroll
       for (int k = 0; k < EPT; ++k) {
         int lds, off;
         M::at(k * NT + tid, stride_q, lds, off);
-        buf[k] = (a.zread && in_gap(k * NT + tid)) ? make_float2(0.f, 0.f) : load_stream(src + off);
+        buf[k] = (a.zread && in_rgap(k * NT + tid)) ? make_float2(0.f, 0.f) : load_stream(src + off);
       }
     }
     memory_phase_end();
@@ -601,7 +611,7 @@ __attribute__((amdgpu_waves_per_eu(fft_odd(N) == 5 ? 2 : 1, 8))) void k_pass(Pas
           for (int k = 0; k < CHUNK; ++k) {
             int lds, off;
             M::at(c0 + k * NT + tid, stride_q, lds, off);
-            st[k] = (a.zread && in_gap(c0 + k * NT + tid)) ? make_float2(0.f, 0.f) : load_stream(item + off);
+            st[k] = (a.zread && in_rgap(c0 + k * NT + tid)) ? make_float2(0.f, 0.f) : load_stream(item + off);
           }
 #pragma unroll
           for (int k = 0; k < CHUNK; ++k) {
@@ -1046,8 +1056,9 @@ static hipError_t pass_launch(const PassArgs& a0, int lines, int B, hipStream_t 
   }
   PassArgs a = a0;
   a.B = B;
-  if (a.zlo < 0 || a.zhi < a.zlo || a.zhi > a.nx / TW) return hipErrorInvalidValue;
-  constexpr bool kGapItems = MODE == PASS_COL || MODE == PASS_GATHER || MODE == PASS_REDUCE;
+  if (a.zlo < 0 || a.zhi < a.zlo || a.zhi > a.nx / TW || a.rlo < 0 || a.rhi < a.rlo || a.rhi > a.nx / TW)
+    return hipErrorInvalidValue;
+  constexpr bool kGapItems = MODE == PASS_COL || MODE == PASS_GATHER || MODE == PASS_REDUCE || MODE == PASS_INIT;
   const int64_t items = (int64_t)B * (lines / TW - (kGapItems ? a.zhi - a.zlo : 0));
   if (items <= 0) return hipSuccess;
   int64_t grid = std::min<int64_t>(items, (int64_t)resident * device_cus());
@@ -1134,15 +1145,23 @@ static PassArgs pass_args(const Tables& T, float2* work) {
   const int tw = tw_of(T);
   const int lo = (T.zc0 + tw - 1) / tw, hi = T.zc1 / tw;
   if (T.zc0 >= 0 && T.zc1 <= T.nx && hi > lo) {
-    a.zlo = lo;
-    a.zhi = hi;
+    a.zlo = a.rlo = lo;
+    a.zhi = a.rhi = hi;
   }
   return a;
+}
+// tile columns wholly inside the input spectrum's gap
+static void input_gap_tiles(const Tables& T, int* lo, int* hi) {
+  const int tw = tw_of(T);
+  *lo = (T.ic0 + tw - 1) / tw;
+  *hi = T.ic1 / tw;
+  if (T.ic0 < 0 || T.ic1 > T.nx || *hi <= *lo) *lo = *hi = 0;
 }
 
 hipError_t init_waves(const Tables& T, float2* work, const int64_t* wave_u, int B, hipStream_t s) {
   PassArgs a = pass_args(T, work);
-  a.zlo = a.zhi = 0;                 // the input wave need not vanish in the gap
+  input_gap_tiles(T, &a.zlo, &a.zhi);   // items skipped: the spectrum vanishes there
+  a.rlo = a.rhi = 0;
   a.table = T.specT;
   a.tw = T.twy;
   a.wave_u = wave_u;
@@ -1151,7 +1170,8 @@ hipError_t init_waves(const Tables& T, float2* work, const int64_t* wave_u, int 
 
 hipError_t row_pass(const Tables& T, float2* work, const float2* trans_j, int B, bool after_column, hipStream_t s) {
   PassArgs a = pass_args(T, work);
-  a.zread = after_column ? 1 : 0;
+  if (!after_column) input_gap_tiles(T, &a.rlo, &a.rhi);   // the initial waves skipped these
+  a.zread = 1;
   a.table = trans_j;
   a.tw = T.twx;
   return pass_dispatch<PASS_ROW>(T.nx, tw_of(T), T.ny, a, B, s);
@@ -1161,7 +1181,8 @@ hipError_t row_pass_window(const Tables& Tw, float2* work, const float2* trans_j
                            const int64_t* wave_u, int64_t Qx, int64_t Qy, bool last, bool after_column, int B,
                            hipStream_t s) {
   PassArgs a = pass_args(Tw, work);
-  a.zread = after_column ? 1 : 0;
+  if (!after_column) input_gap_tiles(Tw, &a.rlo, &a.rhi);
+  a.zread = 1;
   a.table = trans_j;
   a.tw = Tw.twx;
   a.wave_u = wave_u;

@@ -23,6 +23,10 @@ struct Tables {
   // columns inside the range; row passes write only the others, and read only the others
   // when their input comes from a column pass.
   int zc0 = 0, zc1 = 0;
+  // kx columns [ic0, ic1) where the spectrum the initial waves start from (specT) vanishes for
+  // every ky: the initial-wave pass skips their tile columns and the first row pass does not
+  // read them
+  int ic0 = 0, ic1 = 0;
 };
 
 struct Contraction {
@@ -97,7 +101,8 @@ bool tile_width_ok(int nx, int ny, int tw);
 hipError_t init_waves(const Tables& T, float2* work, const int64_t* wave_u, int B, hipStream_t s);
 // row pass of slice j: row IFFT, * t_j, row FFT
 // after_column: the waves come from a column pass (every slice but the first), so their
-// zero kx columns need not be read
+// zero kx columns (the band gap) need not be read; otherwise they come from init_waves and
+// the columns of the input spectrum's gap (ic0, ic1) are not read
 hipError_t row_pass(const Tables& T, float2* work, const float2* trans_j, int B, bool after_column, hipStream_t s);
 // row pass of slice j for waves propagated on windows (Tw: the window's tables): row IFFT,
 // * t_j of the cell at each wave's window (origin: its position in pixels minus half the

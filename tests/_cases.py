@@ -41,3 +41,19 @@ def rel_l2(a, b):
     a = np.asarray(a)
     b = np.asarray(b)
     return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
+
+
+def longest_zero_run(zero):
+    """(start, end) of the longest run of True in a 1-D boolean sequence ((0, 0) if none)."""
+    best, x, n = (0, 0), 0, len(zero)
+    while x < n:
+        if not zero[x]:
+            x += 1
+            continue
+        e = x
+        while e < n and zero[e]:
+            e += 1
+        if e - x > best[1] - best[0]:
+            best = (x, e)
+        x = e
+    return best

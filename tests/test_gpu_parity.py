@@ -18,7 +18,7 @@ from oracle.lma import LMA, Lattice, phonon_average, recompute_sets
 from oracle.multislice import Setup, plain_image
 from synth import WORKLOADS, potential_slices
 from synth.specimen import edit_column, potential_from_atoms
-from tests._cases import det_rad, rel_l2
+from tests._cases import det_rad, longest_zero_run, rel_l2
 
 pytestmark = pytest.mark.gpu
 
@@ -127,21 +127,6 @@ def test_tiny_plain_image(tiny):
     img = tiny["plan"].plain_image(tiny["v"])
     e = image_errors(img, tiny["img_plain"], TOL32)
     say("  per-detector rel L2", e)
-
-
-def longest_zero_run(zero):
-    best, x, n = (0, 0), 0, len(zero)
-    while x < n:
-        if not zero[x]:
-            x += 1
-            continue
-        e = x
-        while e < n and zero[e]:
-            e += 1
-        if e - x > best[1] - best[0]:
-            best = (x, e)
-        x = e
-    return best
 
 
 @pytest.mark.parametrize("side", [128, 96, 640])

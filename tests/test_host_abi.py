@@ -15,7 +15,7 @@ from oracle import physics as ph
 from oracle.lma import LMA, Lattice, translate_wave
 from oracle.multislice import Setup
 from synth import WORKLOADS
-from tests._cases import det_rad, oracle_lattice, oracle_setup, rel_l2
+from tests._cases import det_rad, longest_zero_run, oracle_lattice, oracle_setup, rel_l2
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
@@ -185,6 +185,27 @@ def test_host_only_plan_refuses_device_work():
         with pytest.raises(lma.LmaError) as e:
             call()
         assert e.value.status == _lib.LMA_ERR_STATE
+
+
+@pytest.mark.parametrize("side,bandlimit", [(128, None), (96, None), (640, None), (128, 1.0), (128, 0.3)])
+def test_kx_gaps_match_the_oracle(side, bandlimit):
+    # the band gap (columns where the band-limited propagator vanishes for every ky and no ring
+    # has a pixel) and the input gap (columns where the probe spectrum vanishes), against the
+    # oracle's propagator, ring masks and probe spectrum
+    w = WORKLOADS["tiny"]
+    bl = bandlimit or w.bandlimit
+    lx = w.lx * side / w.nx
+    lam, sig = lma.electron_constants(w.kv)
+    rings = det_rad(w)
+    opt = lma.optics(side, side, lx, lx, lam, sig, w.dz, bl, w.alpha_mrad * 1e-3, w.defocus, w.cs)
+    lat = lma.lattice(16, 16, 16, 16, 1, w.offset_frac, 9)
+    i = lma.Plan(opt, lat, lma.detectors(rings), flags=lma.LMA_HOST_ONLY).info()
+    st = Setup(side, side, lx, lx, lam, sig, w.dz, bl, w.alpha_mrad * 1e-3, w.defocus, w.cs, (16, 16), rings)
+    band = np.all(st.prop == 0, axis=0) & ~np.any([m.any(axis=0) for m in st.masks], axis=0)
+    assert (i.gap_lo, i.gap_hi) == longest_zero_run(band)
+    assert (i.input_gap_lo, i.input_gap_hi) == longest_zero_run(np.all(st.spec0 == 0, axis=0))
+    # the aperture (20 mrad) lies inside the band: the input gap holds the band gap
+    assert i.input_gap_lo <= i.gap_lo and i.gap_hi <= i.input_gap_hi
 
 
 def test_footprint_grows_with_slices_and_basis():
