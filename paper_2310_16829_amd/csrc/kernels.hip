@@ -374,8 +374,8 @@ struct PassArgs {
   int hx, hy;                //   of wave w: its position in pixels minus (hx, hy)
   int zlo, zhi;              // tile columns [zlo, zhi) stay zero between passes (kx band gap);
                              //   INIT: the tile columns of the input spectrum's gap
-  int zread;                 // ROW: skip reading tile columns [rlo, rhi), which hold zeros
-  int rlo, rhi;
+  int zread;                 // row passes: skip reading tile columns [rlo, rhi), which hold
+  int rlo, rhi;              //   zeros
 };
 
 __device__ __forceinline__ void split_bf16(float x, __hip_bfloat16& hi, __hip_bfloat16& lo) {
@@ -515,8 +515,9 @@ __attribute__((amdgpu_waves_per_eu(fft_odd(N) == 5 ? 2 : 1, 8))) void k_pass(Pas
   const int j = C::WL ? lane % T : tid % T;                // thread within the transform
   const int tslot = C::WL ? (tid >> 6) * S + sub : tid / T;  // transform slot within the block
   const bool active = !C::WL || sub < S;
-  // column passes after the first skip the tile columns of the band gap: item group g' maps
-  // to tile column g' below the gap and g' + (zhi - zlo) above it
+  // column-layout passes skip the tile columns [zlo, zhi) of a gap (the band gap; for the
+  // initial waves, the input spectrum's gap): item group g' maps to tile column g' below the
+  // gap and g' + (zhi - zlo) above it
   constexpr bool kGapItems = MODE == PASS_COL || MODE == PASS_GATHER || MODE == PASS_REDUCE || MODE == PASS_INIT;
   const int gap = kGapItems ? a.zhi - a.zlo : 0;
   const int ngroups = (ROWS ? a.ny : a.nx) / TW - gap;
@@ -527,9 +528,10 @@ __attribute__((amdgpu_waves_per_eu(fft_odd(N) == 5 ? 2 : 1, 8))) void k_pass(Pas
     const int gg = l / B;
     return (kGapItems && gg >= a.zlo) ? gg + gap : gg;
   };
-  // row passes: tile q of a row item lies in the gap. Every row pass may skip reading it
-  // (zread: its input comes from a column pass); those whose output goes to a column pass
-  // skip writing it (not PASS_ROW_LAST, which leaves its wave in real space).
+  // row passes: tile q of a row item lies in a gap. They do not read tile columns [rlo, rhi),
+  // which hold zeros (the band gap after a column pass, the input gap after the initial
+  // waves); those whose output goes to a column pass do not write the band gap [zlo, zhi)
+  // (not PASS_ROW_LAST, which leaves its wave in real space).
   auto in_gap = [&](int c) -> bool {
     if constexpr (ROWS) {
       const int q = c / (TW * TW);
