@@ -335,7 +335,10 @@ typedef struct {
   int32_t nslices;                 /* IMAGE, PLAIN, EDIT; BUILD: slices the footprint holds */
   double* image;                   /* IMAGE, PLAIN: [n_det][h][w] (host, or device with    */
                                    /* LMA_PTR_DEVICE); EDIT: host image patched in place   */
-  int32_t flags;                   /* IMAGE, PLAIN: LMA_PTR_DEVICE, LMA_ACCUMULATE          */
+  int32_t flags;                   /* IMAGE, PLAIN: LMA_PTR_DEVICE, LMA_ACCUMULATE; BUILD:  */
+                                   /* LMA_HOST_ONLY plans on the host only (no device work; */
+                                   /* the specimen then answers IMAGE, PLAIN and EDIT with  */
+                                   /* LMA_ERR_STATE)                                         */
   double weight;                   /* IMAGE, PLAIN                                          */
   int32_t bbox[4];                 /* EDIT: edited pixels x0, y0, x1, y1 (half-open)        */
   double radius;                   /* EDIT: recompute radius, Angstrom                      */
@@ -348,7 +351,10 @@ lma_status lma_server_create(int32_t slots, int32_t max_specimens, int64_t budge
 lma_status lma_server_submit(lma_server* server, const lma_request* request, int64_t* ticket);
 /* Blocks until the ticket's request has completed and returns its status (the call's own
  * lma_status, with its message in lma_last_error); latency_ms (submission to completion) and
- * service_ms (start to completion) may be NULL. Each ticket can be waited for once. */
+ * service_ms (start to completion) may be NULL. Each ticket can be waited for once: a ticket
+ * never issued, or already waited for, returns LMA_ERR_ARG at once. A BUILD for a specimen
+ * that is resident when it runs fails with LMA_ERR_STATE and leaves the specimen and the
+ * admitted bytes as they were. */
 lma_status lma_server_wait(lma_server* server, int64_t ticket, double* latency_ms, double* service_ms);
 /* The specimen's resident plan (NULL if none); valid until a RELEASE of it completes. */
 lma_status lma_server_plan(lma_server* server, int32_t specimen, lma_plan** plan);

@@ -6,14 +6,19 @@ and reusing those shared with the next part, costs
 
     T = sum_j |I_{f,P_j,L}| - sum_{j<l} |I_{f,P_j,L} intersect I_{f,P_{j+1},L}|
 
-multislice runs. Two of the paper's strategies are written here: row by row and
-rectangles (the greedy one draws a random start and is not reproducible from the text).
+multislice runs. Of the paper's three strategies only the rectangle one is written here
+(the row strategy is not used by the library, and the greedy one draws a random start).
 
-Reading of the rectangle strategy: among all rectangle shapes w x h, take the one of
-largest area (ties: the wider one) whose every tile in the row-major tiling of the
-region, edge tiles clipped, satisfies |I_{f,P_j,L}| <= M. A device may restrict the
-shapes to sides that are multiples of a granule (gx, gy), or the whole region side;
-granule (1, 1) is the strategy as the paper states it.
+Reading of the rectangle strategy ("rectangles of the same size, as large as possible
+while every part keeps at most M solutions; smaller rectangles fill the rest; row-major or
+column-major order"): the parts are taken row-major, so the rectangles are made as wide
+as possible first, up to the whole region width, and then as tall as possible at that
+width; edge rectangles are clipped. The paper fixes this reading through its second
+example (Fig. lmastrategy_examples, bottom row): the rectangle partition stores about a
+quarter of the trivial strategy's solutions, makes exactly its number of multislice
+calls, and has l = 48 parts on the 48 x 48 sub-image. A largest-area reading cannot do
+that: at a quarter of the memory it picks squares, whose row-major order recomputes the
+translates shared between rows of rectangles.
 """
 from __future__ import annotations
 
@@ -33,48 +38,23 @@ def multislice_calls(sets_by_probe, parts) -> int:
     return t
 
 
-def row_by_row(sets_by_probe, region, M: int):
-    """Strategy 1: walk the region row-major, start a new part when the next probe would
-    push the part's translate count above M. ``region`` = (a0, b0, width, height)."""
+def _fits(sets_by_probe, region, w, h, M) -> bool:
+    return all(len(union(sets_by_probe, part)) <= M for part in tiling(region, w, h))
+
+
+def rectangles(sets_by_probe, region, M: int):
+    """The rectangle strategy (reading in the module docstring); ``region`` = (a0, b0, width,
+    height) in probe indices. Returns the parts in row-major order."""
     a0, b0, wd, ht = region
-    order = [(a0 + a, b0 + b) for b in range(ht) for a in range(wd)]
-    parts, cur, cur_u = [], [], set()
-    for p in order:
-        nu = cur_u | set(sets_by_probe[p])
-        if cur and len(nu) > M:
-            parts.append(cur)
-            cur, cur_u = [p], set(sets_by_probe[p])
-        else:
-            cur.append(p)
-            cur_u = nu
-    if cur:
-        parts.append(cur)
-    return parts
+    for w in range(wd, 0, -1):
+        for h in range(ht, 0, -1):
+            if _fits(sets_by_probe, region, w, h, M):
+                return tiling(region, w, h)
+    raise ValueError("M smaller than one probe's translate set")
 
 
-def rectangles(sets_by_probe, region, M: int, granule=(1, 1)):
-    """Strategy 2 (reading in the module docstring). Returns the parts, row-major."""
-    a0, b0, wd, ht = region
-    gx, gy = granule
-    best = None
-    for h in range(1, ht + 1):
-        if h % gy and h != ht:
-            continue
-        for w in range(1, wd + 1):
-            if w % gx and w != wd:
-                continue
-            if best is not None and w * h < best[0] * best[1]:
-                continue
-            parts = _tiling(region, w, h)
-            if all(len(union(sets_by_probe, part)) <= M for part in parts):
-                if best is None or w * h > best[0] * best[1] or (w * h == best[0] * best[1] and w > best[0]):
-                    best = (w, h)
-    if best is None:
-        raise ValueError("M smaller than one probe's translate set")
-    return _tiling(region, *best)
-
-
-def _tiling(region, w, h):
+def tiling(region, w, h):
+    """Row-major tiling of the region by w x h rectangles, clipped at its right and bottom."""
     a0, b0, wd, ht = region
     parts = []
     for by in range(0, ht, h):

@@ -377,9 +377,10 @@ class Server:
             import torch
             torch.cuda.current_stream().synchronize()
 
-    def build(self, specimen: int, opt: lma_optics, lat: lma_lattice, det: "_Detectors", nslices: int) -> int:
+    def build(self, specimen: int, opt: lma_optics, lat: lma_lattice, det: "_Detectors", nslices: int,
+              flags: int = 0) -> int:
         r = lma_request()
-        r.kind, r.specimen, r.nslices = LMA_REQ_BUILD, int(specimen), int(nslices)
+        r.kind, r.specimen, r.nslices, r.flags = LMA_REQ_BUILD, int(specimen), int(nslices), int(flags)
         r.optics, r.lattice, r.detectors = C.pointer(opt), C.pointer(lat), C.pointer(det.s)
         return self._submit(r, (opt, lat, det))
 

@@ -281,33 +281,12 @@ int auto_batch(const HostPlan& h) {
   return (int)std::max<int64_t>(1, std::min<int64_t>(b, 4096));
 }
 
-// launch bookkeeping for kernel timing
-struct Launch {
-  lma_plan* p;
-  const char* name;
-  hipEvent_t a = nullptr;
-  Launch(lma_plan* plan, const char* n) : p(plan), name(n) {
-    if (!p->timing) return;
-    a = take_event(p);
-    (void)hipEventRecord(a, p->stream);
-  }
-  static hipEvent_t take_event(lma_plan* p) {
-    if (!p->event_pool.empty()) {
-      hipEvent_t e = p->event_pool.back();
-      p->event_pool.pop_back();
-      return e;
-    }
-    hipEvent_t e = nullptr;
-    (void)hipEventCreate(&e);
-    return e;
-  }
-  void done() {
-    if (!p->timing) return;
-    hipEvent_t b = take_event(p);
-    (void)hipEventRecord(b, p->stream);
-    p->pending.push_back({name, a, b});
-  }
-};
+// launch bookkeeping for kernel timing. A plan that times its launches holds a fixed pool of
+// kTimingEvents events, created by lma_set_timing; each launch records a pair. When the pool
+// runs dry, the recorded pairs are read out (the stream is synchronised) and their events
+// return to the pool, so the live events stay bounded however many launches a call makes (a
+// medium-workload propagation makes about 6,500).
+constexpr size_t kTimingEvents = 256;
 
 void collect_timing(lma_plan* p) {
   if (p->pending.empty()) return;
@@ -327,6 +306,37 @@ void collect_timing(lma_plan* p) {
   }
   p->pending.clear();
 }
+
+struct Launch {
+  lma_plan* p;
+  const char* name;
+  hipEvent_t a = nullptr;
+  Launch(lma_plan* plan, const char* n) : p(plan), name(n) {
+    if (!p->timing) return;
+    a = take_event(p);
+    if (a && hipEventRecord(a, p->stream) != hipSuccess) {
+      p->event_pool.push_back(a);
+      a = nullptr;
+    }
+  }
+  static hipEvent_t take_event(lma_plan* p) {
+    if (p->event_pool.empty()) collect_timing(p);
+    if (p->event_pool.empty()) return nullptr;
+    hipEvent_t e = p->event_pool.back();
+    p->event_pool.pop_back();
+    return e;
+  }
+  void done() {
+    if (!a) return;   // timing off, or this launch is not timed
+    hipEvent_t b = take_event(p);
+    if (!b || hipEventRecord(b, p->stream) != hipSuccess) {
+      if (b) p->event_pool.push_back(b);
+      p->event_pool.push_back(a);
+      return;
+    }
+    p->pending.push_back({name, a, b});
+  }
+};
 
 #define LAUNCH(plan, name, call)                                                          \
   do {                                                                                    \
@@ -538,6 +548,10 @@ lma::dev::Stencil stencil(const lma_plan* p) {
   c.abf = p->d_stencil_abf;
   c.ww = h.ww;
   c.wh = h.wh;
+  c.pa0 = 0;
+  c.pa1 = h.ww;
+  c.pb0 = 0;
+  c.pb1 = h.wh;
   c.chunk_start = p->d_chunk_start;
   c.chunk_len = p->d_chunk_len;
   c.chunk_mask = p->d_chunk_mask;
@@ -702,8 +716,7 @@ lma_status lma_build_basis(const lma_optics* optics, const lma_lattice* lattice,
       }
       if (max_rows >= 0 && (int64_t)h.rows.size() > max_rows) {
         std::string why;
-        const int gx = p->st.ok ? 8 : h.ncls_x, gy = p->st.ok ? 8 : h.ncls_y;
-        if (!lma::build_partition(h, max_rows, gx, gy, &p->pp, &why)) {
+        if (!lma::build_partition(h, max_rows, &p->pp, &why)) {
           delete p;
           return fail(LMA_ERR_OOM, why);
         }
@@ -944,10 +957,16 @@ lma_status lma_image(lma_plan* plan, const float* potential, int32_t nslices, do
       if (plan->st.ok) {
         lma::dev::Stencil c = stencil(plan);
         c.row_of = plan->d_part_row_of + j * NT;
+        // the super-tiles (8 x 8 probes, aligned) that meet the rectangle; only the
+        // rectangle's probes are added to the image
         c.tile_x0 = q.a0 / 8;
         c.tile_y0 = q.b0 / 8;
-        c.tiles_x = (q.w + 7) / 8;
-        c.tiles_y = (q.h + 7) / 8;
+        c.tiles_x = (q.a0 + q.w - 1) / 8 - c.tile_x0 + 1;
+        c.tiles_y = (q.b0 + q.h - 1) / 8 - c.tile_y0 + 1;
+        c.pa0 = q.a0;
+        c.pa1 = q.a0 + q.w;
+        c.pb0 = q.b0;
+        c.pb1 = q.b0 + q.h;
         LAUNCH(plan, "contract_mfma", lma::dev::contract_stencil(c, plan->stream));
       } else {
         lma::dev::Contraction c = contraction(plan);
@@ -1462,6 +1481,20 @@ lma_status lma_set_timing(lma_plan* p, int32_t enable) {
   if (!p) return fail(LMA_ERR_ARG, "plan is null");
   if (p->host_only) return fail(LMA_ERR_STATE, "host-only plan has no device state");
   collect_timing(p);
+  if (enable && p->event_pool.size() < kTimingEvents) {
+    while (p->event_pool.size() < kTimingEvents) {
+      hipEvent_t e = nullptr;
+      const hipError_t err = hipEventCreate(&e);
+      if (err != hipSuccess) {
+        (void)hipGetLastError();
+        for (hipEvent_t x : p->event_pool) (void)hipEventDestroy(x);
+        p->event_pool.clear();
+        p->timing = false;
+        return fail(LMA_ERR_DEVICE, std::string("timing events: hipEventCreate: ") + hipGetErrorString(err));
+      }
+      p->event_pool.push_back(e);
+    }
+  }
   p->timing = enable != 0;
   return LMA_OK;
 }

@@ -1004,7 +1004,7 @@ __global__ __launch_bounds__(256) void k_contract_mfma(Stencil c) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int bx = ti * 8 + (wv & 1) * 4 + r;
-      if (bx < c.ww && by < c.wh) {
+      if (bx >= c.pa0 && bx < c.pa1 && by >= c.pb0 && by < c.pb1) {
         const double v = val[r] * c.scale;
         for (int d = 0; d < c.ndet; ++d)
           if (mask & (1u << d)) atomicAdd(c.img + (int64_t)d * stride + (int64_t)by * c.ww + bx, v);
@@ -1469,7 +1469,7 @@ __global__ __launch_bounds__(512) void k_contract_mfma2(Stencil c) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int bx = ti * 8 + (sb & 1) * 4 + r;
-      if (bx < c.ww && by < c.wh) {
+      if (bx >= c.pa0 && bx < c.pa1 && by >= c.pb0 && by < c.pb1) {
         const double v = val[r] * c.scale;
         for (int d = 0; d < c.ndet; ++d)
           if (mask & (1u << d)) atomicAdd(c.img + (int64_t)d * stride + (int64_t)by * c.ww + bx, v);
@@ -1560,7 +1560,7 @@ __global__ __launch_bounds__(512) void k_contract_mfma2_dma(Stencil c) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int bx = ti * 8 + (sb & 1) * 4 + r;
-      if (bx < c.ww && by < c.wh) {
+      if (bx >= c.pa0 && bx < c.pa1 && by >= c.pb0 && by < c.pb1) {
         const double v = val[r] * c.scale;
         for (int d = 0; d < c.ndet; ++d)
           if (mask & (1u << d)) atomicAdd(c.img + (int64_t)d * stride + (int64_t)by * c.ww + bx, v);
@@ -1699,7 +1699,7 @@ __global__ __launch_bounds__(512) void k_contract_bf16(Stencil c) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int bx = ti * 8 + (sb & 1) * 4 + r;
-      if (bx < c.ww && by < c.wh) {
+      if (bx >= c.pa0 && bx < c.pa1 && by >= c.pb0 && by < c.pb1) {
         const double v = val[r] * c.scale;
         for (int d = 0; d < c.ndet; ++d)
           if (mask & (1u << d)) atomicAdd(c.img + (int64_t)d * stride + (int64_t)by * c.ww + bx, v);

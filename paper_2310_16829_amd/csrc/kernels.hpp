@@ -71,6 +71,8 @@ struct Stencil {
   const int32_t* ks_off = nullptr;   // [nks]
   const float2* a = nullptr;         // [nks][64] A fragments
   int ww = 0, wh = 0;
+  int pa0 = 0, pa1 = 0, pb0 = 0, pb1 = 0;  // probes [pa0, pa1) x [pb0, pb1) of the window are
+                                           // added to the image; the others are not formed
   const int32_t* chunk_start = nullptr;
   const int32_t* chunk_len = nullptr;
   const uint32_t* chunk_mask = nullptr;

@@ -38,48 +38,37 @@ std::vector<int32_t> rect_translates(const HostPlan& h, int a0, int b0, int w, i
   return out;
 }
 
-// candidate sides: multiples of g below n, and n itself
-std::vector<int> sides(int n, int g) {
-  std::vector<int> v;
-  for (int s = g; s < n; s += g) v.push_back(s);
-  v.push_back(n);
-  return v;
-}
-
 }  // namespace
 
-bool build_partition(const HostPlan& h, int64_t max_rows, int gx, int gy, PartPlan* pp, std::string* why) {
+bool build_partition(const HostPlan& h, int64_t max_rows, PartPlan* pp, std::string* why) {
   *pp = PartPlan();
   pp->max_rows = max_rows;
-  pp->gx = gx;
-  pp->gy = gy;
   std::vector<uint8_t> mark((size_t)h.n_translates(), 0);
-  // With sides multiples of the granules (themselves multiples of the coefficient-set counts)
-  // every full rectangle of the tiling is a whole-translate shift of the first one, so its
-  // translate count is the first one's; clipped edge rectangles are subsets of a full one.
-  auto count = [&](int w, int hh) { return (int64_t)rect_translates(h, 0, 0, w, hh, &mark).size(); };
-  const std::vector<int> ws = sides(h.ww, gx), hs = sides(h.wh, gy);
+  // every part of the row-major tiling by w x hh rectangles (edge ones clipped) needs at most
+  // max_rows translates
+  auto fits = [&](int w, int hh) {
+    for (int b0 = 0; b0 < h.wh; b0 += hh)
+      for (int a0 = 0; a0 < h.ww; a0 += w)
+        if ((int64_t)rect_translates(h, a0, b0, std::min(w, h.ww - a0), std::min(hh, h.wh - b0), &mark).size() >
+            max_rows)
+          return false;
+    return true;
+  };
+  // the widest rectangles first, then the tallest at that width. A tiling that fits at some
+  // height fits at height 1 (each one-row part lies inside a part of the taller tiling), so the
+  // widest usable width is the widest whose one-row tiling fits.
   int bw = 0, bh = 0;
-  for (int w : ws) {
-    // largest feasible height for this width (the count grows with the height)
-    int lo = -1, hi = (int)hs.size() - 1;
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) / 2;
-      if (count(w, hs[mid]) <= max_rows) lo = mid;
-      else hi = mid - 1;
-    }
-    if (lo < 0) break;   // wider rectangles need at least as many translates
-    const int hh = hs[lo];
-    if ((int64_t)w * hh > (int64_t)bw * bh || ((int64_t)w * hh == (int64_t)bw * bh && w > bw)) {
-      bw = w;
-      bh = hh;
-    }
-  }
+  for (int w = h.ww; w >= 1 && bw == 0; --w)
+    if (fits(w, 1)) bw = w;
   if (bw == 0) {
-    *why = "the residency budget holds fewer translates than one " + std::to_string(gx) + " x " +
-           std::to_string(gy) + " rectangle of probes needs";
+    *why = "the residency budget holds fewer translates than one probe needs";
     return false;
   }
+  for (int hh = h.wh; hh >= 1; --hh)
+    if (fits(bw, hh)) {
+      bh = hh;
+      break;
+    }
   pp->w = bw;
   pp->h = bh;
   const int64_t NT = h.n_translates();

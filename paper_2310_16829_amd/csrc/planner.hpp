@@ -121,11 +121,11 @@ namespace lma {
 
 // Partition of the scan window into rectangles P_1..P_l under a residency budget of M
 // propagated translates (Sec. 4.2.4, rectangle strategy). Every rectangle but those clipped
-// at the window's right and bottom edges has the same size w x h: among the candidate sizes
-// (sides multiples of the granules gx, gy, or the whole window side) the one of largest area,
-// ties to the wider, whose translate set I_{f,P_j,L} holds at most M translates. Parts are
-// taken row-major; translates shared by consecutive parts stay resident, so the number of
-// multislice runs is T = sum_j |I_{f,P_j,L}| - sum_j |I_{f,P_j,L} cap I_{f,P_{j+1},L}|.
+// at the window's right and bottom edges has the same size w x h: the widest (up to the
+// window width) whose row-major tiling keeps every part's translate set I_{f,P_j,L} within M
+// translates, and at that width the tallest. Parts are taken row-major; translates shared by
+// consecutive parts stay resident, so the number of multislice runs is
+// T = sum_j |I_{f,P_j,L}| - sum_j |I_{f,P_j,L} cap I_{f,P_{j+1},L}|.
 struct PartPlan {
   struct Part {
     int a0 = 0, b0 = 0, w = 0, h = 0;        // probes, relative to the window origin
@@ -135,7 +135,6 @@ struct PartPlan {
     std::vector<int32_t> row_of;             // [Rfy*Rfx] -> resident row while this part is formed, or -1
   };
   int64_t max_rows = 0;          // M
-  int gx = 1, gy = 1;            // side granules
   int w = 0, h = 0;              // rectangle size
   int64_t slots = 0;             // resident rows needed: max_j |I_{f,P_j,L}|
   int64_t multislice_calls = 0;  // T
@@ -146,8 +145,8 @@ struct PartPlan {
 void probe_translates(const HostPlan& h, int a, int b, std::vector<int32_t>* out);
 
 // Rectangle partition of the window for at most max_rows resident translates. Returns false
-// (with a reason) when even one granule-sized rectangle needs more than max_rows.
-bool build_partition(const HostPlan& h, int64_t max_rows, int gx, int gy, PartPlan* pp, std::string* why);
+// (with a reason) when even one probe needs more than max_rows.
+bool build_partition(const HostPlan& h, int64_t max_rows, PartPlan* pp, std::string* why);
 
 }  // namespace lma
 

@@ -8,6 +8,7 @@
 #include <deque>
 #include <map>
 #include <mutex>
+#include <set>
 #include <string>
 #include <thread>
 #include <vector>
@@ -48,6 +49,7 @@ struct lma_server {
   std::condition_variable work_cv, done_cv;
   std::deque<Request> queue;
   std::map<int64_t, Done> done;
+  std::set<int64_t> active;               // tickets queued or running
   std::vector<Specimen> spec;
   std::vector<std::thread> workers;
   int64_t budget = 0, in_use = 0, next_ticket = 1;
@@ -68,7 +70,7 @@ struct lma_server {
         build_seen |= is_build;
         continue;
       }
-      if (is_build) {
+      if (is_build && !spec[s].plan) {
         if (build_seen || in_use + it->need > budget) {
           build_seen = true;
           continue;
@@ -76,6 +78,7 @@ struct lma_server {
         in_use += it->need;
         spec[s].bytes = it->need;
       }
+      // a build for a resident specimen is refused when it runs: no bytes are admitted for it
       spec[s].busy = true;
       *out = std::move(*it);
       queue.erase(it);
@@ -96,9 +99,14 @@ struct lma_server {
       return s == LMA_OK;
     };
     if (r.kind == LMA_REQ_BUILD) {
+      if (sp.plan) {
+        *msg = "specimen " + std::to_string(r.specimen) + " is already resident (release it first)";
+        return LMA_ERR_STATE;
+      }
       lma_detectors d{(int32_t)q.inner.size(), q.inner.data(), q.outer.data()};
       lma_plan* plan = nullptr;
-      if (check(lma_build_basis(&q.optics, &q.lattice, &d, nullptr, LMA_OWN_STREAM, &plan))) sp.plan = plan;
+      const int32_t flags = (r.flags & LMA_HOST_ONLY) ? LMA_HOST_ONLY : LMA_OWN_STREAM;
+      if (check(lma_build_basis(&q.optics, &q.lattice, &d, nullptr, flags, &plan))) sp.plan = plan;
       return st;
     }
     if (r.kind == LMA_REQ_RELEASE) {
@@ -131,6 +139,7 @@ struct lma_server {
       d.status = LMA_ERR_OOM;
       d.message = "server stopped before the request could be admitted";
       done[q.ticket] = std::move(d);
+      active.erase(q.ticket);
       queue.pop_front();
     }
     done_cv.notify_all();
@@ -163,12 +172,15 @@ struct lma_server {
       --running;
       Specimen& sp = spec[q.r.specimen];
       sp.busy = false;
+      // a release frees the specimen's bytes, and so does a build that left no plan; a refused
+      // build for a resident specimen admitted none
       const bool freed = (q.r.kind == LMA_REQ_RELEASE) || (q.r.kind == LMA_REQ_BUILD && !sp.plan);
       if (freed) {
         in_use -= sp.bytes;
         sp.bytes = 0;
       }
       done[q.ticket] = std::move(d);
+      active.erase(q.ticket);
       done_cv.notify_all();
       work_cv.notify_all();
     }
@@ -245,6 +257,7 @@ lma_status lma_server_submit(lma_server* s, const lma_request* r, int64_t* ticke
     if (s->stopping) return server_fail(LMA_ERR_STATE, "server is stopping");
     q.ticket = s->next_ticket++;
     *ticket = q.ticket;
+    s->active.insert(q.ticket);
     s->queue.push_back(std::move(q));
   }
   s->work_cv.notify_all();
@@ -255,11 +268,9 @@ lma_status lma_server_wait(lma_server* s, int64_t ticket, double* latency_ms, do
   if (!s) return server_fail(LMA_ERR_ARG, "server is null");
   std::unique_lock<std::mutex> lk(s->m);
   if (ticket < 1 || ticket >= s->next_ticket) return server_fail(LMA_ERR_ARG, "unknown ticket");
-  s->done_cv.wait(lk, [&] {
-    if (s->done.count(ticket)) return true;
-    // a ticket neither queued, running nor done was already waited for
-    return false;
-  });
+  // a ticket neither queued, running nor done was already waited for
+  s->done_cv.wait(lk, [&] { return s->done.count(ticket) || !s->active.count(ticket); });
+  if (!s->done.count(ticket)) return server_fail(LMA_ERR_ARG, "ticket " + std::to_string(ticket) + " was already waited for");
   Done d = std::move(s->done[ticket]);
   s->done.erase(ticket);
   lk.unlock();

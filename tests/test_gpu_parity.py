@@ -18,12 +18,17 @@ from oracle.lma import LMA, Lattice, phonon_average, recompute_sets
 from oracle.multislice import Setup, plain_image
 from synth import WORKLOADS, potential_slices
 from synth.specimen import edit_column, potential_from_atoms
-from tests._cases import det_rad, longest_zero_run, rel_l2
+from tests._cases import (c64_basis, c64_exit_spectrum, c64_lma_image, c64_plain_image, det_rad, longest_zero_run,
+                          rel_l2, ring_floor)
 
 pytestmark = pytest.mark.gpu
 
 TOL32 = 1e-4
 TOL_BF16 = 1e-3
+# the paper's detectors (Fig. lma_inputoutputerror): BF 0-15, ADF 16-40, HAADF 41-200 mrad;
+# the tiny workload's own 70-200 mrad ring (clipped by the band at 83.6 mrad, ~1e-13 of the
+# incident intensity) is checked in the tests that also measure its FP32 floor
+PAPER_RINGS = det_rad(WORKLOADS["medium"])
 
 
 def say(*a):
@@ -44,7 +49,7 @@ def build(w, L=None, scan=None, R=None, f=1, offset=None, window=(0, 0, 0, 0), p
         R = (nx // w.basis_px * f, ny // w.basis_px * f)
     L = w.L if L is None else L
     offset = offset or w.offset_frac
-    rings = detectors or det_rad(w)
+    rings = detectors or PAPER_RINGS
     lat = lma.lattice(scan[0], scan[1], R[0], R[1], f, offset, L, precision, window, batch, hbm_budget_bytes=budget,
                       basis_kind=basis_kind, basis_param=basis_param, prop_window=prop_window)
     plan = lma.Plan(opt, lat, lma.detectors(rings), flags=flags)
@@ -67,21 +72,21 @@ def per_det(gpu, ref):
     return [rel_l2(gpu[r], ref[r]) for r in range(ref.shape[0])]
 
 
-RESOLVABLE = 1e-6   # ring intensity fraction above the FP32 noise floor
+FLOOR_FACTOR = 4.0
 
 
-def image_errors(gpu, ref, tol, wave_tol=TOL32):
-    """Checks an image against the oracle. Rings whose mean intensity is at least RESOLVABLE
-    of the (unit) incident intensity must agree to ``tol`` in relative L2. Every pixel of
-    every ring must satisfy the bound that the exit-wave tolerance e implies by
-    Cauchy-Schwarz: |dI| <= 2 e sqrt(I) + e^2 (incident intensity 1). Returns the per-ring
-    relative L2 errors."""
+def image_errors(gpu, ref, tol, floor=None):
+    """Checks an image against the oracle, ring by ring (relative L2 over the image). Every
+    ring must agree to ``tol``, except a ring whose FP32 floor (``floor[r]``: the relative L2
+    that the same steps carried out in complex64 leave against the oracle, on the same input
+    and probes) already exceeds ``tol``: that ring must stay within FLOOR_FACTOR times its
+    floor. Returns the per-ring errors."""
     errs = per_det(gpu, ref)
     for r in range(ref.shape[0]):
-        if np.mean(ref[r]) >= RESOLVABLE:
+        if floor is not None and floor[r] > tol:
+            assert errs[r] <= FLOOR_FACTOR * floor[r], f"ring {r}: relative L2 {errs[r]:.3e} > {FLOOR_FACTOR} x floor {floor[r]:.3e}"
+        else:
             assert errs[r] < tol, f"ring {r}: relative L2 {errs[r]:.3e} >= {tol}"
-        bound = 2 * wave_tol * np.sqrt(np.abs(ref[r])) + wave_tol ** 2
-        assert np.all(np.abs(gpu[r] - ref[r]) <= bound), f"ring {r} outside the exit-wave bound"
     return errs
 
 
@@ -89,13 +94,30 @@ def image_errors(gpu, ref, tol, wave_tol=TOL32):
 def tiny():
     w = WORKLOADS["tiny"]
     v = potential_slices(w, 0)
-    plan, st, ol = build(w)
+    plan, st, ol = build(w, detectors=det_rad(w))
     say("tiny: oracle LMA (1024 translates)")
     om = LMA(st, ol)
-    basis = om.propagate(v, [(t % ol.Rfx, t // ol.Rfx) for t in range(ol.n_translates)])
+    allt = [(t % ol.Rfx, t // ol.Rfx) for t in range(ol.n_translates)]
+    basis = om.propagate(v, allt)
     img_lma = om.image(v, basis=basis)
     img_plain = plain_image(st, v)
-    return dict(w=w, v=v, plan=plan, st=st, ol=ol, om=om, basis=basis, img_lma=img_lma, img_plain=img_plain)
+    say("tiny: the same images in complex64 (FP32 floor)")
+    cb = c64_basis(om, v, allt)
+    probes = [(a, b) for b in range(st.Py) for a in range(st.Px)]
+    c64_lma, c64_plain = c64_lma_image(om, cb, probes), c64_plain_image(st, v, probes)
+    d = dict(w=w, v=v, plan=plan, st=st, ol=ol, om=om, basis=basis, img_lma=img_lma, img_plain=img_plain,
+             c64_basis=cb, c64_lma=c64_lma, c64_plain=c64_plain,
+             floor_lma=ring_floor(c64_lma, img_lma, probes), floor_plain=ring_floor(c64_plain, img_plain, probes))
+    say("  FP32 floor per ring: LMA", ["%.1e" % x for x in d["floor_lma"]], "plain",
+        ["%.1e" % x for x in d["floor_plain"]])
+    return d
+
+
+def tiny_floor(tiny, kind, plan):
+    """FP32 floor per ring of the tiny workload's image over the probes of ``plan``'s window."""
+    probes = window_probes(plan)
+    c64, ref = (tiny["c64_lma"], tiny["img_lma"]) if kind == "lma" else (tiny["c64_plain"], tiny["img_plain"])
+    return ring_floor(c64, ref, probes)
 
 
 def test_tiny_exit_waves(tiny):
@@ -118,14 +140,14 @@ def test_tiny_lma_image(tiny):
     plan = tiny["plan"]
     plan.propagate(tiny["v"])
     img = plan.probe_image()
-    e = image_errors(img, tiny["img_lma"], TOL32)
+    e = image_errors(img, tiny["img_lma"], TOL32, tiny["floor_lma"])
     say("  per-detector rel L2", e)
 
 
 def test_tiny_plain_image(tiny):
     say("tiny plain image")
     img = tiny["plan"].plain_image(tiny["v"])
-    e = image_errors(img, tiny["img_plain"], TOL32)
+    e = image_errors(img, tiny["img_plain"], TOL32, tiny["floor_plain"])
     say("  per-detector rel L2", e)
 
 
@@ -171,10 +193,10 @@ def test_band_gap_extremes(tiny, bandlimit):
     probes = [(0, 0), (7, 11), (15, 15)]
     pimg = plan.plain_image(v)
     pref = plain_image(st, v, probes)
-    for a, b in probes:
-        for r in range(pref.shape[0]):
-            want, have = pref[r, b, a], pimg[r, b, a]
-            assert abs(have - want) <= TOL32 * abs(want) + 2e-4 * np.sqrt(abs(want)) + 1e-8, (a, b, r)
+    idx = (slice(None), [b for _, b in probes], [a for a, _ in probes])
+    e = per_det(pimg[idx], pref[idx])
+    say(f"    plain pixels {probes}: per-detector rel L2 {e}")
+    assert max(e) < TOL32
     plan.close()
 
 
@@ -200,6 +222,7 @@ def test_4d_and_3d_outputs(tiny):
     width, nbins = 0.005, 17
     rad = plan.probe_radial(width, nbins)
     ref_rad = np.zeros((nbins, 16, 16))
+    c64_rad = np.zeros((nbins, 16, 16))
     worst = [0.0, 0.0]
     for a, b in probes:
         spec = om.exit_spectrum(a, b, basis)
@@ -207,9 +230,13 @@ def test_4d_and_3d_outputs(tiny):
         ep = rel_l2(ppat[b, a], _pattern_ref(pspec[(a, b)], pixels, flat))
         worst = [max(worst[0], e), max(worst[1], ep)]
         ref_rad[:, b, a] = ph.annulus_values(spec, st.lx, st.ly, st.wavelength, width, nbins, pixels)
+        c64_spec = c64_exit_spectrum(om, a, b, tiny["c64_basis"]).astype(np.complex128)
+        c64_rad[:, b, a] = ph.annulus_values(c64_spec, st.lx, st.ly, st.wavelength, width, nbins, pixels)
     say(f"  4-D patterns, worst probe rel L2: LMA {worst[0]:.2e}, plain {worst[1]:.2e}")
     assert worst[0] < TOL32 and worst[1] < TOL32
-    errs = image_errors(rad, ref_rad, TOL32)
+    rad_floor = per_det(c64_rad, ref_rad)
+    say("  3-D annuli FP32 floor", ["%.1e" % x for x in rad_floor])
+    errs = image_errors(rad, ref_rad, TOL32, rad_floor)
     say("  3-D annuli rel L2", ["%.1e" % x for x in errs])
     # a pattern summed over a ring's pixels gives that ring's 2-D value
     img = plan.probe_image()
@@ -235,11 +262,11 @@ def test_mfma_and_per_pixel_contractions(tiny):
     plan.propagate(tiny["v"])
     a = plan.probe_image()
     b = plan.probe_image(flags=lma.LMA_CONTRACT_PER_PIXEL)
-    ea = image_errors(a, tiny["img_lma"], TOL32)
-    eb = image_errors(b, tiny["img_lma"], TOL32)
+    ea = image_errors(a, tiny["img_lma"], TOL32, tiny["floor_lma"])
+    eb = image_errors(b, tiny["img_lma"], TOL32, tiny["floor_lma"])
     say("  MFMA", ea, " per-pixel", eb)
     for r in range(a.shape[0]):
-        if np.mean(b[r]) >= RESOLVABLE:
+        if tiny["floor_lma"][r] < 1e-5:
             assert rel_l2(a[r], b[r]) < 1e-5
 
 
@@ -262,10 +289,10 @@ def test_mfma_contraction_k_steps(tiny, L, ks_template):
     b = plan.probe_image(flags=lma.LMA_CONTRACT_PER_PIXEL)
     ref = LMA(st, ol).image(tiny["v"], basis=tiny["basis"])
     e = image_errors(a, ref, TOL32)
-    say("  per-detector rel L2", e)
+    eb = image_errors(b, ref, TOL32)
+    say("  per-detector rel L2: MFMA", e, "per-pixel", eb)
     for r in range(a.shape[0]):
-        if np.mean(b[r]) >= RESOLVABLE:
-            assert rel_l2(a[r], b[r]) < 1e-5
+        assert rel_l2(a[r], b[r]) < TOL32
 
 
 # Split BF16 against the FP32 basis: bf16 rounds to nearest with an 8-bit significand, so
@@ -290,10 +317,9 @@ def test_split_bf16_contraction_k_steps(tiny, L):
     bplan.propagate(tiny["v"])
     a, b = plan.probe_image(), bplan.probe_image()
     for r in range(a.shape[0]):
-        if np.mean(a[r]) >= RESOLVABLE:
-            e = rel_l2(b[r], a[r])
-            say(f"  ring {r}: split vs FP32 rel L2 {e:.2e}")
-            assert e < SPLIT_VS_FP32
+        e = rel_l2(b[r], a[r])
+        say(f"  ring {r}: split vs FP32 rel L2 {e:.2e}")
+        assert e < SPLIT_VS_FP32
     image_errors(b, LMA(st, ol).image(tiny["v"], basis=tiny["basis"]), TOL_BF16)
     plan.close()
     bplan.close()
@@ -320,13 +346,13 @@ def test_partitioned_image_case1(tiny):
     say("tiny: rectangle partition, M = 600")
     w = tiny["w"]
     D = tiny["plan"].info().n_pix
-    plan, _, _ = build(w, budget=600 * D * 8)
+    plan, _, _ = build(w, budget=600 * D * 8, detectors=det_rad(w))
     i = plan.info()
     say(f"  {i.n_parts} rectangles of {i.part_w} x {i.part_h}, {i.multislice_calls} multislice runs, "
         f"{i.resident_rows} resident rows")
     assert i.partitioned == 1 and i.n_parts > 1 and i.contract_kernel == 1 and i.resident_rows <= 600
     img = plan.image(tiny["v"])
-    image_errors(img, tiny["img_lma"], TOL32)
+    image_errors(img, tiny["img_lma"], TOL32, tiny["floor_lma"])
     tiny["plan"].propagate(tiny["v"])
     ref = tiny["plan"].probe_image()
     assert np.allclose(img, ref, rtol=1e-12, atol=0)
@@ -336,6 +362,18 @@ def test_partitioned_image_case1(tiny):
         assert e.value.status == lma._lib.LMA_ERR_STATE
     # on a plan that is not partitioned, lma_image is propagate + probe_image
     assert np.allclose(tiny["plan"].image(tiny["v"]), ref, rtol=1e-12, atol=0)
+    # budgets whose rectangles do not align with the MFMA's 8 x 8-probe super-tiles: each
+    # super-tile is formed once per rectangle it meets, with only that rectangle's probes added
+    unaligned = 0
+    for M in (400, 260, 150):
+        plan2, _, _ = build(w, budget=M * D * 8, detectors=det_rad(w))
+        i2 = plan2.info()
+        say(f"  M = {M}: {i2.n_parts} rectangles of {i2.part_w} x {i2.part_h}, {i2.multislice_calls} runs")
+        assert i2.partitioned == 1 and i2.resident_rows <= M and i2.contract_kernel == 1
+        unaligned += (i2.part_w % 8 != 0) or (i2.part_h % 8 != 0)
+        assert np.allclose(plan2.image(tiny["v"]), ref, rtol=1e-12, atol=0)
+        plan2.close()
+    assert unaligned > 0
 
 
 def test_partitioned_image_case2_three_sets():
@@ -369,8 +407,8 @@ def test_gaussian_input_wave(tiny):
     ref = om.image(tiny["v"])
     e = image_errors(img, ref, TOL32)
     say(f"  vs oracle, per-detector rel L2 {e}; probe residual {plan.info().max_residual:.3e}")
-    say("  LMA(Gaussian) vs plain, per-detector rel L2", per_det(img, tiny["img_plain"]))
-    image_errors(plan.plain_image(tiny["v"]), tiny["img_plain"], TOL32)
+    say("  LMA(Gaussian) vs plain, per-detector rel L2", per_det(img, tiny["img_plain"][1:]))
+    image_errors(plan.plain_image(tiny["v"]), tiny["img_plain"][1:], TOL32)
 
 
 def test_windowed_translates(tiny):
@@ -436,9 +474,9 @@ def test_single_slice_and_vacuum(tiny):
 
 def test_tiny_split_bf16_image(tiny):
     say("tiny split-bf16 LMA image")
-    plan, _, _ = build(tiny["w"], precision=lma.LMA_GEMM_SPLIT_BF16)
+    plan, _, _ = build(tiny["w"], precision=lma.LMA_GEMM_SPLIT_BF16, detectors=det_rad(tiny["w"]))
     plan.propagate(tiny["v"])
-    e = image_errors(plan.probe_image(), tiny["img_lma"], TOL_BF16)
+    e = image_errors(plan.probe_image(), tiny["img_lma"], TOL_BF16, tiny["floor_lma"])
     say("  per-detector rel L2", e)
 
 
@@ -446,12 +484,12 @@ def test_lma_with_L1_on_probe_lattice_equals_plain(tiny):
     # u = psi_0, I = P, f = 1, L = 1 (Sec. 4.2.3): both GPU paths give the plain image
     say("L = 1 special case")
     w = tiny["w"]
-    plan, _, _ = build(w, L=1, R=w.scan, offset=(0.0, 0.0))
+    plan, _, _ = build(w, L=1, R=w.scan, offset=(0.0, 0.0), detectors=det_rad(w))
     plan.propagate(tiny["v"])
     a = plan.probe_image()
     b = plan.plain_image(tiny["v"])
     assert max(per_det(a, b)) < 1e-6
-    image_errors(a, tiny["img_plain"], TOL32)
+    image_errors(a, tiny["img_plain"], TOL32, tiny["floor_plain"])
 
 
 def test_ragged_batch_and_wrapping_window(tiny):
@@ -459,13 +497,13 @@ def test_ragged_batch_and_wrapping_window(tiny):
     w = tiny["w"]
     n_rows = build(w, window=(13, 14, 3, 2))[0].info().n_rows
     batch = next(b for b in (7, 9, 11, 13) if n_rows % b)
-    plan, st, ol = build(w, window=(13, 14, 3, 2), batch=batch)
+    plan, st, ol = build(w, window=(13, 14, 3, 2), batch=batch, detectors=det_rad(w))
     plan.propagate(tiny["v"])
     img = plan.probe_image()
     ref = crop(tiny["img_lma"], plan)
-    image_errors(img, ref, TOL32)
+    image_errors(img, ref, TOL32, tiny_floor(tiny, "lma", plan))
     pimg = plan.plain_image(tiny["v"])
-    image_errors(pimg, crop(tiny["img_plain"], plan), TOL32)
+    image_errors(pimg, crop(tiny["img_plain"], plan), TOL32, tiny_floor(tiny, "plain", plan))
 
 
 def test_case2_nonsquare_f2():
@@ -608,12 +646,12 @@ def test_local_recompute(tiny):
         mixed = dict(b0)
         for t in R:
             mixed[t] = b1[t]
-        ref = om.image(v1, basis=mixed)
+        ref = om.image(v1, basis=mixed)[1:]       # the oracle's set-up has the tiny workload's rings
         e = image_errors(img, ref, TOL32)
         say("  vs oracle with the same selection, per-detector rel L2", e)
-        say("  approximation vs full recompute (oracle), per-detector rel L2", per_det(ref, full_ref))
+        say("  approximation vs full recompute (oracle), per-detector rel L2", per_det(ref, full_ref[1:]))
     assert (nt, npr) == (ol.n_translates, st.Px * st.Py)
-    image_errors(img, full_ref, TOL32)
+    image_errors(img, full_ref[1:], TOL32)
 
 
 def test_local_recompute_with_translate_windows(tiny):

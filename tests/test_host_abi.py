@@ -235,10 +235,15 @@ def _partition_case(w, M, **kw):
     ol = oracle_lattice(w, st, **{k: v for k, v in kw.items() if k in ("R", "f", "offset", "L")})
     a0, b0, ww, wh = window
     sets = {(a, b): ol.nearest((a0 + a) % st.Px, (b0 + b) % st.Py) for b in range(wh) for a in range(ww)}
-    granule = (8, 8) if stencil else (ol.ncls_x, ol.ncls_y)
-    parts = rectangles(sets, (0, 0, ww, wh), M, granule)
+    parts = rectangles(sets, (0, 0, ww, wh), M)
     assert info.partitioned == 1
     assert (info.part_w, info.part_h) == (max(a for a, _ in parts[0]) + 1, max(b for _, b in parts[0]) + 1)
+    # the same parts in the same order
+    assert info.n_parts == len(parts)
+    pw, ph = info.part_w, info.part_h
+    for j, q in enumerate(parts):
+        a_lo, b_lo = min(a for a, _ in q), min(b for _, b in q)
+        assert (a_lo, b_lo) == ((j % -(-ww // pw)) * pw, (j // -(-ww // pw)) * ph)
     assert info.n_parts == len(parts)
     assert info.multislice_calls == multislice_calls(sets, parts)
     assert info.resident_rows == max(len(union(sets, q)) for q in parts) <= M
@@ -246,13 +251,16 @@ def _partition_case(w, M, **kw):
 
 
 def test_partition_case1_matches_oracle_rectangles():
-    # tiny workload (Case 1, two translates per probe step), MFMA contraction: sides in 8s
+    # tiny workload (Case 1, two translates per probe step), MFMA contraction; rectangles of
+    # any side (probes outside a rectangle in its super-tiles are not formed)
     info, parts = _partition_case(WORKLOADS["tiny"], 600)
     assert info.contract_kernel == 1 and info.n_parts > 1
+    for M in (150, 260, 400):
+        _partition_case(WORKLOADS["tiny"], M)
 
 
 def test_partition_case2_three_sets_matches_oracle_rectangles():
-    # Case 2 with three coefficient sets per axis: per-pixel contraction, sides in 3s
+    # Case 2 with three coefficient sets per axis: per-pixel contraction
     w = WORKLOADS["tiny"]
     info, parts = _partition_case(w, 30, scan=(48, 48), R=(16, 16), L=12, window=(5, 7, 13, 10))
     assert info.contract_kernel == 0 and info.n_parts > 1
@@ -308,6 +316,47 @@ def test_server_reports_request_failures():
         lat, svc = s.wait(s.release(1))
         assert lat >= svc >= 0.0
         assert s.in_use() == 0
+
+
+def test_server_refuses_a_second_build_of_a_resident_specimen():
+    # host-only specimens: a BUILD of a specimen that is already resident fails with
+    # LMA_ERR_STATE and neither replaces its plan nor admits more bytes; after a RELEASE the
+    # same slot builds again
+    w = WORKLOADS["tiny"]
+    opt, lat, det = _plan_args(w)
+    need = lma.footprint(opt, lat, det, w.nslices)
+    with lma.Server(2, 2, 3 * need) as s:
+        s.wait(s.build(0, opt, lat, det, w.nslices, flags=lma.LMA_HOST_ONLY))
+        assert s.in_use() == need
+        n_rows = s.plan_info(0).n_rows
+        with pytest.raises(lma.LmaError) as e:
+            s.wait(s.build(0, opt, lat, det, w.nslices, flags=lma.LMA_HOST_ONLY))
+        assert e.value.status == _lib.LMA_ERR_STATE and "already resident" in str(e.value)
+        assert s.in_use() == need and s.plan_info(0).n_rows == n_rows
+        s.wait(s.release(0))
+        assert s.in_use() == 0
+        s.wait(s.build(0, opt, lat, det, w.nslices, flags=lma.LMA_HOST_ONLY))
+        assert s.in_use() == need
+        # a host-only specimen answers image requests with LMA_ERR_STATE
+        with pytest.raises(lma.LmaError) as e:
+            s.wait(s.image(0, np.zeros((w.nslices, w.ny, w.nx), np.float32), np.zeros((4, 16, 16))))
+        assert e.value.status == _lib.LMA_ERR_STATE
+
+
+def test_server_wait_twice_returns_an_error():
+    # each ticket is waited for once; a second wait returns LMA_ERR_ARG at once instead of
+    # blocking, and so does a ticket that was never issued
+    w = WORKLOADS["tiny"]
+    opt, lat, det = _plan_args(w)
+    with lma.Server(1, 2, 1 << 40) as s:
+        t = s.build(1, opt, lat, det, w.nslices, flags=lma.LMA_HOST_ONLY)
+        s.wait(t)
+        with pytest.raises(lma.LmaError) as e:
+            s.wait(t)
+        assert e.value.status == _lib.LMA_ERR_ARG and "already waited" in str(e.value)
+        with pytest.raises(lma.LmaError) as e:
+            s.wait(t + 1000)
+        assert e.value.status == _lib.LMA_ERR_ARG
 
 
 def test_server_build_failure_returns_its_bytes():

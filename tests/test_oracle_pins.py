@@ -137,6 +137,33 @@ def test_defocus_equals_free_propagation():
     assert rel_l2(psi, stz.probe(0, 0)) < 1e-12
 
 
+def test_aberration_stationary_phase_centroid():
+    # eq. aberration_function through its physical effect: a wave packet A(k) exp(-i chi(k))
+    # with a narrow real A around k0 is centred at <x> = <grad chi> / (2 pi) (the position
+    # operator is i/(2 pi) d/dk in Fourier space; the A A' term integrates to zero). With
+    # chi = 1/2 pi C_s lambda^3 |k|^4 - pi Z lambda |k|^2 the gradient over 2 pi is
+    # C_s lambda^3 |k|^2 k - Z lambda k, averaged here with the weights |A|^2. A wrong
+    # factor or power in the C_s term, or a wrong sign, moves the centroid by Angstroms.
+    nx = ny = 512
+    lx = ly = 160.0
+    lam = 0.0250793
+    k0, s = np.array([0.5, 0.2]), 0.04
+    kx, ky, k2 = ph.k_grid(nx, ny, lx, ly)
+    amp = np.exp(-((kx - k0[0]) ** 2 + (ky - k0[1]) ** 2) / (2 * s * s))
+    w2 = amp ** 2 / (amp ** 2).sum()
+    x = np.arange(nx) * (lx / nx)
+    x = x - lx * np.round(x / lx)                  # minimum image about the origin
+    y = np.arange(ny) * (ly / ny)
+    y = y - ly * np.round(y / ly)
+    for cs, z in ((1.0e7, 0.0), (1.0e7, 100.0), (-2.0e6, -50.0)):
+        psi = np.fft.ifft2(amp * np.exp(-1j * ph.aberration(k2, lam, z, cs)))
+        p = np.abs(psi) ** 2
+        got = np.array([(p.sum(axis=0) * x).sum(), (p.sum(axis=1) * y).sum()]) / p.sum()
+        want = np.array([(w2 * (cs * lam ** 3 * k2 * kg - z * lam * kg)).sum() for kg in (kx, ky)])
+        assert np.abs(got - want).max() < 1e-6, (cs, z, got, want)
+        assert np.abs(want).max() > 1.0              # the shift is many pixels (0.31 A)
+
+
 # ---------------------------------------------------------------------------------------
 # transmission, norm, linearity, equivariance
 # ---------------------------------------------------------------------------------------
@@ -461,6 +488,37 @@ def test_printed_minimum_multislice_calls_L75():
     strips = [[(a, b) for a in range(48)] for b in range(48)]
     assert multislice_calls(sets, strips) == 1077
     assert multislice_calls(sets, [list(sets.keys())]) == 1077
+
+
+def test_rectangle_partition_second_example():
+    # Fig. lmastrategy_examples, bottom row (L = 51): the rectangle strategy keeps about a
+    # quarter of the trivial strategy's multislice solutions (P_1 = P, T = |I_{f,P,L}|) in
+    # memory, yet makes exactly as many multislice calls, with l = 48 rectangles
+    from oracle.partition import rectangles, tiling
+    sets = _partition_example_sets(51)
+    region = (0, 0, 48, 48)
+    U = len(union(sets, sets.keys()))               # the paper prints 953; our tie rule gives 955
+    assert abs(U - 953) <= 2
+    M = -(-U // 4)
+    parts = rectangles(sets, region, M)
+    assert len(parts) == 48
+    assert multislice_calls(sets, parts) == U
+    peak = max(len(union(sets, q)) for q in parts)
+    assert peak <= M and peak > 0.2 * U
+    # no partition beats the trivial strategy's count, which is reached with M = |I_{f,P,L}|;
+    # every partition covers the sub-image once, its parts within M
+    for m in (60, 100, 170, M, 300, 600, U):
+        parts = rectangles(sets, region, m)
+        cover = [p for q in parts for p in q]
+        assert sorted(cover) == sorted(sets.keys())
+        assert all(len(union(sets, q)) <= m for q in parts)
+        assert multislice_calls(sets, parts) >= U
+    assert len(rectangles(sets, region, U)) == 1
+    # the widest rectangles first: at M no wider tiling fits, and the chosen height is the
+    # tallest that fits at that width
+    parts = rectangles(sets, region, M)
+    h = max(b for _, b in parts[0]) + 1
+    assert any(len(union(sets, q)) > M for q in tiling(region, 48, h + 1))
 
 
 def test_cost_model_log_base_two():
