@@ -75,73 +75,83 @@ def _oracle_init(spec):
                             [(a * 1e-3, b * 1e-3) for _, a, b in w.detectors])
 
 
-def sample_translates(w, plan, n):
-    """n translates spread over the plan's rows: (row, exact position) from the oracle's lattice."""
-    import numpy as np
-    from oracle.lma import Lattice
-    if not hasattr(_oracle_wave, "st"):
-        _oracle_init(WORKLOAD)
-    R = (w.nx // w.basis_px, w.ny // w.basis_px)
-    ol = Lattice(_oracle_wave.st, R, 1, w.offset_frac, w.L)
-    rows = plan.rows()
-    pick = np.linspace(0, len(rows) - 1, n).round().astype(int)
-    return [(int(r), tuple(float(c) for c in ol.translate_position(int(rows[r]) % ol.Rfx, int(rows[r]) // ol.Rfx)))
-            for r in pick]
+BASELINE_PROBE = (37, 101)       # the medium workload's probe whose LMA pixel the oracle forms
 
 
-def cpu_baseline(w, n_translates, n_probes, plan=None):
-    """Times the oracle on a sample (waves propagated in parallel, one process per core, then
-    the per-probe combination and detector sums) and scales to one full image of one phonon
-    configuration: T = |I_f| t_wave + |P| t_probe. The sample waves are translates of the plan's
-    lattice: with `plan` holding the basis of phonon configuration 0, their exit waves at the
-    detector pixels are also compared with the GPU's (relative L2 per translate)."""
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(w, n_translates, n_probes, plan, images):
+    """Times the oracle on a sample and scales to one full image of one phonon configuration,
+    T = |I_f| t_wave + |P| t_probe. The sample is one probe's LMA pixel: its L nearest translates
+    propagated by the FP64 oracle in parallel (one process per core), then their combination
+    with the oracle's own least-squares coefficients and the detector sums. With `plan` holding
+    the FP32 basis of phonon configuration 0, the same run states the GPU's error against the
+    oracle: every sampled translate's exit wave at the detector pixels, and the LMA pixel of
+    `images` ({name: [n_det][Py][Px] image of configuration 0}) per detector."""
     import numpy as np
     from concurrent.futures import ProcessPoolExecutor
     from oracle import physics as ph
-    cores = max(1, min(16, len(os.sched_getaffinity(0))))
-    n_waves = cores
-    if plan is not None:
-        sample = sample_translates(w, plan, n_waves)
-        positions = [p for _, p in sample]
-    else:
-        rng = np.random.default_rng(0)
-        positions = [(float(x), float(y)) for x, y in rng.uniform(0, w.lx, size=(n_waves, 2))]
+    from oracle.lma import Lattice, least_squares
+    affinity = len(os.sched_getaffinity(0))
+    # one GPU's share of the host: 16 cores (the process count this machine allows per GPU)
+    cores = max(1, min(16, affinity))
+    if not hasattr(_oracle_wave, "st"):
+        _oracle_init(WORKLOAD)
+    st = _oracle_wave.st
+    R = (w.nx // w.basis_px, w.ny // w.basis_px)
+    ol = Lattice(st, R, 1, w.offset_frac, w.L)
+    nbr = ol.nearest(*BASELINE_PROBE)
+    positions = [tuple(float(c) for c in ol.translate_position(ta, tb)) for ta, tb in nbr]
     with ProcessPoolExecutor(cores, initializer=_oracle_init, initargs=(WORKLOAD,)) as ex:
         list(ex.map(_oracle_wave, positions[:cores]))          # start-up and potential generation
         t0 = time.perf_counter()
         spectra = list(ex.map(_oracle_wave, positions))
         t_waves = time.perf_counter() - t0
-    t_wave = t_waves / n_waves                                  # wall time per wave at `cores` workers
-    # combination of L translates and the detector sums for a few probes (single process)
-    if not hasattr(_oracle_wave, "st"):
-        _oracle_init(WORKLOAD)
-    st = _oracle_wave.st
-    n_p = 2
+    t_wave = t_waves / len(positions)                          # wall time per wave at `cores` workers
+    alpha, _, resid = least_squares(st, ol, st.spec0, *BASELINE_PROBE)
     t0 = time.perf_counter()
-    for _ in range(n_p):
-        spec = np.zeros_like(spectra[0])
-        for j in range(w.L):
-            spec += (0.5 + 0.1j) * spectra[j % len(spectra)]
-        ph.detector_values(spec, st.masks)
-    t_probe = (time.perf_counter() - t0) / n_p / cores          # probes spread over the same cores
+    spec = np.zeros_like(spectra[0])
+    for c, sp in zip(alpha, spectra):
+        spec += c * sp
+    ref = ph.detector_values(spec, st.masks)
+    t_probe = (time.perf_counter() - t0) / cores                # probes spread over the same cores
     t_image = n_translates * t_wave + n_probes * t_probe
     t_plain = n_probes * t_wave
-    errors = None
-    if plan is not None:
-        flat, _ = plan.detector_pixels()
-        errors = []
-        for (r, _), ref in zip(sample, spectra):
-            ref = ref.ravel()[flat]
-            got = plan.basis_rows(r, 1)[0]
-            errors.append(float(np.linalg.norm(got - ref) / np.linalg.norm(ref)))
+    flat, _ = plan.detector_pixels()
+    rows = plan.rows()
+    row_of = {int(t): r for r, t in enumerate(rows)}
+    wave_err = []
+    for (ta, tb), sp in zip(nbr, spectra):
+        got = plan.basis_rows(row_of[tb * ol.Rfx + ta], 1)[0]
+        ref_w = sp.ravel()[flat]
+        wave_err.append(float(np.linalg.norm(got - ref_w) / np.linalg.norm(ref_w)))
+    a, b = BASELINE_PROBE
+    pixel_err = {name: [float(abs(img[r, b, a] - ref[r]) / abs(ref[r])) for r in range(len(ref))]
+                 for name, img in images.items()}
     return {
         "value": n_probes / t_image, "unit": "STEM pixels/s", "cores": cores, "kind": "oracle",
+        "cpu_model": cpu_model(), "cores_in_affinity": affinity,
         "plain_value": n_probes / t_plain,
-        "sample": (f"{n_waves} medium-workload waves (512^2, 100 slices) propagated by the FP64 oracle on "
-                   f"{cores} processes ({t_wave:.3f} s wall per wave) plus {n_p} probe combinations of "
-                   f"L={w.L} translates ({t_probe * cores:.3f} s each); scaled to one phonon image: "
-                   f"{n_translates} translates + {n_probes} probes"),
-        "exit_wave_rel_l2_vs_oracle": errors,
+        "sample": (f"the LMA pixel of probe {BASELINE_PROBE} of the medium workload: its {len(positions)} nearest "
+                   f"translates (512^2, 100 slices) propagated by the FP64 oracle on {cores} processes "
+                   f"({t_wave:.3f} s wall per wave), combined with the oracle's least-squares coefficients "
+                   f"({t_probe * cores:.3f} s); scaled to one phonon image: {n_translates} translates + "
+                   f"{n_probes} probes"),
+        "error_vs_oracle": {
+            "exit_wave_rel_l2_max": max(wave_err), "exit_wave_rel_l2_median": float(np.median(wave_err)),
+            "translates": len(wave_err), "lma_pixel": list(BASELINE_PROBE),
+            "lma_pixel_rel_err_per_detector": pixel_err, "probe_lsq_residual": float(resid),
+            "what": "GPU exit waves (FP32) at the detector pixels and the LMA pixel's detector values against the "
+                    "FP64 oracle, phonon configuration 0"},
     }
 
 
@@ -331,7 +341,7 @@ def summarize_pmc(run_dirs, n_cu=256):
     print(json.dumps({"kernel_source_hash": kernel_source_hash(), "workload": WORKLOAD, "kernels": out}, indent=1))
 
 
-def serve(rates=(2.0, 10.0, 50.0, 200.0), n_requests=60, slots=4):
+def serve(rates=(2.0, 10.0, 50.0, 200.0), n_requests=60, slots=4, emit=True, cap_seconds=8.0):
     """Serving under Poisson arrivals, once with FP32 basis rows and contraction and once with
     the basis stored as split BF16 (hi + lo): see serve_mode."""
     import paper_2310_16829_amd as lma
@@ -340,11 +350,13 @@ def serve(rates=(2.0, 10.0, 50.0, 200.0), n_requests=60, slots=4):
                     "images, 30 % local edits", "slots": slots}
     for name, prec in (("fp32", lma.LMA_GEMM_FP32), ("split_bf16", lma.LMA_GEMM_SPLIT_BF16)):
         log(f"serve: {name}")
-        out[name] = serve_mode(prec, rates, n_requests, slots)
-    print(json.dumps(out), flush=True)
+        out[name] = serve_mode(prec, rates, n_requests, slots, cap_seconds)
+    if emit:
+        print(json.dumps(out), flush=True)
+    return out
 
 
-def serve_mode(precision, rates, n_requests, slots):
+def serve_mode(precision, rates, n_requests, slots, cap_seconds=8.0):
     """Six resident specimens of mixed sizes (128^2 x 10 slices, 256^2 x 20 slices, the 512^2 x
     100-slice medium specimen on a 16 x 16-probe window), 70 % image requests (a new
     frozen-phonon configuration of a random specimen) and 30 % local edits (one raised 12 x
@@ -386,7 +398,8 @@ def serve_mode(precision, rates, n_requests, slots):
             srv.wait(srv.image(k, s["pots"][0], torch.zeros(s["shape"], dtype=torch.float64, device="cuda")))
         out["resident_bytes"] = srv.in_use()
         for rate in rates:
-            n_req = max(16, min(n_requests, int(rate * 8)))     # about 8 s of arrivals at most
+            # about cap_seconds of arrivals at most (all n_requests without a cap)
+            n_req = n_requests if cap_seconds is None else max(16, min(n_requests, int(rate * cap_seconds)))
             gaps = rng.exponential(1.0 / rate, size=n_req)
             reqs = []
             for i in range(n_req):
@@ -435,7 +448,7 @@ def serve_mode(precision, rates, n_requests, slots):
     return out
 
 
-def paper_shaped():
+def paper_shaped(emit=True):
     """The paper's local-edit experiment in shape (1024^2 px over 84.536 x 79.941 A, scan
     424 x 400, I = P + p/2, f = 2, L = 59, 200 kV, 26 mrad, Z = 100 A, C_s = -2000 A) with the
     synthetic FCC specimen, 50 slices, one phonon configuration: the full LMA image (42400
@@ -487,7 +500,7 @@ def paper_shaped():
     plain_rate = win[2] * win[3] / t_plain
     err = {name: float(np.linalg.norm(lma_win[r] - pimg[r]) / np.linalg.norm(pimg[r]))
            for r, (name, _, _) in enumerate(w.detectors)}
-    print(json.dumps({
+    res = {
         "study": "paper-shaped stand-in: 1024^2 px over 84.536 x 79.941 A, scan 424x400, I=P+p/2, f=2, L=59, "
                  "200 kV, 26 mrad, Z=100 A, Cs=-2000 A, synthetic FCC specimen, 50 slices of 2 A, one configuration",
         "translates": info.n_rows, "probes": n_probes, "detector_pixels": info.n_pix,
@@ -497,7 +510,10 @@ def paper_shaped():
         "lma_pixels_per_s": lma_rate,
         "plain_window": list(win), "plain_seconds": t_plain, "plain_pixels_per_s": plain_rate,
         "speedup_vs_plain": lma_rate / plain_rate,
-        "lma_vs_plain_rel_l2_on_window": err}), flush=True)
+        "lma_vs_plain_rel_l2_on_window": err}
+    if emit:
+        print(json.dumps(res), flush=True)
+    return res
 
 
 def uneven(n_specimens=64):
@@ -605,12 +621,14 @@ def uneven(n_specimens=64):
 
 
 def contraction_roofline(plan, info, kt, split=False):
-    """Flop rate of the contraction launch. Algorithmic: 8 real flops per complex multiply-add,
-    |P| L D of them. Implemented (MFMA kernel): every 4 x 4-probe sub-block multiplies a 16 x K
-    coefficient block (K = contract_k translates, zero where a translate is not a neighbour)
-    into 16-pixel slabs of each detector-pixel chunk: FP32, four real 16x16x4 products per K-step
-    of 4 translates; split BF16 (K up to 320), twelve bf16 16x16x16 products per 16 translates,
-    against the dense bf16 MFMA peak."""
+    """Flop rate of the contraction launch against the MFMA peak of its data type. Useful
+    (algorithmic) flops: 8 real flops per complex multiply-add, |P| L D of them; with the basis
+    stored as split BF16 each real product is three bf16 products (hi hi, hi lo, lo hi), so its
+    algorithmic count is 3 x that. `frac` is on those. Implemented flops (MFMA kernel): every
+    4 x 4-probe sub-block multiplies a 16 x K coefficient block (K = contract_k translates, zero
+    where a translate is not a neighbour) into 16-pixel slabs of each detector-pixel chunk: FP32,
+    four real 16x16x4 products per K-step of 4 translates; split BF16, twelve bf16 16x16x16
+    products per 16 translates; reported beside it."""
     name = "contract_mfma" if info.contract_kernel else "contract"
     if name not in kt:
         return None
@@ -628,22 +646,26 @@ def contraction_roofline(plan, info, kt, split=False):
         else:
             run += 1
     alg = 8.0 * info.n_probes * info.L * info.n_pix
+    nks = info.contract_k // 4
+    bf16 = split and nks <= 80
+    alg_mfma = alg * (3 if bf16 else 1)
+    peak, dt = (BF16_MFMA_PEAK_TFLOPS, "bf16") if bf16 else (FP32_MFMA_PEAK_TFLOPS, "f32")
     out = {"kernel": name, "avg_launch_ms": avg_s * 1e3, "algorithmic_tflop": alg / 1e12,
            "useful_tflops": alg / avg_s / 1e12, "L": info.L, "K": info.contract_k,
-           "traffic": load_traffic(name), "algorithmic_bytes": 8.0 * info.n_rows * info.n_pix}
+           "traffic": load_traffic(name), "algorithmic_bytes": 8.0 * info.n_rows * info.n_pix,
+           "bound": "mfma", "mfma_dtype": dt, "achieved": alg_mfma / avg_s / 1e12, "peak": peak,
+           "unit": "TFLOP/s", "frac": alg_mfma / avg_s / 1e12 / peak,
+           "what": ("useful flops: 8 |P| L D" + (" x 3 bf16 products per real product" if bf16 else "") +
+                    " per launch over its hipEvent-timed duration")}
     if info.contract_kernel:
         ww, wh = plan.window[2], plan.window[3]
         sub_blocks = 4 * (-(-ww // 8)) * (-(-wh // 8))
-        nks = info.contract_k // 4
-        if split and nks <= 80:
+        if bf16:
             impl = sub_blocks * slabs * (-(-nks // 4)) * 12 * (2 * 16 * 16 * 16)
-            peak, dt = BF16_MFMA_PEAK_TFLOPS, "bf16"
         else:
             impl = sub_blocks * slabs * nks * 4 * (2 * 16 * 16 * 4)
-            peak, dt = FP32_MFMA_PEAK_TFLOPS, "f32"
-        out.update({"bound": "mfma", "mfma_dtype": dt, "implemented_tflop": impl / 1e12,
-                    "achieved": impl / avg_s / 1e12, "peak": peak, "unit": "TFLOP/s",
-                    "frac": impl / avg_s / 1e12 / peak, "density": info.L / info.contract_k})
+        out.update({"implemented_tflop": impl / 1e12, "implemented_tflops": impl / avg_s / 1e12,
+                    "implemented_frac": impl / avg_s / 1e12 / peak, "density": info.L / info.contract_k})
     return out
 
 
@@ -655,6 +677,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--batch", type=int, default=0)
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")
+    ap.add_argument("--serve-rate", type=float, default=20.0, help="arrival rate of the serving leg (requests/s)")
+    ap.add_argument("--serve-requests", type=int, default=200, help="requests of the serving leg per precision")
+    ap.add_argument("--no-paper-shaped", action="store_true", help="skip the paper-shaped LMA-vs-plain leg")
     ap.add_argument("--no-kernel-timing", action="store_true",
                     help="skip the extra step that times every launch with hipEvents")
     ap.add_argument("--spacing-study", action="store_true",
@@ -810,10 +836,12 @@ def main():
     # contraction on the bf16 MFMA (propagation untimed), its launch time and its image error
     # against the FP32 basis
     split = None
+    images = {}
+    ref = torch.zeros_like(img)
+    plan.propagate(pots[0])
+    plan.probe_image(ref)
+    images["fp32"] = ref.cpu().numpy()
     if not args.no_kernel_timing:
-        ref = torch.zeros_like(img)
-        plan.propagate(pots[0])
-        plan.probe_image(ref)
         slat = lma.lattice(w.scan[0], w.scan[1], R[0], R[1], 1, w.offset_frac, w.L, lma.LMA_GEMM_SPLIT_BF16,
                            batch=args.batch)
         with lma.Plan(opt, slat, lma.detectors(rings)) as sp:
@@ -825,7 +853,8 @@ def main():
                 sp.probe_image(simg)
             skt = sp.timing(reset=True)
             split = contraction_roofline(sp, sp.info(), skt, split=True)
-        r, s_ = ref.cpu().numpy(), simg.cpu().numpy()
+        r, s_ = images["fp32"], simg.cpu().numpy()
+        images["split_bf16"] = s_
         split["image_rel_l2_vs_fp32_basis"] = [float(np.linalg.norm(s_[i] - r[i]) / np.linalg.norm(r[i]))
                                                for i in range(r.shape[0])]
     out = {
@@ -865,15 +894,22 @@ def main():
     }
     if not args.no_cpu_baseline:
         log("bench: oracle CPU baseline")
-        if split is None:
-            plan.propagate(pots[0])
         torch.cuda.synchronize()
-        out["cpu_baseline"] = cpu_baseline(w, n_waves, n_probes, plan)
-        e = out["cpu_baseline"]["exit_wave_rel_l2_vs_oracle"]
-        out["error_vs_oracle"] = {"exit_wave_rel_l2_max": max(e), "translates": len(e),
-                                  "what": "FP32 GPU exit waves at the detector pixels against the FP64 oracle, "
-                                          "phonon configuration 0, translates spread over the lattice"}
+        out["cpu_baseline"] = cpu_baseline(w, n_waves, n_probes, plan, images)
+        out["error_vs_oracle"] = out["cpu_baseline"].pop("error_vs_oracle")
+        if split is not None:
+            split["lma_pixel_rel_err_vs_oracle"] = out["error_vs_oracle"]["lma_pixel_rel_err_per_detector"]["split_bf16"]
     plan.close()
+    del pots
+    torch.cuda.empty_cache()
+    if not args.no_serving:
+        # loaded latency: the request loop under Poisson arrivals of mixed-size image and edit requests
+        log("bench: serving leg")
+        out["serving"] = serve(rates=(args.serve_rate,), n_requests=args.serve_requests, slots=4, emit=False,
+                               cap_seconds=None)
+    if not args.no_paper_shaped:
+        log("bench: paper-shaped leg")
+        out["paper_shaped"] = paper_shaped(emit=False)
     print(json.dumps(out), flush=True)
 
 

@@ -50,8 +50,16 @@ typedef struct lma_plan lma_plan;   /* opaque */
 /* lma_lattice.basis_kind: the input wave u whose translates are propagated (Sec. 4.2.3) */
 enum {
   LMA_BASIS_PROBE = 0,      /* u = psi_0^init, the probe at the origin                      */
-  LMA_BASIS_GAUSSIAN = 1    /* u = g_sigma(x) = exp(-|x|^2 / (2 sigma^2)), sigma = basis_param */
+  LMA_BASIS_GAUSSIAN = 1,   /* u = g_sigma(x) = exp(-|x|^2 / (2 sigma^2)), sigma = basis_param */
                             /* (Angstrom; 0 selects lambda / (2 alpha_max))                  */
+  LMA_BASIS_TRIGPOLY = 2    /* u(x, y) = phi_nx(2 pi x / lx) phi_ny(2 pi y / ly), the tensor   */
+                            /* product of localised trigonometric polynomials (Sec. 2, eq.   */
+                            /* rauhut) with the cell as their period; I_f must have 2n + 1   */
+                            /* points per axis (odd, at most the grid side), which fixes the */
+                            /* degrees. The translates span the frequencies |m| <= n, and the */
+                            /* coefficients are the closed form of Sec. 2 (M^-1 per axis), no */
+                            /* least squares: exact for probes inside that range when L =    */
+                            /* |I_f|; kept at the L nearest translates otherwise             */
 };
 /* lma_lattice.precision: arithmetic of the probe-coefficient contraction */
 enum { LMA_GEMM_FP32 = 0, LMA_GEMM_SPLIT_BF16 = 1 };

@@ -126,6 +126,46 @@ def least_squares(setup: Setup, lat: Lattice, spec_u: np.ndarray, a: int, b: int
     return alpha, nbr, res
 
 
+def trig_transform(n: int):
+    """(M, M^-1) of Sec. 2 for degree n: with W[k, j] = exp(-2 pi i j k / (2n + 1)) (the
+    modulation matrix; the printed entry lacks the i) and c_k = cos(k pi / (2n + 2)),
+    M = W diag(c) holds in row j the coefficients of the translate phi_n(t - 2 pi j / (2n + 1))
+    over the elementary waves exp(i k t) (W is symmetric), so a function with coefficient row
+    vector f has translate coefficients f M^-1. M^-1 = (1 / (2n + 1)) diag(1 / c) W*: the
+    paper prints the factor 1 / (2n + 1)^2, but W W* = (2n + 1) I (W / sqrt(2n + 1) is unitary),
+    so that factor gives M M^-1 = I / (2n + 1). Indices k, j run over -n..n."""
+    k = np.arange(-n, n + 1)
+    W = np.exp(-2j * np.pi * np.outer(k, k) / (2 * n + 1))
+    c = np.cos(k * np.pi / (2 * n + 2))
+    M = W @ np.diag(c)
+    Minv = np.diag(1.0 / c) @ W.conj().T / (2 * n + 1)
+    return M, Minv
+
+
+def trig_coefficients(setup: Setup, lat: "Lattice", spec_u: np.ndarray, a: int, b: int) -> np.ndarray:
+    """Closed-form coefficients of probe (a, b) over every translate of I_f for the tensor
+    trigonometric input wave (Sec. 2, Sec. 4.2.3): the cell is the period and I_f has
+    2n + 1 points per axis (R_f = 2n + 1). The probe's spectrum on K_+ (|k_x| <= n_x,
+    |k_y| <= n_y, grid frequency indices), divided by u's scale s (u_hat = s c_kx c_ky), times
+    M^-1 along each axis; the translate lattice's offset o enters as the probe shifted by -o.
+    Returns alpha[tb][ta] (translate (ta, tb) at (ta r_x f + o_x, tb r_y f + o_y)); frequencies
+    outside K_+ are dropped (projection of the probe onto span(u_i))."""
+    if lat.Rfx % 2 == 0 or lat.Rfy % 2 == 0:
+        raise ValueError("the trigonometric input wave needs an odd number of translates per axis")
+    nx_, ny_ = (lat.Rfx - 1) // 2, (lat.Rfy - 1) // 2
+    st = setup
+    px, py = setup.probe_position(a, b)
+    spec_p = ph.shift_spectrum(st.spec0, st.lx, st.ly, (px - float(lat.ox), py - float(lat.oy)))
+    kxs, kys = np.arange(-nx_, nx_ + 1), np.arange(-ny_, ny_ + 1)
+    f = spec_p[np.ix_(kys % st.ny, kxs % st.nx)] / spec_u[0, 0]      # [ky][kx], u_hat[0, 0] = s
+    _, Mx = trig_transform(nx_)
+    _, My = trig_transform(ny_)
+    # row-vector convention per axis: alpha[jy][jx] = sum_ky sum_kx f[ky][kx] My[ky, jy] Mx[kx, jx]
+    al = My.T @ f @ Mx                                                # [jy][jx], j = -n..n
+    # translate index ta = j mod (2n + 1)
+    return np.roll(np.roll(al, -ny_, axis=0), -nx_, axis=1)
+
+
 class LMA:
     """LMA with u = psi_0^init (Sec. 4.2.3). Coefficients are computed once per class
     (the Case 1 / Case 2 reuse of Sec. 4.2.2).
@@ -138,7 +178,8 @@ class LMA:
     embedded (zero outside) in the cell and the last propagation step is taken there, so the
     exit spectrum is P F(embedded wave) on the cell's frequency grid, as without a window."""
 
-    def __init__(self, setup: Setup, lat: Lattice, spec_u: np.ndarray | None = None, window=None):
+    def __init__(self, setup: Setup, lat: Lattice, spec_u: np.ndarray | None = None, window=None,
+                 coefficients: str = "least_squares"):
         self.setup, self.lat = setup, lat
         self.window = None if window is None else (int(window[0]), int(window[1]))
         self.spec_u = setup.spec0 if spec_u is None else spec_u
@@ -146,9 +187,17 @@ class LMA:
         self.residual = {}
         for sy in range(lat.ncls_y):
             for sx in range(lat.ncls_x):
-                al, _, res = least_squares(setup, lat, self.spec_u, sx, sy)
-                self.alpha[(sx, sy)] = al
-                self.residual[(sx, sy)] = res
+                if coefficients == "trigpoly":
+                    # the closed form over all of I_f, kept at the L nearest translates
+                    full = trig_coefficients(setup, lat, self.spec_u, sx, sy)
+                    self.alpha[(sx, sy)] = np.array([full[tb, ta] for ta, tb in lat.nearest(sx, sy)])
+                    target = setup.probe(sx, sy)
+                    self.residual[(sx, sy)] = (np.linalg.norm(target - self.approximant(sx, sy)) /
+                                               np.linalg.norm(target))
+                else:
+                    al, _, res = least_squares(setup, lat, self.spec_u, sx, sy)
+                    self.alpha[(sx, sy)] = al
+                    self.residual[(sx, sy)] = res
 
     def approximant(self, a: int, b: int) -> np.ndarray:
         """sum_j alpha_j u_{i_j} for probe (a, b) in real space."""

@@ -86,6 +86,27 @@ def gaussian_spectrum(nx, ny, lx, ly, sigma: float) -> np.ndarray:
     return np.fft.fft2(g)
 
 
+def trig_weights(n: int) -> np.ndarray:
+    """cos(k pi / (2n + 2)) for k = -n..n: the weights of the localised trigonometric polynomial
+    phi_n(t) = sum_k exp(i k t) cos(k pi / (2n + 2)) of eq. rauhut (index k + n)."""
+    k = np.arange(-n, n + 1)
+    return np.cos(k * np.pi / (2 * n + 2))
+
+
+def trigpoly_spectrum(nx, ny, lx, ly, n_x: int, n_y: int) -> np.ndarray:
+    """Input wave u(x, y) = phi_{n_x}(2 pi x / lx) phi_{n_y}(2 pi y / ly) of Sec. 2 / Sec. 4.2.3
+    (the tensor product of localised trigonometric polynomials, eq. rauhut, with the cell as
+    their period): phi_n evaluated at the grid points by its defining sum, the product taken,
+    scaled to unit L2 norm like the probe, then the DFT (sum_k |u_hat|^2 = XY)."""
+    def phi(n, npts, length):
+        t = 2.0 * np.pi * np.arange(npts) * (length / npts) / length
+        w = trig_weights(n)
+        return np.array([np.sum(w * np.exp(1j * np.arange(-n, n + 1) * tt)) for tt in t])
+    u = phi(n_y, ny, ly)[:, None] * phi(n_x, nx, lx)[None, :]
+    u = u / np.linalg.norm(u)
+    return np.fft.fft2(u)
+
+
 def shift_spectrum(spec: np.ndarray, lx: float, ly: float, pos) -> np.ndarray:
     """Spectrum of f(. - pos): multiply by the modulation mu_{-pos}(k) = exp(-2 pi i k.pos)
     (Sec. 4.1, translations become modulations)."""

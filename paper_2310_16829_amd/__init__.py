@@ -13,14 +13,14 @@ import os
 import numpy as np
 
 from . import _lib
-from ._lib import (LMA_ACCUMULATE, LMA_AUTOTUNE, LMA_BASIS_GAUSSIAN, LMA_BASIS_PROBE, LMA_CONTRACT_PER_PIXEL,
+from ._lib import (LMA_ACCUMULATE, LMA_AUTOTUNE, LMA_BASIS_GAUSSIAN, LMA_BASIS_PROBE, LMA_BASIS_TRIGPOLY, LMA_CONTRACT_PER_PIXEL,
                    LMA_GEMM_FP32, LMA_GEMM_SPLIT_BF16, LMA_GRAPH, LMA_HOST_ONLY, LMA_OWN_STREAM, LMA_PTR_DEVICE,
                    LMA_REQ_BUILD, LMA_REQ_EDIT, LMA_REQ_IMAGE, LMA_REQ_PLAIN, LMA_REQ_RELEASE, lma_detectors,
                    lma_info, lma_kernel_time, lma_lattice, lma_optics, lma_request, lma_tuning)
 
 __all__ = ["LmaError", "Plan", "electron_constants", "footprint", "optics", "lattice", "detectors",
            "LMA_ACCUMULATE", "LMA_PTR_DEVICE", "LMA_HOST_ONLY", "LMA_GEMM_FP32", "LMA_GEMM_SPLIT_BF16",
-           "LMA_BASIS_PROBE", "LMA_BASIS_GAUSSIAN", "LMA_CONTRACT_PER_PIXEL", "LMA_OWN_STREAM", "LMA_AUTOTUNE",
+           "LMA_BASIS_PROBE", "LMA_BASIS_GAUSSIAN", "LMA_BASIS_TRIGPOLY", "LMA_CONTRACT_PER_PIXEL", "LMA_OWN_STREAM", "LMA_AUTOTUNE",
            "LMA_GRAPH", "Server", "Batch", "autotune", "lib"]
 
 

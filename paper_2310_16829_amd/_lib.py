@@ -8,7 +8,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liblma.so")
 
 LMA_OK, LMA_ERR_ARG, LMA_ERR_OOM, LMA_ERR_DEVICE, LMA_ERR_STATE, LMA_ERR_UNSUPPORTED = 0, -1, -2, -3, -4, -5
-LMA_BASIS_PROBE, LMA_BASIS_GAUSSIAN = 0, 1
+LMA_BASIS_PROBE, LMA_BASIS_GAUSSIAN, LMA_BASIS_TRIGPOLY = 0, 1, 2
 LMA_GEMM_FP32, LMA_GEMM_SPLIT_BF16 = 0, 1
 LMA_PTR_DEVICE, LMA_ACCUMULATE, LMA_HOST_ONLY, LMA_CONTRACT_PER_PIXEL, LMA_OWN_STREAM = 1, 2, 4, 8, 16
 LMA_AUTOTUNE, LMA_GRAPH = 32, 64

@@ -381,30 +381,42 @@ lma_status prepare_transmission(lma_plan* p, const float* potential, int nslices
   return LMA_OK;
 }
 
+// Buffers a slice loop works in: the wave batch (B waves, tiled), the transmission tables and
+// the image accumulator. The plan's own, or caller-provided ones of the same layout.
+struct WaveBufs {
+  float2* work;
+  const float2* trans;
+  double* img;
+  int B;
+};
+WaveBufs plan_bufs(const lma_plan* p) { return {p->d_work, p->d_trans, p->d_img, p->B}; }
+
 // multislice of waves [first, first + n) of a position list; the last column pass either
 // gathers the detector pixels into rows of `target` (wave_row != null; the resident basis
 // unless given) or reduces into the image (wave_out != null). Probe waves (no wave_row) start
 // from psi_0, translates from u.
 lma_status run_waves(lma_plan* p, const int64_t* d_u, const int32_t* d_row, const int32_t* d_out, int n, int nslices,
-                     void* target = nullptr, bool probes = false) {
+                     void* target = nullptr, bool probes = false, const WaveBufs* wb = nullptr) {
+  const WaveBufs bf = wb ? *wb : plan_bufs(p);
   const lma::dev::Tables T = tables(p);
   const int64_t XY = (int64_t)p->h.op.nx * p->h.op.ny;
   const int split = target ? 0 : p->h.lat.precision == LMA_GEMM_SPLIT_BF16;
   if (p->h.wnx > 0 && d_row && !probes) {
     // option (ii): translates on windows centred on them, the last step on the cell
+    if (bf.B > p->B) return fail(LMA_ERR_ARG, "wave batch larger than the window buffer");
     const lma::dev::Tables Tw = window_tables(p);
-    for (int first = 0; first < n; first += p->B) {
-      const int nb = std::min(p->B, n - first);
+    for (int first = 0; first < n; first += bf.B) {
+      const int nb = std::min(bf.B, n - first);
       const int64_t* u = d_u + 2 * (int64_t)first;
       LAUNCH(p, "init", lma::dev::init_waves(Tw, p->d_wwork, p->d_zero_u, nb, p->stream));
       for (int j = 0; j < nslices; ++j) {
         const bool last = j + 1 == nslices;
-        LAUNCH(p, "row_pass", lma::dev::row_pass_window(Tw, p->d_wwork, p->d_trans + (size_t)j * XY, T.nx, T.ny, u,
+        LAUNCH(p, "row_pass", lma::dev::row_pass_window(Tw, p->d_wwork, bf.trans + (size_t)j * XY, T.nx, T.ny, u,
                                                         T.Qx, T.Qy, last, j > 0, nb, p->stream));
         if (!last) LAUNCH(p, "col_pass", lma::dev::col_pass(Tw, p->d_wwork, nb, p->stream));
       }
-      LAUNCH(p, "embed", lma::dev::embed_windows(T, p->d_work, Tw, p->d_wwork, u, nb, p->stream));
-      LAUNCH(p, "col_gather", lma::dev::col_gather(T, p->d_work, nb, target ? target : p->d_basis, p->h.D(),
+      LAUNCH(p, "embed", lma::dev::embed_windows(T, bf.work, Tw, p->d_wwork, u, nb, p->stream));
+      LAUNCH(p, "col_gather", lma::dev::col_gather(T, bf.work, nb, target ? target : p->d_basis, p->h.D(),
                                                    d_row + first, split, p->stream));
     }
     return LMA_OK;
@@ -416,18 +428,18 @@ lma_status run_waves(lma_plan* p, const int64_t* d_u, const int32_t* d_row, cons
   if (from_u) Ti.specT = p->d_uspecT;
   Ti.ic0 = from_u ? p->uc0 : p->sc0;
   Ti.ic1 = from_u ? p->uc1 : p->sc1;
-  for (int first = 0; first < n; first += p->B) {
-    const int nb = std::min(p->B, n - first);
-    LAUNCH(p, "init", lma::dev::init_waves(Ti, p->d_work, d_u + 2 * (int64_t)first, nb, p->stream));
+  for (int first = 0; first < n; first += bf.B) {
+    const int nb = std::min(bf.B, n - first);
+    LAUNCH(p, "init", lma::dev::init_waves(Ti, bf.work, d_u + 2 * (int64_t)first, nb, p->stream));
     for (int j = 0; j < nslices; ++j) {
-      LAUNCH(p, "row_pass", lma::dev::row_pass(Ti, p->d_work, p->d_trans + (size_t)j * XY, nb, j > 0, p->stream));
+      LAUNCH(p, "row_pass", lma::dev::row_pass(Ti, bf.work, bf.trans + (size_t)j * XY, nb, j > 0, p->stream));
       if (j + 1 < nslices) {
-        LAUNCH(p, "col_pass", lma::dev::col_pass(T, p->d_work, nb, p->stream));
+        LAUNCH(p, "col_pass", lma::dev::col_pass(T, bf.work, nb, p->stream));
       } else if (d_row) {
-        LAUNCH(p, "col_gather", lma::dev::col_gather(T, p->d_work, nb, target ? target : p->d_basis, p->h.D(), d_row + first,
+        LAUNCH(p, "col_gather", lma::dev::col_gather(T, bf.work, nb, target ? target : p->d_basis, p->h.D(), d_row + first,
                                                      split, p->stream));
       } else {
-        LAUNCH(p, "col_reduce", lma::dev::col_reduce(T, p->d_work, nb, d_out + first, p->d_img, p->h.ndet,
+        LAUNCH(p, "col_reduce", lma::dev::col_reduce(T, bf.work, nb, d_out + first, bf.img, p->h.ndet,
                                                      p->h.n_probes(), (double)XY, p->stream));
       }
     }

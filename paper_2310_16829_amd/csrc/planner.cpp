@@ -143,9 +143,15 @@ lma_status check_arguments(const lma_optics* op, const lma_lattice* lat, const l
   if ((int64_t)rfx * rfy > (int64_t)1 << 28) { *err = "too many translates"; return LMA_ERR_UNSUPPORTED; }
   if (lat->L < 1 || (int64_t)lat->L > (int64_t)rfx * rfy) { *err = "L must be in [1, |I_f|]"; return LMA_ERR_ARG; }
   if (lat->L > 2048) { *err = "L above 2048"; return LMA_ERR_UNSUPPORTED; }
-  if (lat->basis_kind != LMA_BASIS_PROBE && lat->basis_kind != LMA_BASIS_GAUSSIAN) {
+  if (lat->basis_kind != LMA_BASIS_PROBE && lat->basis_kind != LMA_BASIS_GAUSSIAN &&
+      lat->basis_kind != LMA_BASIS_TRIGPOLY) {
     *err = "unknown input wave kind";
     return LMA_ERR_UNSUPPORTED;
+  }
+  if (lat->basis_kind == LMA_BASIS_TRIGPOLY &&
+      (rfx % 2 == 0 || rfy % 2 == 0 || rfx > op->nx || rfy > op->ny)) {
+    *err = "the trigonometric input wave needs an odd number of translates per axis (2n + 1), at most the grid side";
+    return LMA_ERR_ARG;
   }
   if (!std::isfinite(lat->basis_param) || lat->basis_param < 0.0) { *err = "basis_param must be >= 0"; return LMA_ERR_ARG; }
   if (lat->prop_nx != 0 || lat->prop_ny != 0) {
@@ -266,6 +272,26 @@ lma_status build_host_plan(const lma_optics* op, const lma_lattice* lat, const l
       for (int mx = 0; mx < nx; ++mx) {
         const double kx = (double)freq_index(mx, nx) / op->lx;
         const double g = std::exp(-2.0 * kPi * kPi * sg * sg * (kx * kx + ky * ky));
+        h.uspec[(size_t)my * nx + mx] = cd(g, 0.0);
+        s2 += g * g;
+      }
+    }
+    const double un = std::sqrt(XY / s2);
+    for (auto& u : h.uspec) u *= un;
+  } else if (lat->basis_kind == LMA_BASIS_TRIGPOLY) {
+    // u = phi_nx(2 pi x / lx) phi_ny(2 pi y / ly) with phi_n(t) = sum_{|k| <= n} e^{ikt}
+    // cos(k pi / (2n + 2)) (eq. rauhut), the cell as its period and 2n + 1 translates per axis:
+    // its DFT holds the weights at the grid frequencies |m| <= n and nothing else
+    const int nxd = (lat->rx / lat->f - 1) / 2, nyd = (lat->ry / lat->f - 1) / 2;
+    h.uspec.assign((size_t)nx * ny, cd(0.0));
+    double s2 = 0.0;
+    for (int my = 0; my < ny; ++my) {
+      const int ky = freq_index(my, ny);
+      if (std::abs(ky) > nyd) continue;
+      for (int mx = 0; mx < nx; ++mx) {
+        const int kx = freq_index(mx, nx);
+        if (std::abs(kx) > nxd) continue;
+        const double g = std::cos(kx * kPi / (2.0 * nxd + 2.0)) * std::cos(ky * kPi / (2.0 * nyd + 2.0));
         h.uspec[(size_t)my * nx + mx] = cd(g, 0.0);
         s2 += g * g;
       }
@@ -410,7 +436,31 @@ lma_status build_host_plan(const lma_optics* op, const lma_lattice* lat, const l
         bn2 += std::norm(b[r]);
       }
       const double rcond = 2.220446049250313e-16 * XY;
-      if (m < L) {
+      if (lat->basis_kind == LMA_BASIS_TRIGPOLY) {
+        // closed form (Sec. 2): the translates span the frequencies K_+ = {|m_x| <= n_x,
+        // |m_y| <= n_y}, and on K_+ the combination is an inverse DFT of length 2n + 1 per axis,
+        //   alpha_j = 1/(Rfx Rfy) sum_{k in K_+} psi_hat_p[k] / u_hat[k] e^{+2 pi i k.i_j}
+        // (M^-1 = diag(1/c) W* / (2n + 1) per axis); kept at the set's L nearest translates,
+        // with the relative residual of that combination over every frequency
+        std::vector<int32_t> kplus;
+        for (int r = 0; r < m; ++r)
+          if (std::abs(h.uspec[kidx[r]]) > 0.0) kplus.push_back(r);
+        const double inv = 1.0 / ((double)h.Rfx * (double)h.Rfy);
+        std::vector<cd> approx(m, cd(0.0));
+        for (int j = 0; j < L; ++j) {
+          const int t = h.set_nbr[(size_t)s * L + j];
+          const int64_t txu = ((t % h.Rfx) * h.stepTx + h.oxu) % h.Qx;
+          const int64_t tyu = ((t / h.Rfx) * h.stepTy + h.oyu) % h.Qy;
+          cd acc(0.0);
+          for (int r : kplus) acc += b[r] / h.uspec[kidx[r]] * std::conj(phase(kidx[r], txu, tyu));
+          acc *= inv;
+          h.alpha[(size_t)s * L + j] = acc;
+          for (int r = 0; r < m; ++r) approx[r] += acc * A[(size_t)j * m + r];
+        }
+        double rn2 = 0.0;
+        for (int r = 0; r < m; ++r) rn2 += std::norm(b[r] - approx[r]);
+        h.residual[s] = std::sqrt(rn2 / bn2);
+      } else if (m < L) {
         // fewer equations than unknowns: pad with zero rows (the minimum-norm solution is unchanged)
         std::vector<cd> A2((size_t)L * L, cd(0.0)), b2(L, cd(0.0));
         for (int j = 0; j < L; ++j)

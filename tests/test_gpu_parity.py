@@ -83,6 +83,11 @@ def image_errors(gpu, ref, tol, floor=None):
     floor. Returns the per-ring errors."""
     errs = per_det(gpu, ref)
     for r in range(ref.shape[0]):
+        if not np.any(ref[r]):
+            # a ring outside the band limit holds nothing: neither may the GPU's
+            assert not np.any(gpu[r]), f"ring {r} is empty in the oracle but not on the GPU"
+            errs[r] = 0.0
+            continue
         if floor is not None and floor[r] > tol:
             assert errs[r] <= FLOOR_FACTOR * floor[r], f"ring {r}: relative L2 {errs[r]:.3e} > {FLOOR_FACTOR} x floor {floor[r]:.3e}"
         else:
@@ -404,11 +409,46 @@ def test_gaussian_input_wave(tiny):
     img = plan.probe_image()
     sg = st.wavelength / (2 * st.alpha_max)
     om = LMA(st, ol, spec_u=ph.gaussian_spectrum(st.nx, st.ny, st.lx, st.ly, sg))
-    ref = om.image(tiny["v"])
-    e = image_errors(img, ref, TOL32)
+    probes = [(a, b) for b in range(st.Py) for a in range(st.Px)]
+    need = om.needed_translates(probes)
+    ref = om.image(tiny["v"], probes, basis=om.propagate(tiny["v"], need))
+    # the Gaussian translates overlap strongly: the coefficients cancel (sum |alpha| ~ 1.5e3
+    # against a unit probe), which raises the FP32 floor of the faint HAADF ring to ~1e-2
+    floor = ring_floor(c64_lma_image(om, c64_basis(om, tiny["v"], need), probes), ref, probes)
+    say("  FP32 floor per ring", ["%.1e" % x for x in floor])
+    e = image_errors(img, ref, TOL32, floor)
     say(f"  vs oracle, per-detector rel L2 {e}; probe residual {plan.info().max_residual:.3e}")
     say("  LMA(Gaussian) vs plain, per-detector rel L2", per_det(img, tiny["img_plain"][1:]))
     image_errors(plan.plain_image(tiny["v"]), tiny["img_plain"][1:], TOL32)
+
+
+def test_trigpoly_input_wave(tiny):
+    # u = phi_10 x phi_10 (Sec. 2, Sec. 4.2.3) over a 21 x 21 translate lattice on the tiny
+    # workload (its aperture needs |m| <= 10), probes on a 42 x 42 scan: with all 441 translates
+    # the closed-form coefficients represent every probe exactly, so the LMA image is the plain
+    # multislice image; with the 81 nearest, the oracle's truncated combination
+    w, v = tiny["w"], tiny["v"]
+    win = (10, 12, 8, 6)
+    for L in (441, 81):
+        say(f"tiny: trigonometric input wave, L = {L}")
+        plan, st, ol = build(w, scan=(42, 42), R=(21, 21), offset=(0.0, 0.0), L=L, window=win,
+                             basis_kind=lma.LMA_BASIS_TRIGPOLY)
+        i = plan.info()
+        say(f"  {i.n_rows} translates, contraction kernel {i.contract_kernel}, residual {i.max_residual:.2e}")
+        plan.propagate(v)
+        img = plan.probe_image()
+        probes = window_probes(plan)
+        om = LMA(st, ol, spec_u=ph.trigpoly_spectrum(st.nx, st.ny, st.lx, st.ly, 10, 10), coefficients="trigpoly")
+        ref = crop(om.image(v, probes), plan)
+        e = image_errors(img, ref, TOL32)
+        say("  vs oracle LMA, per-detector rel L2", e)
+        if L == 441:
+            assert i.max_residual < 1e-10
+            pref = crop(plain_image(st, v, probes), plan)
+            e = image_errors(img, pref, TOL32)
+            say("  vs oracle plain multislice, per-detector rel L2", e)
+            image_errors(plan.plain_image(v), pref, TOL32)
+        plan.close()
 
 
 def test_windowed_translates(tiny):
@@ -683,6 +723,8 @@ def test_local_recompute_with_translate_windows(tiny):
 # medium workload at full size, in the benchmark's launch configuration, on sampled outputs
 # ------------------------------------------------------------------------------------------
 def _oracle_exit(args):
+    """F(psi_exit) of the probe spectrum shifted to spec_pos (a translate of u = psi_0, or a probe
+    of the plain path), keyed by t."""
     w_name, t, spec_pos = args
     w = WORKLOADS[w_name]
     v = _oracle_exit.v
@@ -727,40 +769,41 @@ def test_medium_full_size_sampled():
     pimg = plan.plain_image(v)
     rows = plan.rows()
     flat, _ = plan.detector_pixels()
-    # sampled outputs: two translates' exit waves, three plain pixels, one LMA pixel
-    probe = (37, 101)
-    nbr = ol.nearest(*probe)
+    # an 8 x 8-probe sub-scan of the full-size images: all 64 LMA pixels (the oracle propagates
+    # the union of their neighbour sets and combines with its own coefficients) and all 64 plain
+    # pixels (each probe propagated by the oracle), plus two translates far apart
+    from oracle.lma import least_squares
+    sub = [(a, b) for b in range(96, 104) for a in range(36, 44)]
     sample_t = [int(rows[0]), int(rows[-1])]
     jobs = {}
-    for ta, tb in nbr:
-        jobs[tb * ol.Rfx + ta] = ol.translate_position(ta, tb)
+    for a, b in sub:
+        for ta, tb in ol.nearest(a, b):
+            jobs[tb * ol.Rfx + ta] = ol.translate_position(ta, tb)
     for t in sample_t:
         jobs[t] = ol.translate_position(t % ol.Rfx, t // ol.Rfx)
     n_workers = max(1, min(16, len(os.sched_getaffinity(0))))
-    say(f"medium: oracle for {len(jobs)} translates on {n_workers} processes")
+    say(f"medium: oracle for {len(jobs)} translates and {len(sub)} probes on {n_workers} processes")
+    work = [("medium", t, (float(p[0]), float(p[1]))) for t, p in jobs.items()]
+    work += [("medium", ("probe", a, b), tuple(float(c) for c in st.probe_position(a, b))) for a, b in sub]
     with ProcessPoolExecutor(n_workers, initializer=_pool_init, initargs=("medium",)) as ex:
-        res = dict(ex.map(_oracle_exit, [("medium", t, (float(p[0]), float(p[1]))) for t, p in jobs.items()]))
+        res = dict(ex.map(_oracle_exit, work))
     row_of = {int(t): r for r, t in enumerate(rows)}
     for t in sample_t:
         got = plan.basis_rows(row_of[t], 1)[0]
         e = rel_l2(got, res[t].ravel()[flat])
         say(f"  exit wave of translate {t}: rel L2 {e:.2e}")
         assert e < TOL32
-    # LMA pixel: combination with the oracle's own coefficients
-    om_alpha, _, _ = __import__("oracle.lma", fromlist=["least_squares"]).least_squares(st, ol, st.spec0, *probe)
-    spec = sum(a * res[tb * ol.Rfx + ta] for a, (ta, tb) in zip(om_alpha, nbr))
-    ref = ph.detector_values(spec, st.masks)
-    got = img[:, probe[1], probe[0]]
-    e = np.abs(got - ref) / np.abs(ref)
-    say("  LMA pixel per-detector rel err", e)
-    assert e.max() < TOL32
-    # plain pixels
-    probes = [(0, 0), (64, 17), (127, 127)]
-    pref = plain_image(st, v, probes)
-    for a, b in probes:
-        e = np.abs(pimg[:, b, a] - pref[:, b, a]) / np.abs(pref[:, b, a])
-        say(f"  plain pixel {(a, b)} rel err", e)
-        assert e.max() < TOL32
+    alpha = least_squares(st, ol, st.spec0, *sub[0])[0]   # Case 1, c = 1: one coefficient set
+    ref = np.zeros((len(st.detectors), 8, 8))
+    pref = np.zeros_like(ref)
+    for a, b in sub:
+        spec = sum(c * res[tb * ol.Rfx + ta] for c, (ta, tb) in zip(alpha, ol.nearest(a, b)))
+        ref[:, b - 96, a - 36] = ph.detector_values(spec, st.masks)
+        pref[:, b - 96, a - 36] = ph.detector_values(res[("probe", a, b)], st.masks)
+    e = image_errors(img[:, 96:104, 36:44], ref, TOL32)
+    say("  8 x 8 LMA sub-scan, per-detector rel L2", e)
+    e = image_errors(pimg[:, 96:104, 36:44], pref, TOL32)
+    say("  8 x 8 plain sub-scan, per-detector rel L2", e)
 
 
 _LARGE = {}
@@ -778,21 +821,22 @@ def _large_potential(args):
 
 def _large_job(job):
     """Oracle work for the large workload in a worker (inherits _LARGE from the parent)."""
-    kind, arg = job
+    kind, key, arg = job
     st, v = _LARGE["st"], _LARGE["v"]
     if kind == "translate":
         from oracle.lma import translate_wave
         from oracle.multislice import multislice
-        return kind, np.fft.fft2(multislice(translate_wave(st, st.spec0, arg), v, st.sigma, st.prop))
-    return kind, plain_image(st, v, [arg])[:, arg[1], arg[0]]
+        return key, np.fft.fft2(multislice(translate_wave(st, st.spec0, arg), v, st.sigma, st.prop))
+    return key, plain_image(st, v, [arg])[:, arg[1], arg[0]]
 
 
 @pytest.mark.slow
 def test_large_full_size_sampled():
     # the large precision workload at full size: 2048^2 over 204.8 A, 250 slices, 300 kV, 25 mrad,
     # defocus -50 A, the 256 x 256 scan and translates every 4 px; a 4 x 4-probe window with the
-    # basis in FP32 and in split BF16 (hi + lo); one translate's exit wave and one plain pixel
-    # against the oracle (each about a minute of FP64 CPU time)
+    # basis in FP32 and in split BF16 (hi + lo) against each other; one LMA pixel (L = 15, FP32
+    # and split BF16), one translate's exit wave and one plain pixel against the oracle (each
+    # oracle wave about a minute of FP64 CPU time)
     w = WORKLOADS["large"]
     n_workers = max(1, min(16, len(os.sched_getaffinity(0))))
     say(f"large: potential (250 x 2048^2) on {n_workers} processes")
@@ -814,25 +858,46 @@ def test_large_full_size_sampled():
         say(f"  ring {r}: split-BF16 vs FP32 basis rel L2 {e:.2e}")
         assert e < TOL_BF16
     pimg = plan.plain_image(v)
-    rows = plan.rows()
-    flat, _ = plan.detector_pixels()
-    t = int(rows[len(rows) // 2])
-    tpos = ol.translate_position(t % ol.Rfx, t // ol.Rfx)
+    plan.close()
+    # one LMA pixel against the oracle with L = 15 nearest translates, its basis in FP32 and in
+    # split BF16: the oracle propagates the 15 translates and the probe itself (16 waves, one per
+    # process) and combines them with its own least-squares coefficients
+    from oracle.lma import Lattice, least_squares
     probe = (win[0] + 1, win[1] + 2)
+    L15 = 15
+    one = (probe[0], probe[1], 1, 1)
+    p32, _, _ = build(w, L=L15, window=one)
+    p16, _, _ = build(w, L=L15, window=one, precision=lma.LMA_GEMM_SPLIT_BF16)
+    p32.propagate(v)
+    p16.propagate(v)
+    px32, px16 = p32.probe_image()[:, 0, 0], p16.probe_image()[:, 0, 0]
+    rows = p32.rows()
+    flat, _ = p32.detector_pixels()
+    ol15 = Lattice(st, (ol.Rx, ol.Ry), 1, w.offset_frac, L15)
+    nbr = ol15.nearest(*probe)
+    jobs = [("translate", tb * ol15.Rfx + ta, tuple(float(c) for c in ol15.translate_position(ta, tb)))
+            for ta, tb in nbr] + [("plain", "plain", probe)]
     _LARGE.update(st=st, v=v)
-    say("large: oracle (one translate, one plain probe) on 2 processes")
-    with ProcessPoolExecutor(2) as ex:
-        res = dict(ex.map(_large_job, [("translate", (float(tpos[0]), float(tpos[1]))), ("plain", probe)]))
+    say(f"large: oracle ({len(nbr)} translates, one plain probe) on {len(jobs)} processes")
+    with ProcessPoolExecutor(min(16, len(jobs))) as ex:
+        res = dict(ex.map(_large_job, jobs))
     _LARGE.clear()
-    got = plan.basis_rows(int(np.nonzero(rows == t)[0][0]), 1)[0]
-    e = rel_l2(got, res["translate"].ravel()[flat])
+    t = int(rows[0])
+    e = rel_l2(p32.basis_rows(0, 1)[0], res[t].ravel()[flat])
     say(f"  exit wave of translate {t}: rel L2 {e:.2e}")
     assert e < TOL32
+    alpha = least_squares(st, ol15, st.spec0, *probe)[0]
+    ref = ph.detector_values(sum(c * res[tb * ol15.Rfx + ta] for c, (ta, tb) in zip(alpha, nbr)), st.masks)
+    e32 = np.abs(px32 - ref) / np.abs(ref)
+    e16 = np.abs(px16 - ref) / np.abs(ref)
+    say(f"  LMA pixel {probe}, L = {L15}: per-detector rel err FP32 {e32}, split BF16 {e16}")
+    assert e32.max() < TOL32 and e16.max() < TOL_BF16
     a, b = probe
     e = np.abs(pimg[:, b - win[1], a - win[0]] - res["plain"]) / np.abs(res["plain"])
     say(f"  plain pixel {probe} rel err", e)
     assert e.max() < TOL32
-    plan.close()
+    p32.close()
+    p16.close()
 
 
 @pytest.mark.slow

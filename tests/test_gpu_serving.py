@@ -9,7 +9,8 @@ import pytest
 
 import paper_2310_16829_amd as lma
 from synth import WORKLOADS, potential_slices
-from tests._cases import det_rad
+from tests._cases import det_rad, oracle_lattice, oracle_setup
+from tests.test_gpu_parity import PAPER_RINGS, TOL32, image_errors
 
 pytestmark = pytest.mark.gpu
 
@@ -76,7 +77,7 @@ def _specimens():
         opt = lma.optics(n, n, l, l, lam, sig, w.dz, w.bandlimit, w.alpha_mrad * 1e-3)
         scan = (n // 8, n // 8)
         lat = lma.lattice(scan[0], scan[1], n // 4, n // 4, 1, (0.5, 0.5), 36)
-        det = lma.detectors(det_rad(w))
+        det = lma.detectors(PAPER_RINGS)
         if k == 0:
             v = potential_slices(w, 0)
         else:
@@ -85,7 +86,7 @@ def _specimens():
         x0, y0 = 20 + 7 * k, 30 + 5 * k
         v_new[:, y0:y0 + 12, x0:x0 + 12] += 15.0
         out.append(dict(opt=opt, lat=lat, det=det, v=v, vd=torch.from_numpy(v).cuda(), v_new=v_new,
-                        bbox=(x0, y0, x0 + 12, y0 + 12), shape=(len(det_rad(w)), scan[1], scan[0])))
+                        bbox=(x0, y0, x0 + 12, y0 + 12), shape=(len(PAPER_RINGS), scan[1], scan[0])))
     return out
 
 
@@ -135,6 +136,29 @@ def test_same_results_alone_and_in_the_mix():
         p.propagate(s0["vd"])
         direct = p.probe_image()
     assert np.allclose(alone[0]["lma"], direct, rtol=1e-12, atol=0)
+    # and the served results of the tiny specimen against the FP64 oracle: its LMA image, its
+    # plain image, and the local edit (the oracle re-propagating the translates within the
+    # radius with the edited potential and re-forming the probes that use them; the request
+    # patches those probes into a zero image)
+    from oracle.lma import LMA, recompute_sets
+    from oracle.multislice import plain_image
+    w = WORKLOADS["tiny"]
+    st = oracle_setup(w, detectors=PAPER_RINGS)
+    ol = oracle_lattice(w, st, L=36)
+    om = LMA(st, ol)
+    allt = [(t % ol.Rfx, t // ol.Rfx) for t in range(ol.n_translates)]
+    say("serving: oracle LMA, plain and edit of the tiny specimen")
+    b0 = om.propagate(s0["v"], allt)
+    R, Pp = recompute_sets(ol, s0["bbox"], 1.5)
+    mixed = dict(b0)
+    mixed.update(om.propagate(s0["v_new"], sorted(R)))
+    ref_edit = np.zeros(s0["shape"])
+    img_edit = om.image(s0["v_new"], basis=mixed)
+    for a, b in Pp:
+        ref_edit[:, b, a] = img_edit[:, b, a]
+    for key, ref in (("lma", om.image(s0["v"], basis=b0)), ("plain", plain_image(st, s0["v"])), ("edit", ref_edit)):
+        e = image_errors(mix[0][key], ref, TOL32)
+        say(f"  served {key} image vs oracle, per-detector rel L2 {e}")
 
 
 def test_admission_by_footprint():

@@ -69,7 +69,7 @@ def test_electron_constants_match_oracle():
 
 
 @pytest.mark.parametrize("case", ["tiny", "case2", "nonsquare", "f2_paper_style", "gaussian", "gaussian_sigma",
-                                  "grid_96_by_640"])
+                                  "grid_96_by_640", "trigpoly_exact", "trigpoly_nearest", "trigpoly_offset"])
 def test_host_plan_matches_oracle(case):
     w = WORKLOADS["tiny"]
     kw = {}
@@ -86,6 +86,13 @@ def test_host_plan_matches_oracle(case):
         kw = dict(nx=128, ny=64, lx=12.8, ly=7.2, scan=(16, 16), R=(32, 16), L=24)
     elif case == "f2_paper_style":  # I = P + p/2, f = 2 (Sec. 4.2.3)
         kw = dict(scan=(32, 32), R=(32, 32), f=2, L=25, offset=(0.5, 0.5))
+    elif case == "trigpoly_exact":   # phi_10 x phi_10 over all 21 x 21 translates: exact (Sec. 2)
+        kw = dict(scan=(42, 42), R=(21, 21), L=441, offset=(0.0, 0.0), basis_kind=lma.LMA_BASIS_TRIGPOLY)
+    elif case == "trigpoly_nearest":  # closed-form coefficients kept at the 81 nearest translates
+        kw = dict(scan=(42, 42), R=(21, 21), L=81, offset=(0.0, 0.0), basis_kind=lma.LMA_BASIS_TRIGPOLY)
+    elif case == "trigpoly_offset":   # non-square cell, degrees 10 and 6, offset lattice, f = 2
+        kw = dict(nx=128, ny=64, lx=12.8, ly=7.2, scan=(21, 13), R=(42, 26), f=2, L=150, offset=(0.5, 0.5),
+                  basis_kind=lma.LMA_BASIS_TRIGPOLY)
     opt, lat, det = _plan_args(w, **kw)
     plan = lma.Plan(opt, lat, det, flags=lma.LMA_HOST_ONLY)
     info = plan.info()
@@ -96,7 +103,10 @@ def test_host_plan_matches_oracle(case):
     assert info.n_translates == ol.n_translates
     # probe spectrum, and the input wave's
     assert np.abs(plan.probe_spectrum() - st.spec0).max() < 1e-12
-    if kw.get("basis_kind"):
+    trig = kw.get("basis_kind") == lma.LMA_BASIS_TRIGPOLY
+    if trig:
+        spec_u = ph.trigpoly_spectrum(st.nx, st.ny, st.lx, st.ly, (ol.Rfx - 1) // 2, (ol.Rfy - 1) // 2)
+    elif kw.get("basis_kind"):
         sg = kw.get("basis_param") or st.wavelength / (2 * st.alpha_max)
         spec_u = ph.gaussian_spectrum(st.nx, st.ny, st.lx, st.ly, sg)
     else:
@@ -117,7 +127,7 @@ def test_host_plan_matches_oracle(case):
         assert abs(pos[t, 0] - float(ex[0])) < 1e-12 and abs(pos[t, 1] - float(ex[1])) < 1e-12
     # neighbour lists (ordered, exact) and approximants of every coefficient set
     tr, al = plan.coefficients()
-    lm = LMA(st, ol, spec_u=spec_u)
+    lm = LMA(st, ol, spec_u=spec_u, coefficients="trigpoly" if trig else "least_squares")
     for sy in range(ol.ncls_y):
         for sx in range(ol.ncls_x):
             s = sy * ol.ncls_x + sx
@@ -126,7 +136,10 @@ def test_host_plan_matches_oracle(case):
             appr = sum(a * translate_wave(st, spec_u, ol.translate_position(t % ol.Rfx, t // ol.Rfx))
                        for a, t in zip(al[s], tr[s]))
             assert rel_l2(appr, lm.approximant(sx, sy)) < 1e-8
-    assert info.max_residual == pytest.approx(max(lm.residual.values()), rel=1e-6)
+    if case == "trigpoly_exact":
+        assert info.max_residual < 1e-12 and max(lm.residual.values()) < 1e-12
+    else:
+        assert info.max_residual == pytest.approx(max(lm.residual.values()), rel=1e-6)
 
 
 def test_window_rows_are_the_union_of_neighbour_sets():

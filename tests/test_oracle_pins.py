@@ -521,6 +521,75 @@ def test_rectangle_partition_second_example():
     assert any(len(union(sets, q)) > M for q in tiling(region, 48, h + 1))
 
 
+# ---------------------------------------------------------------------------------------
+# trigonometric input waves (Sec. 2, Sec. 4.2.3)
+# ---------------------------------------------------------------------------------------
+def test_trig_transform_inverse_factor():
+    # M M^-1 = I with the factor 1 / (2n + 1); the printed 1 / (2n + 1)^2 leaves I / (2n + 1)
+    from oracle.lma import trig_transform
+    for n in (1, 3, 7, 10):
+        M, Minv = trig_transform(n)
+        assert np.abs(M @ Minv - np.eye(2 * n + 1)).max() < 1e-13
+        assert np.abs(Minv @ M - np.eye(2 * n + 1)).max() < 1e-13
+        printed = Minv / (2 * n + 1)
+        assert np.abs((2 * n + 1) * (M @ printed) - np.eye(2 * n + 1)).max() < 1e-13
+
+
+def test_trigpoly_wave_is_the_shifted_dirichlet_sum():
+    # cos(k theta) = (e^{ik theta} + e^{-ik theta}) / 2 with theta = pi / (2n + 2) turns eq. rauhut
+    # into phi_n(t) = (D_n(t + theta) + D_n(t - theta)) / 2, D_n(x) = sin((n + 1/2) x) / sin(x / 2)
+    # (the Dirichlet kernel); the oracle's u is the product of two such functions
+    n_x, n_y, nx, ny = 6, 4, 48, 40
+    u = np.fft.ifft2(ph.trigpoly_spectrum(nx, ny, 9.6, 8.0, n_x, n_y))
+
+    def dirichlet_form(n, npts):
+        th = np.pi / (2 * n + 2)
+        t = 2 * np.pi * np.arange(npts) / npts
+        def d(x):
+            s2 = np.sin(x / 2)
+            small = np.abs(s2) < 1e-12                 # x = 0 mod 2 pi: D_n = 2n + 1
+            return np.where(small, 2 * n + 1, np.sin((n + 0.5) * x) / np.where(small, 1.0, s2))
+        return 0.5 * (d(t + th) + d(t - th))
+    want = dirichlet_form(n_y, ny)[:, None] * dirichlet_form(n_x, nx)[None, :]
+    want = want / np.linalg.norm(want)
+    assert rel_l2(u, want) < 1e-12
+    assert np.abs(u.imag).max() < 1e-14               # real and even, peaked at the origin
+    assert np.argmax(np.abs(u)) == 0
+
+
+def test_trigpoly_basis_represents_every_probe_exactly():
+    # the tensor phi_n over the full (2n + 1)^2 lattice spans K_+, which holds the aperture:
+    # every probe, wherever it sits, is an exact combination of the translates, with the closed
+    # form M^-1 coefficients; the least-squares solver finds the same coefficients
+    from oracle.lma import trig_coefficients
+    st = _setup(nx=64, ny=64, lx=12.8, ly=12.8, scan=(42, 42))
+    n = 10                                            # lambda |k| < 20 mrad needs |m| <= 10 at 12.8 A
+    assert int(np.floor(st.alpha_max / st.wavelength * st.lx)) == n
+    su = ph.trigpoly_spectrum(64, 64, 12.8, 12.8, n, n)
+    for offset in ((0, 0), (0.5, 0.5)):
+        lat = Lattice(st, (21, 21), 1, offset, 441)
+        for a, b in ((0, 0), (1, 0), (5, 7), (13, 30)):
+            al = trig_coefficients(st, lat, su, a, b)
+            approx = sum(al[tb, ta] * translate_wave(st, su, lat.translate_position(ta, tb))
+                         for tb in range(21) for ta in range(21))
+            assert rel_l2(approx, st.probe(a, b)) < 1e-12
+        al_ls, nbr, res = least_squares(st, lat, su, 1, 0)
+        full = trig_coefficients(st, lat, su, 1, 0)
+        al_cf = np.array([full[tb, ta] for ta, tb in nbr])
+        assert res < 1e-12 and np.abs(al_cf - al_ls).max() < 1e-9 * np.abs(al_ls).max()
+    # too low a degree: the coefficients project the probe onto K_+ (its error is the energy
+    # outside K_+)
+    st15 = _setup(nx=64, ny=64, lx=12.8, ly=12.8, scan=(15, 15))
+    lat = Lattice(st15, (15, 15), 1, (0, 0), 225)
+    su7 = ph.trigpoly_spectrum(64, 64, 12.8, 12.8, 7, 7)
+    om = LMA(st15, lat, spec_u=su7, coefficients="trigpoly")
+    spec = st.spec0
+    k = np.fft.fftfreq(64, 1 / 64)
+    outside = (np.abs(k)[None, :] > 7) | (np.abs(k)[:, None] > 7)
+    want = np.sqrt((np.abs(spec[outside]) ** 2).sum() / (np.abs(spec) ** 2).sum())
+    assert abs(om.residual[(0, 0)] - want) < 1e-12
+
+
 def test_cost_model_log_base_two():
     # Sec. 4.2.1: at 2048^2 with a 25 x 25 kernel, real-space propagation wins iff f >= 4
     assert math.ceil(costs.realspace_breakeven_f(2048, 2048, 25, 25)) == 4
