@@ -234,6 +234,23 @@ lma_status lma_image(lma_plan* plan, const float* potential, int32_t nslices, do
 lma_status lma_plain_image(lma_plan* plan, const float* potential, int32_t nslices,
                            double* image, int32_t flags, double weight);
 
+/* For callers that cannot allocate device memory: code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc. lma_plain_image with device pointers only
+ * (LMA_PTR_DEVICE required; LMA_ACCUMULATE optional), making no allocation: its transmission
+ * tables, wave batch and image accumulator live in a device array of
+ * LMA_NOALLOC_SCRATCH_BYTES that the library holds on every GPU it runs on until the process
+ * ends (the plan's own tables, built by lma_build_basis, are read as usual). The call needs
+ * ndet x probes x 8 bytes for the image, nslices x nx x ny x 8 bytes for the transmission
+ * tables and at least one wave of nx x ny x 8 bytes (each rounded up to 256 bytes) within
+ * that size, and returns LMA_ERR_ARG otherwise (for example the medium workload's 100 slices
+ * of 512^2 do not fit; the tiny workload's 10 slices of 128^2 do). The plan's device must be
+ * current. Every call on a GPU shares that GPU's array, which keeps the last call's contents:
+ * calls that overlap on one GPU (on different streams or host threads) race and must be
+ * ordered by the caller. Results equal lma_plain_image's up to the order of FP64 additions. */
+#define LMA_NOALLOC_SCRATCH_BYTES (64 * 1024 * 1024)
+lma_status lma_plain_image_noalloc(lma_plan* plan, const float* potential, int32_t nslices, double* image,
+                                   int32_t flags, double weight);
+
 /* 4-D STEM output (Sec. 3.1, step 3, the pixelated detector): for every probe of the window,
  * |F(psi_p^exit)(k)|^2 / (XY) (unit incident intensity) at each of the plan's D detector
  * pixels k, the union of its rings in the order of lma_get_detector_pixels: out

@@ -196,6 +196,15 @@ class Plan:
         _check(lib().lma_plain_image(self._h, pp, int(potential.shape[0]), pi, int(flags) | fi, float(weight)))
         return image
 
+    def plain_image_noalloc(self, potential, image, flags: int = 0, weight: float = 1.0):
+        """lma_plain_image_noalloc: device tensors only, no allocation by the library."""
+        pp, fp = _ptr(potential, np.float32)
+        pi, fi = _ptr(image, np.float64)
+        if not (fp and fi):
+            raise ValueError("lma_plain_image_noalloc takes device tensors")
+        _check(lib().lma_plain_image_noalloc(self._h, pp, int(potential.shape[0]), pi, int(flags) | fi, float(weight)))
+        return image
+
     def _pattern_out(self, out, device):
         shape = (self.window[3], self.window[2], self.n_pix)
         if out is None:

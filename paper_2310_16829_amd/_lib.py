@@ -73,6 +73,7 @@ SIGNATURES = {
     "lma_propagate": (C.c_int, [P, P, C.c_int32, C.c_int32]),
     "lma_probe_image": (C.c_int, [P, P, C.c_int32, C.c_double]),
     "lma_plain_image": (C.c_int, [P, P, C.c_int32, P, C.c_int32, C.c_double]),
+    "lma_plain_image_noalloc": (C.c_int, [P, P, C.c_int32, P, C.c_int32, C.c_double]),
     "lma_image": (C.c_int, [P, P, C.c_int32, P, C.c_int32, C.c_double]),
     "lma_probe_patterns": (C.c_int, [P, P, C.c_int32]),
     "lma_probe_radial": (C.c_int, [P, C.c_double, C.c_int32, P, C.c_int32, C.c_double]),

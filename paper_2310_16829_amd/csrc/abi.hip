@@ -1010,6 +1010,79 @@ lma_status lma_plain_image(lma_plan* plan, const float* potential, int32_t nslic
   }
 }
 
+}  // extern "C"
+
+// ---- the plain image without allocation ----------------------------------------------------
+// Its transmission tables, wave batch and image accumulator live in one file-scope device
+// array, so the call makes no allocation. In host code the array's name is a host-side
+// stand-in: kernels get its device address, looked up once per device.
+namespace {
+static __device__ __align__(256) unsigned char scratch[LMA_NOALLOC_SCRATCH_BYTES];
+constexpr int kScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch[kScratchDevices] = {};
+
+// the scratch array's address on device `dev`, which must be the current device
+lma_status scratch_address(int dev, unsigned char** out) {
+  if (dev < 0 || dev >= kScratchDevices) return fail(LMA_ERR_UNSUPPORTED, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+      (void)hipGetLastError();
+      return fail(LMA_ERR_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    }
+    g_scratch[dev] = ptr;
+  }
+  *out = static_cast<unsigned char*>(g_scratch[dev]);
+  return LMA_OK;
+}
+
+int64_t round256(int64_t b) { return (b + 255) & ~(int64_t)255; }
+}  // namespace
+
+extern "C" {
+
+lma_status lma_plain_image_noalloc(lma_plan* plan, const float* potential, int32_t nslices, double* image,
+                                   int32_t flags, double weight) {
+  lma_status s = check_device_call(plan, potential, nslices);
+  if (s != LMA_OK) return s;
+  if (!image) return fail(LMA_ERR_ARG, "image is null");
+  if (!std::isfinite(weight)) return fail(LMA_ERR_ARG, "weight must be finite");
+  if (!(flags & LMA_PTR_DEVICE)) return fail(LMA_ERR_ARG, "lma_plain_image_noalloc takes device pointers only (LMA_PTR_DEVICE)");
+  if (flags & ~(int32_t)(LMA_PTR_DEVICE | LMA_ACCUMULATE)) return fail(LMA_ERR_ARG, "unsupported flags");
+  const HostPlan& h = plan->h;
+  const int64_t XY = (int64_t)h.op.nx * h.op.ny, np = h.n_probes(), n = (int64_t)h.ndet * np;
+  const int64_t img_bytes = round256(n * 8), trans_bytes = round256((int64_t)nslices * XY * 8), wave = XY * 8;
+  const int64_t cap = (int64_t)LMA_NOALLOC_SCRATCH_BYTES;
+  if (img_bytes + trans_bytes + wave > cap)
+    return fail(LMA_ERR_ARG, "lma_plain_image_noalloc needs " + std::to_string(img_bytes + trans_bytes + wave) +
+                                 " bytes of scratch (image, transmission tables, one wave); the library holds " +
+                                 std::to_string(cap));
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev != plan->device)
+    return fail(LMA_ERR_ARG, "call lma_plain_image_noalloc with the plan's device current");
+  unsigned char* base = nullptr;
+  if ((s = scratch_address(dev, &base)) != LMA_OK) return s;
+  WaveBufs wb;
+  wb.img = reinterpret_cast<double*>(base);
+  wb.trans = reinterpret_cast<const float2*>(base + img_bytes);
+  wb.work = reinterpret_cast<float2*>(base + img_bytes + trans_bytes);
+  wb.B = (int)std::max<int64_t>(1, std::min<int64_t>({(int64_t)plan->B, np, (cap - img_bytes - trans_bytes) / wave}));
+  try {
+    LAUNCH(plan, "fill_zero", lma::dev::fill_zero(wb.img, n, plan->stream));
+    LAUNCH(plan, "transmission", lma::dev::transmission(potential, reinterpret_cast<float2*>(base + img_bytes),
+                                                        (int64_t)nslices * XY, h.op.sigma, plan->stream));
+    if ((s = run_waves(plan, plan->d_probe_u, nullptr, plan->d_probe_out, (int)np, nslices, nullptr, false, &wb)) != LMA_OK)
+      return s;
+    LAUNCH(plan, "scale_out", lma::dev::scale_out(image, wb.img, n, weight, (flags & LMA_ACCUMULATE) ? 1 : 0, plan->stream));
+    return LMA_OK;
+  } catch (const std::exception& e) {
+    return fail(LMA_ERR_DEVICE, e.what());
+  }
+}
+
 lma_status lma_probe_patterns(lma_plan* plan, float* out, int32_t flags) {
   lma_status s = check_device_call(plan, out, 1);
   if (s != LMA_OK) return s;

@@ -1013,6 +1013,11 @@ __global__ __launch_bounds__(256) void k_contract_mfma(Stencil c) {
   }
 }
 
+__global__ void k_fill_zero(double* out, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = 0.0;
+}
+
 __global__ void k_scale_out(double* out, const double* img, int64_t n, double w, int acc) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
@@ -1769,6 +1774,12 @@ hipError_t contract_stencil(const Stencil& c, hipStream_t s) {
   if (c.nks <= 0 || c.nks > kStencilMaxKs || c.W * c.H > kStencilMaxRect || c.W <= 0 || c.H <= 0)
     return hipErrorInvalidValue;
   return c.split_bf16 ? stencil_split<1>(c, s) : stencil_split<0>(c, s);
+}
+
+hipError_t fill_zero(double* out, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  k_fill_zero<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(out, n);
+  return hipGetLastError();
 }
 
 hipError_t scale_out(double* out, const double* img, int64_t n, double w, int acc, hipStream_t s) {

@@ -132,6 +132,8 @@ constexpr int kMaxRadialBins = 512;
 hipError_t intensity(const float2* in, float* out, int64_t n, double scale, hipStream_t s);
 // the same contraction for a whole window on MFMA
 hipError_t contract_stencil(const Stencil& c, hipStream_t s);
+// out[0..n) = 0 by a kernel (no memset node when a caller captures the stream)
+hipError_t fill_zero(double* out, int64_t n, hipStream_t s);
 // out = (acc ? out : 0) + w * img, n doubles, device memory
 hipError_t scale_out(double* out, const double* img, int64_t n, double w, int acc, hipStream_t s);
 
