@@ -448,6 +448,150 @@ def serve_mode(precision, rates, n_requests, slots, cap_seconds=8.0):
     return out
 
 
+def _edit_potential(w, base, c, col_xy, seed):
+    """The potential of workload w (configuration c, whose potential is `base`) after one local
+    edit of the generator (one atomic column: a new species amplitude, each of its atoms kept
+    with probability 1/2), and the edited pixel box: base minus the column's old Gaussians plus
+    its new ones (the column: the atoms within 1 A of its site in x, y; the nearest other
+    column is 2.9 A away)."""
+    import numpy as np
+    from synth.specimen import atom_sites, edit_column, phonon_positions, potential_from_atoms
+    sites, amps0 = atom_sites(w)
+    pos0 = phonon_positions(w, c, sites)
+    pos1, amps1, bbox = edit_column(w, c, col_xy, seed=seed)
+    d2 = (sites[:, 0] - col_xy[0]) ** 2 + (sites[:, 1] - col_xy[1]) ** 2
+    centres = np.unique(sites[d2 <= d2.min() + 1e-9][:, :2], axis=0)   # the edited column(s)
+
+    def column(pos):
+        hit = np.zeros(len(pos), dtype=bool)
+        for cx, cy in centres:
+            dx = pos[:, 0] - cx
+            dx -= w.lx * np.round(dx / w.lx)
+            dy = pos[:, 1] - cy
+            dy -= w.ly * np.round(dy / w.ly)
+            hit |= dx * dx + dy * dy < 1.0
+        return hit
+    c0, c1 = column(pos0), column(pos1)
+    v = base.copy()
+    v += potential_from_atoms(w, pos1[c1], amps1[c1])
+    v -= potential_from_atoms(w, pos0[c0], amps0[c0])
+    return v, bbox
+
+
+def serve_c5(precision, rates, n_requests=200, slots=4):
+    """The serving workload drawn from the sizes of the other workloads: the tiny specimen (128^2,
+    10 slices, its full 16 x 16 scan), the medium one (512^2, 100 slices) on a 16 x 16-probe
+    window, the large one (2048^2, 250 slices, 300 kV) on a 16 x 16-probe sub-scan, and one
+    specimen of every side of the uneven batch (96 ... 640 px, 20-200 slices) on a window of up
+    to 16 x 16 probes. Requests: 70 % LMA images of a frozen-phonon configuration, 30 % local
+    edits that replace one atomic column (species amplitude and occupancy) and recompute the
+    affected translates; a specimen is drawn with weight 1, the large one with weight 0.2 (an
+    image of its sub-scan is ~15 s of device time). Poisson arrivals, n_requests per rate."""
+    from concurrent.futures import ProcessPoolExecutor
+    import numpy as np
+    import torch
+    import paper_2310_16829_amd as lma
+    from synth import WORKLOADS, potential_slices
+    from synth.specimen import uneven_batch
+
+    rng = np.random.default_rng(5)
+    cores = max(1, min(16, len(os.sched_getaffinity(0))))
+    ws = [WORKLOADS["tiny"], WORKLOADS["medium"], WORKLOADS["large"]]
+    seen = set()
+    for w in uneven_batch(64):
+        if w.nx not in seen:
+            seen.add(w.nx)
+            ws.append(w)
+    specs = []
+    for w in ws:
+        big = w.name == "large"
+        log(f"serve c5: specimen {w.name} ({w.nx}^2 x {w.nslices} slices)")
+        lam, sig = lma.electron_constants(w.kv)
+        rings = [(a * 1e-3, b * 1e-3) for _, a, b in w.detectors]
+        opt = lma.optics(w.nx, w.ny, w.lx, w.ly, lam, sig, w.dz, w.bandlimit, w.alpha_mrad * 1e-3, w.defocus, w.cs)
+        (Rx, Ry), f = w.lattice_size()
+        side = max(2, min(16, w.scan[0], (16 * w.scan[0]) // Rx))
+        a0 = int(rng.integers(0, w.scan[0] - side + 1))
+        b0 = int(rng.integers(0, w.scan[1] - side + 1))
+        lat = lma.lattice(w.scan[0], w.scan[1], Rx, Ry, f, w.offset_frac, w.L, precision, window=(a0, b0, side, side))
+        n_cfg = 1 if big else 2
+        if big:
+            step = -(-w.nslices // cores)
+            with ProcessPoolExecutor(cores) as ex:
+                pots = [np.concatenate(list(ex.map(_large_slices, [(lo, min(lo + step, w.nslices))
+                                                                   for lo in range(0, w.nslices, step)])))]
+        else:
+            pots = [potential_slices(w, c) for c in range(n_cfg)]
+        # edited potentials: columns near the window's centre
+        cx = (a0 + side / 2) * w.lx / w.scan[0]
+        cy = (b0 + side / 2) * w.ly / w.scan[1]
+        n_edits = 1 if big else 2
+        edits = [_edit_potential(w, pots[0], 0, (cx + 2.0 * e, cy - 1.5 * e), e) for e in range(n_edits)]
+        specs.append(dict(w=w, opt=opt, lat=lat, det=lma.detectors(rings), weight=0.2 if big else 1.0,
+                          pots=[torch.from_numpy(v).cuda() for v in pots], edits=edits,
+                          shape=(len(rings), side, side)))
+        del pots
+    torch.cuda.synchronize()
+    weights = np.array([s["weight"] for s in specs])
+    weights /= weights.sum()
+    out = {"study": "serving, config-5 mix: " + ", ".join(f"{s['w'].name} {s['w'].nx}^2x{s['w'].nslices}" for s in specs),
+           "precision": "split_bf16" if precision == lma.LMA_GEMM_SPLIT_BF16 else "fp32", "slots": slots,
+           "rates": []}
+    with lma.Server(slots, len(specs), 200 << 30) as srv:
+        t = [srv.build(k, s["opt"], s["lat"], s["det"], s["w"].nslices) for k, s in enumerate(specs)]
+        for x in t:
+            srv.wait(x)
+        for k, s in enumerate(specs):
+            srv.wait(srv.image(k, s["pots"][0], torch.zeros(s["shape"], dtype=torch.float64, device="cuda")))
+        out["resident_bytes"] = srv.in_use()
+        for rate in rates:
+            gaps = rng.exponential(1.0 / rate, size=n_requests)
+            reqs = []
+            for i in range(n_requests):
+                k = int(rng.choice(len(specs), p=weights))
+                s = specs[k]
+                if rng.random() < 0.3:
+                    reqs.append(("edit", k, int(rng.integers(0, len(s["edits"])))))
+                else:
+                    reqs.append(("image", k, int(rng.integers(0, len(s["pots"])))))
+            torch.cuda.synchronize()
+            tickets = []
+            t0 = time.monotonic()
+            arrival = t0
+            for (kind, k, arg), gap in zip(reqs, gaps):
+                arrival += gap
+                delay = arrival - time.monotonic()
+                if delay > 0:
+                    time.sleep(delay)
+                s = specs[k]
+                if kind == "edit":
+                    v, bbox = s["edits"][arg]
+                    tickets.append((kind, k, srv.edit(k, v, bbox, 2.5, np.zeros(s["shape"]))))
+                else:
+                    img = torch.empty(s["shape"], dtype=torch.float64, device="cuda")
+                    tickets.append((kind, k, srv.image(k, s["pots"][arg], img)))
+            lat = {"image": [], "edit": []}
+            per_spec = {}
+            for kind, k, tk in tickets:
+                l, _ = srv.wait(tk)
+                lat[kind].append(l)
+                per_spec.setdefault(specs[k]["w"].name, []).append(l)
+            wall = time.monotonic() - t0
+            allv = lat["image"] + lat["edit"]
+            row = {"rate_per_s": rate, "requests": n_requests, "throughput_per_s": n_requests / wall,
+                   "p50_ms": float(np.percentile(allv, 50)), "p99_ms": float(np.percentile(allv, 99)),
+                   "image_p50_ms": float(np.percentile(lat["image"], 50)) if lat["image"] else None,
+                   "image_p99_ms": float(np.percentile(lat["image"], 99)) if lat["image"] else None,
+                   "edit_p50_ms": float(np.percentile(lat["edit"], 50)) if lat["edit"] else None,
+                   "edit_p99_ms": float(np.percentile(lat["edit"], 99)) if lat["edit"] else None,
+                   "p50_ms_by_specimen": {n: float(np.percentile(v, 50)) for n, v in per_spec.items()},
+                   "requests_by_specimen": {n: len(v) for n, v in per_spec.items()}}
+            log(f"serve c5: rate {rate}/s: p50 {row['p50_ms']:.1f} ms, p99 {row['p99_ms']:.1f} ms, "
+                f"{row['throughput_per_s']:.1f} req/s")
+            out["rates"].append(row)
+    return out
+
+
 def paper_shaped(emit=True):
     """The paper's local-edit experiment in shape (1024^2 px over 84.536 x 79.941 A, scan
     424 x 400, I = P + p/2, f = 2, L = 59, 200 kV, 26 mrad, Z = 100 A, C_s = -2000 A) with the
@@ -513,6 +657,143 @@ def paper_shaped(emit=True):
         "lma_vs_plain_rel_l2_on_window": err}
     if emit:
         print(json.dumps(res), flush=True)
+    return res
+
+
+def _large_slices(args):
+    """Slices [lo, hi) of the large workload's configuration-0 potential (the generator's own
+    per-slice computation, run in a worker)."""
+    from synth import WORKLOADS
+    from synth.specimen import atom_sites, phonon_positions, potential_from_atoms
+    lo, hi = args
+    w = WORKLOADS["large"]
+    sites, amps = atom_sites(w)
+    return potential_from_atoms(w, phonon_positions(w, 0, sites), amps, range(lo, hi))
+
+
+_LARGE_ORACLE = {}
+
+
+def _large_oracle_wave(job):
+    """An FP64 oracle exit spectrum at the large workload (a translate of psi_0 or a probe)."""
+    import numpy as np
+    from oracle.lma import translate_wave
+    from oracle.multislice import multislice
+    key, pos = job
+    st, v = _LARGE_ORACLE["st"], _LARGE_ORACLE["v"]
+    return key, np.fft.fft2(multislice(translate_wave(st, st.spec0, pos), v, st.sigma, st.prop))
+
+
+def large_subscan(window=(120, 120, 16, 16), steps=2):
+    """The large precision workload on a 16 x 16-probe sub-scan (2048^2 px over 204.8 A, 250
+    slices, 300 kV, 25 mrad, defocus -50 A, translates every 4 px, L = 144, one phonon
+    configuration): STEM pixels/s of the LMA image (propagation of the sub-scan's translates and
+    the contraction) with the basis stored as split BF16 and as FP32, the slice passes' HBM
+    roofline, and the error against the FP64 oracle of one LMA pixel formed from its 15 nearest
+    translates (FP32 and split BF16) and one plain pixel."""
+    from concurrent.futures import ProcessPoolExecutor
+    import numpy as np
+    import torch
+    import paper_2310_16829_amd as lma
+    from oracle import physics as ph
+    from oracle.lma import Lattice, least_squares
+    from oracle.multislice import Setup
+    from synth import WORKLOADS
+
+    w = WORKLOADS["large"]
+    cores = max(1, min(16, len(os.sched_getaffinity(0))))
+    step = -(-w.nslices // cores)
+    log(f"large: potential ({w.nslices} x {w.nx}^2) on {cores} processes")
+    with ProcessPoolExecutor(cores) as ex:
+        v = np.concatenate(list(ex.map(_large_slices, [(lo, min(lo + step, w.nslices))
+                                                       for lo in range(0, w.nslices, step)])))
+    vd = torch.from_numpy(v).cuda()
+    lam, sig = lma.electron_constants(w.kv)
+    rings = [(a * 1e-3, b * 1e-3) for _, a, b in w.detectors]
+    opt = lma.optics(w.nx, w.ny, w.lx, w.ly, lam, sig, w.dz, w.bandlimit, w.alpha_mrad * 1e-3, w.defocus, w.cs)
+    R = (w.nx // w.basis_px, w.ny // w.basis_px)
+    det = lma.detectors(rings)
+    res = {"study": ("large workload, 16 x 16-probe sub-scan: 2048^2 px over 204.8 A, 250 slices of 2 A, FCC "
+                     "{29,79} V*A random alloy, 300 kV, 25 mrad, defocus -50 A, translates every 4 px, L=144, one "
+                     "phonon configuration"), "window": list(window)}
+    for name, prec in (("split_bf16", lma.LMA_GEMM_SPLIT_BF16), ("fp32", lma.LMA_GEMM_FP32)):
+        lat = lma.lattice(w.scan[0], w.scan[1], R[0], R[1], 1, w.offset_frac, w.L, prec, window=window)
+        with lma.Plan(opt, lat, det) as plan:
+            info = plan.info()
+            img = torch.zeros(plan.image_shape(), dtype=torch.float64, device="cuda")
+            plan.propagate(vd)                                   # first launches
+            plan.probe_image(img)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                plan.propagate(vd)
+                plan.probe_image(img)
+            torch.cuda.synchronize()
+            t = (time.perf_counter() - t0) / steps
+            plan.set_timing(True)
+            plan.propagate(vd)
+            plan.probe_image(img)
+            kt = plan.timing(reset=True)
+            plan.set_timing(False)
+            n_probes = window[2] * window[3]
+            row = {"seconds": t, "stem_pixels_per_s": n_probes / t, "translates": info.n_rows,
+                   "detector_pixels": info.n_pix, "basis_GB": info.n_rows * info.n_pix * 8 / 1e9,
+                   "probe_residual": info.max_residual, "batch": info.batch,
+                   "kernels_ms": {k: {"launches": a, "total_ms": b} for k, (a, b) in kt.items()},
+                   "contraction": contraction_roofline(plan, info, kt, split=prec == lma.LMA_GEMM_SPLIT_BF16)}
+            XY = w.nx * w.ny
+            batches = -(-info.n_rows // info.batch)
+            wpl = info.n_rows / batches
+            tw = info.tile_width
+            kept = 1.0 - max(0, info.gap_hi // tw - (-(-info.gap_lo // tw))) * tw / w.nx
+            first = 1.0 - max(0, info.input_gap_hi // tw - (-(-info.input_gap_lo // tw))) * tw / w.nx
+            for pname in ("row_pass", "col_pass"):
+                if pname not in kt:
+                    continue
+                n, ms = kt[pname]
+                if pname == "row_pass":
+                    rd = ((w.nslices - 1) * kept + first) / w.nslices
+                    b = wpl * XY * 8 * (rd + kept) + XY * 8
+                else:
+                    b = (wpl * XY * 16 + XY * 8) * kept
+                row[pname] = {"avg_launch_ms": ms / n, "algorithmic_bytes_per_launch": b,
+                              "achieved_GBs": b / (ms / n * 1e-3) / 1e9,
+                              "frac": b / (ms / n * 1e-3) / 1e9 / HBM_PEAK_GBS}
+            res[name] = row
+            log(f"large: {name}: {t:.2f} s per image, {n_probes / t:.1f} STEM pixels/s")
+    # one LMA pixel (L = 15) and one plain pixel against the FP64 oracle, 16 oracle waves
+    probe = (window[0] + 3, window[1] + 5)
+    L15 = 15
+    px = {}
+    for name, prec in (("fp32", lma.LMA_GEMM_FP32), ("split_bf16", lma.LMA_GEMM_SPLIT_BF16)):
+        lat = lma.lattice(w.scan[0], w.scan[1], R[0], R[1], 1, w.offset_frac, L15, prec, window=(probe[0], probe[1], 1, 1))
+        with lma.Plan(opt, lat, det) as plan:
+            plan.propagate(vd)
+            px[name] = plan.probe_image()[:, 0, 0]
+            if name == "fp32":
+                ppx = plan.plain_image(vd)[:, 0, 0]
+    st = Setup(w.nx, w.ny, w.lx, w.ly, lam, sig, w.dz, w.bandlimit, w.alpha_mrad * 1e-3, w.defocus, w.cs, w.scan,
+               rings)
+    ol = Lattice(st, R, 1, w.offset_frac, L15)
+    nbr = ol.nearest(*probe)
+    jobs = [((ta, tb), tuple(float(c) for c in ol.translate_position(ta, tb))) for ta, tb in nbr]
+    jobs.append(("plain", st.probe_position(*probe)))
+    _LARGE_ORACLE.update(st=st, v=v)
+    log(f"large: FP64 oracle, {len(jobs)} waves on {min(cores, len(jobs))} processes")
+    t0 = time.perf_counter()
+    with ProcessPoolExecutor(min(cores, len(jobs))) as ex:
+        waves = dict(ex.map(_large_oracle_wave, jobs))
+    t_oracle = time.perf_counter() - t0
+    _LARGE_ORACLE.clear()
+    alpha = least_squares(st, ol, st.spec0, *probe)[0]
+    ref = ph.detector_values(sum(c * waves[t] for c, t in zip(alpha, nbr)), st.masks)
+    pref = ph.detector_values(waves["plain"], st.masks)
+    res["error_vs_oracle"] = {
+        "lma_pixel": list(probe), "L": L15,
+        "lma_pixel_rel_err_fp32": [float(x) for x in np.abs(px["fp32"] - ref) / np.abs(ref)],
+        "lma_pixel_rel_err_split_bf16": [float(x) for x in np.abs(px["split_bf16"] - ref) / np.abs(ref)],
+        "plain_pixel_rel_err": [float(x) for x in np.abs(ppx - pref) / np.abs(pref)],
+        "oracle_wall_s": t_oracle, "oracle_waves": len(jobs), "oracle_processes": min(cores, len(jobs))}
     return res
 
 
@@ -687,12 +968,19 @@ def main():
                     help="LMA at translate spacings 4, 8, 16 px against plain multislice (one configuration)")
     ap.add_argument("--summarize-counters", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "CAL_FETCH_DIR", "CAL_WRITE_DIR"),
                     help="print the HBM-traffic summary (JSON) of four rocprofv3 --pmc output directories")
+    ap.add_argument("--serve-c5", choices=("fp32", "split_bf16"),
+                    help="serving with requests drawn from the other workloads' sizes (one precision per run)")
+    ap.add_argument("--serve-rates", type=str, default="1,2,5,10,20,50,100,200",
+                    help="arrival rates of --serve-c5 (requests/s, comma separated)")
     ap.add_argument("--serve", action="store_true",
                     help="p50/p99 latency of the request loop under Poisson arrivals of image and local-edit requests")
     ap.add_argument("--paper-shaped", action="store_true",
                     help="LMA against plain multislice in the paper's regime (1024^2, 424x400 scan, f=2)")
     ap.add_argument("--window-study", action="store_true",
                     help="LMA with translates propagated on 64, 128, 256 px windows against plain multislice")
+    ap.add_argument("--large-subscan", action="store_true",
+                    help="the large precision workload on a 16 x 16-probe sub-scan (split BF16 and FP32), with its "
+                         "error against the FP64 oracle")
     ap.add_argument("--uneven", action="store_true",
                     help="64 specimens of mixed sizes: eager, one batch graph, autotuned plans with graphs")
     ap.add_argument("--summarize-pmc", nargs="+", metavar="RUN_DIR",
@@ -710,10 +998,18 @@ def main():
         import torch
         a = torch.ones(1 << 27, dtype=torch.float64, device="cuda")   # 1 GiB
         b = torch.empty_like(a)
-        for _ in range(4):
+        b.copy_(a)
+        # the copies run on torch's current stream, so its events time them
+        t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0.record()
+        for _ in range(3):
             b.copy_(a)
+        t1.record()
         torch.cuda.synchronize()
-        print(json.dumps({"copy_bytes_each_way": a.numel() * 8, "copies": 4}), flush=True)
+        ms = t0.elapsed_time(t1) / 3
+        nbytes = a.numel() * 8
+        print(json.dumps({"copy_bytes_each_way": nbytes, "copies": 4, "ms_per_copy": ms,
+                          "read_plus_write_GBps": 2 * nbytes / (ms * 1e-3) / 1e9}), flush=True)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the library has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
@@ -733,8 +1029,16 @@ def main():
     if args.serve:
         serve()
         return
+    if args.serve_c5:
+        prec = lma.LMA_GEMM_SPLIT_BF16 if args.serve_c5 == "split_bf16" else lma.LMA_GEMM_FP32
+        rates = tuple(float(x) for x in args.serve_rates.split(","))
+        print(json.dumps(serve_c5(prec, rates, n_requests=args.serve_requests)), flush=True)
+        return
     if args.uneven:
         uneven()
+        return
+    if args.large_subscan:
+        print(json.dumps(large_subscan()), flush=True)
         return
     if args.spacing_study:
         spacing_study(w)

@@ -75,6 +75,7 @@ struct lma_plan {
   int wzc0 = 0, wzc1 = 0;            // the same on the translate windows
   int sc0 = 0, sc1 = 0;              // kx columns where the probe spectrum vanishes
   int uc0 = 0, uc1 = 0;              // ... and where the input wave u's spectrum does
+  int pz34 = 0, wpz34 = 0;           // the propagator vanishes at ky in [3ny/8, 5ny/8) (cell, windows)
   int32_t *d_row_of = nullptr, *d_set_dx = nullptr, *d_set_dy = nullptr;
   int32_t *d_chunk_start = nullptr, *d_chunk_len = nullptr;
   uint32_t* d_chunk_mask = nullptr;
@@ -208,6 +209,17 @@ void compute_gaps(lma_plan* p) {
     band_gap(f2T(h.uspec, nx, ny, 1.0 / XY), nx, ny, nullptr, &p->uc0, &p->uc1);
   }
   if (h.wnx > 0) band_gap(f2T(h.wprop, h.wnx, h.wny, 1.0), h.wnx, h.wny, nullptr, &p->wzc0, &p->wzc1);
+  // ky positions [3n/8, 5n/8) where the propagator (as uploaded, FP32) is zero for every kx
+  auto zero34 = [](const std::vector<cd>& prop, int w, int hh) {
+    for (int y = 3 * hh / 8; y < 5 * hh / 8; ++y)
+      for (int x = 0; x < w; ++x) {
+        const cd& z = prop[(size_t)y * w + x];
+        if ((float)z.real() != 0.f || (float)z.imag() != 0.f) return 0;
+      }
+    return 1;
+  };
+  p->pz34 = zero34(h.prop, nx, ny);
+  if (h.wnx > 0) p->wpz34 = zero34(h.wprop, h.wnx, h.wny);
 }
 
 lma::dev::Tables window_tables(const lma_plan* p) {
@@ -223,6 +235,7 @@ lma::dev::Tables window_tables(const lma_plan* p) {
   t.twy = p->d_wtwy;
   t.zc0 = p->wzc0;
   t.zc1 = p->wzc1;
+  t.prop_z34 = p->wpz34;
   return t;
 }
 
@@ -241,6 +254,7 @@ lma::dev::Tables tables(const lma_plan* p) {
   t.maskT = p->d_maskT;
   t.zc0 = p->zc0;
   t.zc1 = p->zc1;
+  t.prop_z34 = p->pz34;
   return t;
 }
 

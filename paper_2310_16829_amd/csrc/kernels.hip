@@ -107,6 +107,98 @@ __device__ __forceinline__ void dft5(float2* a) {
   a[3] = csub(r2, i2);
 }
 
+// c + w b with four FMAs, and 2 b - s with two: a twiddled butterfly pair a +- w b becomes
+// s = a + w b and d = 2 a - s, six operations instead of eight
+__device__ __forceinline__ float2 cfma(float2 b, float2 w, float2 c) {
+  return make_float2(__builtin_fmaf(b.x, w.x, __builtin_fmaf(-b.y, w.y, c.x)),
+                     __builtin_fmaf(b.x, w.y, __builtin_fmaf(b.y, w.x, c.y)));
+}
+__device__ __forceinline__ float2 ctwice_minus(float2 b, float2 s) {
+  return make_float2(__builtin_fmaf(2.f, b.x, -s.x), __builtin_fmaf(2.f, b.y, -s.y));
+}
+
+// 8-point DFT with optional input twiddles w[m - 1] (m = 1..7, already conjugated for the
+// direction) folded into its first butterfly level. Z34: inputs 3 and 4 are known zeros (not
+// read); SKIP34: outputs 3 and 4 are not needed (not computed). Levels: pairs (0,4), (2,6),
+// (1,5), (3,7); then the two 4-point combinations; then the W8 twiddles and the final pairs.
+#ifndef LMA_FUSED_TW
+#define LMA_FUSED_TW 1
+#endif
+template <int DIR, bool TW, bool Z34, bool SKIP34>
+__device__ __forceinline__ void dft8x(float2* a, const float2* w) {
+  static_assert(!(TW && Z34), "known-zero inputs only without twiddles (the first stage)");
+  float2 s04, d04, s26, d26, s15, d15, s37, d37;
+  if constexpr (TW && !LMA_FUSED_TW) {
+    const float2 a1 = cmul(a[1], w[0]), a2 = cmul(a[2], w[1]), a3 = cmul(a[3], w[2]), a4 = cmul(a[4], w[3]);
+    const float2 a5 = cmul(a[5], w[4]), a6 = cmul(a[6], w[5]), a7 = cmul(a[7], w[6]);
+    s04 = cadd(a[0], a4);
+    d04 = csub(a[0], a4);
+    s26 = cadd(a2, a6);
+    d26 = csub(a2, a6);
+    s15 = cadd(a1, a5);
+    d15 = csub(a1, a5);
+    s37 = cadd(a3, a7);
+    d37 = csub(a3, a7);
+  } else if constexpr (TW) {
+    s04 = cfma(a[4], w[3], a[0]);
+    d04 = ctwice_minus(a[0], s04);
+    const float2 b2 = cmul(a[2], w[1]);
+    s26 = cfma(a[6], w[5], b2);
+    d26 = ctwice_minus(b2, s26);
+    const float2 b1 = cmul(a[1], w[0]);
+    s15 = cfma(a[5], w[4], b1);
+    d15 = ctwice_minus(b1, s15);
+    const float2 b3 = cmul(a[3], w[2]);
+    s37 = cfma(a[7], w[6], b3);
+    d37 = ctwice_minus(b3, s37);
+  } else if constexpr (Z34) {
+    s04 = a[0];
+    d04 = a[0];
+    s26 = cadd(a[2], a[6]);
+    d26 = csub(a[2], a[6]);
+    s15 = cadd(a[1], a[5]);
+    d15 = csub(a[1], a[5]);
+    s37 = a[7];
+    d37 = make_float2(-a[7].x, -a[7].y);
+  } else {
+    s04 = cadd(a[0], a[4]);
+    d04 = csub(a[0], a[4]);
+    s26 = cadd(a[2], a[6]);
+    d26 = csub(a[2], a[6]);
+    s15 = cadd(a[1], a[5]);
+    d15 = csub(a[1], a[5]);
+    s37 = cadd(a[3], a[7]);
+    d37 = csub(a[3], a[7]);
+  }
+  // the two 4-point DFTs (evens e, odds o)
+  const float2 e0 = cadd(s04, s26), e2 = csub(s04, s26);
+  const float2 i26 = mul_unit_i<DIR>(d26);
+  const float2 e1 = cadd(d04, i26), e3 = csub(d04, i26);
+  float2 o0 = cadd(s15, s37), o2 = csub(s15, s37);
+  const float2 i37 = mul_unit_i<DIR>(d37);
+  float2 o1 = cadd(d15, i37), o3 = csub(d15, i37);
+  const float r = 0.70710678118654752440f;
+  // o1 *= W8^1, o2 *= W8^2, o3 *= W8^3 (W8 = exp(DIR * 2 pi i / 8))
+  if (DIR < 0) {
+    o1 = make_float2(r * (o1.x + o1.y), r * (o1.y - o1.x));
+    o3 = make_float2(r * (o3.y - o3.x), -r * (o3.x + o3.y));
+  } else {
+    o1 = make_float2(r * (o1.x - o1.y), r * (o1.x + o1.y));
+    o3 = make_float2(-r * (o3.x + o3.y), r * (o3.x - o3.y));
+  }
+  o2 = mul_unit_i<DIR>(o2);
+  a[0] = cadd(e0, o0);
+  a[1] = cadd(e1, o1);
+  a[2] = cadd(e2, o2);
+  a[5] = csub(e1, o1);
+  a[6] = csub(e2, o2);
+  a[7] = csub(e3, o3);
+  if constexpr (!SKIP34) {
+    a[3] = cadd(e3, o3);
+    a[4] = csub(e0, o0);
+  }
+}
+
 template <int R, int DIR>
 __device__ __forceinline__ void dft_r(float2* a) {
   if constexpr (R == 8) dft8<DIR>(a);
@@ -218,7 +310,21 @@ __device__ __forceinline__ void exchange_sync() {
   else __syncthreads();
 }
 
-template <int N, int DIR, int S, bool WL, int TAG = 0>
+// Pruning bits of a transform whose stages are all radix 8 with one butterfly per thread
+// (E = 8): PRUNE_IN, its inputs at positions [3N/8, 5N/8) are zeros (the first stage's inputs
+// 3 and 4); PRUNE_OUT, its outputs there are not needed (the last stage's outputs 3 and 4).
+enum { PRUNE_IN = 1, PRUNE_OUT = 2 };
+#ifndef LMA_PRUNE
+#define LMA_PRUNE 1
+#endif
+__host__ __device__ constexpr bool fft_prunable(int n) {
+  if (!fft_pow2(n) || fft_elems(n) != 8) return false;
+  for (int s = 0; s < fft_nstages(n); ++s)
+    if (fft_radix(n, s) != 8) return false;
+  return true;
+}
+
+template <int N, int DIR, int S, bool WL, int TAG = 0, int PRUNE = 0>
 __device__ __forceinline__ void fft_stage(float2 (&v)[fft_elems(N)], int j, const float2* w, const float2* twg,
                                           const Slot& slot) {
   constexpr int E = fft_elems(N);
@@ -228,6 +334,44 @@ __device__ __forceinline__ void fft_stage(float2 (&v)[fft_elems(N)], int j, cons
   constexpr int T = N / E;
   constexpr bool last = (S == fft_nstages(N) - 1);
   constexpr int off = tw_off(N, S);
+  static_assert(PRUNE == 0 || fft_prunable(N), "pruning needs radix-8 stages with E = 8");
+  constexpr bool z34 = (PRUNE & PRUNE_IN) && S == 0;
+  constexpr bool skip34 = (PRUNE & PRUNE_OUT) && last;
+  if constexpr (r == 8 && tw_in_regs(N)) {
+    // radix 8 with register twiddles: the twiddles folded into the first butterfly level
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      float2 a[8];
+#pragma unroll
+      for (int m = 0; m < 8; ++m) a[m] = (z34 && (m == 3 || m == 4)) ? make_float2(0.f, 0.f) : v[q + m * Q];
+      const int b = j + T * q;
+      const int k = mod_c<Ns>(b);
+      if constexpr (Ns > 1) {
+        float2 tw7[7];
+#pragma unroll
+        for (int m = 1; m < 8; ++m) tw7[m - 1] = conj_if_inv<DIR>(w[off + q * 7 + (m - 1)]);
+        dft8x<DIR, true, false, skip34>(a, tw7);
+      } else {
+        dft8x<DIR, false, z34, skip34>(a, nullptr);
+      }
+      if constexpr (last) {
+#pragma unroll
+        for (int m = 0; m < 8; ++m)
+          if (!(skip34 && (m == 3 || m == 4))) v[q + m * Q] = a[m];
+      } else {
+        const int base = div_c<Ns>(b) * Ns * 8 + k;
+#pragma unroll
+        for (int m = 0; m < 8; ++m) slot.put(base + m * Ns, a[m]);
+      }
+    }
+    if constexpr (!last) {
+      exchange_sync<WL>();
+#pragma unroll
+      for (int m = 0; m < E; ++m) v[m] = slot.get(j + T * m);
+      exchange_sync<WL>();
+    }
+    return;
+  }
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
     float2 a[r];
@@ -272,17 +416,17 @@ __device__ __forceinline__ void fft_stage(float2 (&v)[fft_elems(N)], int j, cons
 // twiddle table (lengths whose twiddles are not held in registers). TAG gives a kernel its
 // own instantiation: the embedding kernel sharing the passes' changed their register
 // allocation (640 points: 33-58 spilled registers).
-template <int N, int DIR, bool WL, int TAG = 0>
+template <int N, int DIR, bool WL, int TAG = 0, int PRUNE = 0>
 __device__ __forceinline__ void fft(float2 (&v)[fft_elems(N)], int j, const float2* w, const float2* twg,
                                     const Slot& slot) {
   constexpr int ns = fft_nstages(N);
   static_assert(ns <= 6, "at most six stages");
-  fft_stage<N, DIR, 0, WL, TAG>(v, j, w, twg, slot);
-  if constexpr (ns > 1) fft_stage<N, DIR, (ns > 1 ? 1 : 0), WL, TAG>(v, j, w, twg, slot);
-  if constexpr (ns > 2) fft_stage<N, DIR, (ns > 2 ? 2 : 0), WL, TAG>(v, j, w, twg, slot);
-  if constexpr (ns > 3) fft_stage<N, DIR, (ns > 3 ? 3 : 0), WL, TAG>(v, j, w, twg, slot);
-  if constexpr (ns > 4) fft_stage<N, DIR, (ns > 4 ? 4 : 0), WL, TAG>(v, j, w, twg, slot);
-  if constexpr (ns > 5) fft_stage<N, DIR, (ns > 5 ? 5 : 0), WL, TAG>(v, j, w, twg, slot);
+  fft_stage<N, DIR, 0, WL, TAG, PRUNE>(v, j, w, twg, slot);
+  if constexpr (ns > 1) fft_stage<N, DIR, (ns > 1 ? 1 : 0), WL, TAG, PRUNE>(v, j, w, twg, slot);
+  if constexpr (ns > 2) fft_stage<N, DIR, (ns > 2 ? 2 : 0), WL, TAG, PRUNE>(v, j, w, twg, slot);
+  if constexpr (ns > 3) fft_stage<N, DIR, (ns > 3 ? 3 : 0), WL, TAG, PRUNE>(v, j, w, twg, slot);
+  if constexpr (ns > 4) fft_stage<N, DIR, (ns > 4 ? 4 : 0), WL, TAG, PRUNE>(v, j, w, twg, slot);
+  if constexpr (ns > 5) fft_stage<N, DIR, (ns > 5 ? 5 : 0), WL, TAG, PRUNE>(v, j, w, twg, slot);
 }
 
 // Blocks are dispatched round-robin over the 8 XCDs; give each XCD a contiguous range of
@@ -376,6 +520,10 @@ struct PassArgs {
                              //   INIT: the tile columns of the input spectrum's gap
   int zread;                 // row passes: skip reading tile columns [rlo, rhi), which hold
   int rlo, rhi;              //   zeros
+  int prune;                 // column-type passes of 512- and 64-point lines (radix-8 stages, 8
+                             //   per thread): the propagator vanishes at ky positions [3N/8, 5N/8)
+                             //   of every column, so the column FFT does not form them and the
+                             //   inverse FFT takes them as zeros
 };
 
 __device__ __forceinline__ void split_bf16(float x, __hip_bfloat16& hi, __hip_bfloat16& lo) {
@@ -397,14 +545,15 @@ __device__ __forceinline__ void store_stream(float2* p, float2 v) {
 #ifndef LMA_PASS_PRIORITY
 #define LMA_PASS_PRIORITY 2
 #endif
-// Column-layout passes address their items through buffer resources (32-bit offsets, 37
-// fewer registers per thread at 512 points); row passes keep 64-bit global addressing, which
-// measured faster for their contiguous items.
+// Passes address their items through buffer resources (32-bit offsets, 37 fewer registers per
+// thread at 512 points for column items); elements in a gap are read and written at an offset
+// past the item's extent, which reads zero and drops the store without touching memory, so the
+// item's loads and stores carry no branches.
 #ifndef LMA_BUFFER_IO_COL
 #define LMA_BUFFER_IO_COL 1
 #endif
 #ifndef LMA_BUFFER_IO_ROW
-#define LMA_BUFFER_IO_ROW 0
+#define LMA_BUFFER_IO_ROW 1
 #endif
 // Raw buffer access to one work item: the resource (base, byte extent) lives in scalar
 // registers, each lane supplies a 32-bit byte offset; accesses past the extent read zero and
@@ -413,6 +562,7 @@ typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t item_rsrc(const float2* base, uint32_t bytes) {
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<float2*>(base), 0, (int)bytes, 0x00020000);
 }
+constexpr int kOutOfItem = 0x0FFFFFFF;   // element offset beyond every item's extent
 __device__ __forceinline__ float2 load_item_elem(__amdgpu_buffer_rsrc_t r, int off) {
   return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, off * 8, 0, 2));
 }
@@ -488,9 +638,18 @@ constexpr int pass_waves() { return pass_rows(MODE) ? LMA_WL_WAVES_ROW : LMA_WL_
 // Register budget: lengths 5 * 2^a are held to two wavefronts per SIMD (at most 256 VGPRs;
 // unlimited they take 280-310 and run one wavefront per SIMD, measured 30 % slower at 640);
 // the others are not limited.
+#ifndef LMA_MIN_WAVES_512
+#define LMA_MIN_WAVES_512 1
+#endif
+template <int N, int MODE>
+constexpr int pass_min_waves() {
+  if (fft_odd(N) == 5) return 2;
+  if (N == 512 && (MODE == PASS_ROW || MODE == PASS_COL)) return LMA_MIN_WAVES_512;
+  return 1;
+}
 template <int N, int TW, int MODE>
 __global__ __launch_bounds__((PassCfg<N, TW, pass_waves<MODE>()>::WAVES * 64))
-__attribute__((amdgpu_waves_per_eu(fft_odd(N) == 5 ? 2 : 1, 8))) void k_pass(PassArgs a) {
+__attribute__((amdgpu_waves_per_eu(pass_min_waves<N, MODE>(), 8))) void k_pass(PassArgs a) {
   using C = PassCfg<N, TW, pass_waves<MODE>()>;
   constexpr int T = C::T, S = C::S, RS = C::RS, TPB = C::TPB, RPW = C::RPW;
   constexpr int NT = C::WAVES * 64;
@@ -500,6 +659,27 @@ __attribute__((amdgpu_waves_per_eu(fft_odd(N) == 5 ? 2 : 1, 8))) void k_pass(Pas
 #ifndef LMA_PREFETCH
 #define LMA_PREFETCH 1
 #endif
+// The next item's loads are issued after the first round's table loads have been used: a
+// wait for the table (issued mid-transform) also waits for every vector-memory operation
+// issued before it, which would otherwise hold each line's transform until the whole
+// prefetch had arrived from HBM.
+#ifndef LMA_LATE_PREFETCH
+#define LMA_LATE_PREFETCH 1
+#endif
+#ifndef LMA_EARLY_TABLE
+#define LMA_EARLY_TABLE 1
+#endif
+#ifndef LMA_ENTRY_STORES_ROW
+#define LMA_ENTRY_STORES_ROW 1
+#endif
+#ifndef LMA_ENTRY_STORES_COL
+#define LMA_ENTRY_STORES_COL 0
+#endif
+  // measured on the 512-point passes: the late prefetch pays in row and column passes and not
+  // in the gather (no write-back to overlap with), the entry stores in row passes only
+  constexpr bool kLate = LMA_LATE_PREFETCH && MODE != PASS_GATHER && MODE != PASS_REDUCE && MODE != PASS_INIT;
+  constexpr bool kEntryStores = kLate && (ROWS ? LMA_ENTRY_STORES_ROW : LMA_ENTRY_STORES_COL);
+
   constexpr bool PREF = LMA_PREFETCH && EPT <= 16;         // next item prefetched into registers
   constexpr int CHUNK = stage_chunk(EPT);                  // staging step otherwise
   static_assert(TOTAL % NT == 0, "work item must split evenly over the threads");
@@ -563,16 +743,22 @@ __attribute__((amdgpu_waves_per_eu(fft_odd(N) == 5 ? 2 : 1, 8))) void k_pass(Pas
   constexpr bool kBufferIO = ROWS ? LMA_BUFFER_IO_ROW : LMA_BUFFER_IO_COL;
   // bytes a work item spans in HBM (row item: TW contiguous lines; column item: N / TW tiles)
   const uint32_t item_bytes = (uint32_t)(ROWS ? (size_t)TW * a.nx * 8 : ((size_t)(N / TW - 1) * stride_q + M::TT) * 8);
-  auto load_item = [&](int l) {
+
+  // extent: the bytes the loads may touch (0: every load reads zero without a memory access)
+  auto load_item = [&](int l, uint32_t extent) {
     const float2* src = item_ptr(l);
     memory_phase_begin();
     if constexpr (kBufferIO) {
-      const __amdgpu_buffer_rsrc_t r = item_rsrc(src, item_bytes);
+      const __amdgpu_buffer_rsrc_t r = item_rsrc(src, extent);
 #pragma unroll
       for (int k = 0; k < EPT; ++k) {
         int lds, off;
         M::at(k * NT + tid, stride_q, lds, off);
-        buf[k] = (a.zread && in_rgap(k * NT + tid)) ? make_float2(0.f, 0.f) : load_item_elem(r, off);
+        // a gap element is read at an offset past the item's extent: zero, no memory access,
+        // and no branch (every load of the prefetch is issued, so waits on the loads after it
+        // are counted exactly)
+        if (a.zread && in_rgap(k * NT + tid)) off = kOutOfItem;
+        buf[k] = load_item_elem(r, off);
       }
     } else {
 #pragma unroll
@@ -585,13 +771,41 @@ __attribute__((amdgpu_waves_per_eu(fft_odd(N) == 5 ? 2 : 1, 8))) void k_pass(Pas
     memory_phase_end();
   };
   if constexpr (PREF && MODE != PASS_INIT) {
-    if (walk.valid(walk.l)) load_item(walk.l);
+    if (walk.valid(walk.l)) load_item(walk.l, item_bytes);
+    // as many stores as an item writes back, to an empty extent (dropped): the loop is then
+    // entered with the memory operations its back edge carries, so the waits at its head
+    // cover the prefetch alone instead of the previous item's stores as well
+    if constexpr (kBufferIO && kEntryStores) {
+      const __amdgpu_buffer_rsrc_t r0 = item_rsrc(a.work, 0u);
+#pragma unroll
+      for (int k = 0; k < EPT; ++k) store_item_elem(r0, k * NT + tid, make_float2(0.f, 0.f));
+    }
   }
+  int next_item = -1;                                      // the item a late prefetch loads
+  int cur_item = walk.l;
+  auto late_prefetch = [&](int round) {
+    if constexpr (PREF && kLate) {
+      if (round == 0) {
+        // keep the loads after the table's uses: hoisted above them, they would share its wait
+        __builtin_amdgcn_sched_barrier(0);
+        if constexpr (kBufferIO) {
+          // issued on every path, past the last item with an empty extent: the waits on the
+          // loads before them then count these too, and need not cover all of them
+          const bool more = next_item >= 0;
+          load_item(more ? next_item : cur_item, more ? item_bytes : 0u);
+        } else if (next_item >= 0) {
+          load_item(next_item, item_bytes);
+        }
+      }
+    }
+  };
 
 #pragma unroll 1
   for (int l = walk.l; walk.valid(l); l += walk.step) {
     const int g = group_of(l), w = l % B;
     float2* item = item_ptr(l);
+    next_item = walk.valid(l + walk.step) ? l + walk.step : -1;
+    cur_item = l;
     __syncthreads();                                       // the previous item is out of LDS
 
     // ---- stage the item's lines into LDS, then start loading the next item ----------------
@@ -604,7 +818,7 @@ __attribute__((amdgpu_waves_per_eu(fft_odd(N) == 5 ? 2 : 1, 8))) void k_pass(Pas
           tile[lds] = buf[k];
         }
         __syncthreads();
-        if (walk.valid(l + walk.step)) load_item(l + walk.step);
+        if (!kLate && walk.valid(l + walk.step)) load_item(l + walk.step, item_bytes);
       } else {
 #pragma unroll 1
         for (int c0 = 0; c0 < TOTAL; c0 += NT * CHUNK) {
@@ -676,6 +890,24 @@ __attribute__((amdgpu_waves_per_eu(fft_odd(N) == 5 ? 2 : 1, 8))) void k_pass(Pas
         }
         fft<N, +1, C::WL>(v, j, tw, a.tw, slot);
       } else {
+        // column-type passes of 512 or 64 points prune their transforms where the propagator
+        // vanishes (the row pass would prune the band gap the same way, but measured 5 % slower
+        // with it: its two code paths cost more than the skipped work)
+        constexpr bool kPrunable = fft_prunable(N) && (MODE == PASS_COL || MODE == PASS_GATHER || MODE == PASS_REDUCE);
+        const bool prune = kPrunable && a.prune;
+        // the line's table values (t_j or the propagator), loaded before the first transform so
+        // that it covers their latency (measured on the 512-point passes: 4 % off the row pass,
+        // neutral in the column pass, 8 % slower in the gather, which has no write-back)
+        constexpr bool kEarly = LMA_EARLY_TABLE && (MODE == PASS_ROW || MODE == PASS_COL);
+        [[maybe_unused]] float2 tv[kEarly ? C::E : 1];
+        if constexpr (kEarly) {
+#pragma unroll
+          for (int m = 0; m < C::E; ++m) tv[m] = tab[j + T * m];
+        }
+        auto tab_at = [&](int m) -> float2 {
+          if constexpr (kEarly) return tv[m];
+          else return tab[j + T * m];
+        };
 #pragma unroll
         for (int m = 0; m < C::E; ++m) v[m] = slot.get(j + T * m);
         // the first stage overwrites the line: every thread of the transform must have read it
@@ -683,7 +915,8 @@ __attribute__((amdgpu_waves_per_eu(fft_odd(N) == 5 ? 2 : 1, 8))) void k_pass(Pas
         if constexpr (MODE == PASS_ROW) {
           fft<N, +1, C::WL>(v, j, tw, a.tw, slot);
 #pragma unroll
-          for (int m = 0; m < C::E; ++m) v[m] = cmul(v[m], tab[j + T * m]);
+          for (int m = 0; m < C::E; ++m) v[m] = cmul(v[m], tab_at(m));
+          late_prefetch(rr);
           fft<N, -1, C::WL>(v, j, tw, a.tw, slot);
         } else if constexpr (MODE == PASS_ROW_WIN || MODE == PASS_ROW_LAST) {
           fft<N, +1, C::WL>(v, j, tw, a.tw, slot);
@@ -701,13 +934,34 @@ __attribute__((amdgpu_waves_per_eu(fft_odd(N) == 5 ? 2 : 1, 8))) void k_pass(Pas
             if (col >= a.tnx) col -= a.tnx;
             v[m] = cmul(v[m], trow[col]);
           }
+          late_prefetch(rr);
           if constexpr (MODE == PASS_ROW_WIN) fft<N, -1, C::WL>(v, j, tw, a.tw, slot);
         } else {
-          fft<N, -1, C::WL>(v, j, tw, a.tw, slot);
+          // column FFT, propagator; with pruning the outputs in [3N/8, 5N/8), where the
+          // propagator vanishes for every column, are not formed and stay zeros
+          bool pruned = false;
+          if constexpr (kPrunable) {
+            if (prune) {
+              fft<N, -1, C::WL, 0, PRUNE_OUT>(v, j, tw, a.tw, slot);
 #pragma unroll
-          for (int m = 0; m < C::E; ++m) v[m] = cmul(v[m], tab[j + T * m]);
+              for (int m = 0; m < C::E; ++m)
+                v[m] = (m == 3 || m == 4) ? make_float2(0.f, 0.f) : cmul(v[m], tab_at(m));
+              pruned = true;
+            }
+          }
+          if (!pruned) {
+            fft<N, -1, C::WL>(v, j, tw, a.tw, slot);
+#pragma unroll
+            for (int m = 0; m < C::E; ++m) v[m] = cmul(v[m], tab_at(m));
+          }
+          late_prefetch(rr);
           if constexpr (MODE == PASS_COL) {
-            fft<N, +1, C::WL>(v, j, tw, a.tw, slot);
+            if constexpr (kPrunable) {
+              if (prune) fft<N, +1, C::WL, 0, PRUNE_IN>(v, j, tw, a.tw, slot);
+              else fft<N, +1, C::WL>(v, j, tw, a.tw, slot);
+            } else {
+              fft<N, +1, C::WL>(v, j, tw, a.tw, slot);
+            }
           } else if constexpr (MODE == PASS_GATHER) {
             if (active) {
               const int64_t brow = a.wave_row[w];
@@ -776,7 +1030,8 @@ __attribute__((amdgpu_waves_per_eu(fft_odd(N) == 5 ? 2 : 1, 8))) void k_pass(Pas
         for (int k = 0; k < EPT; ++k) {
           int lds, off;
           M::at(k * NT + tid, stride_q, lds, off);
-          if (!kGapStores || !in_gap(k * NT + tid)) store_item_elem(r, off, tile[lds]);
+          if (kGapStores && in_gap(k * NT + tid)) off = kOutOfItem;
+          store_item_elem(r, off, tile[lds]);
         }
       } else {
 #pragma unroll
@@ -925,14 +1180,31 @@ __global__ __launch_bounds__(kCT) void k_contract(Contraction c) {
 // ------------------------------------------------------------------------------------------
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
+// Work item of a contraction workgroup: (super-tile, detector-pixel chunk), in chunk-major
+// order. Blocks are dispatched round-robin over the 8 XCDs; each XCD takes a contiguous range
+// of that order, so the XCDs work on different chunks at once (no basis segment is fetched by
+// two XCDs together) and an XCD's consecutive workgroups are neighbouring super-tiles of one
+// chunk, whose translate rectangles overlap in its L2.
+__device__ __forceinline__ void stencil_item(const Stencil& c, int& ti, int& tj, int& chunk) {
+  const int nt = c.tiles_x * c.tiles_y;
+#ifndef LMA_CONTRACT_XCD
+#define LMA_CONTRACT_XCD 1
+#endif
+  const int l = LMA_CONTRACT_XCD ? xcd_remap((int)blockIdx.x, (int)gridDim.x) : (int)blockIdx.x;
+  const int t = l % nt;
+  chunk = l / nt;
+  ti = c.tile_x0 + t % c.tiles_x;
+  tj = c.tile_y0 + t / c.tiles_x;
+}
+
 template <int SPLIT, int KS>
 __global__ __launch_bounds__(256) void k_contract_mfma(Stencil c) {
   extern __shared__ unsigned char dyn[];
   const int nt = c.W * c.H;
   float2* slab = reinterpret_cast<float2*>(dyn);                          // [nt][16]
   int32_t* rowid = reinterpret_cast<int32_t*>(slab + (size_t)nt * 16);    // [nt]
-  const int ti = c.tile_x0 + (int)blockIdx.x % c.tiles_x, tj = c.tile_y0 + (int)blockIdx.x / c.tiles_x;
-  const int chunk = blockIdx.y;
+  int ti, tj, chunk;
+  stencil_item(c, ti, tj, chunk);
   const int ox = (c.ox0 + ti * c.tile_dx) % c.Rfx;
   const int oy = (c.oy0 + tj * c.tile_dy) % c.Rfy;
   for (int t = threadIdx.x; t < nt; t += 256) {
@@ -1155,6 +1427,7 @@ static PassArgs pass_args(const Tables& T, float2* work) {
     a.zlo = a.rlo = lo;
     a.zhi = a.rhi = hi;
   }
+  a.prune = LMA_PRUNE && T.prop_z34 && fft_prunable(T.ny) ? 1 : 0;   // column-type passes
   return a;
 }
 // tile columns wholly inside the input spectrum's gap
@@ -1179,6 +1452,7 @@ hipError_t row_pass(const Tables& T, float2* work, const float2* trans_j, int B,
   PassArgs a = pass_args(T, work);
   if (!after_column) input_gap_tiles(T, &a.rlo, &a.rhi);   // the initial waves skipped these
   a.zread = 1;
+  a.prune = 0;
   a.table = trans_j;
   a.tw = T.twx;
   return pass_dispatch<PASS_ROW>(T.nx, tw_of(T), T.ny, a, B, s);
@@ -1395,8 +1669,8 @@ __global__ __launch_bounds__(512) void k_contract_mfma2(Stencil c) {
   float2* slab = reinterpret_cast<float2*>(dyn);                          // [nt][16]
   int32_t* rowid = reinterpret_cast<int32_t*>(slab + (size_t)nt * 16);    // [nt]
   __shared__ f32x4 part[4][2][64];                                        // upper halves' sums
-  const int ti = c.tile_x0 + (int)blockIdx.x % c.tiles_x, tj = c.tile_y0 + (int)blockIdx.x / c.tiles_x;
-  const int chunk = blockIdx.y;
+  int ti, tj, chunk;
+  stencil_item(c, ti, tj, chunk);
   const int ox = (c.ox0 + ti * c.tile_dx) % c.Rfx;
   const int oy = (c.oy0 + tj * c.tile_dy) % c.Rfy;
   for (int t = threadIdx.x; t < nt; t += 512) {
@@ -1497,8 +1771,8 @@ __global__ __launch_bounds__(512) void k_contract_mfma2_dma(Stencil c) {
   float2* slab = reinterpret_cast<float2*>(dyn);                          // [ntp][16]
   int32_t* rowid = reinterpret_cast<int32_t*>(slab + (size_t)ntp * 16);   // [ntp]
   __shared__ f32x4 part[4][2][64];
-  const int ti = c.tile_x0 + (int)blockIdx.x % c.tiles_x, tj = c.tile_y0 + (int)blockIdx.x / c.tiles_x;
-  const int chunk = blockIdx.y;
+  int ti, tj, chunk;
+  stencil_item(c, ti, tj, chunk);
   const int ox = (c.ox0 + ti * c.tile_dx) % c.Rfx;
   const int oy = (c.oy0 + tj * c.tile_dy) % c.Rfy;
   for (int t = threadIdx.x; t < ntp; t += 512) {
@@ -1609,8 +1883,8 @@ __global__ __launch_bounds__(512) void k_contract_bf16(Stencil c) {
   float2* slab = reinterpret_cast<float2*>(dyn);                          // [ntp][16] raw split values
   int32_t* rowid = reinterpret_cast<int32_t*>(slab + (size_t)ntp * 16);   // [ntp]
   __shared__ f32x4 part[4][2][64];
-  const int ti = c.tile_x0 + (int)blockIdx.x % c.tiles_x, tj = c.tile_y0 + (int)blockIdx.x / c.tiles_x;
-  const int chunk = blockIdx.y;
+  int ti, tj, chunk;
+  stencil_item(c, ti, tj, chunk);
   const int ox = (c.ox0 + ti * c.tile_dx) % c.Rfx;
   const int oy = (c.oy0 + tj * c.tile_dy) % c.Rfy;
   for (int t = threadIdx.x; t < ntp; t += 512) {
@@ -1729,7 +2003,7 @@ static hipError_t stencil_ks(const Stencil& c, hipStream_t s) {
       const void* fb = reinterpret_cast<const void*>(&k_contract_bf16<GH>);
       hipError_t e = hipFuncSetAttribute(fb, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shd);
       if (e != hipSuccess) return e;
-      dim3 grid((unsigned)(c.tiles_x * c.tiles_y), (unsigned)c.nchunks);
+      dim3 grid((unsigned)((int64_t)c.tiles_x * c.tiles_y * c.nchunks));
       k_contract_bf16<GH><<<grid, 512, shd, s>>>(c);
       return hipGetLastError();
     }
@@ -1739,21 +2013,21 @@ static hipError_t stencil_ks(const Stencil& c, hipStream_t s) {
       const void* fd = reinterpret_cast<const void*>(&k_contract_mfma2_dma<KS / 2>);
       hipError_t e = hipFuncSetAttribute(fd, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shd);
       if (e != hipSuccess) return e;
-      dim3 grid((unsigned)(c.tiles_x * c.tiles_y), (unsigned)c.nchunks);
+      dim3 grid((unsigned)((int64_t)c.tiles_x * c.tiles_y * c.nchunks));
       k_contract_mfma2_dma<KS / 2><<<grid, 512, shd, s>>>(c);
       return hipGetLastError();
     }
     const void* fn = reinterpret_cast<const void*>(&k_contract_mfma2<SPLIT, KS / 2>);
     hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
     if (e != hipSuccess) return e;
-    dim3 grid((unsigned)(c.tiles_x * c.tiles_y), (unsigned)c.nchunks);
+    dim3 grid((unsigned)((int64_t)c.tiles_x * c.tiles_y * c.nchunks));
     k_contract_mfma2<SPLIT, KS / 2><<<grid, 512, shm, s>>>(c);
     return hipGetLastError();
   }
   const void* fn = reinterpret_cast<const void*>(&k_contract_mfma<SPLIT, KS>);
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
   if (e != hipSuccess) return e;
-  dim3 grid((unsigned)(c.tiles_x * c.tiles_y), (unsigned)c.nchunks);
+  dim3 grid((unsigned)((int64_t)c.tiles_x * c.tiles_y * c.nchunks));
   k_contract_mfma<SPLIT, KS><<<grid, 256, shm, s>>>(c);
   return hipGetLastError();
 }

@@ -27,6 +27,10 @@ struct Tables {
   // every ky: the initial-wave pass skips their tile columns and the first row pass does not
   // read them
   int ic0 = 0, ic1 = 0;
+  // the propagator (with its band limit) vanishes at ky positions [3 ny/8, 5 ny/8) of every
+  // column: column transforms of 512 or 64 points skip forming those outputs and treat them
+  // as zeros on the way back
+  int prop_z34 = 0;
 };
 
 struct Contraction {
