@@ -291,8 +291,11 @@ __device__ __forceinline__ void tw_load(float2* w, const float2* __restrict__ ta
 #ifndef LMA_SLOT_PAD
 #define LMA_SLOT_PAD 3
 #endif
-#ifndef LMA_TILE_EXTRA
-#define LMA_TILE_EXTRA 3
+#ifndef LMA_TILE_EXTRA_ROW
+#define LMA_TILE_EXTRA_ROW 9
+#endif
+#ifndef LMA_TILE_EXTRA_COL
+#define LMA_TILE_EXTRA_COL 3
 #endif
 __host__ __device__ constexpr int slot_pos(int p) { return p + (p >> LMA_SLOT_PAD); }
 struct Slot {
@@ -489,9 +492,11 @@ struct PassCfg {
   static constexpr int WAVES = WL ? ((TW / S) < WLW ? TW / S : WLW) : WPT * KMW;
   static constexpr int TPB = WAVES * S / WPT;                       // transforms in flight
   static constexpr int RPW = TW / TPB;                              // rounds per workgroup
-  // LDS line stride: a padded slot plus LMA_TILE_EXTRA, so that the TW lines touched by one
-  // tile row fall on distinct banks
-  static constexpr int RS = slot_pos(N - 1) + 1 + LMA_TILE_EXTRA;
+  // LDS line stride: a padded slot plus a few elements, so that the TW lines touched by one
+  // tile row fall on distinct banks (row passes stage a tile row by row, column passes
+  // column by column: each has its own stride)
+  static constexpr int RS_ROW = slot_pos(N - 1) + 1 + LMA_TILE_EXTRA_ROW;
+  static constexpr int RS_COL = slot_pos(N - 1) + 1 + LMA_TILE_EXTRA_COL;
   static constexpr int NTW = tw_count(N);
   static_assert(TPB >= 1 && TW % TPB == 0, "lines must split evenly over the workgroup");
 };
@@ -569,6 +574,14 @@ __device__ __forceinline__ float2 load_item_elem(__amdgpu_buffer_rsrc_t r, int o
 __device__ __forceinline__ void store_item_elem(__amdgpu_buffer_rsrc_t r, int off, float2 v) {
   __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, off * 8, 0, 2);
 }
+// the same with the offset split into a per-lane part (voff) and a wavefront-uniform part
+// (soff, bytes); the range check covers the per-lane part, so an empty extent still drops them
+__device__ __forceinline__ float2 load_item_elem2(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+  return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 2));
+}
+__device__ __forceinline__ void store_item_elem2(__amdgpu_buffer_rsrc_t r, int voff, int soff, float2 v) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, voff, soff, 2);
+}
 
 __device__ __forceinline__ void memory_phase_begin() {
   if constexpr (LMA_PASS_PRIORITY > 0) __builtin_amdgcn_s_setprio(LMA_PASS_PRIORITY);
@@ -583,7 +596,7 @@ __device__ __forceinline__ void memory_phase_end() {
 template <int N, int TW, bool ROWS>
 struct TileMap {
   static constexpr int TT = TW * TW;
-  static constexpr int RS = PassCfg<N, TW>::RS;   // independent of the wavefront count
+  static constexpr int RS = ROWS ? PassCfg<N, TW>::RS_ROW : PassCfg<N, TW>::RS_COL;  // any wavefront count
   __device__ __forceinline__ static int64_t item_base(int g, int nx) {
     return ROWS ? (int64_t)g * TW * nx : (int64_t)g * TT;
   }
@@ -651,7 +664,7 @@ template <int N, int TW, int MODE>
 __global__ __launch_bounds__((PassCfg<N, TW, pass_waves<MODE>()>::WAVES * 64))
 __attribute__((amdgpu_waves_per_eu(pass_min_waves<N, MODE>(), 8))) void k_pass(PassArgs a) {
   using C = PassCfg<N, TW, pass_waves<MODE>()>;
-  constexpr int T = C::T, S = C::S, RS = C::RS, TPB = C::TPB, RPW = C::RPW;
+  constexpr int T = C::T, S = C::S, RS = pass_rows(MODE) ? C::RS_ROW : C::RS_COL, TPB = C::TPB, RPW = C::RPW;
   constexpr int NT = C::WAVES * 64;
   constexpr bool ROWS = pass_rows(MODE);
   constexpr int TOTAL = TW * N;                            // elements of one work item
@@ -659,10 +672,10 @@ __attribute__((amdgpu_waves_per_eu(pass_min_waves<N, MODE>(), 8))) void k_pass(P
 #ifndef LMA_PREFETCH
 #define LMA_PREFETCH 1
 #endif
-// The next item's loads are issued after the first round's table loads have been used: a
-// wait for the table (issued mid-transform) also waits for every vector-memory operation
-// issued before it, which would otherwise hold each line's transform until the whole
-// prefetch had arrived from HBM.
+// The next item's loads are issued in the item's last round, after its table values have
+// been used: a wait for the table also waits for every vector-memory operation issued before
+// it, which would otherwise hold each line's transform until the whole prefetch had arrived
+// from HBM (and the prefetch registers are free in the rounds before).
 #ifndef LMA_LATE_PREFETCH
 #define LMA_LATE_PREFETCH 1
 #endif
@@ -744,11 +757,38 @@ __attribute__((amdgpu_waves_per_eu(pass_min_waves<N, MODE>(), 8))) void k_pass(P
   // bytes a work item spans in HBM (row item: TW contiguous lines; column item: N / TW tiles)
   const uint32_t item_bytes = (uint32_t)(ROWS ? (size_t)TW * a.nx * 8 : ((size_t)(N / TW - 1) * stride_q + M::TT) * 8);
 
+  // When a wavefront's 64 elements of a step lie in one tile, their offsets are one uniform
+  // part per step (held in scalar registers) plus the lane's own 8 bytes times the lane, and a
+  // gap tile is skipped by an empty extent for that step rather than by per-lane offsets.
+  // Measured on the 512-point passes: 11 of 86 us off the initial waves, 1 us off the column
+  // pass, but 9 us onto the row pass and 3 onto the gather, so those keep per-lane offsets.
+#ifndef LMA_SPLIT_OFFSETS
+#define LMA_SPLIT_OFFSETS 1
+#endif
+  constexpr bool kSplitOff = kBufferIO && LMA_SPLIT_OFFSETS && (MODE == PASS_COL || MODE == PASS_INIT) &&
+                             M::TT % 64 == 0 && NT % 64 == 0;
+  const int wid = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int lane_off = lane * 8;
+  // step k: the uniform byte offset of this wavefront's elements and their tile q
+  auto step_soff = [&](int k, int& q) -> int {
+    const int cb = k * NT + wid * 64;
+    q = cb / M::TT;
+    return ROWS ? cb * 8 : (q * stride_q + cb % M::TT) * 8;
+  };
+
   // extent: the bytes the loads may touch (0: every load reads zero without a memory access)
   auto load_item = [&](int l, uint32_t extent) {
     const float2* src = item_ptr(l);
     memory_phase_begin();
-    if constexpr (kBufferIO) {
+    if constexpr (kSplitOff) {
+#pragma unroll
+      for (int k = 0; k < EPT; ++k) {
+        int q;
+        const int so = step_soff(k, q);
+        const bool skip = a.zread && ROWS && q >= a.rlo && q < a.rhi;
+        buf[k] = load_item_elem2(item_rsrc(src, skip ? 0u : extent), lane_off, so);
+      }
+    } else if constexpr (kBufferIO) {
       const __amdgpu_buffer_rsrc_t r = item_rsrc(src, extent);
 #pragma unroll
       for (int k = 0; k < EPT; ++k) {
@@ -778,14 +818,15 @@ __attribute__((amdgpu_waves_per_eu(pass_min_waves<N, MODE>(), 8))) void k_pass(P
     if constexpr (kBufferIO && kEntryStores) {
       const __amdgpu_buffer_rsrc_t r0 = item_rsrc(a.work, 0u);
 #pragma unroll
-      for (int k = 0; k < EPT; ++k) store_item_elem(r0, k * NT + tid, make_float2(0.f, 0.f));
+      for (int k = 0; k < EPT; ++k) store_item_elem2(r0, lane_off, 0, make_float2(0.f, 0.f));
     }
   }
   int next_item = -1;                                      // the item a late prefetch loads
   int cur_item = walk.l;
   auto late_prefetch = [&](int round) {
     if constexpr (PREF && kLate) {
-      if (round == 0) {
+      if (round == RPW - 1) {                              // the last round: the prefetch
+                                                           // registers are free until then
         // keep the loads after the table's uses: hoisted above them, they would share its wait
         __builtin_amdgcn_sched_barrier(0);
         if constexpr (kBufferIO) {
@@ -806,7 +847,16 @@ __attribute__((amdgpu_waves_per_eu(pass_min_waves<N, MODE>(), 8))) void k_pass(P
     float2* item = item_ptr(l);
     next_item = walk.valid(l + walk.step) ? l + walk.step : -1;
     cur_item = l;
-    __syncthreads();                                       // the previous item is out of LDS
+    // the previous item is out of LDS. Passes that stage their items from registers and write
+    // them back through the same LDS slots skip this: each slot is read back (for the store)
+    // and then restaged by the same thread, and the write-back sits behind the barrier that
+    // follows the transforms.
+#ifndef LMA_TOP_BARRIER
+#define LMA_TOP_BARRIER 0
+#endif
+    constexpr bool kOwnSlots = PREF && !LMA_TOP_BARRIER &&
+                               (MODE == PASS_ROW || MODE == PASS_COL || MODE == PASS_ROW_WIN || MODE == PASS_ROW_LAST);
+    if constexpr (!kOwnSlots) __syncthreads();
 
     // ---- stage the item's lines into LDS, then start loading the next item ----------------
     if constexpr (MODE != PASS_INIT) {
@@ -1024,7 +1074,16 @@ __attribute__((amdgpu_waves_per_eu(pass_min_waves<N, MODE>(), 8))) void k_pass(P
       // ---- write the lines back, whole tiles, in place ------------------------------------
       __syncthreads();
       memory_phase_begin();
-      if constexpr (kBufferIO) {
+      if constexpr (kSplitOff) {
+#pragma unroll
+        for (int k = 0; k < EPT; ++k) {
+          int lds, off, q;
+          M::at(k * NT + tid, stride_q, lds, off);
+          const int so = step_soff(k, q);
+          const bool skip = kGapStores && q >= a.zlo && q < a.zhi;
+          store_item_elem2(item_rsrc(item, skip ? 0u : item_bytes), lane_off, so, tile[lds]);
+        }
+      } else if constexpr (kBufferIO) {
         const __amdgpu_buffer_rsrc_t r = item_rsrc(item, item_bytes);
 #pragma unroll
         for (int k = 0; k < EPT; ++k) {
