@@ -684,7 +684,7 @@ def _large_oracle_wave(job):
     return key, np.fft.fft2(multislice(translate_wave(st, st.spec0, pos), v, st.sigma, st.prop))
 
 
-def large_subscan(window=(120, 120, 16, 16), steps=2):
+def large_subscan(window=(120, 120, 16, 16), steps=1):
     """The large precision workload on a 16 x 16-probe sub-scan (2048^2 px over 204.8 A, 250
     slices, 300 kV, 25 mrad, defocus -50 A, translates every 4 px, L = 144, one phonon
     configuration): STEM pixels/s of the LMA image (propagation of the sub-scan's translates and
@@ -771,7 +771,7 @@ def large_subscan(window=(120, 120, 16, 16), steps=2):
             plan.propagate(vd)
             px[name] = plan.probe_image()[:, 0, 0]
             if name == "fp32":
-                ppx = plan.plain_image(vd)[:, 0, 0]
+                ppx = plan.plain_image(vd, device=True)[:, 0, 0].cpu().numpy()
     st = Setup(w.nx, w.ny, w.lx, w.ly, lam, sig, w.dz, w.bandlimit, w.alpha_mrad * 1e-3, w.defocus, w.cs, w.scan,
                rings)
     ol = Lattice(st, R, 1, w.offset_frac, L15)
