@@ -478,7 +478,7 @@ __host__ __device__ constexpr bool pass_rows(int mode) { return mode == PASS_ROW
 #ifndef LMA_WL_WAVES_ROW
 #define LMA_WL_WAVES_ROW 8
 #endif
-template <int N, int TW, int WLW = LMA_WL_WAVES>
+template <int N, int TW, int WLW = LMA_WL_WAVES, int KM = 2>
 struct PassCfg {
   static constexpr int E = fft_elems(N);                            // elements per thread
   static constexpr int T = N / E;                                   // threads per transform
@@ -488,7 +488,7 @@ struct PassCfg {
   // wavefronts per workgroup: single-wavefront transforms up to WLW lines at once; lines of
   // several wavefronts two at a time between the workgroup barriers (4 wavefronts at 1024
   // points, 8 at 2048)
-  static constexpr int KMW = TW < 2 ? TW : 2;   // multi-wavefront transforms in flight
+  static constexpr int KMW = TW < KM ? TW : KM;   // multi-wavefront transforms in flight
   static constexpr int WAVES = WL ? ((TW / S) < WLW ? TW / S : WLW) : WPT * KMW;
   static constexpr int TPB = WAVES * S / WPT;                       // transforms in flight
   static constexpr int RPW = TW / TPB;                              // rounds per workgroup
@@ -647,6 +647,15 @@ constexpr int stage_chunk(int ept) {
 
 template <int MODE>
 constexpr int pass_waves() { return pass_rows(MODE) ? LMA_WL_WAVES_ROW : LMA_WL_WAVES; }
+// lines spanning several wavefronts in flight per workgroup: 2048-point lines one at a time
+// (4-wavefront workgroups, two per CU: each exchange barrier holds one line's wavefronts; 13-15 %
+// faster row, column and gather passes than two lines per 8-wavefront workgroup), except the
+// initial waves (35 % slower so)
+#ifndef LMA_KMW_2048
+#define LMA_KMW_2048 1
+#endif
+template <int N, int MODE>
+constexpr int pass_kmw() { return N == 2048 && MODE != PASS_INIT ? LMA_KMW_2048 : 2; }
 
 // Register budget: lengths 5 * 2^a are held to two wavefronts per SIMD (at most 256 VGPRs;
 // unlimited they take 280-310 and run one wavefront per SIMD, measured 30 % slower at 640);
@@ -661,9 +670,9 @@ constexpr int pass_min_waves() {
   return 1;
 }
 template <int N, int TW, int MODE>
-__global__ __launch_bounds__((PassCfg<N, TW, pass_waves<MODE>()>::WAVES * 64))
+__global__ __launch_bounds__((PassCfg<N, TW, pass_waves<MODE>(), pass_kmw<N, MODE>()>::WAVES * 64))
 __attribute__((amdgpu_waves_per_eu(pass_min_waves<N, MODE>(), 8))) void k_pass(PassArgs a) {
-  using C = PassCfg<N, TW, pass_waves<MODE>()>;
+  using C = PassCfg<N, TW, pass_waves<MODE>(), pass_kmw<N, MODE>()>;
   constexpr int T = C::T, S = C::S, RS = pass_rows(MODE) ? C::RS_ROW : C::RS_COL, TPB = C::TPB, RPW = C::RPW;
   constexpr int NT = C::WAVES * 64;
   constexpr bool ROWS = pass_rows(MODE);
@@ -1383,7 +1392,7 @@ static int device_cus() {
 template <int N, int TW, int MODE>
 static hipError_t pass_launch(const PassArgs& a0, int lines, int B, hipStream_t s) {
   if (lines % TW) return hipErrorInvalidValue;
-  constexpr int threads = PassCfg<N, TW, pass_waves<MODE>()>::WAVES * 64;
+  constexpr int threads = PassCfg<N, TW, pass_waves<MODE>(), pass_kmw<N, MODE>()>::WAVES * 64;
   static std::atomic<int> cached{0};   // workgroups of this kernel resident per CU
   int resident = cached.load(std::memory_order_relaxed);
   if (resident == 0) {
