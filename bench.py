@@ -804,8 +804,10 @@ def uneven(n_specimens=64):
     so that every specimen propagates a few hundred translates. Timed with potentials
     resident in HBM, host planning excluded: (a) plan after plan, eager launches; (b) the
     same plans as one lma_batch graph launch; (c) plans built with LMA_AUTOTUNE | LMA_GRAPH,
-    plan after plan from captured graphs; (d) those plans as one lma_batch launch. Each
-    image is checked against (a)."""
+    plan after plan from captured graphs; (d) those plans as one lma_batch launch; (e) the
+    eager-layout plans as one grouped lma_batch (plans of one length class share each slice's
+    row and column pass launch); (f) the autotuned plans grouped. Each image is checked
+    against (a)."""
     from concurrent.futures import ProcessPoolExecutor
     import numpy as np
     import torch
@@ -871,6 +873,13 @@ def uneven(n_specimens=64):
     t_batch = timed(lambda: (batch.propagate(pots), images(plans, imgs)))
     err_batch = max(float(np.abs(im.cpu().numpy() - r).max() / np.abs(r).max()) for im, r in zip(imgs, ref))
     batch.close()
+    log("uneven: grouped batch (eager layout)")
+    batch = lma.Batch(plans, nsl, grouped=True)
+    batch.propagate(pots)
+    images(plans, imgs)
+    t_grouped = timed(lambda: (batch.propagate(pots), images(plans, imgs)))
+    err_grouped = max(float(np.abs(im.cpu().numpy() - r).max() / np.abs(r).max()) for im, r in zip(imgs, ref))
+    batch.close()
     for p in plans:
         p.close()
     del plans
@@ -885,9 +894,17 @@ def uneven(n_specimens=64):
     t_tuned_batch = timed(lambda: (batch.propagate(pots), images(plans, imgs)))
     err_tuned = max(float(np.abs(im.cpu().numpy() - r).max() / np.abs(r).max()) for im, r in zip(imgs, ref))
     batch.close()
+    log("uneven: grouped batch (autotuned layout)")
+    batch = lma.Batch(plans, nsl, grouped=True)
+    batch.propagate(pots)
+    images(plans, imgs)
+    t_tuned_grouped = timed(lambda: (batch.propagate(pots), images(plans, imgs)))
+    err_tuned_grouped = max(float(np.abs(im.cpu().numpy() - r).max() / np.abs(r).max()) for im, r in zip(imgs, ref))
+    batch.close()
     for p in plans:
         p.close()
-    res = {"eager": t_eager, "batch_graph": t_batch, "tuned_plan_graphs": t_graph, "tuned_batch_graph": t_tuned_batch}
+    res = {"eager": t_eager, "batch_graph": t_batch, "tuned_plan_graphs": t_graph, "tuned_batch_graph": t_tuned_batch,
+           "grouped_batch": t_grouped, "tuned_grouped_batch": t_tuned_grouped}
     print(json.dumps({
         "study": f"uneven batch: {len(ws)} specimens, sides {sides} at 0.1 A/px, 20-200 slices of 2 A, FCC "
                  "{14,29,79} V*A, 200 kV, 20 mrad, translates every 4 px, L=144, scans 32-128 per side; "
@@ -898,7 +915,8 @@ def uneven(n_specimens=64):
         "seconds": res,
         "stem_pixels_per_s": {k: pixels / t for k, t in res.items()},
         "translate_slices_per_s": {k: wave_slices / t for k, t in res.items()},
-        "max_rel_diff_vs_eager": {"batch_graph": err_batch, "tuned_batch_graph": err_tuned}}), flush=True)
+        "max_rel_diff_vs_eager": {"batch_graph": err_batch, "tuned_batch_graph": err_tuned,
+                                  "grouped_batch": err_grouped, "tuned_grouped_batch": err_tuned_grouped}}), flush=True)
 
 
 def contraction_roofline(plan, info, kt, split=False):

@@ -322,6 +322,19 @@ lma_status lma_batch_create(lma_plan* const* plans, int32_t n, const int32_t* ns
  * call returns when the propagation has finished. */
 lma_status lma_batch_propagate(lma_batch* batch, const float* const* potentials, int32_t flags);
 void lma_batch_destroy(lma_batch* batch);
+/* The same batch with plans of one transform-length class sharing their passes (the uneven
+ * batch's persistent launches per length class; the multislice step of Fig.
+ * multislice_pseudocode): plans with the same grid, tile width and band gap, bitwise the same
+ * propagator table and no translate windows hold all their translate waves in one device
+ * buffer of at most max_group_bytes (0: 32 GiB; a class that needs more is split), and each
+ * slice's row pass (every wave multiplied by its own plan's t_j) and column pass are one
+ * persistent launch over all of that buffer's waves still propagating; each plan's initial
+ * waves and its last column pass (the gather into its basis) stay its own. Other plans run
+ * their own slice loop as in lma_batch_create. Groups and those plans are spread over the
+ * graph's four branches. Same arguments and use otherwise; LMA_ERR_OOM when a group buffer
+ * cannot be allocated (nothing is kept). */
+lma_status lma_batch_create_grouped(lma_plan* const* plans, int32_t n, const int32_t* nslices, void* hip_stream,
+                                    int64_t max_group_bytes, lma_batch** out);
 
 /* Device bytes a plan with these arguments would hold for nslices slices. */
 lma_status lma_footprint(const lma_optics* optics, const lma_lattice* lattice,

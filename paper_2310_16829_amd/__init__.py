@@ -326,16 +326,21 @@ class Plan:
 
 
 class Batch:
-    """An lma_batch: the translate propagation of several plans as one graph launch."""
+    """An lma_batch: the translate propagation of several plans as one graph launch. With
+    grouped=True (lma_batch_create_grouped) plans of one transform-length class share their row
+    and column pass launches; max_group_bytes bounds each class's wave buffer (0: 32 GiB)."""
 
-    def __init__(self, plans, nslices, stream=None):
+    def __init__(self, plans, nslices, stream=None, grouped: bool = False, max_group_bytes: int = 0):
         self._plans = list(plans)
         n = len(self._plans)
         hs = (C.c_void_p * n)(*[p._h.value for p in self._plans])
         ns = (C.c_int32 * n)(*[int(x) for x in nslices])
         self._h = C.c_void_p()
         st = C.c_void_p(None) if stream is None else C.c_void_p(stream)
-        _check(lib().lma_batch_create(hs, n, ns, st, C.byref(self._h)))
+        if grouped:
+            _check(lib().lma_batch_create_grouped(hs, n, ns, st, int(max_group_bytes), C.byref(self._h)))
+        else:
+            _check(lib().lma_batch_create(hs, n, ns, st, C.byref(self._h)))
 
     def propagate(self, potentials, flags: int = 0):
         ptrs, fl = [], set()

@@ -101,6 +101,7 @@ SIGNATURES = {
     "lma_batch_create": (C.c_int, [C.POINTER(P), C.c_int32, C.POINTER(C.c_int32), P, C.POINTER(P)]),
     "lma_batch_propagate": (C.c_int, [P, C.POINTER(P), C.c_int32]),
     "lma_batch_destroy": (None, [P]),
+    "lma_batch_create_grouped": (C.c_int, [C.POINTER(P), C.c_int32, C.POINTER(C.c_int32), P, C.c_int64, C.POINTER(P)]),
     "lma_server_create": (C.c_int, [C.c_int32, C.c_int32, C.c_int64, C.POINTER(P)]),
     "lma_server_submit": (C.c_int, [P, C.POINTER(lma_request), C.POINTER(C.c_int64)]),
     "lma_server_wait": (C.c_int, [P, C.c_int64, C.POINTER(C.c_double), C.POINTER(C.c_double)]),

@@ -10,6 +10,7 @@
 #include <cstring>
 #include <mutex>
 #include <new>
+#include <stdexcept>
 #include <string>
 #include <vector>
 
@@ -1741,6 +1742,22 @@ lma_status lma_autotune(int32_t nx, int32_t ny, int64_t max_bytes, void* hip_str
 struct lma_batch {
   std::vector<lma_plan*> plans;
   std::vector<int32_t> nslices;
+  // grouped batches (lma_batch_create_grouped): plans of one transform-length class hold their
+  // translate waves in one buffer, and each row or column pass of a slice is one launch over
+  // every wave of the class still propagating
+  struct Group {
+    std::vector<int> plans;              // indices into `plans`, by decreasing slice count
+    std::vector<int64_t> first;          // first wave of each in the group's buffer
+    int64_t waves = 0;
+    double work = 0.0;                   // pixel-slices of its waves (for balancing branches)
+    float2* d_work = nullptr;            // [waves][tiles]
+    int32_t* d_wave_spec = nullptr;      // [waves] position in `plans` of the wave's plan
+    const float2** d_spec_trans = nullptr;  // [plans] transmission tables of each plan
+  };
+  std::vector<Group> groups;
+  std::vector<int> solo;                 // plans that run their own slice loop
+  std::vector<int> branch_of_group, branch_of_solo;
+  bool grouped = false;
   hipStream_t origin = nullptr;
   bool own_origin = false;
   std::vector<hipStream_t> branch;   // capture branches
@@ -1756,6 +1773,11 @@ constexpr int kBatchBranches = 4;
 void batch_release(lma_batch* b) {
   if (!b) return;
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  for (auto& g : b->groups) {
+    if (g.d_work) (void)hipFree(g.d_work);
+    if (g.d_wave_spec) (void)hipFree(g.d_wave_spec);
+    if (g.d_spec_trans) (void)hipFree(g.d_spec_trans);
+  }
   for (hipEvent_t e : b->plan_ev) (void)hipEventDestroy(e);
   for (hipEvent_t e : b->join) (void)hipEventDestroy(e);
   if (b->fork) (void)hipEventDestroy(b->fork);
@@ -1765,7 +1787,61 @@ void batch_release(lma_batch* b) {
   delete b;
 }
 
-// captures every plan's slice loop, plan i on branch i % kBatchBranches
+// The slice loop of a group (the translates of every plan in it): each plan's initial waves
+// into its part of the buffer, then per slice one row pass over the waves of every plan that
+// has the slice (plans sorted by decreasing slice count, so those waves are a prefix), one
+// column pass over the waves that go on, and the gather of each plan whose last slice it was.
+lma_status run_group(lma_batch* b, const lma_batch::Group& g, hipStream_t st) {
+  lma_plan* p0 = b->plans[g.plans[0]];
+  const lma::dev::Tables T = tables(p0);
+  const int64_t XY = (int64_t)T.nx * T.ny;
+  const size_t np = g.plans.size();
+  auto check = [](hipError_t e, const char* what) -> lma_status {
+    return e == hipSuccess ? LMA_OK : fail(LMA_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+  };
+  lma_status s = LMA_OK;
+  // the first row pass skips only the columns every plan's initial waves left zero
+  lma::dev::Tables Tr = T;
+  Tr.ic0 = 0;
+  Tr.ic1 = T.nx;
+  for (size_t k = 0; k < np && s == LMA_OK; ++k) {
+    lma_plan* p = b->plans[g.plans[k]];
+    lma::dev::Tables Ti = tables(p);
+    Ti.specT = p->d_uspecT;
+    Ti.ic0 = p->uc0;
+    Ti.ic1 = p->uc1;
+    Tr.ic0 = std::max(Tr.ic0, p->uc0);
+    Tr.ic1 = std::min(Tr.ic1, p->uc1);
+    s = check(lma::dev::init_waves(Ti, g.d_work + g.first[k] * XY, p->d_row_u, (int)p->h.rows.size(), st), "init");
+  }
+  if (Tr.ic1 <= Tr.ic0) Tr.ic0 = Tr.ic1 = 0;
+  const int maxns = b->nslices[g.plans[0]];
+  // waves of the plans with more than j slices
+  auto waves_beyond = [&](int j) -> int64_t {
+    for (size_t k = 0; k < np; ++k)
+      if (b->nslices[g.plans[k]] <= j) return g.first[k];
+    return g.waves;
+  };
+  for (int j = 0; j < maxns && s == LMA_OK; ++j) {
+    const int64_t W = waves_beyond(j), Wn = waves_beyond(j + 1);
+    s = check(lma::dev::row_pass_specimens(j == 0 ? Tr : T, g.d_work, g.d_spec_trans, g.d_wave_spec, (int64_t)j * XY,
+                                           (int)W, j > 0, st),
+              "row_pass");
+    if (s == LMA_OK && Wn > 0) s = check(lma::dev::col_pass(T, g.d_work, (int)Wn, st), "col_pass");
+    for (size_t k = 0; k < np && s == LMA_OK; ++k) {
+      if (b->nslices[g.plans[k]] != j + 1) continue;
+      lma_plan* p = b->plans[g.plans[k]];
+      const int split = p->h.lat.precision == LMA_GEMM_SPLIT_BF16;
+      s = check(lma::dev::col_gather(tables(p), g.d_work + g.first[k] * XY, (int)p->h.rows.size(), p->d_basis,
+                                     p->h.D(), p->d_row_id, split, st),
+                "col_gather");
+    }
+  }
+  return s;
+}
+
+// captures every plan's slice loop, plan i on branch i % kBatchBranches; in a grouped batch,
+// group k on branch k % kBatchBranches and the plans outside groups after them
 lma_status batch_capture(lma_batch* b) {
   hipGraph_t g = nullptr;
   HIP_TRY(hipStreamBeginCapture(b->origin, hipStreamCaptureModeRelaxed));
@@ -1773,13 +1849,21 @@ lma_status batch_capture(lma_batch* b) {
   hipError_t e = hipEventRecord(b->fork, b->origin);
   for (hipStream_t br : b->branch)
     if (e == hipSuccess) e = hipStreamWaitEvent(br, b->fork, 0);
-  for (size_t i = 0; i < b->plans.size() && e == hipSuccess && s == LMA_OK; ++i) {
-    lma_plan* p = b->plans[i];
+  for (size_t k = 0; k < b->groups.size() && e == hipSuccess && s == LMA_OK; ++k)
+    s = run_group(b, b->groups[k], b->branch[b->branch_of_group[k] % b->branch.size()]);
+  std::vector<int> order;
+  if (b->grouped) {
+    order = b->solo;
+  } else {
+    for (size_t i = 0; i < b->plans.size(); ++i) order.push_back((int)i);
+  }
+  for (size_t q = 0; q < order.size() && e == hipSuccess && s == LMA_OK; ++q) {
+    lma_plan* p = b->plans[order[q]];
     const hipStream_t keep = p->stream;
     const bool timing = p->timing;
-    p->stream = b->branch[i % b->branch.size()];
+    p->stream = b->branch[(b->grouped ? b->branch_of_solo[q] : (int)q) % b->branch.size()];
     p->timing = false;
-    s = run_waves(p, p->d_row_u, p->d_row_id, nullptr, (int)p->h.rows.size(), b->nslices[i]);
+    s = run_waves(p, p->d_row_u, p->d_row_id, nullptr, (int)p->h.rows.size(), b->nslices[order[q]]);
     p->stream = keep;
     p->timing = timing;
   }
@@ -1861,6 +1945,126 @@ lma_status lma_batch_create(lma_plan* const* plans, int32_t n, const int32_t* ns
     }
   }
   *out = b;
+  return LMA_OK;
+}
+
+lma_status lma_batch_create_grouped(lma_plan* const* plans, int32_t n, const int32_t* nslices, void* hip_stream,
+                                    int64_t max_group_bytes, lma_batch** out) {
+  lma_status s = lma_batch_create(plans, n, nslices, hip_stream, out);
+  if (s != LMA_OK) return s;
+  lma_batch* b = *out;
+  b->grouped = true;
+  if (max_group_bytes <= 0) max_group_bytes = (int64_t)32 << 30;
+  try {
+    // a class: same grid, tile width and band gap, bitwise the same propagator table, no
+    // translate windows
+    std::vector<std::vector<float2>> prop(n);
+    auto same_class = [&](int i, int k) {
+      const lma_plan *a = plans[i], *c = plans[k];
+      if (a->h.op.nx != c->h.op.nx || a->h.op.ny != c->h.op.ny || a->tw != c->tw || a->zc0 != c->zc0 ||
+          a->zc1 != c->zc1 || a->pz34 != c->pz34)
+        return false;
+      return std::memcmp(prop[i].data(), prop[k].data(), prop[i].size() * sizeof(float2)) == 0;
+    };
+    std::vector<int> cls(n, -1);
+    std::vector<std::vector<int>> classes;
+    for (int32_t i = 0; i < n; ++i) {
+      lma_plan* p = plans[i];
+      const int64_t XY = (int64_t)p->h.op.nx * p->h.op.ny;
+      const int64_t bytes = (int64_t)p->h.rows.size() * XY * (int64_t)sizeof(float2);
+      if (p->h.wnx > 0 || p->h.rows.empty() || bytes > max_group_bytes) {
+        b->solo.push_back(i);
+        continue;
+      }
+      prop[i].resize((size_t)XY);
+      if (hipMemcpy(prop[i].data(), p->d_propT, (size_t)XY * sizeof(float2), hipMemcpyDeviceToHost) != hipSuccess) {
+        (void)hipGetLastError();
+        throw std::runtime_error("reading a propagator table");
+      }
+      for (size_t c = 0; c < classes.size() && cls[i] < 0; ++c)
+        if (same_class(i, classes[c][0])) cls[i] = (int)c;
+      if (cls[i] < 0) {
+        cls[i] = (int)classes.size();
+        classes.emplace_back();
+      }
+      classes[cls[i]].push_back(i);
+    }
+    // groups: a class's plans by decreasing slice count, split where the buffer would exceed
+    // max_group_bytes or the group's work would pass an eighth of the batch's (so that the
+    // graph's four branches can be balanced)
+    auto work_of = [&](int i) {
+      return (double)plans[i]->h.rows.size() * plans[i]->h.op.nx * plans[i]->h.op.ny * nslices[i];
+    };
+    double total = 0.0;
+    for (int32_t i = 0; i < n; ++i) total += work_of(i);
+    const double target = total / (2.0 * kBatchBranches);
+    for (auto& c : classes) {
+      std::stable_sort(c.begin(), c.end(), [&](int x, int y) { return nslices[x] > nslices[y]; });
+      const int64_t XY = (int64_t)plans[c[0]]->h.op.nx * plans[c[0]]->h.op.ny;
+      lma_batch::Group g;
+      for (int i : c) {
+        const int64_t w = (int64_t)plans[i]->h.rows.size();
+        if (!g.plans.empty() &&
+            ((g.waves + w) * XY * (int64_t)sizeof(float2) > max_group_bytes || g.work >= target)) {
+          b->groups.push_back(std::move(g));
+          g = lma_batch::Group();
+        }
+        g.plans.push_back(i);
+        g.first.push_back(g.waves);
+        g.waves += w;
+        g.work += work_of(i);
+      }
+      if (!g.plans.empty()) b->groups.push_back(std::move(g));
+    }
+    // branches: the largest work first, each to the least loaded branch
+    {
+      std::vector<std::pair<double, int>> items;   // (work, group k >= 0 or solo ~q)
+      for (size_t k = 0; k < b->groups.size(); ++k) items.push_back({b->groups[k].work, (int)k});
+      for (size_t q = 0; q < b->solo.size(); ++q) items.push_back({work_of(b->solo[q]), ~(int)q});
+      std::stable_sort(items.begin(), items.end(), [](const auto& x, const auto& y) { return x.first > y.first; });
+      std::vector<double> load(kBatchBranches, 0.0);
+      b->branch_of_group.assign(b->groups.size(), 0);
+      b->branch_of_solo.assign(b->solo.size(), 0);
+      for (const auto& it : items) {
+        const int br = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        load[br] += it.first;
+        if (it.second >= 0) b->branch_of_group[it.second] = br;
+        else b->branch_of_solo[~it.second] = br;
+      }
+    }
+    for (auto& g : b->groups) {
+      const lma_plan* p0 = plans[g.plans[0]];
+      const int64_t XY = (int64_t)p0->h.op.nx * p0->h.op.ny;
+      if (g.waves > (int64_t)INT32_MAX / std::max(1, p0->h.op.ny)) throw std::runtime_error("group too large");
+      std::vector<int32_t> spec((size_t)g.waves);
+      std::vector<const float2*> trans(g.plans.size());
+      for (size_t k = 0; k < g.plans.size(); ++k) {
+        const int64_t end = k + 1 < g.plans.size() ? g.first[k + 1] : g.waves;
+        std::fill(spec.begin() + g.first[k], spec.begin() + end, (int32_t)k);
+        trans[k] = plans[g.plans[k]]->d_trans;
+      }
+      hipError_t e = hipMalloc((void**)&g.d_work, (size_t)(g.waves * XY) * sizeof(float2));
+      if (e == hipSuccess) e = hipMalloc((void**)&g.d_wave_spec, spec.size() * sizeof(int32_t));
+      if (e == hipSuccess) e = hipMalloc((void**)&g.d_spec_trans, trans.size() * sizeof(float2*));
+      if (e != hipSuccess) {
+        (void)hipGetLastError();
+        batch_release(b);
+        *out = nullptr;
+        return fail(LMA_ERR_OOM, std::string("group wave buffer: ") + hipGetErrorString(e));
+      }
+      e = hipMemcpy(g.d_wave_spec, spec.data(), spec.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+      if (e == hipSuccess)
+        e = hipMemcpy((void*)g.d_spec_trans, trans.data(), trans.size() * sizeof(float2*), hipMemcpyHostToDevice);
+      if (e != hipSuccess) {
+        (void)hipGetLastError();
+        throw std::runtime_error(std::string("group tables: ") + hipGetErrorString(e));
+      }
+    }
+  } catch (const std::exception& ex) {
+    batch_release(b);
+    *out = nullptr;
+    return fail(LMA_ERR_DEVICE, ex.what());
+  }
   return LMA_OK;
 }
 

@@ -529,6 +529,11 @@ struct PassArgs {
                              //   per thread): the propagator vanishes at ky positions [3N/8, 5N/8)
                              //   of every column, so the column FFT does not form them and the
                              //   inverse FFT takes them as zeros
+  // ROW over the waves of several specimens: wave w multiplies by the transmission of its own
+  // specimen, spec_table[wave_spec[w]] + slice_off (null wave_spec: `table` for every wave)
+  const float2* const* spec_table;
+  const int32_t* wave_spec;
+  int64_t slice_off;
 };
 
 __device__ __forceinline__ void split_bf16(float x, __hip_bfloat16& hi, __hip_bfloat16& lo) {
@@ -923,7 +928,11 @@ __attribute__((amdgpu_waves_per_eu(pass_min_waves<N, MODE>(), 8))) void k_pass(P
       const int r = rr * TPB + (active ? tslot : 0);       // line within the workgroup
       const int line = g * TW + r;                          // y (row pass) or x (column passes)
       const Slot slot{tile + (active ? r : TW) * RS};
-      const float2* tab = a.table + (size_t)line * N;
+      const float2* tab_base = a.table;
+      if constexpr (MODE == PASS_ROW) {
+        if (a.wave_spec) tab_base = a.spec_table[a.wave_spec[w]] + a.slice_off;
+      }
+      const float2* tab = tab_base + (size_t)line * N;
       float2 v[C::E];
       if constexpr (MODE == PASS_INIT) {
         // u(. - pos_w): spectrum times exp(-2 pi i mx ux / Qx) exp(-2 pi i my uy / Qy), each
@@ -1522,6 +1531,20 @@ hipError_t row_pass(const Tables& T, float2* work, const float2* trans_j, int B,
   a.zread = 1;
   a.prune = 0;
   a.table = trans_j;
+  a.tw = T.twx;
+  return pass_dispatch<PASS_ROW>(T.nx, tw_of(T), T.ny, a, B, s);
+}
+
+hipError_t row_pass_specimens(const Tables& T, float2* work, const float2* const* spec_trans, const int32_t* wave_spec,
+                              int64_t slice_off, int B, bool after_column, hipStream_t s) {
+  PassArgs a = pass_args(T, work);
+  if (!after_column) input_gap_tiles(T, &a.rlo, &a.rhi);
+  a.zread = 1;
+  a.prune = 0;
+  a.table = nullptr;
+  a.spec_table = spec_trans;
+  a.wave_spec = wave_spec;
+  a.slice_off = slice_off;
   a.tw = T.twx;
   return pass_dispatch<PASS_ROW>(T.nx, tw_of(T), T.ny, a, B, s);
 }

@@ -110,6 +110,10 @@ hipError_t init_waves(const Tables& T, float2* work, const int64_t* wave_u, int 
 // zero kx columns (the band gap) need not be read; otherwise they come from init_waves and
 // the columns of the input spectrum's gap (ic0, ic1) are not read
 hipError_t row_pass(const Tables& T, float2* work, const float2* trans_j, int B, bool after_column, hipStream_t s);
+// row pass of slice j over the waves of several specimens of one grid (their column passes
+// share T): wave w multiplies by spec_trans[wave_spec[w]] + slice_off (each specimen's t_j)
+hipError_t row_pass_specimens(const Tables& T, float2* work, const float2* const* spec_trans, const int32_t* wave_spec,
+                              int64_t slice_off, int B, bool after_column, hipStream_t s);
 // row pass of slice j for waves propagated on windows (Tw: the window's tables): row IFFT,
 // * t_j of the cell at each wave's window (origin: its position in pixels minus half the
 // window), row FFT; with last, no row FFT (the window's wave is left in real space)

@@ -107,3 +107,44 @@ def test_uneven_batch_matches_each_plan_alone():
     ref = crop(LMA(st, ol).image(pots[1], window_probes(p)), p)
     image_errors(p.probe_image(), ref, TOL32)
     batch.close()
+
+
+def test_grouped_batch_matches_each_plan_alone():
+    """lma_batch_create_grouped: plans of one length class (same grid and optics) share their row
+    and column passes over one wave buffer, with different slice counts and potentials; a plan
+    of another size forms a class of its own and a windowed plan runs its own slice loop. Every
+    plan's basis rows equal those of the plan run alone, bit for bit (the same arithmetic per
+    wave), over three launches; with a 1-byte group limit every plan runs alone."""
+    w = WORKLOADS["tiny"]
+    rng = np.random.default_rng(11)
+    specs = [dict(window=(3, 3, 6, 5)),
+             dict(window=(1, 1, 4, 4)),
+             dict(window=(5, 2, 3, 3)),
+             dict(nx=96, ny=96, lx=9.6, ly=9.6, scan=(12, 12), R=(24, 24), L=9, window=(1, 2, 5, 4)),
+             dict(window=(8, 1, 5, 6), prop_window=(64, 32))]
+    nsl = [10, 6, 10, 4, 7]
+    pots = [potential_slices(w, 0),
+            rng.uniform(0, 40, size=(nsl[1], 128, 128)).astype(np.float32),
+            potential_slices(w, 1),
+            rng.uniform(0, 40, size=(nsl[3], 96, 96)).astype(np.float32),
+            potential_slices(w, 2)[:nsl[4]]]
+    alone = [_plan(w, **s)[0] for s in specs]
+    refs = []
+    for p, v in zip(alone, pots):
+        p.propagate(v)
+        refs.append((p.basis_rows(0, p.n_rows), p.probe_image()))
+    for limit in (0, 1):
+        inb = [_plan(w, **s) for s in specs]
+        batch = lma.Batch([p for p, _, _ in inb], nsl, grouped=True, max_group_bytes=limit)
+        for rep in range(3):
+            say(f"grouped batch (limit {limit}), launch {rep}")
+            batch.propagate(pots)
+            for i, (p, _, _) in enumerate(inb):
+                assert np.array_equal(p.basis_rows(0, p.n_rows), refs[i][0]), f"launch {rep}, plan {i}: basis rows"
+                assert _rel(p.probe_image(), refs[i][1]) < 1e-12
+            inb[0][0].plain_image(pots[0])
+        if limit == 0:
+            p, st, ol = inb[2]
+            ref = crop(LMA(st, ol).image(pots[2], window_probes(p)), p)
+            image_errors(p.probe_image(), ref, TOL32)
+        batch.close()
