@@ -163,6 +163,10 @@ typedef struct {
   int32_t input_gap_lo, input_gap_hi; /* kx columns where the input wave u's spectrum     */
                              /* vanishes for every ky: the initial-wave pass skips    */
                              /* their tile columns and the first row pass reads none  */
+  int32_t radix_schedule;    /* order of the transforms' radices: 0 the base order    */
+                             /* (radix 8 first, or the odd radix first), 1 its last   */
+                             /* stage first, 2 its first stage last (lma_tuning); -1  */
+                             /* each length's default (640: 2, the others 0)           */
 } lma_info;
 
 /* Result of lma_autotune for one grid. */
@@ -170,7 +174,9 @@ typedef struct {
   int32_t tile_width;        /* fastest tile width of the wave layout (4, 8 or 16)    */
   int32_t batch;             /* fastest waves per propagation batch                  */
   double us_per_wave_slice;  /* its time for one slice (row + column pass) per wave  */
-  int32_t candidates;        /* (tile width, batch) pairs timed                      */
+  int32_t candidates;        /* (tile width, batch, radix schedule) triples timed     */
+  int32_t radix_schedule;    /* fastest order of the radices (see lma_info); lengths  */
+                             /* 256, 384, 640, 1024 and 2048 are built with three     */
 } lma_tuning;
 
 /* Per-kernel timing of the last timed calls (enable with lma_set_timing). */

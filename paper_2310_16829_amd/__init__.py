@@ -87,12 +87,13 @@ def footprint(opt: lma_optics, lat: lma_lattice, det: _Detectors, nslices: int) 
 
 
 def autotune(nx: int, ny: int, max_bytes: int = 0, stream=None) -> dict:
-    """lma_autotune: the fastest (tile width, batch) of the slice passes for an nx x ny grid."""
+    """lma_autotune: the fastest (tile width, batch, radix schedule) of the slice passes for an
+    nx x ny grid."""
     t = lma_tuning()
     st = _current_stream() if stream is None else C.c_void_p(stream)
     _check(lib().lma_autotune(int(nx), int(ny), int(max_bytes), st, C.byref(t)))
     return dict(tile_width=t.tile_width, batch=t.batch, us_per_wave_slice=t.us_per_wave_slice,
-                candidates=t.candidates)
+                candidates=t.candidates, radix_schedule=t.radix_schedule)
 
 
 def _is_torch(x) -> bool:

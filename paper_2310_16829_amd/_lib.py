@@ -45,12 +45,12 @@ class lma_info(C.Structure):
                 ("resident_rows", C.c_int64), ("multislice_calls", C.c_int64), ("tile_width", C.c_int32),
                 ("graphs", C.c_int32), ("prop_nx", C.c_int32), ("prop_ny", C.c_int32),
                 ("gap_lo", C.c_int32), ("gap_hi", C.c_int32), ("input_gap_lo", C.c_int32),
-                ("input_gap_hi", C.c_int32)]
+                ("input_gap_hi", C.c_int32), ("radix_schedule", C.c_int32)]
 
 
 class lma_tuning(C.Structure):
     _fields_ = [("tile_width", C.c_int32), ("batch", C.c_int32), ("us_per_wave_slice", C.c_double),
-                ("candidates", C.c_int32)]
+                ("candidates", C.c_int32), ("radix_schedule", C.c_int32)]
 
 
 class lma_request(C.Structure):

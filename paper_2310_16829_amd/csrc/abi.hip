@@ -51,6 +51,7 @@ struct lma_plan {
   int device = 0;
   int B = 1;                         // waves per batch
   int tw = 0;                        // tile width of the wave layout
+  int sched = -1;                    // radix schedule of the transforms (lma_tuning; -1: per length)
   bool basis_valid = false;
   // LMA_GRAPH: wave sequences by their buffers; a sequence seen twice is captured and replayed
   bool use_graph = false;
@@ -256,6 +257,7 @@ lma::dev::Tables tables(const lma_plan* p) {
   t.zc0 = p->zc0;
   t.zc1 = p->zc1;
   t.prop_z34 = p->pz34;
+  t.sched = p->sched;
   return t;
 }
 
@@ -717,6 +719,8 @@ lma_status lma_build_basis(const lma_optics* optics, const lma_lattice* lattice,
     p->use_graph = (flags & LMA_GRAPH) != 0;
     if (const char* e = std::getenv("LMA_TILE_WIDTH")) lma::dev::set_tile_width(std::atoi(e));
     p->tw = lma::dev::tile_width(h.op.nx, h.op.ny);
+    // a forced radix schedule (tuning and tests), 0 to 2
+    if (const char* e = std::getenv("LMA_RADIX_SCHEDULE")) p->sched = std::min(2, std::max(0, std::atoi(e)));
     if (!p->host_only && (flags & LMA_AUTOTUNE)) {
       lma_tuning t{};
       if (lma_status ts = lma_autotune(h.op.nx, h.op.ny, 0, p->stream, &t); ts != LMA_OK) {
@@ -724,6 +728,7 @@ lma_status lma_build_basis(const lma_optics* optics, const lma_lattice* lattice,
         return ts;
       }
       p->tw = t.tile_width;
+      p->sched = t.radix_schedule;
       if (h.lat.batch <= 0)
         p->B = std::max(1, std::min<int>(t.batch, (int)std::max<int64_t>(std::max<int64_t>((int64_t)h.rows.size(), h.n_probes()), 1)));
     }
@@ -1343,6 +1348,7 @@ lma_status lma_plan_info(const lma_plan* p, lma_info* out) {
   out->contract_kernel = p->st.ok ? 1 : 0;
   out->contract_k = p->st.ok ? 4 * p->st.nks : (int32_t)h.lat.L;
   out->tile_width = p->tw;
+  out->radix_schedule = p->sched;
   out->graphs = p->n_captured;
   out->prop_nx = p->h.wnx;
   out->gap_lo = p->zc0;
@@ -1673,12 +1679,14 @@ lma_status measure_tuning(int nx, int ny, int64_t max_bytes, hipStream_t st, lma
   best.us_per_wave_slice = 1e300;
   int tried = 0;
   for (int tw : widths) {
+    for (int sched = 0; sched < lma::dev::radix_schedules(nx, ny, tw); ++sched)
     for (int B : batches) {
       if (e != hipSuccess) break;
       lma::dev::Tables T;
       T.nx = nx;
       T.ny = ny;
       T.tw = tw;
+      T.sched = sched;
       T.propT = prop;
       T.twx = twx;
       T.twy = twy;
@@ -1701,6 +1709,7 @@ lma_status measure_tuning(int nx, int ny, int64_t max_bytes, hipStream_t st, lma
         best.us_per_wave_slice = us;
         best.tile_width = tw;
         best.batch = B;
+        best.radix_schedule = sched;
       }
     }
   }

@@ -225,13 +225,21 @@ __host__ __device__ constexpr int fft_nstages(int n) {
   return fft_pow2(n) ? fft_full8(n) + (fft_rest(n) > 1 ? 1 : 0)
                      : 1 + fft_log2(n / fft_odd(n)) / 2 + fft_log2(n / fft_odd(n)) % 2;
 }
-__host__ __device__ constexpr int fft_radix(int n, int s) {
+__host__ __device__ constexpr int fft_radix_base(int n, int s) {
   if (fft_pow2(n)) return s < fft_full8(n) ? 8 : fft_rest(n);
   return s == 0 ? fft_odd(n) : (s <= fft_log2(n / fft_odd(n)) / 2 ? 4 : 2);
 }
-__host__ __device__ constexpr int fft_span(int n, int s) {  // product of the radices before stage s
+// Radix schedules: the same radices in another order (every order is a valid Stockham
+// transform, the per-thread element count E is divisible by each). 0: the base order; 1: its
+// last stage first; 2: its first stage last. Lengths whose radices are all equal have one.
+__host__ __device__ constexpr int fft_radix(int n, int s, int sched = 0) {
+  const int ns = fft_nstages(n);
+  const int b = sched == 1 ? (s == 0 ? ns - 1 : s - 1) : sched == 2 ? (s == ns - 1 ? 0 : s + 1) : s;
+  return fft_radix_base(n, b);
+}
+__host__ __device__ constexpr int fft_span(int n, int s, int sched = 0) {  // product of the radices before stage s
   int p = 1;
-  for (int i = 0; i < s; ++i) p *= fft_radix(n, i);
+  for (int i = 0; i < s; ++i) p *= fft_radix(n, i, sched);
   return p;
 }
 // b mod NS and b / NS for b >= 0 (masks and shifts when NS is a power of two)
@@ -252,20 +260,20 @@ __host__ __device__ constexpr bool fft_length_ok(int n) {
 // form w^2, w^3 by complex products (FP32, a few ulp).
 // ------------------------------------------------------------------------------------------
 __host__ __device__ constexpr bool tw_in_regs(int n) { return fft_odd(n) != 5; }
-__host__ __device__ constexpr int tw_off(int n, int s) {
+__host__ __device__ constexpr int tw_off(int n, int s, int sched = 0) {
   int o = 0;
-  for (int i = 1; i < s; ++i) o += fft_elems(n) - fft_elems(n) / fft_radix(n, i);
+  for (int i = 1; i < s; ++i) o += fft_elems(n) - fft_elems(n) / fft_radix(n, i, sched);
   return o;
 }
-__host__ __device__ constexpr int tw_count(int n) {
-  return tw_in_regs(n) && tw_off(n, fft_nstages(n)) > 0 ? tw_off(n, fft_nstages(n)) : 1;
+__host__ __device__ constexpr int tw_count(int n, int sched = 0) {
+  return tw_in_regs(n) && tw_off(n, fft_nstages(n), sched) > 0 ? tw_off(n, fft_nstages(n), sched) : 1;
 }
 
-template <int N, int S>
+template <int N, int S, int SCHED = 0>
 __device__ __forceinline__ void tw_load_stage(float2* w, const float2* __restrict__ tab, int j) {
   constexpr int E = fft_elems(N);
-  constexpr int r = fft_radix(N, S), Ns = fft_span(N, S), Q = E / r, T = N / E;
-  constexpr int off = tw_off(N, S);
+  constexpr int r = fft_radix(N, S, SCHED), Ns = fft_span(N, S, SCHED), Q = E / r, T = N / E;
+  constexpr int off = tw_off(N, S, SCHED);
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
     const int k = mod_c<Ns>(j + T * q);
@@ -274,15 +282,15 @@ __device__ __forceinline__ void tw_load_stage(float2* w, const float2* __restric
   }
 }
 
-template <int N>
+template <int N, int SCHED = 0>
 __device__ __forceinline__ void tw_load(float2* w, const float2* __restrict__ tab, int j) {
   constexpr int ns = fft_nstages(N);
   if constexpr (!tw_in_regs(N)) return;
-  if constexpr (ns > 1) tw_load_stage<N, 1>(w, tab, j);
-  if constexpr (ns > 2) tw_load_stage<N, (ns > 2 ? 2 : 1)>(w, tab, j);
-  if constexpr (ns > 3) tw_load_stage<N, (ns > 3 ? 3 : 1)>(w, tab, j);
-  if constexpr (ns > 4) tw_load_stage<N, (ns > 4 ? 4 : 1)>(w, tab, j);
-  if constexpr (ns > 5) tw_load_stage<N, (ns > 5 ? 5 : 1)>(w, tab, j);
+  if constexpr (ns > 1) tw_load_stage<N, 1, SCHED>(w, tab, j);
+  if constexpr (ns > 2) tw_load_stage<N, (ns > 2 ? 2 : 1), SCHED>(w, tab, j);
+  if constexpr (ns > 3) tw_load_stage<N, (ns > 3 ? 3 : 1), SCHED>(w, tab, j);
+  if constexpr (ns > 4) tw_load_stage<N, (ns > 4 ? 4 : 1), SCHED>(w, tab, j);
+  if constexpr (ns > 5) tw_load_stage<N, (ns > 5 ? 5 : 1), SCHED>(w, tab, j);
 }
 
 // One transform's exchange slot inside the pass tile: position p lives at p + p/2^PAD (one
@@ -327,16 +335,16 @@ __host__ __device__ constexpr bool fft_prunable(int n) {
   return true;
 }
 
-template <int N, int DIR, int S, bool WL, int TAG = 0, int PRUNE = 0>
+template <int N, int DIR, int S, bool WL, int TAG = 0, int PRUNE = 0, int SCHED = 0>
 __device__ __forceinline__ void fft_stage(float2 (&v)[fft_elems(N)], int j, const float2* w, const float2* twg,
                                           const Slot& slot) {
   constexpr int E = fft_elems(N);
-  constexpr int r = fft_radix(N, S);
-  constexpr int Ns = fft_span(N, S);
+  constexpr int r = fft_radix(N, S, SCHED);
+  constexpr int Ns = fft_span(N, S, SCHED);
   constexpr int Q = E / r;
   constexpr int T = N / E;
   constexpr bool last = (S == fft_nstages(N) - 1);
-  constexpr int off = tw_off(N, S);
+  constexpr int off = tw_off(N, S, SCHED);
   static_assert(PRUNE == 0 || fft_prunable(N), "pruning needs radix-8 stages with E = 8");
   constexpr bool z34 = (PRUNE & PRUNE_IN) && S == 0;
   constexpr bool skip34 = (PRUNE & PRUNE_OUT) && last;
@@ -419,17 +427,17 @@ __device__ __forceinline__ void fft_stage(float2 (&v)[fft_elems(N)], int j, cons
 // twiddle table (lengths whose twiddles are not held in registers). TAG gives a kernel its
 // own instantiation: the embedding kernel sharing the passes' changed their register
 // allocation (640 points: 33-58 spilled registers).
-template <int N, int DIR, bool WL, int TAG = 0, int PRUNE = 0>
+template <int N, int DIR, bool WL, int TAG = 0, int PRUNE = 0, int SCHED = 0>
 __device__ __forceinline__ void fft(float2 (&v)[fft_elems(N)], int j, const float2* w, const float2* twg,
                                     const Slot& slot) {
   constexpr int ns = fft_nstages(N);
   static_assert(ns <= 6, "at most six stages");
-  fft_stage<N, DIR, 0, WL, TAG, PRUNE>(v, j, w, twg, slot);
-  if constexpr (ns > 1) fft_stage<N, DIR, (ns > 1 ? 1 : 0), WL, TAG, PRUNE>(v, j, w, twg, slot);
-  if constexpr (ns > 2) fft_stage<N, DIR, (ns > 2 ? 2 : 0), WL, TAG, PRUNE>(v, j, w, twg, slot);
-  if constexpr (ns > 3) fft_stage<N, DIR, (ns > 3 ? 3 : 0), WL, TAG, PRUNE>(v, j, w, twg, slot);
-  if constexpr (ns > 4) fft_stage<N, DIR, (ns > 4 ? 4 : 0), WL, TAG, PRUNE>(v, j, w, twg, slot);
-  if constexpr (ns > 5) fft_stage<N, DIR, (ns > 5 ? 5 : 0), WL, TAG, PRUNE>(v, j, w, twg, slot);
+  fft_stage<N, DIR, 0, WL, TAG, PRUNE, SCHED>(v, j, w, twg, slot);
+  if constexpr (ns > 1) fft_stage<N, DIR, (ns > 1 ? 1 : 0), WL, TAG, PRUNE, SCHED>(v, j, w, twg, slot);
+  if constexpr (ns > 2) fft_stage<N, DIR, (ns > 2 ? 2 : 0), WL, TAG, PRUNE, SCHED>(v, j, w, twg, slot);
+  if constexpr (ns > 3) fft_stage<N, DIR, (ns > 3 ? 3 : 0), WL, TAG, PRUNE, SCHED>(v, j, w, twg, slot);
+  if constexpr (ns > 4) fft_stage<N, DIR, (ns > 4 ? 4 : 0), WL, TAG, PRUNE, SCHED>(v, j, w, twg, slot);
+  if constexpr (ns > 5) fft_stage<N, DIR, (ns > 5 ? 5 : 0), WL, TAG, PRUNE, SCHED>(v, j, w, twg, slot);
 }
 
 // Blocks are dispatched round-robin over the 8 XCDs; give each XCD a contiguous range of
@@ -478,7 +486,7 @@ __host__ __device__ constexpr bool pass_rows(int mode) { return mode == PASS_ROW
 #ifndef LMA_WL_WAVES_ROW
 #define LMA_WL_WAVES_ROW 8
 #endif
-template <int N, int TW, int WLW = LMA_WL_WAVES, int KM = 2>
+template <int N, int TW, int WLW = LMA_WL_WAVES, int KM = 2, int SCHED = 0>
 struct PassCfg {
   static constexpr int E = fft_elems(N);                            // elements per thread
   static constexpr int T = N / E;                                   // threads per transform
@@ -497,7 +505,7 @@ struct PassCfg {
   // column by column: each has its own stride)
   static constexpr int RS_ROW = slot_pos(N - 1) + 1 + LMA_TILE_EXTRA_ROW;
   static constexpr int RS_COL = slot_pos(N - 1) + 1 + LMA_TILE_EXTRA_COL;
-  static constexpr int NTW = tw_count(N);
+  static constexpr int NTW = tw_count(N, SCHED);
   static_assert(TPB >= 1 && TW % TPB == 0, "lines must split evenly over the workgroup");
 };
 
@@ -674,10 +682,10 @@ constexpr int pass_min_waves() {
   if (N == 512 && (MODE == PASS_ROW || MODE == PASS_COL)) return LMA_MIN_WAVES_512;
   return 1;
 }
-template <int N, int TW, int MODE>
+template <int N, int TW, int MODE, int SCHED = 0>
 __global__ __launch_bounds__((PassCfg<N, TW, pass_waves<MODE>(), pass_kmw<N, MODE>()>::WAVES * 64))
 __attribute__((amdgpu_waves_per_eu(pass_min_waves<N, MODE>(), 8))) void k_pass(PassArgs a) {
-  using C = PassCfg<N, TW, pass_waves<MODE>(), pass_kmw<N, MODE>()>;
+  using C = PassCfg<N, TW, pass_waves<MODE>(), pass_kmw<N, MODE>(), SCHED>;
   constexpr int T = C::T, S = C::S, RS = pass_rows(MODE) ? C::RS_ROW : C::RS_COL, TPB = C::TPB, RPW = C::RPW;
   constexpr int NT = C::WAVES * 64;
   constexpr bool ROWS = pass_rows(MODE);
@@ -758,7 +766,7 @@ __attribute__((amdgpu_waves_per_eu(pass_min_waves<N, MODE>(), 8))) void k_pass(P
   constexpr bool kGapStores = MODE == PASS_ROW || MODE == PASS_ROW_WIN;
 
   float2 tw[C::NTW];
-  tw_load<N>(tw, a.tw, j);
+  tw_load<N, SCHED>(tw, a.tw, j);
 
   using M = TileMap<N, TW, ROWS>;
   const int stride_q = ntx * M::TT;                        // column items: tile-to-tile stride
@@ -956,7 +964,7 @@ __attribute__((amdgpu_waves_per_eu(pass_min_waves<N, MODE>(), 8))) void k_pass(P
           const double cs = xc * yf.x - xs * yf.y, sn = xc * yf.y + xs * yf.x;
           v[m] = cmul(tab[ky], make_float2((float)cs, (float)sn));
         }
-        fft<N, +1, C::WL>(v, j, tw, a.tw, slot);
+        fft<N, +1, C::WL, 0, 0, SCHED>(v, j, tw, a.tw, slot);
       } else {
         // column-type passes of 512 or 64 points prune their transforms where the propagator
         // vanishes (the row pass would prune the band gap the same way, but measured 5 % slower
@@ -981,13 +989,13 @@ __attribute__((amdgpu_waves_per_eu(pass_min_waves<N, MODE>(), 8))) void k_pass(P
         // the first stage overwrites the line: every thread of the transform must have read it
         exchange_sync<C::WL>();
         if constexpr (MODE == PASS_ROW) {
-          fft<N, +1, C::WL>(v, j, tw, a.tw, slot);
+          fft<N, +1, C::WL, 0, 0, SCHED>(v, j, tw, a.tw, slot);
 #pragma unroll
           for (int m = 0; m < C::E; ++m) v[m] = cmul(v[m], tab_at(m));
           late_prefetch(rr);
-          fft<N, -1, C::WL>(v, j, tw, a.tw, slot);
+          fft<N, -1, C::WL, 0, 0, SCHED>(v, j, tw, a.tw, slot);
         } else if constexpr (MODE == PASS_ROW_WIN || MODE == PASS_ROW_LAST) {
-          fft<N, +1, C::WL>(v, j, tw, a.tw, slot);
+          fft<N, +1, C::WL, 0, 0, SCHED>(v, j, tw, a.tw, slot);
           // the cell's transmission at the window: row (y0 + line) mod tny, columns
           // (x0 + x) mod tnx with (x0, y0) the window origin of wave w (exact integers)
           const int64_t px = a.wave_u[2 * w] * a.tnx / a.Qx, py = a.wave_u[2 * w + 1] * a.tny / a.Qy;
@@ -1003,14 +1011,14 @@ __attribute__((amdgpu_waves_per_eu(pass_min_waves<N, MODE>(), 8))) void k_pass(P
             v[m] = cmul(v[m], trow[col]);
           }
           late_prefetch(rr);
-          if constexpr (MODE == PASS_ROW_WIN) fft<N, -1, C::WL>(v, j, tw, a.tw, slot);
+          if constexpr (MODE == PASS_ROW_WIN) fft<N, -1, C::WL, 0, 0, SCHED>(v, j, tw, a.tw, slot);
         } else {
           // column FFT, propagator; with pruning the outputs in [3N/8, 5N/8), where the
           // propagator vanishes for every column, are not formed and stay zeros
           bool pruned = false;
           if constexpr (kPrunable) {
             if (prune) {
-              fft<N, -1, C::WL, 0, PRUNE_OUT>(v, j, tw, a.tw, slot);
+              fft<N, -1, C::WL, 0, PRUNE_OUT, SCHED>(v, j, tw, a.tw, slot);
 #pragma unroll
               for (int m = 0; m < C::E; ++m)
                 v[m] = (m == 3 || m == 4) ? make_float2(0.f, 0.f) : cmul(v[m], tab_at(m));
@@ -1018,17 +1026,17 @@ __attribute__((amdgpu_waves_per_eu(pass_min_waves<N, MODE>(), 8))) void k_pass(P
             }
           }
           if (!pruned) {
-            fft<N, -1, C::WL>(v, j, tw, a.tw, slot);
+            fft<N, -1, C::WL, 0, 0, SCHED>(v, j, tw, a.tw, slot);
 #pragma unroll
             for (int m = 0; m < C::E; ++m) v[m] = cmul(v[m], tab_at(m));
           }
           late_prefetch(rr);
           if constexpr (MODE == PASS_COL) {
             if constexpr (kPrunable) {
-              if (prune) fft<N, +1, C::WL, 0, PRUNE_IN>(v, j, tw, a.tw, slot);
-              else fft<N, +1, C::WL>(v, j, tw, a.tw, slot);
+              if (prune) fft<N, +1, C::WL, 0, PRUNE_IN, SCHED>(v, j, tw, a.tw, slot);
+              else fft<N, +1, C::WL, 0, 0, SCHED>(v, j, tw, a.tw, slot);
             } else {
-              fft<N, +1, C::WL>(v, j, tw, a.tw, slot);
+              fft<N, +1, C::WL, 0, 0, SCHED>(v, j, tw, a.tw, slot);
             }
           } else if constexpr (MODE == PASS_GATHER) {
             if (active) {
@@ -1398,14 +1406,20 @@ static int device_cus() {
   return cus;
 }
 
-template <int N, int TW, int MODE>
-static hipError_t pass_launch(const PassArgs& a0, int lines, int B, hipStream_t s) {
+// lengths built with the other radix schedules as well (those with unequal radices whose
+// passes take measurable time), in 4 x 4 and 8 x 8 tiles
+__host__ __device__ constexpr bool sched_variants(int n, int tw) {
+  return (tw == 4 || tw == 8) && (n == 256 || n == 384 || n == 640 || n == 1024 || n == 2048);
+}
+template <int N, int TW, int MODE, int SCHED>
+static hipError_t pass_launch_s(const PassArgs& a0, int lines, int B, hipStream_t s) {
   if (lines % TW) return hipErrorInvalidValue;
-  constexpr int threads = PassCfg<N, TW, pass_waves<MODE>(), pass_kmw<N, MODE>()>::WAVES * 64;
+  constexpr int threads = PassCfg<N, TW, pass_waves<MODE>(), pass_kmw<N, MODE>(), SCHED>::WAVES * 64;
   static std::atomic<int> cached{0};   // workgroups of this kernel resident per CU
   int resident = cached.load(std::memory_order_relaxed);
   if (resident == 0) {
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&resident, (const void*)k_pass<N, TW, MODE>, threads, 0) != hipSuccess ||
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&resident, (const void*)k_pass<N, TW, MODE, SCHED>, threads, 0) !=
+            hipSuccess ||
         resident <= 0)
       resident = 1;
     cached.store(resident, std::memory_order_relaxed);
@@ -1419,50 +1433,63 @@ static hipError_t pass_launch(const PassArgs& a0, int lines, int B, hipStream_t 
   if (items <= 0) return hipSuccess;
   int64_t grid = std::min<int64_t>(items, (int64_t)resident * device_cus());
   if (grid >= 8) grid &= ~(int64_t)7;
-  k_pass<N, TW, MODE><<<(unsigned)grid, threads, 0, s>>>(a);
+  k_pass<N, TW, MODE, SCHED><<<(unsigned)grid, threads, 0, s>>>(a);
   return hipGetLastError();
+}
+// the schedule a length takes unless one is asked for: 640 points run 25-29 % faster with the
+// radix-5 stage last (row and column passes, 512-wave launches); the other lengths are fastest
+// in the base order or within 4 % of it
+__host__ __device__ constexpr int default_sched(int n) { return n == 640 ? 2 : 0; }
+template <int N, int TW, int MODE>
+static hipError_t pass_launch(const PassArgs& a, int lines, int B, hipStream_t s, int sched) {
+  if (sched < 0) sched = default_sched(N);
+  if constexpr (sched_variants(N, TW)) {
+    if (sched == 1) return pass_launch_s<N, TW, MODE, 1>(a, lines, B, s);
+    if (sched == 2) return pass_launch_s<N, TW, MODE, 2>(a, lines, B, s);
+  }
+  return pass_launch_s<N, TW, MODE, 0>(a, lines, B, s);
 }
 
 template <int MODE>
-static hipError_t pass_dispatch(int N, int TW, int lines, const PassArgs& a, int B, hipStream_t s) {
+static hipError_t pass_dispatch(int N, int TW, int lines, const PassArgs& a, int B, hipStream_t s, int sched = -1) {
   if (TW == 16) {
     switch (N) {
-      case 16: return pass_launch<16, 16, MODE>(a, lines, B, s);
-      case 32: return pass_launch<32, 16, MODE>(a, lines, B, s);
-      case 64: return pass_launch<64, 16, MODE>(a, lines, B, s);
-      case 128: return pass_launch<128, 16, MODE>(a, lines, B, s);
-      case 256: return pass_launch<256, 16, MODE>(a, lines, B, s);
-      case 512: return pass_launch<512, 16, MODE>(a, lines, B, s);
+      case 16: return pass_launch<16, 16, MODE>(a, lines, B, s, sched);
+      case 32: return pass_launch<32, 16, MODE>(a, lines, B, s, sched);
+      case 64: return pass_launch<64, 16, MODE>(a, lines, B, s, sched);
+      case 128: return pass_launch<128, 16, MODE>(a, lines, B, s, sched);
+      case 256: return pass_launch<256, 16, MODE>(a, lines, B, s, sched);
+      case 512: return pass_launch<512, 16, MODE>(a, lines, B, s, sched);
     }
   } else if (TW == 4) {
     switch (N) {
-      case 16: return pass_launch<16, 4, MODE>(a, lines, B, s);
-      case 32: return pass_launch<32, 4, MODE>(a, lines, B, s);
-      case 64: return pass_launch<64, 4, MODE>(a, lines, B, s);
-      case 128: return pass_launch<128, 4, MODE>(a, lines, B, s);
-      case 256: return pass_launch<256, 4, MODE>(a, lines, B, s);
-      case 512: return pass_launch<512, 4, MODE>(a, lines, B, s);
-      case 1024: return pass_launch<1024, 4, MODE>(a, lines, B, s);
-      case 2048: return pass_launch<2048, 4, MODE>(a, lines, B, s);
-      case 96: return pass_launch<96, 4, MODE>(a, lines, B, s);
-      case 192: return pass_launch<192, 4, MODE>(a, lines, B, s);
-      case 384: return pass_launch<384, 4, MODE>(a, lines, B, s);
-      case 640: return pass_launch<640, 4, MODE>(a, lines, B, s);
+      case 16: return pass_launch<16, 4, MODE>(a, lines, B, s, sched);
+      case 32: return pass_launch<32, 4, MODE>(a, lines, B, s, sched);
+      case 64: return pass_launch<64, 4, MODE>(a, lines, B, s, sched);
+      case 128: return pass_launch<128, 4, MODE>(a, lines, B, s, sched);
+      case 256: return pass_launch<256, 4, MODE>(a, lines, B, s, sched);
+      case 512: return pass_launch<512, 4, MODE>(a, lines, B, s, sched);
+      case 1024: return pass_launch<1024, 4, MODE>(a, lines, B, s, sched);
+      case 2048: return pass_launch<2048, 4, MODE>(a, lines, B, s, sched);
+      case 96: return pass_launch<96, 4, MODE>(a, lines, B, s, sched);
+      case 192: return pass_launch<192, 4, MODE>(a, lines, B, s, sched);
+      case 384: return pass_launch<384, 4, MODE>(a, lines, B, s, sched);
+      case 640: return pass_launch<640, 4, MODE>(a, lines, B, s, sched);
     }
   } else if (TW == 8) {
     switch (N) {
-      case 16: return pass_launch<16, 8, MODE>(a, lines, B, s);
-      case 32: return pass_launch<32, 8, MODE>(a, lines, B, s);
-      case 64: return pass_launch<64, 8, MODE>(a, lines, B, s);
-      case 128: return pass_launch<128, 8, MODE>(a, lines, B, s);
-      case 256: return pass_launch<256, 8, MODE>(a, lines, B, s);
-      case 512: return pass_launch<512, 8, MODE>(a, lines, B, s);
-      case 1024: return pass_launch<1024, 8, MODE>(a, lines, B, s);
-      case 2048: return pass_launch<2048, 8, MODE>(a, lines, B, s);
-      case 96: return pass_launch<96, 8, MODE>(a, lines, B, s);
-      case 192: return pass_launch<192, 8, MODE>(a, lines, B, s);
-      case 384: return pass_launch<384, 8, MODE>(a, lines, B, s);
-      case 640: return pass_launch<640, 8, MODE>(a, lines, B, s);
+      case 16: return pass_launch<16, 8, MODE>(a, lines, B, s, sched);
+      case 32: return pass_launch<32, 8, MODE>(a, lines, B, s, sched);
+      case 64: return pass_launch<64, 8, MODE>(a, lines, B, s, sched);
+      case 128: return pass_launch<128, 8, MODE>(a, lines, B, s, sched);
+      case 256: return pass_launch<256, 8, MODE>(a, lines, B, s, sched);
+      case 512: return pass_launch<512, 8, MODE>(a, lines, B, s, sched);
+      case 1024: return pass_launch<1024, 8, MODE>(a, lines, B, s, sched);
+      case 2048: return pass_launch<2048, 8, MODE>(a, lines, B, s, sched);
+      case 96: return pass_launch<96, 8, MODE>(a, lines, B, s, sched);
+      case 192: return pass_launch<192, 8, MODE>(a, lines, B, s, sched);
+      case 384: return pass_launch<384, 8, MODE>(a, lines, B, s, sched);
+      case 640: return pass_launch<640, 8, MODE>(a, lines, B, s, sched);
     }
   }
   return hipErrorInvalidValue;
@@ -1474,6 +1501,7 @@ static hipError_t pass_dispatch(int N, int TW, int lines, const PassArgs& a, int
 // 16 x 16 tiles (2 KB) measured slower and need N <= 512.
 static std::atomic<int> g_tile_width{0};   // 0: default; 4, 8 or 16 forces a tile width (tuning)
 void set_tile_width(int tw) { g_tile_width.store((tw == 4 || tw == 8 || tw == 16) ? tw : 0); }
+int radix_schedules(int nx, int ny, int tw) { return sched_variants(nx, tw) || sched_variants(ny, tw) ? 3 : 1; }
 int tile_width(int nx, int ny) {
   const int forced = g_tile_width.load();
   if (nx > 512 || ny > 512) return forced == 8 ? 8 : 4;
@@ -1522,7 +1550,7 @@ hipError_t init_waves(const Tables& T, float2* work, const int64_t* wave_u, int 
   a.table = T.specT;
   a.tw = T.twy;
   a.wave_u = wave_u;
-  return pass_dispatch<PASS_INIT>(T.ny, tw_of(T), T.nx, a, B, s);
+  return pass_dispatch<PASS_INIT>(T.ny, tw_of(T), T.nx, a, B, s, T.sched);
 }
 
 hipError_t row_pass(const Tables& T, float2* work, const float2* trans_j, int B, bool after_column, hipStream_t s) {
@@ -1532,7 +1560,7 @@ hipError_t row_pass(const Tables& T, float2* work, const float2* trans_j, int B,
   a.prune = 0;
   a.table = trans_j;
   a.tw = T.twx;
-  return pass_dispatch<PASS_ROW>(T.nx, tw_of(T), T.ny, a, B, s);
+  return pass_dispatch<PASS_ROW>(T.nx, tw_of(T), T.ny, a, B, s, T.sched);
 }
 
 hipError_t row_pass_specimens(const Tables& T, float2* work, const float2* const* spec_trans, const int32_t* wave_spec,
@@ -1546,7 +1574,7 @@ hipError_t row_pass_specimens(const Tables& T, float2* work, const float2* const
   a.wave_spec = wave_spec;
   a.slice_off = slice_off;
   a.tw = T.twx;
-  return pass_dispatch<PASS_ROW>(T.nx, tw_of(T), T.ny, a, B, s);
+  return pass_dispatch<PASS_ROW>(T.nx, tw_of(T), T.ny, a, B, s, T.sched);
 }
 
 hipError_t row_pass_window(const Tables& Tw, float2* work, const float2* trans_j, int cell_nx, int cell_ny,
@@ -1564,8 +1592,8 @@ hipError_t row_pass_window(const Tables& Tw, float2* work, const float2* trans_j
   a.tny = cell_ny;
   a.hx = Tw.nx / 2;
   a.hy = Tw.ny / 2;
-  return last ? pass_dispatch<PASS_ROW_LAST>(Tw.nx, tw_of(Tw), Tw.ny, a, B, s)
-              : pass_dispatch<PASS_ROW_WIN>(Tw.nx, tw_of(Tw), Tw.ny, a, B, s);
+  return last ? pass_dispatch<PASS_ROW_LAST>(Tw.nx, tw_of(Tw), Tw.ny, a, B, s, Tw.sched)
+              : pass_dispatch<PASS_ROW_WIN>(Tw.nx, tw_of(Tw), Tw.ny, a, B, s, Tw.sched);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -1673,7 +1701,7 @@ hipError_t col_pass(const Tables& T, float2* work, int B, hipStream_t s) {
   PassArgs a = pass_args(T, work);
   a.table = T.propT;
   a.tw = T.twy;
-  return pass_dispatch<PASS_COL>(T.ny, tw_of(T), T.nx, a, B, s);
+  return pass_dispatch<PASS_COL>(T.ny, tw_of(T), T.nx, a, B, s, T.sched);
 }
 
 hipError_t col_gather(const Tables& T, float2* work, int B, void* basis, int D, const int32_t* wave_row, int split,
@@ -1686,7 +1714,7 @@ hipError_t col_gather(const Tables& T, float2* work, int B, void* basis, int D, 
   a.comp = T.compT;
   a.wave_row = wave_row;
   a.split_bf16 = split;
-  return pass_dispatch<PASS_GATHER>(T.ny, tw_of(T), T.nx, a, B, s);
+  return pass_dispatch<PASS_GATHER>(T.ny, tw_of(T), T.nx, a, B, s, T.sched);
 }
 
 hipError_t col_reduce(const Tables& T, float2* work, int B, const int32_t* wave_out, double* img, int ndet,
@@ -1700,7 +1728,7 @@ hipError_t col_reduce(const Tables& T, float2* work, int B, const int32_t* wave_
   a.ndet = ndet;
   a.img_stride = img_stride;
   a.scale = scale;
-  return pass_dispatch<PASS_REDUCE>(T.ny, tw_of(T), T.nx, a, B, s);
+  return pass_dispatch<PASS_REDUCE>(T.ny, tw_of(T), T.nx, a, B, s, T.sched);
 }
 
 static size_t contract_shm(const Contraction& c, int pt, int out) {

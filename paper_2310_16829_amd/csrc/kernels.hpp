@@ -31,6 +31,9 @@ struct Tables {
   // column: column transforms of 512 or 64 points skip forming those outputs and treat them
   // as zeros on the way back
   int prop_z34 = 0;
+  // radix schedule of the transforms (0: base order; 1: its last stage first; 2: its first
+  // stage last; -1: each length's own default); lengths built with one schedule ignore it
+  int sched = -1;
 };
 
 struct Contraction {
@@ -103,6 +106,8 @@ int tile_width(int nx, int ny);
 void set_tile_width(int tw);
 // whether the passes are built for this grid with tile width tw
 bool tile_width_ok(int nx, int ny, int tw);
+// radix schedules the passes of this grid are built with at tile width tw (1 or 3)
+int radix_schedules(int nx, int ny, int tw);
 // initial waves u(. - pos_w): column IFFT of spectrum * modulation
 hipError_t init_waves(const Tables& T, float2* work, const int64_t* wave_u, int B, hipStream_t s);
 // row pass of slice j: row IFFT, * t_j, row FFT

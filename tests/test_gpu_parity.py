@@ -960,3 +960,20 @@ def test_paper_shaped_full_size_sampled():
     e = np.abs(pgot - pref) / np.abs(pref)
     say("  plain pixel per-detector rel err", e)
     assert e.max() < TOL32
+
+
+@pytest.mark.parametrize("sched", [1, 2])
+def test_radix_schedules(sched, monkeypatch):
+    """The other radix orders (last stage first, first stage last) of the lengths built with
+    them (256, 384, 640, 1024, 2048), forced through LMA_RADIX_SCHEDULE: images against the
+    oracle at the same tolerance as the base order."""
+    monkeypatch.setenv("LMA_RADIX_SCHEDULE", str(sched))
+    for n in (256, 384):
+        test_small_and_mid_grids(n)
+    test_mixed_radix_grid_640_by_96()
+    test_mixed_grid_1024_by_256()
+    test_largest_grid_2048()
+    w = WORKLOADS["tiny"]
+    plan, _, _ = build(w, nx=384, ny=384, lx=38.4, ly=38.4, scan=(48, 48), R=(96, 96), L=9, window=(0, 0, 2, 2))
+    assert plan.info().radix_schedule == sched
+    plan.close()
