@@ -719,6 +719,15 @@ __attribute__((amdgpu_waves_per_eu(pass_min_waves<N, MODE>(), 8))) void k_pass(P
   constexpr int CHUNK = stage_chunk(EPT);                  // staging step otherwise
   static_assert(TOTAL % NT == 0, "work item must split evenly over the threads");
   __shared__ float2 tile[(TW + (C::WL ? 1 : 0)) * RS];     // extra line: scratch of idle lanes
+  // Row pass: the item's TW lines of t_j held in LDS while the workgroup's consecutive items
+  // share them (in the XCD-contiguous walk a workgroup takes runs of one tile row over several
+  // waves), read back by each round instead of from L2
+#ifndef LMA_ROW_TAB_LDS
+#define LMA_ROW_TAB_LDS 1
+#endif
+  constexpr bool kTabLds = LMA_ROW_TAB_LDS && MODE == PASS_ROW && PREF && N == 512 && TW == 8;
+  [[maybe_unused]] __shared__ float2 ttab[kTabLds ? TW * N : 1];
+  [[maybe_unused]] int tab_g = -1;                         // tile row whose t_j lines ttab holds
   [[maybe_unused]] __shared__ double part[C::WAVES][8];
   // PASS_INIT: exp(-2 pi i my uy / Qy) at every ky of the item's wave, shared by its lines
   // (when the LDS has room next to the tile: not for 2048-point lines in 8 x 8 tiles)
@@ -889,6 +898,16 @@ __attribute__((amdgpu_waves_per_eu(pass_min_waves<N, MODE>(), 8))) void k_pass(P
           M::at(k * NT + tid, stride_q, lds, off);
           tile[lds] = buf[k];
         }
+        if constexpr (kTabLds) {
+          // every wavefront has finished the previous item's table product (it precedes the
+          // barrier before the write-back)
+          if (g != tab_g) {
+            const float2* src = a.table + (size_t)g * TW * N;
+#pragma unroll
+            for (int k = 0; k < TW * N / NT; ++k) ttab[k * NT + tid] = src[k * NT + tid];
+            tab_g = g;
+          }
+        }
         __syncthreads();
         if (!kLate && walk.valid(l + walk.step)) load_item(l + walk.step, item_bytes);
       } else {
@@ -978,7 +997,10 @@ __attribute__((amdgpu_waves_per_eu(pass_min_waves<N, MODE>(), 8))) void k_pass(P
         [[maybe_unused]] float2 tv[kEarly ? C::E : 1];
         if constexpr (kEarly) {
 #pragma unroll
-          for (int m = 0; m < C::E; ++m) tv[m] = tab[j + T * m];
+          for (int m = 0; m < C::E; ++m) {
+            if constexpr (kTabLds) tv[m] = ttab[r * N + j + T * m];
+            else tv[m] = tab[j + T * m];
+          }
         }
         auto tab_at = [&](int m) -> float2 {
           if constexpr (kEarly) return tv[m];
