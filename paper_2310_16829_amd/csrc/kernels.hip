@@ -719,13 +719,18 @@ __attribute__((amdgpu_waves_per_eu(pass_min_waves<N, MODE>(), 8))) void k_pass(P
   constexpr int CHUNK = stage_chunk(EPT);                  // staging step otherwise
   static_assert(TOTAL % NT == 0, "work item must split evenly over the threads");
   __shared__ float2 tile[(TW + (C::WL ? 1 : 0)) * RS];     // extra line: scratch of idle lanes
-  // Row pass: the item's TW lines of t_j held in LDS while the workgroup's consecutive items
-  // share them (in the XCD-contiguous walk a workgroup takes runs of one tile row over several
-  // waves), read back by each round instead of from L2
+  // Row and column passes: the item's TW lines of the table (t_j, or the propagator) held in
+  // LDS while the workgroup's consecutive items share them (in the XCD-contiguous walk a
+  // workgroup takes runs of one tile row or column over several waves), read back by each
+  // round instead of from L2
 #ifndef LMA_ROW_TAB_LDS
 #define LMA_ROW_TAB_LDS 1
 #endif
-  constexpr bool kTabLds = LMA_ROW_TAB_LDS && MODE == PASS_ROW && PREF && N == 512 && TW == 8;
+#ifndef LMA_COL_TAB_LDS
+#define LMA_COL_TAB_LDS 0   // the column pass measured the same either way (269.1 / 269.6 us)
+#endif
+  constexpr bool kTabLds = ((LMA_ROW_TAB_LDS && MODE == PASS_ROW) || (LMA_COL_TAB_LDS && MODE == PASS_COL)) && PREF &&
+                           N == 512 && TW == 8;
   [[maybe_unused]] __shared__ float2 ttab[kTabLds ? TW * N : 1];
   [[maybe_unused]] int tab_g = -1;                         // tile row whose t_j lines ttab holds
   [[maybe_unused]] __shared__ double part[C::WAVES][8];
