@@ -290,11 +290,12 @@ int64_t wave_bytes(const lma_optics& op) { return (int64_t)op.nx * op.ny * (int6
 
 int auto_batch(const HostPlan& h) {
   if (h.lat.batch > 0) return h.lat.batch;
-  // 1 GiB of waves, but at least 256 waves while they fit 4 GiB, at most 4096 (measured: at
-  // 512^2, 2048-wave batches made each pass 3 % slower per wave than 512; at 1024^2, 256 waves
-  // ran 9 % faster per wave than 128, and at 2048^2 128 waves 4 % faster than 32)
+  // 2 GiB of waves, but at least 256 waves while they fit 4 GiB, at most 4096 (measured at the
+  // medium workload, 512^2 with its band gap: 1024-wave batches 2.5 % faster per step than 512
+  // and as fast as 2048, 64-256 waves 5-25 % slower; at 1024^2, 256 waves ran 9 % faster per
+  // wave than 128, and at 2048^2 128 waves 4 % faster than 32)
   const int64_t wb = wave_bytes(h.op);
-  int64_t b = std::max(((int64_t)1 << 30) / wb, std::min<int64_t>(256, ((int64_t)4 << 30) / wb));
+  int64_t b = std::max(((int64_t)2 << 30) / wb, std::min<int64_t>(256, ((int64_t)4 << 30) / wb));
   return (int)std::max<int64_t>(1, std::min<int64_t>(b, 4096));
 }
 
