@@ -38,9 +38,13 @@ def random_wave(rng, ny, nx):
 
 
 def rel_l2(a, b):
+    """||a - b|| / ||b||; for an all-zero b, 0 if a is zero too, else inf."""
     a = np.asarray(a)
     b = np.asarray(b)
-    return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
+    d, n = np.linalg.norm((a - b).ravel()), np.linalg.norm(b.ravel())
+    if n == 0.0:
+        return 0.0 if d == 0.0 else float("inf")
+    return float(d / n)
 
 
 def longest_zero_run(zero):
