@@ -328,6 +328,9 @@ enum { PRUNE_IN = 1, PRUNE_OUT = 2 };
 #ifndef LMA_PRUNE
 #define LMA_PRUNE 1
 #endif
+#ifndef LMA_PRUNE_ROWS
+#define LMA_PRUNE_ROWS 1
+#endif
 __host__ __device__ constexpr bool fft_prunable(int n) {
   if (!fft_pow2(n) || fft_elems(n) != 8) return false;
   for (int s = 0; s < fft_nstages(n); ++s)
@@ -682,7 +685,10 @@ constexpr int pass_min_waves() {
   if (N == 512 && (MODE == PASS_ROW || MODE == PASS_COL)) return LMA_MIN_WAVES_512;
   return 1;
 }
-template <int N, int TW, int MODE, int SCHED = 0>
+// PR (row passes of 512 and 64 points): positions [3N/8, 5N/8) of every line are zeros on the
+// way in and not stored on the way out, so the inverse transform takes them as zeros and the
+// forward one does not form them
+template <int N, int TW, int MODE, int SCHED = 0, int PR = 0>
 __global__ __launch_bounds__((PassCfg<N, TW, pass_waves<MODE>(), pass_kmw<N, MODE>()>::WAVES * 64))
 __attribute__((amdgpu_waves_per_eu(pass_min_waves<N, MODE>(), 8))) void k_pass(PassArgs a) {
   using C = PassCfg<N, TW, pass_waves<MODE>(), pass_kmw<N, MODE>(), SCHED>;
@@ -1016,11 +1022,11 @@ __attribute__((amdgpu_waves_per_eu(pass_min_waves<N, MODE>(), 8))) void k_pass(P
         // the first stage overwrites the line: every thread of the transform must have read it
         exchange_sync<C::WL>();
         if constexpr (MODE == PASS_ROW) {
-          fft<N, +1, C::WL, 0, 0, SCHED>(v, j, tw, a.tw, slot);
+          fft<N, +1, C::WL, 0, PR ? PRUNE_IN : 0, SCHED>(v, j, tw, a.tw, slot);
 #pragma unroll
           for (int m = 0; m < C::E; ++m) v[m] = cmul(v[m], tab_at(m));
           late_prefetch(rr);
-          fft<N, -1, C::WL, 0, 0, SCHED>(v, j, tw, a.tw, slot);
+          fft<N, -1, C::WL, 0, PR ? PRUNE_OUT : 0, SCHED>(v, j, tw, a.tw, slot);
         } else if constexpr (MODE == PASS_ROW_WIN || MODE == PASS_ROW_LAST) {
           fft<N, +1, C::WL, 0, 0, SCHED>(v, j, tw, a.tw, slot);
           // the cell's transmission at the window: row (y0 + line) mod tny, columns
@@ -1438,14 +1444,14 @@ static int device_cus() {
 __host__ __device__ constexpr bool sched_variants(int n, int tw) {
   return (tw == 4 || tw == 8) && (n == 256 || n == 384 || n == 640 || n == 1024 || n == 2048);
 }
-template <int N, int TW, int MODE, int SCHED>
+template <int N, int TW, int MODE, int SCHED, int PR = 0>
 static hipError_t pass_launch_s(const PassArgs& a0, int lines, int B, hipStream_t s) {
   if (lines % TW) return hipErrorInvalidValue;
   constexpr int threads = PassCfg<N, TW, pass_waves<MODE>(), pass_kmw<N, MODE>(), SCHED>::WAVES * 64;
   static std::atomic<int> cached{0};   // workgroups of this kernel resident per CU
   int resident = cached.load(std::memory_order_relaxed);
   if (resident == 0) {
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&resident, (const void*)k_pass<N, TW, MODE, SCHED>, threads, 0) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&resident, (const void*)k_pass<N, TW, MODE, SCHED, PR>, threads, 0) !=
             hipSuccess ||
         resident <= 0)
       resident = 1;
@@ -1460,7 +1466,7 @@ static hipError_t pass_launch_s(const PassArgs& a0, int lines, int B, hipStream_
   if (items <= 0) return hipSuccess;
   int64_t grid = std::min<int64_t>(items, (int64_t)resident * device_cus());
   if (grid >= 8) grid &= ~(int64_t)7;
-  k_pass<N, TW, MODE, SCHED><<<(unsigned)grid, threads, 0, s>>>(a);
+  k_pass<N, TW, MODE, SCHED, PR><<<(unsigned)grid, threads, 0, s>>>(a);
   return hipGetLastError();
 }
 // the schedule a length takes unless one is asked for: 640 points run 25-29 % faster with the
@@ -1473,6 +1479,13 @@ static hipError_t pass_launch(const PassArgs& a, int lines, int B, hipStream_t s
   if constexpr (sched_variants(N, TW)) {
     if (sched == 1) return pass_launch_s<N, TW, MODE, 1>(a, lines, B, s);
     if (sched == 2) return pass_launch_s<N, TW, MODE, 2>(a, lines, B, s);
+  }
+  if constexpr (MODE == PASS_ROW && fft_prunable(N) && LMA_PRUNE_ROWS) {
+    // the zeros read (tile columns [rlo, rhi)) and the columns not stored ([zlo, zhi)) both
+    // cover [3N/8, 5N/8)
+    const bool in = a.zread && a.rlo * TW <= 3 * N / 8 && a.rhi * TW >= 5 * N / 8;
+    const bool out = a.zlo * TW <= 3 * N / 8 && a.zhi * TW >= 5 * N / 8;
+    if (in && out) return pass_launch_s<N, TW, MODE, 0, 1>(a, lines, B, s);
   }
   return pass_launch_s<N, TW, MODE, 0>(a, lines, B, s);
 }
