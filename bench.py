@@ -258,7 +258,7 @@ PASS_MODES = {"0": "row_pass", "1": "col_pass", "2": "init", "3": "col_gather", 
 
 def _short_name(kernel: str):
     import re
-    m = re.search(r"k_pass<\d+, \d+, (\d)(?:, \d)?>", kernel)
+    m = re.search(r"k_pass<\d+, \d+, (\d)(?:, \d+)*>", kernel)
     if m:
         return PASS_MODES.get(m.group(1))
     for tag, name in KERNEL_NAMES:
