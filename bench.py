@@ -1152,6 +1152,19 @@ def main():
         bytes_per_launch = (waves_per_launch * XY * 16 + XY * 8) * kept
     avg_s = total_ms / launches * 1e-3
     achieved = bytes_per_launch / avg_s / 1e9
+    # both slice passes together (every row and column pass of the step): their algorithmic
+    # bytes over their summed launch time
+    read_avg = ((w.nslices - 1) * kept + first_read) / w.nslices
+    row_bytes = waves_per_launch * XY * 8 * (read_avg + kept) + XY * 8
+    col_bytes = (waves_per_launch * XY * 16 + XY * 8) * kept
+    n_row, t_row = kt.get("row_pass", (0, 0.0))
+    n_col, t_col = kt.get("col_pass", (0, 0.0))
+    both_bytes = n_row * row_bytes + n_col * col_bytes
+    both_s = (t_row + t_col) * 1e-3
+    slice_passes = {"bound": "hbm", "kernels": ["row_pass", "col_pass"], "launches": [n_row, n_col],
+                    "achieved": both_bytes / both_s / 1e9 if both_s > 0 else None, "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": both_bytes / both_s / 1e9 / HBM_PEAK_GBS if both_s > 0 else None,
+                    "algorithmic_bytes": both_bytes, "total_ms": t_row + t_col}
     traffic = load_traffic(dom)
     contraction = contraction_roofline(plan, info, kt)
     # the precision mode: the same configuration with the basis stored as split BF16 and the
@@ -1210,6 +1223,7 @@ def main():
                      "band_gap_columns": [info.gap_lo, info.gap_hi], "kept_fraction": kept,
                      "input_gap_columns": [info.input_gap_lo, info.input_gap_hi],
                      "avg_launch_ms": avg_s * 1e3},
+        "slice_passes": slice_passes,
         "contraction": contraction,
         "contraction_split_bf16": split,
         "plan_build_s": t_build,
