@@ -1938,13 +1938,19 @@ __global__ __launch_bounds__(512) void k_contract_mfma2_dma(Stencil c) {
     const int x = t % c.W, y = t / c.W;
     rowid[t] = t < nt ? c.row_of[((oy + y) % c.Rfy) * c.Rfx + (ox + x) % c.Rfx] : -1;
   }
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  // the wavefront index as a uniform value: the tests of the K-steps' tail are scalar branches
+  // (as per-lane branches, each K-step waited on a vector load of its offset before its LDS read)
+  const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const int sb = wv & 3, kh = wv >> 2;
   const int kk = lane >> 4, n = lane & 15;
   const int k0 = kh * KH;
   float2 A[KH];
 #pragma unroll
   for (int q = 0; q < KH; ++q) A[q] = k0 + q < c.nks ? c.a[(k0 + q) * 64 + lane] : make_float2(0.f, 0.f);
+  // the wavefront's K-step offsets, lane q holding step k0 + q (0 past the last step): each
+  // step reads its offset from that lane into a scalar register
+  static_assert(KH <= 64, "one offset per lane");
+  const int koff = lane < KH && k0 + lane < c.nks ? c.ks_off[k0 + lane] : 0;
   const int base = (sb >> 1) * c.sub_dy * c.W + (sb & 1) * c.sub_dx + kk;
   const int start = c.chunk_start[chunk], len = c.chunk_len[chunk];
   const uint32_t mask = c.chunk_mask[chunk];
@@ -1962,14 +1968,19 @@ __global__ __launch_bounds__(512) void k_contract_mfma2_dma(Stencil c) {
     __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): this wavefront's copies are in LDS
     __syncthreads();
     f32x4 cre = {0.f, 0.f, 0.f, 0.f}, cim = {0.f, 0.f, 0.f, 0.f};
+    // runs of four K-steps under one uniform test: a run's steps past the last one multiply
+    // zero A fragments by the slab's first rows (finite values) and add exact zeros
 #pragma unroll
-    for (int q = 0; q < KH; ++q) {
-      if (k0 + q < c.nks) {
-        const float2 b = slab[(base + c.ks_off[k0 + q]) * 16 + n];
-        cre = __builtin_amdgcn_mfma_f32_16x16x4f32(A[q].x, b.x, cre, 0, 0, 0);
-        cim = __builtin_amdgcn_mfma_f32_16x16x4f32(A[q].x, b.y, cim, 0, 0, 0);
-        cre = __builtin_amdgcn_mfma_f32_16x16x4f32(-A[q].y, b.y, cre, 0, 0, 0);
-        cim = __builtin_amdgcn_mfma_f32_16x16x4f32(A[q].y, b.x, cim, 0, 0, 0);
+    for (int qb = 0; qb < KH; qb += 4) {
+      if (k0 + qb < c.nks) {
+#pragma unroll
+        for (int q = qb; q < qb + 4 && q < KH; ++q) {
+          const float2 b = slab[(base + __builtin_amdgcn_readlane(koff, q)) * 16 + n];
+          cre = __builtin_amdgcn_mfma_f32_16x16x4f32(A[q].x, b.x, cre, 0, 0, 0);
+          cim = __builtin_amdgcn_mfma_f32_16x16x4f32(A[q].x, b.y, cim, 0, 0, 0);
+          cre = __builtin_amdgcn_mfma_f32_16x16x4f32(-A[q].y, b.y, cre, 0, 0, 0);
+          cim = __builtin_amdgcn_mfma_f32_16x16x4f32(A[q].y, b.x, cim, 0, 0, 0);
+        }
       }
     }
     if (kh == 1) {
@@ -2050,7 +2061,9 @@ __global__ __launch_bounds__(512) void k_contract_bf16(Stencil c) {
     const int x = t % c.W, y = t / c.W;
     rowid[t] = t < nt ? c.row_of[((oy + y) % c.Rfy) * c.Rfx + (ox + x) % c.Rfx] : -1;
   }
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  // uniform wavefront index (scalar tail test); each lane's LDS row of every K-step group is
+  // formed once, before the slabs, instead of a vector load of its offset in every group
+  const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const int sb = wv & 3, kh = wv >> 2;
   const int g = lane >> 4, n = lane & 15, kk = lane >> 4;
   const int ng = (c.nks + 3) / 4;
@@ -2068,6 +2081,12 @@ __global__ __launch_bounds__(512) void k_contract_bf16(Stencil c) {
   }
   const bf16x4 sign = {(short)0x8000, (short)0x8000, (short)0x8000, (short)0x8000};
   const int base0 = (sb >> 1) * c.sub_dy * c.W + (sb & 1) * c.sub_dx;
+  int rowq[GH];
+#pragma unroll
+  for (int q = 0; q < GH; ++q) {
+    const int ks = 4 * (g0 + q) + g;
+    rowq[q] = base0 + (g0 + q < ng && ks < c.nks ? c.ks_off[ks] : 0);
+  }
   const int start = c.chunk_start[chunk], len = c.chunk_len[chunk];
   const uint32_t mask = c.chunk_mask[chunk];
   const float2* basis = reinterpret_cast<const float2*>(c.basis);
@@ -2088,8 +2107,7 @@ __global__ __launch_bounds__(512) void k_contract_bf16(Stencil c) {
 #pragma unroll
     for (int q = 0; q < GH; ++q) {
       if (g0 + q < ng) {
-        const int ks = 4 * (g0 + q) + g;
-        const int row = base0 + (ks < c.nks ? c.ks_off[ks] : 0);
+        const int row = rowq[q];
         const uint2 r0 = raw[(row + 0) * 16 + n], r1 = raw[(row + 1) * 16 + n];
         const uint2 r2 = raw[(row + 2) * 16 + n], r3 = raw[(row + 3) * 16 + n];
         // word x: hi_re | lo_re << 16, word y: hi_im | lo_im << 16
