@@ -342,7 +342,15 @@ void lma_batch_destroy(lma_batch* batch);
 lma_status lma_batch_create_grouped(lma_plan* const* plans, int32_t n, const int32_t* nslices, void* hip_stream,
                                     int64_t max_group_bytes, lma_batch** out);
 
-/* Device bytes a plan with these arguments would hold for nslices slices. */
+/* Device bytes a plan with these arguments would hold for nslices slices: the memory side of
+ * the translate reuse of Sec. 4.2.4 (every propagated translate the window needs kept
+ * resident, |rows| x D x 8 bytes, which the paper's partition strategies trade against
+ * multislice runs), plus the wave batch (batch x X x Y x 8 bytes), the nslices transmission
+ * tables and potential staging (12 bytes per pixel each), the window's image and the plan's
+ * tables, counted term by term from the host plan (an upper estimate of what lma_build_basis
+ * and lma_propagate allocate for that slice count; the figure the server admits a specimen
+ * by). Nothing is allocated (host planning only); *bytes is written on success. LMA_ERR_ARG for a null bytes, nslices < 1 or
+ * arguments lma_build_basis would refuse; LMA_ERR_OOM when host planning runs out of memory. */
 lma_status lma_footprint(const lma_optics* optics, const lma_lattice* lattice,
                          const lma_detectors* detectors, int32_t nslices, int64_t* bytes);
 

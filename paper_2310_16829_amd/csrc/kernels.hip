@@ -1329,11 +1329,16 @@ __global__ __launch_bounds__(256) void k_contract_mfma(Stencil c) {
     const int x = t % c.W, y = t / c.W;
     rowid[t] = c.row_of[((oy + y) % c.Rfy) * c.Rfx + (ox + x) % c.Rfx];
   }
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const int kk = lane >> 4, n = lane & 15;
   float2 A[KS];
 #pragma unroll
   for (int ks = 0; ks < KS; ++ks) A[ks] = ks < c.nks ? c.a[ks * 64 + lane] : make_float2(0.f, 0.f);
+  // the K-step offsets one per lane (steps 64 and up in a second register), read into scalar
+  // registers by each step rather than loaded from memory there
+  static_assert(KS <= 128, "two offsets per lane");
+  const int koff0 = lane < c.nks ? c.ks_off[lane] : 0;
+  const int koff1 = KS > 64 && 64 + lane < c.nks ? c.ks_off[64 + lane] : 0;
   // rectangle index of this lane's B element at K-step ks is base + ks_off[ks]
   const int base = (wv >> 1) * c.sub_dy * c.W + (wv & 1) * c.sub_dx + kk;
   const int start = c.chunk_start[chunk], len = c.chunk_len[chunk];
@@ -1365,14 +1370,20 @@ __global__ __launch_bounds__(256) void k_contract_mfma(Stencil c) {
     }
     __syncthreads();
     f32x4 cre = {0.f, 0.f, 0.f, 0.f}, cim = {0.f, 0.f, 0.f, 0.f};
+    // runs of four K-steps under one uniform test; steps past the last multiply zero A
+    // fragments by the slab's first rows and add exact zeros
 #pragma unroll
-    for (int ks = 0; ks < KS; ++ks) {
-      if (ks < c.nks) {
-        const float2 b = slab[(base + c.ks_off[ks]) * 16 + n];
-        cre = __builtin_amdgcn_mfma_f32_16x16x4f32(A[ks].x, b.x, cre, 0, 0, 0);
-        cim = __builtin_amdgcn_mfma_f32_16x16x4f32(A[ks].x, b.y, cim, 0, 0, 0);
-        cre = __builtin_amdgcn_mfma_f32_16x16x4f32(-A[ks].y, b.y, cre, 0, 0, 0);
-        cim = __builtin_amdgcn_mfma_f32_16x16x4f32(A[ks].y, b.x, cim, 0, 0, 0);
+    for (int kb = 0; kb < KS; kb += 4) {
+      if (kb < c.nks) {
+#pragma unroll
+        for (int ks = kb; ks < kb + 4 && ks < KS; ++ks) {
+          const int o = ks < 64 ? __builtin_amdgcn_readlane(koff0, ks) : __builtin_amdgcn_readlane(koff1, ks - 64);
+          const float2 b = slab[(base + o) * 16 + n];
+          cre = __builtin_amdgcn_mfma_f32_16x16x4f32(A[ks].x, b.x, cre, 0, 0, 0);
+          cim = __builtin_amdgcn_mfma_f32_16x16x4f32(A[ks].x, b.y, cim, 0, 0, 0);
+          cre = __builtin_amdgcn_mfma_f32_16x16x4f32(-A[ks].y, b.y, cre, 0, 0, 0);
+          cim = __builtin_amdgcn_mfma_f32_16x16x4f32(A[ks].y, b.x, cim, 0, 0, 0);
+        }
       }
     }
     if (n < rem) {
