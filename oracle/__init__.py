@@ -18,6 +18,7 @@ of Scanning Transmission Electron Microscopy Images"):
   dft         brute-force O(N^2) DFT used to pin the FFT step
 
 Readings of the paper where it is silent or garbled are listed in each function.
-Parity unpinned: the least-squares coefficients themselves (non-unique under
-ill-conditioning; only the approximant they produce is pinned).
+The least-squares coefficients are pinned by the normal equations where the translate set
+has full column rank (they are unique there); for a rank-deficient set only the approximant
+they produce is unique, and only that is pinned.
 """

@@ -12,7 +12,7 @@ import pytest
 import paper_2310_16829_amd as lma
 from paper_2310_16829_amd import _lib
 from oracle import physics as ph
-from oracle.lma import LMA, Lattice, translate_wave
+from oracle.lma import LMA, Lattice, least_squares, translate_wave
 from oracle.multislice import Setup
 from synth import WORKLOADS
 from tests._cases import det_rad, longest_zero_run, oracle_lattice, oracle_setup, rel_l2
@@ -140,6 +140,37 @@ def test_host_plan_matches_oracle(case):
         assert info.max_residual < 1e-12 and max(lm.residual.values()) < 1e-12
     else:
         assert info.max_residual == pytest.approx(max(lm.residual.values()), rel=1e-6)
+
+
+@pytest.mark.parametrize("case", ["tiny", "case2", "f2_paper_style", "nonsquare", "defocus_cs"])
+def test_host_coefficients_equal_the_oracles(case):
+    # where a translate set has full column rank its least-squares coefficients are unique (the
+    # oracle's are pinned by the normal equations), so the planner's own QR / SVD solve must
+    # return those coefficients, not only an equally good approximant (Sec. 4.2.2)
+    w = WORKLOADS["tiny"]
+    kw = {"tiny": {}, "case2": dict(scan=(16, 16), R=(8, 8), L=16),
+          "f2_paper_style": dict(scan=(32, 32), R=(32, 32), f=2, L=25, offset=(0.5, 0.5)),
+          "nonsquare": dict(nx=128, ny=64, lx=12.8, ly=7.2, scan=(16, 16), R=(32, 16), L=24),
+          "defocus_cs": dict(scan=(16, 16), R=(16, 16), L=20)}[case]
+    opt, lat, det = _plan_args(w, **kw)
+    if case == "defocus_cs":            # a complex probe: defocus and spherical aberration
+        opt = lma.optics(opt.nx, opt.ny, opt.lx, opt.ly, opt.wavelength, opt.sigma, opt.dz, opt.bandlimit,
+                         opt.alpha_max, -60.0, 2.0e4)
+    plan = lma.Plan(opt, lat, det, flags=lma.LMA_HOST_ONLY)
+    st = Setup(opt.nx, opt.ny, opt.lx, opt.ly, opt.wavelength, opt.sigma, opt.dz, opt.bandlimit, opt.alpha_max,
+               opt.defocus, opt.cs, (lat.px, lat.py), det_rad(w))
+    ol = Lattice(st, (lat.rx, lat.ry), lat.f, (lat.offset_x, lat.offset_y), lat.L)
+    tr, al = plan.coefficients()
+    for sy in range(ol.ncls_y):
+        for sx in range(ol.ncls_x):
+            s = sy * ol.ncls_x + sx
+            a_o, nbr, res = least_squares(st, ol, st.spec0, sx, sy)
+            assert list(tr[s]) == [tb * ol.Rfx + ta for ta, tb in nbr]
+            B = np.stack([translate_wave(st, st.spec0, ol.translate_position(ta, tb)).ravel() for ta, tb in nbr],
+                         axis=1)
+            sv = np.linalg.svd(B, compute_uv=False)
+            assert sv[-1] > 1e-6 * sv[0]
+            assert np.abs(np.asarray(al[s]) - a_o).max() <= 1e-9 * np.abs(a_o).max()
 
 
 def test_window_rows_are_the_union_of_neighbour_sets():

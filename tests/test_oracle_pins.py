@@ -419,6 +419,27 @@ def test_lma_exit_error_bounded_by_probe_residual():
         assert e_init > 1e-4                         # non-trivial case
 
 
+@pytest.mark.parametrize("R,f,offset,L,probe,defocus", [((8, 8), 1, (0.5, 0.5), 12, (2, 1), 30.0),
+                                                          ((16, 16), 2, (0.5, 0.5), 9, (1, 2), -40.0),
+                                                          ((8, 8), 1, (0.25, 0.5), 16, (3, 0), 0.0)])
+def test_least_squares_coefficients_solve_the_normal_equations(R, f, offset, L, probe, defocus):
+    # Sec. 4.2.2: alpha minimises || psi_p - sum_j alpha_j u_{i_j} ||. The minimiser is the
+    # alpha whose residual is orthogonal to every translate of the set (B^H r = 0), and it is
+    # unique when B has full column rank, so these sets fix the coefficients themselves. A
+    # defocused probe is complex, so a conjugation slip cannot pass
+    st = _setup(scan=(8, 8), defocus=defocus)
+    lat = Lattice(st, R, f, offset, L)
+    al, nbr, res = least_squares(st, lat, st.spec0, *probe)
+    B = np.stack([translate_wave(st, st.spec0, lat.translate_position(ta, tb)).ravel() for ta, tb in nbr], axis=1)
+    psi = st.probe(*probe).ravel()
+    r = psi - B @ al
+    sv = np.linalg.svd(B, compute_uv=False)
+    assert sv[-1] > 1e-3 * sv[0]                     # full column rank, well conditioned
+    assert np.abs(B.conj().T @ r).max() < 1e-12 * sv[0] * np.linalg.norm(psi)
+    assert res == pytest.approx(np.linalg.norm(r) / np.linalg.norm(psi), rel=1e-12)
+    assert 1e-6 < res < 1                            # a true approximation, not an exact one
+
+
 def test_residual_staircase_non_increasing_in_L():
     st = _setup(nx=64, ny=64, lx=12.8, ly=12.8, scan=(16, 16))
     res = []
