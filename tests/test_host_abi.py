@@ -173,6 +173,35 @@ def test_host_coefficients_equal_the_oracles(case):
             assert np.abs(np.asarray(al[s]) - a_o).max() <= 1e-9 * np.abs(a_o).max()
 
 
+@pytest.mark.parametrize("case", ["medium", "tiny", "f2_paper_style"])
+def test_mfma_layout_k_steps_cover_the_sub_block_union(case):
+    # the banded-GEMM layout of the contraction (eqs. lma_approximation_exit1/2): a 4 x 4-probe
+    # sub-block's K-steps are runs of 4 translates along x on each row of the union of its
+    # probes' neighbour sets, so K = 4 x sum over rows of ceil(row span / 4). Counted here from
+    # the oracle's neighbour sets of a sub-block away from the cell's edge (the layout is the
+    # same for every sub-block).
+    w = WORKLOADS["medium" if case == "medium" else "tiny"]
+    kw = dict(scan=(32, 32), R=(32, 32), f=2, L=25, offset=(0.5, 0.5)) if case == "f2_paper_style" else {}
+    opt, lat, det = _plan_args(w, **kw)
+    info = lma.Plan(opt, lat, det, flags=lma.LMA_HOST_ONLY).info()
+    assert info.contract_kernel == 1
+    st = Setup(opt.nx, opt.ny, opt.lx, opt.ly, opt.wavelength, opt.sigma, opt.dz, opt.bandlimit, opt.alpha_max,
+               opt.defocus, opt.cs, (lat.px, lat.py), det_rad(w))
+    ol = Lattice(st, (lat.rx, lat.ry), lat.f, (lat.offset_x, lat.offset_y), lat.L)
+    a0, b0 = lat.px // 8 * 4, lat.py // 8 * 4
+    span = {}
+    for b in range(b0, b0 + 4):
+        for a in range(a0, a0 + 4):
+            for ta, tb in ol.nearest(a, b):
+                lo, hi = span.get(tb, (ta, ta))
+                span[tb] = (min(lo, ta), max(hi, ta))
+    assert all(hi - lo < ol.Rfx // 2 for lo, hi in span.values())     # no wrap-around here
+    nks = sum(-(-(hi - lo + 1) // 4) for lo, hi in span.values())
+    assert info.contract_k == 4 * nks
+    if case == "medium":
+        assert info.contract_k == 272 and lat.L == 144   # the density L / K = 0.53 the bench line reports
+
+
 def test_window_rows_are_the_union_of_neighbour_sets():
     w = WORKLOADS["tiny"]
     opt, lat, det = _plan_args(w, window=(3, 14, 4, 2), L=16)
